@@ -1,0 +1,191 @@
+"""Seeded synthetic inputs for the stray-field operator.
+
+This module only draws and shapes random numbers (NumPy PCG64 generators,
+float64 on the host).  It holds none of the operator's arithmetic, so both the
+GPU path's tests/benchmarks and the CPU reference implementation may use it.
+
+Layout conventions (shared by every caller):
+  * a full-format magnetization is an array ``m[3][nz][ny][nx]`` (x fastest,
+    component index first), matching the column-major vec ordering of the
+    Kronecker form ``A_z (x) A_y (x) A_x`` (Sec. 3, footnote of Cor. kron_op);
+  * grid sizes are given as ``(nx, ny, nz)`` and cell sizes as ``(hx, hy, hz)``;
+  * cell i along an axis has its midpoint at ``origin + (i + 1/2) h``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.default_rng(seed)
+
+
+def _normalize(v: np.ndarray) -> np.ndarray:
+    nrm = np.sqrt(np.sum(v * v, axis=0, keepdims=True))
+    return v / nrm
+
+
+def cell_centres(n: int, h: float, origin: float) -> np.ndarray:
+    """Midpoints of n cells of width h starting at ``origin``."""
+    return origin + (np.arange(n, dtype=np.float64) + 0.5) * h
+
+
+def random_unit_field(n, seed: int = 0) -> np.ndarray:
+    """Independent unit vectors per cell: Gaussian 3-vectors normalised.
+
+    ``n`` is an int (cube) or a triple (nx, ny, nz).  Returns m[3][nz][ny][nx].
+    """
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
+    g = _rng(seed).standard_normal((3, nz, ny, nx))
+    return _normalize(g)
+
+
+def uniform_field(n, axis: int = 2) -> np.ndarray:
+    """Uniform magnetization along ``axis`` (0=x, 1=y, 2=z)."""
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
+    m = np.zeros((3, nz, ny, nx))
+    m[axis] = 1.0
+    return m
+
+
+def vortex_field(n: int = 128, seed: int = 0, noise: float = 0.05) -> np.ndarray:
+    """Smooth vortex on [-1/2, 1/2]^3 plus seeded Gaussian noise, renormalised.
+
+    v = (-y, x, 0.2 exp(-r^2/0.05)) with the cylindrical radius r^2 = x^2 + y^2;
+    m = normalise(normalise(v) + noise * N(0, 1)).
+    """
+    h = 1.0 / n
+    c = cell_centres(n, h, -0.5)
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    v = np.stack([-y, x, 0.2 * np.exp(-(x * x + y * y) / 0.05)])
+    v = _normalize(v)
+    g = _rng(seed).standard_normal(v.shape)
+    return _normalize(v + noise * g)
+
+
+def gaussian_bump_field(n: int) -> np.ndarray:
+    """m(x) = exp(-|x|^2) (1, 1, 1) sampled at the midpoints of [0, 1]^3."""
+    h = 1.0 / n
+    c = cell_centres(n, h, 0.0)
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    s = np.exp(-(x * x + y * y + z * z))
+    return np.stack([s, s, s])
+
+
+def staircase_sphere_field(n: int, axis: int = 2) -> np.ndarray:
+    """Uniform magnetization inside the ball inscribed in the unit cube."""
+    h = 1.0 / n
+    c = cell_centres(n, h, -0.5)
+    z, y, x = np.meshgrid(c, c, c, indexing="ij")
+    inside = (x * x + y * y + z * z) <= 0.25
+    m = np.zeros((3, n, n, n))
+    m[axis][inside] = 1.0
+    return m
+
+
+# ---------------------------------------------------------------- structured
+@dataclass
+class CPInput:
+    """Per magnetization component q: weights lam[q] (r,), factors U[q][d]
+    of shape (n_d, r) for d = x, y, z."""
+    lam: list
+    U: list
+
+
+@dataclass
+class TuckerInput:
+    """Per component q: core C[q] of shape (r_x, r_y, r_z) indexed [a][b][c]
+    and factors U[q][d] of shape (n_d, r_d)."""
+    core: list
+    U: list
+
+
+@dataclass
+class TTInput:
+    """Per component q: G1[q] (n_x, r1), G2[q] (r1, n_y, r2), G3[q] (r2, n_z)."""
+    G1: list
+    G2: list
+    G3: list
+
+
+def cp_input(n, rank: int = 10, seed: int = 1, dtype=np.float64) -> CPInput:
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
+    rng = _rng(seed)
+    lam, U = [], []
+    for _q in range(3):
+        lam.append(np.ones(rank, dtype=dtype))
+        U.append([rng.uniform(-1.0, 1.0, size=(nd, rank)).astype(dtype) for nd in (nx, ny, nz)])
+    return CPInput(lam=lam, U=U)
+
+
+def tucker_input(n, ranks=(8, 8, 8), seed: int = 1, dtype=np.float64) -> TuckerInput:
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
+    rng = _rng(seed)
+    core, U = [], []
+    for _q in range(3):
+        core.append(rng.uniform(-1.0, 1.0, size=tuple(ranks)).astype(dtype))
+        U.append([rng.uniform(-1.0, 1.0, size=(nd, rd)).astype(dtype)
+                  for nd, rd in zip((nx, ny, nz), ranks)])
+    return TuckerInput(core=core, U=U)
+
+
+def tt_input(n, ranks=(8, 8), seed: int = 1, dtype=np.float64) -> TTInput:
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
+    r1, r2 = ranks
+    rng = _rng(seed)
+    G1, G2, G3 = [], [], []
+    for _q in range(3):
+        G1.append(rng.uniform(-1.0, 1.0, size=(nx, r1)).astype(dtype))
+        G2.append(rng.uniform(-1.0, 1.0, size=(r1, ny, r2)).astype(dtype))
+        G3.append(rng.uniform(-1.0, 1.0, size=(r2, nz)).astype(dtype))
+    return TTInput(G1=G1, G2=G2, G3=G3)
+
+
+# ---------------------------------------------------------------- batches
+@dataclass
+class BatchState:
+    n: tuple          # (nx, ny, nz)
+    h: tuple          # (hx, hy, hz), cubic cells, longest edge of the grid = 1
+    seed: int
+    m: np.ndarray = field(repr=False, default=None)
+
+
+def batch_grids(count: int = 256, seed: int = 2, with_fields: bool = True):
+    """Uneven batch: state s with s % 8 == 7 is a 256x256xnz film with
+    nz = (4, 8, 16)[(s // 8) % 3]; every other state is a cube with edge drawn
+    uniformly from {16..96}.  Every grid is scaled so its longest edge is 1 and
+    cells are cubic.  Magnetizations are random unit vectors."""
+    rng = _rng(seed)
+    states = []
+    for s in range(count):
+        if s % 8 == 7:
+            n = (256, 256, (4, 8, 16)[(s // 8) % 3])
+        else:
+            e = int(rng.integers(16, 97))
+            n = (e, e, e)
+        hcell = 1.0 / max(n)
+        st = BatchState(n=n, h=(hcell, hcell, hcell), seed=seed * 100003 + s)
+        if with_fields:
+            st.m = random_unit_field(n, seed=st.seed)
+        states.append(st)
+    return states
+
+
+# ---------------------------------------------------------------- learned rule
+def quad_training_cases(count: int = 20000, seed: int = 3):
+    """Features for the node-proposal network: grids 32^3..64^3 with random
+    aspect ratios, cell size h = 1/n_max (unit longest edge), log10 tolerance
+    uniform in [-9, -4] and a requested node count R' uniform in {16..32}.
+
+    Returns a dict of arrays: n (count, 3) int, h (count,), log10_tol (count,),
+    rprime (count,) int.
+    """
+    rng = _rng(seed)
+    n = rng.integers(32, 65, size=(count, 3))
+    h = 1.0 / n.max(axis=1)
+    log10_tol = rng.uniform(-9.0, -4.0, size=count)
+    rprime = rng.integers(16, 33, size=count)
+    return {"n": n.astype(np.int64), "h": h, "log10_tol": log10_tol,
+            "rprime": rprime.astype(np.int64)}
