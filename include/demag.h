@@ -1,0 +1,167 @@
+/*
+ * demag.h -- C ABI of the MI355X (gfx950) stray-field library.
+ *
+ * Computes the collocated scalar potential and demagnetizing field of a
+ * cell-wise constant magnetization on a uniform tensor grid with the separable
+ * (Kronecker-product) sinc-quadrature operator of Exl et al., "FFT-based
+ * Kronecker product approximation to micromagnetic long-range interactions"
+ * (arXiv 1212.3509): Cor. kron_op, Eq. (kron_operator), with the Toeplitz
+ * (convolution) structure of Sec. 4.2, Eqs. (conv_op)-(conv_pot).
+ *
+ * Conventions shared by every entry point
+ *   - Physical sign: phi(x) = 1/(4 pi) int m(y).(x - y)/|x - y|^3 dy and
+ *     h = -grad phi (Eq. (intop2) with the sign obtained by integrating
+ *     Eq. (intop1) by parts).  A uniformly magnetized cube has h = -m/3 at its
+ *     centre.
+ *   - Full-format arrays are dense, x fastest: m[3][nz][ny][nx],
+ *     phi[nz][ny][nx], h[3][nz][ny][nx] (component index first).
+ *   - The field is the exact derivative of the separable potential with
+ *     respect to the target point (not the finite differences of Sec. 4).
+ *   - Device pointers are HIP device addresses on the context's device; host
+ *     pointers are ordinary process memory.  The caller owns every buffer it
+ *     passes; the library owns its handles and internal workspace.
+ *   - All GPU work is enqueued on the context's stream and returns before it
+ *     completes (the caller synchronizes).  Host outputs documented as such are
+ *     complete on return.
+ *   - Every call returns a status; arguments are validated before anything is
+ *     launched, and on error nothing has been enqueued.  demag_last_error()
+ *     gives a message for the calling thread's last failure.
+ */
+#ifndef DEMAG_H
+#define DEMAG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DEMAG_OK = 0,
+  DEMAG_E_INVAL = 1,        /* argument out of its documented range */
+  DEMAG_E_NOMEM = 2,        /* device or host allocation failed */
+  DEMAG_E_HIP = 3,          /* HIP runtime error */
+  DEMAG_E_UNSUPPORTED = 4   /* valid request this build does not support */
+} demag_status;
+
+/* Arithmetic of the mode products.  Factor assembly is always FP64.
+ *   DEMAG_FP64    FP64 inputs/outputs, FP64 matrix-core products.
+ *   DEMAG_FP32    FP32 inputs/outputs, FP32 matrix-core products.
+ *   DEMAG_BF16X2  FP32 inputs/outputs; each operand split into two bfloat16
+ *                 parts (hi, lo), products hi*hi + hi*lo + lo*hi accumulated
+ *                 in FP32.
+ *   DEMAG_BF16X3  as BF16X2 with a third part; six products, FP32 accumulate. */
+typedef enum {
+  DEMAG_FP64 = 0,
+  DEMAG_FP32 = 1,
+  DEMAG_BF16X2 = 2,
+  DEMAG_BF16X3 = 3
+} demag_prec;
+
+/* Uniform tensor grid (Sec. 3.1): n[d] cells of size h[d] along x, y, z.
+ * Requires 1 <= n[d] <= 4096 and h[d] > 0. */
+typedef struct {
+  int32_t n[3];
+  double h[3];
+} demag_grid;
+
+/* Quadrature rule (Sec. 3.3, Cor. kron_op).  Nodes t_k = k*theta, k = 1..M,
+ * tau_k = sinh t_k, weights alpha_k = 2 theta cosh t_k sinh^2 t_k (the folded
+ * +-k pair of the symmetric sinc rule); the weight of node k in the potential
+ * kernel is alpha_k / (2 pi^(3/2)).
+ *   step_rule 0: theta = c0 ln(M)/M (Cor. kron_op; c0 = 2.15 in Sec. 3.5);
+ *   step_rule 1: theta = ln(2 pi a M / b)/(a M) with a = 2, b = rho_min/4,
+ *                rho_min = (h_min/2)^2 (Thm. sinc_theo), in the scaled domain.
+ * If t and alpha are both non-NULL they give an explicit rule instead (host
+ * arrays of length M, t_k > 0), e.g. a shortened learned rule.
+ * The grid is scaled so its longest edge is 1 before the rule is applied
+ * (Sec. 3.5); the potential is scaled back, the field is scale-free.
+ * Requires 1 <= M <= 256. */
+typedef struct {
+  int32_t M;
+  double c0;
+  int32_t step_rule;
+  const double *t;
+  const double *alpha;
+} demag_quad;
+
+typedef struct demag_ctx demag_ctx;          /* opaque: device, stream, workspace */
+typedef struct demag_factors demag_factors;  /* opaque: assembled 1D factors */
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the device's null stream). */
+demag_status demag_create(int device, void *hip_stream, demag_ctx **out);
+/* Release the context and its workspace (waits for the stream first). */
+demag_status demag_destroy(demag_ctx *ctx);
+/* Change the stream later calls enqueue on. */
+demag_status demag_set_stream(demag_ctx *ctx, void *hip_stream);
+/* Upper bound in bytes of the internal workspace of demag_apply_full (the
+ * node loop is split into chunks that fit).  Default 16 GiB. */
+demag_status demag_set_workspace_limit(demag_ctx *ctx, size_t bytes);
+/* Message of the calling thread's most recent failure ("" if none). */
+const char *demag_last_error(void);
+
+/* Assemble the 1D factors of Cor. kron_op / Eq. (conv_pot) for every axis,
+ * factor type and node, in FP64 on the GPU (erf/erfc differences, expm1
+ * forms; Eq. (f_anal) and Sec. 4.2), plus their FP32 and bfloat16-split
+ * copies.  Layout per axis d: [type][k][J + n_d - 1], J = -(n_d-1)..n_d-1,
+ * types 0 = E~, 1 = X~, 2 = P~ = -X'~, 3 = Q~ = -E'~ = 2 tau^2 X~, each scaled
+ * by w_k = (alpha_k / (2 pi^(3/2)))^(1/3) and computed in the scaled domain
+ * (the potential's length factor is applied by the apply calls), where
+ *   E(J)  = int_a^b exp(-tau^2 x^2) dx,  X(J) = int_a^b x exp(-tau^2 x^2) dx,
+ *   X'(J) = b exp(-tau^2 b^2) - a exp(-tau^2 a^2),  [a, b] = [(J-1/2)h, (J+1/2)h].
+ * On success *out is a new handle (free with demag_factors_free); the
+ * assembly is enqueued on the context's stream. */
+demag_status demag_assemble_factors(demag_ctx *ctx, const demag_grid *grid,
+                                    const demag_quad *quad, demag_factors **out);
+demag_status demag_factors_free(demag_factors *f);
+/* Number of nodes M of an assembled rule. */
+demag_status demag_factors_count(const demag_factors *f, int32_t *M);
+/* Host copies (length M) of t_k, tau_k and alpha_k in the scaled domain; any
+ * pointer may be NULL. */
+demag_status demag_factors_nodes(const demag_factors *f, double *t, double *tau,
+                                 double *alpha);
+/* Copy the FP64 factor table of axis d (0..2), [4][M][2 n_d - 1] doubles, to
+ * host memory `dst`.  Synchronizes the context's stream. */
+demag_status demag_factors_download(demag_ctx *ctx, const demag_factors *f, int32_t d,
+                                    double *dst);
+
+/* Full-format apply, path (a): for every node, the 23 mode products of
+ * Eq. (modemul) (6 along z, 9 along y, 8 along x, sharing partial products
+ * between outputs), accumulated over nodes into
+ *   phi = sum_k sum_q  m_q x_x F x_y F x_z F        (potential, Eq. (kron_operator))
+ *   h_p = sum_k sum_q  (the same with axis p's factor differentiated).
+ * m: device, [3][nz][ny][nx], FP64 if prec == DEMAG_FP64 else FP32.
+ * phi: device [nz][ny][nx] or NULL; h: device [3][nz][ny][nx] or NULL (at
+ * least one non-NULL), same element type as m.  Buffers must not overlap and
+ * must be 16-byte aligned.  The grid is the one the factors were assembled
+ * for. */
+demag_status demag_apply_full(demag_ctx *ctx, const demag_factors *f, demag_prec prec,
+                              const void *m, void *phi, void *h);
+
+/* The bfloat16 split used by DEMAG_BF16X2/X3 on the device, exposed for
+ * checking: x (device, count floats) -> parts (device, [nparts][count]
+ * uint16 bit patterns): hi = bf16(x), lo = bf16(x - hi), lo2 = bf16(x - hi -
+ * lo), each rounded to nearest even.  1 <= nparts <= 3. */
+demag_status demag_bf16_split(demag_ctx *ctx, const float *x, uint16_t *parts, size_t count,
+                              int32_t nparts);
+
+/* Kernel timing.  While enabled, every kernel launch of the library is
+ * bracketed by HIP events on the context's stream and attributed to a label
+ * (e.g. "fp64/x/nout2").  demag_profile_enable(ctx, 1) clears previous
+ * records; 0 stops recording.  demag_profile_read synchronizes the stream and
+ * writes, for up to `max` labels, the label (NUL-terminated, at most 47
+ * chars, into labels + 48*i), the summed milliseconds, the number of launches,
+ * and the algorithmic FLOPs and bytes of those launches (the operation count
+ * and the compulsory HBM traffic defined by the work itself, not by the
+ * tiling); *count receives the number of labels written. */
+demag_status demag_profile_enable(demag_ctx *ctx, int32_t enable);
+demag_status demag_profile_read(demag_ctx *ctx, int32_t max, char *labels, double *total_ms,
+                                int64_t *launches, double *flops, double *bytes, int32_t *count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEMAG_H */

@@ -1,0 +1,144 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "demag.h"
+
+namespace demag {
+
+void set_error(const std::string &msg);
+
+#define DEMAG_TRY_HIP(expr)                                                        \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess) {                                                        \
+      ::demag::set_error(std::string(#expr) + ": " + hipGetErrorString(e_));       \
+      return DEMAG_E_HIP;                                                          \
+    }                                                                              \
+  } while (0)
+
+#define DEMAG_REQUIRE(cond, msg)                                                   \
+  do {                                                                             \
+    if (!(cond)) {                                                                 \
+      ::demag::set_error(msg);                                                     \
+      return DEMAG_E_INVAL;                                                        \
+    }                                                                              \
+  } while (0)
+
+// Factor types per axis, in table order.
+enum FactorType { F_E = 0, F_X = 1, F_P = 2, F_Q = 3, F_NTYPES = 4 };
+
+// One term of a left Toeplitz product: input tensor (buffer id + element
+// offset) times the Toeplitz matrix of generator gen[o] for each output o.
+struct MPTerm {
+  int32_t in_buf;
+  int32_t gen[2];
+  int32_t pad_;
+  int64_t in_off;
+};
+
+// One job: NOUT outputs accumulated over terms [term0, term0 + nterms).
+struct MPJob {
+  int32_t term0;
+  int32_t nterms;
+  int32_t out_buf[2];
+  int64_t out_off[2];
+  double scale[2];
+};
+
+// Geometry of one stage: out[b][i][c] (or out[b][c][i] when transposed)
+//   = sum_terms sum_j T[i][j] in[b][j][c],  i, j < n,  c < C,  b < B.
+struct MPGeom {
+  int n;              // contraction length = output rows = axis length
+  int C;              // columns per batch
+  int B;              // batches
+  int64_t kstride;    // element stride of j in the input
+  int64_t in_bstride; // element stride of b in the input
+  int64_t out_bstride;
+  int transposed;     // store out[b][c][i] instead of out[b][i][c]
+  int genlen;         // 2n - 1
+};
+
+// A stage launch: jobs with the same NOUT and geometry.
+struct StagePlan {
+  MPGeom geom;
+  int axis;           // axis whose generators are used
+  int nout;
+  std::vector<MPJob> jobs;
+  std::vector<MPTerm> terms;
+  MPJob *d_jobs = nullptr;
+  MPTerm *d_terms = nullptr;
+};
+
+// Plan of demag_apply_full for one node chunk size.
+struct FullPlan {
+  int kc = 0;                    // nodes per chunk
+  int nchunks = 0;
+  std::vector<std::vector<StagePlan>> chunks;   // per chunk: stage launches in order
+  size_t ws_elems = 0;           // elements of workspace per chunk
+  ~FullPlan();
+};
+
+} // namespace demag
+
+namespace demag {
+// Optional per-launch timing: an event pair around each kernel launch on the
+// context's stream, accumulated by kernel label when read.
+struct ProfRecord {
+  std::string label;
+  hipEvent_t start, stop;
+  double flops, bytes;
+};
+struct ProfTotals {
+  double ms = 0, flops = 0, bytes = 0;
+  int64_t launches = 0;
+};
+}  // namespace demag
+
+struct demag_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t ws_limit = size_t(16) << 30;
+  bool profiling = false;
+  std::vector<demag::ProfRecord> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  std::map<std::string, demag::ProfTotals> prof_totals;
+};
+
+struct demag_factors {
+  int n[3];
+  double h[3];          // physical cell sizes
+  double hs[3];         // scaled cell sizes (longest grid edge = 1)
+  double L;             // length scale: physical = scaled * L
+  int M;
+  std::vector<double> t, tau, alpha, w;
+  double *f64[3] = {nullptr, nullptr, nullptr};   // [4][M][2n-1] per axis
+  float *f32[3] = {nullptr, nullptr, nullptr};
+  uint16_t *bf[3] = {nullptr, nullptr, nullptr};  // [3 parts][4][M][2n-1] bf16 bits
+  void *bfw[3] = {nullptr, nullptr, nullptr};      // [4][M][2n+151][3 parts] 16-byte windows (n <= 1024)
+  std::map<std::pair<int, int>, std::unique_ptr<demag::FullPlan>> plans;  // (prec class, kc)
+};
+
+namespace demag {
+// Record-start / record-stop helpers (no-ops unless profiling is on).
+demag_status prof_begin(demag_ctx *ctx, hipEvent_t *ev);
+demag_status prof_end(demag_ctx *ctx, hipEvent_t start, const std::string &label, double flops, double bytes);
+size_t axis_table_len(const demag_factors *f, int d);  // 4 * M * (2n_d - 1)
+demag_status launch_assemble(demag_ctx *ctx, demag_factors *f);
+demag_status launch_left_stage(demag_ctx *ctx, const demag_factors *f, demag_prec prec,
+                               const StagePlan &sp, void *const bufs[6], int beta);
+int window_entries(int n);
+demag_status launch_build_windows(demag_ctx *ctx, demag_factors *f);
+demag_status launch_left_stage_bf16(demag_ctx *ctx, const demag_factors *f, demag_prec prec,
+                                    const StagePlan &sp, void *const bufs[6], int beta);
+demag_status launch_split(demag_ctx *ctx, const float *x, uint16_t *parts, size_t count, int nparts);
+} // namespace demag

@@ -1,0 +1,273 @@
+// Left Toeplitz mode products with bfloat16-split operands on the matrix
+// cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation).
+//
+// Same contraction as the FP32/FP64 kernel (Eq. (modemul) with Toeplitz
+// factors, Sec. 4.2), but every FP32 operand x is written as
+// x ~ hi + lo (+ lo2) with hi = bf16(x), lo = bf16(x - hi), lo2 = bf16(x - hi - lo)
+// (round to nearest even) and each product is formed from the split parts:
+//   two parts:   hi*hi + hi*lo + lo*hi                           (3 MFMAs)
+//   three parts: the above + hi*lo2 + lo2*hi + lo*lo              (6 MFMAs)
+// Input tensors (the magnetization and the FP32 intermediates) are split in
+// registers as they are loaded; the factors are split once at assembly.
+//
+// Operand layouts of the 16x16x32 instruction: lane l holds A[l % 16][8 (l/16) + e]
+// and B[8 (l/16) + e][l % 16], e = 0..7.  For the Toeplitz A = T[i][j] =
+// g[i - j + n - 1] the eight values of a lane are consecutive generator
+// entries in decreasing order, so the factors are stored as "windows": entry s
+// of a window table holds R[s..s+7] of the reversed generator R[u] = g[2n-2-u]
+// (zero outside), and a fragment is one aligned 16-byte LDS read.
+#include "internal.h"
+
+namespace demag {
+
+namespace {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+struct Bufs {
+  void *p[6];
+};
+
+__device__ inline void split_value(float x, __bf16 &h, __bf16 &l, __bf16 &l2) {
+  h = __bf16(x);
+  const float r = x - float(h);
+  l = __bf16(r);
+  const float r2 = r - float(l);
+  l2 = __bf16(r2);
+}
+
+union Frag {
+  uint4 u;
+  bf8 v;
+};
+
+template <int RB, int CB, int NOUT, bool TR, int PARTS>
+__global__ __launch_bounds__(256) void k_left_bf16(const MPJob *__restrict__ jobs,
+                                                   const MPTerm *__restrict__ terms, Bufs bufs,
+                                                   const uint4 *__restrict__ wtab, MPGeom g, int nw,
+                                                   int col_tiles, int beta) {
+  extern __shared__ uint4 wl[];
+  const int n = g.n;
+  const int cnt = n + 16 * RB + 23;
+  const MPJob job = jobs[blockIdx.z];
+  const int b = blockIdx.y;
+  const int ct = blockIdx.x % col_tiles;
+  const int rg = blockIdx.x / col_tiles;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int kq = lane >> 4;
+  const int row0 = rg * 16 * RB;
+  const int s0min = n - row0 - 16 * RB;
+  // local window entry of this lane for rb = 0, j0 = 0 (see the bound notes:
+  // 0 <= sbase - 16 rb + j0 < cnt for every rb < RB and j0 < n)
+  const int sbase = 16 * RB - 1 - (lane & 15) + 8 * kq;
+  int cols[CB];
+  bool cval[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    cols[cb] = ct * (64 * CB) + wave * (16 * CB) + 16 * cb + (lane & 15);
+    cval[cb] = cols[cb] < g.C;
+  }
+
+  f4 acc[NOUT][RB][CB];
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) acc[o][rb][cb] = f4{0, 0, 0, 0};
+
+  for (int t = 0; t < job.nterms; ++t) {
+    const MPTerm tm = terms[job.term0 + t];
+    __syncthreads();
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+      const uint4 *src = wtab + (size_t(tm.gen[o]) * nw + (s0min + 128)) * 3;
+      for (int e = threadIdx.x; e < cnt; e += 256) {
+#pragma unroll
+        for (int p = 0; p < PARTS; ++p) wl[(o * PARTS + p) * cnt + e] = src[size_t(e) * 3 + p];
+      }
+    }
+    __syncthreads();
+    const float *in = static_cast<const float *>(bufs.p[tm.in_buf]) + tm.in_off + size_t(b) * g.in_bstride;
+    float raw[CB][8];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int j = 8 * kq + e;
+        raw[cb][e] = (cval[cb] && j < n) ? in[size_t(j) * g.kstride + cols[cb]] : 0.0f;
+      }
+    for (int j0 = 0; j0 < n; j0 += 32) {
+      Frag bh[CB], bl[CB], bl2[CB];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          __bf16 h, l, l2;
+          split_value(raw[cb][e], h, l, l2);
+          bh[cb].v[e] = h;
+          bl[cb].v[e] = l;
+          bl2[cb].v[e] = l2;
+        }
+      // prefetch the next K-step while this one is multiplied
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int j = j0 + 32 + 8 * kq + e;
+          raw[cb][e] = (cval[cb] && j < n) ? in[size_t(j) * g.kstride + cols[cb]] : 0.0f;
+        }
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const int idx = sbase - 16 * rb + j0;
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o) {
+          Frag ah, al, al2;
+          ah.u = wl[(o * PARTS + 0) * cnt + idx];
+          al.u = wl[(o * PARTS + 1) * cnt + idx];
+          if (PARTS == 3) al2.u = wl[(o * PARTS + 2) * cnt + idx];
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            f4 a = acc[o][rb][cb];
+            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah.v, bh[cb].v, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah.v, bl[cb].v, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al.v, bh[cb].v, a, 0, 0, 0);
+            if (PARTS == 3) {
+              a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah.v, bl2[cb].v, a, 0, 0, 0);
+              a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al2.v, bh[cb].v, a, 0, 0, 0);
+              a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al.v, bl[cb].v, a, 0, 0, 0);
+            }
+            acc[o][rb][cb] = a;
+          }
+        }
+      }
+    }
+  }
+
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    float *out = static_cast<float *>(bufs.p[job.out_buf[o]]) + job.out_off[o] + size_t(b) * g.out_bstride;
+    const float scale = float(job.scale[o]);
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      if (!cval[cb]) continue;
+      const int c = cols[cb];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = row0 + 16 * rb + 4 * kq + r;   // 16x16 output: row 4 (l/16) + r
+          if (i < n) {
+            const size_t idx = TR ? size_t(c) * n + i : size_t(i) * g.C + c;
+            float v = scale * acc[o][rb][cb][r];
+            if (beta) v += out[idx];
+            out[idx] = v;
+          }
+        }
+    }
+  }
+}
+
+template <int RB, int CB, int NOUT, int PARTS>
+demag_status launch_bf(hipStream_t s, const StagePlan &sp, const uint4 *wtab, int nw, const Bufs &bufs,
+                       int beta) {
+  const MPGeom &g = sp.geom;
+  const int col_tiles = (g.C + 64 * CB - 1) / (64 * CB);
+  const int row_groups = (g.n + 16 * RB - 1) / (16 * RB);
+  dim3 grid(col_tiles * row_groups, g.B, unsigned(sp.jobs.size()));
+  const size_t lds = size_t(NOUT) * PARTS * (g.n + 16 * RB + 23) * sizeof(uint4);
+  if (g.transposed)
+    k_left_bf16<RB, CB, NOUT, true, PARTS>
+        <<<grid, 256, lds, s>>>(sp.d_jobs, sp.d_terms, bufs, wtab, g, nw, col_tiles, beta);
+  else
+    k_left_bf16<RB, CB, NOUT, false, PARTS>
+        <<<grid, 256, lds, s>>>(sp.d_jobs, sp.d_terms, bufs, wtab, g, nw, col_tiles, beta);
+  DEMAG_TRY_HIP(hipGetLastError());
+  return DEMAG_OK;
+}
+
+template <int NOUT, int PARTS>
+demag_status launch_bf_n(hipStream_t s, const StagePlan &sp, const uint4 *wtab, int nw, const Bufs &bufs,
+                         int beta) {
+  const int n = sp.geom.n;
+  if (n <= 16) return launch_bf<1, 1, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
+  if (n <= 32) return launch_bf<2, 1, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
+  if (n <= 64) return launch_bf<4, 1, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
+  return launch_bf<8, 1, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
+}
+
+__global__ void k_build_windows(const uint16_t *__restrict__ bf, uint4 *__restrict__ wtab, int n, int ngen,
+                                int nw, size_t part_stride) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;  // window entry
+  const int gidx = blockIdx.y;                          // generator (type * M + k)
+  if (s >= nw || gidx >= ngen) return;
+  const int L = 2 * n - 1;
+  for (int p = 0; p < 3; ++p) {
+    const uint16_t *gsrc = bf + p * part_stride + size_t(gidx) * L;
+    uint16_t v[8];
+    for (int e = 0; e < 8; ++e) {
+      const int u = s - 128 + e;        // index into the reversed generator
+      v[e] = (u >= 0 && u <= L - 1) ? gsrc[L - 1 - u] : uint16_t(0);
+    }
+    uint4 w;
+    w.x = uint32_t(v[0]) | (uint32_t(v[1]) << 16);
+    w.y = uint32_t(v[2]) | (uint32_t(v[3]) << 16);
+    w.z = uint32_t(v[4]) | (uint32_t(v[5]) << 16);
+    w.w = uint32_t(v[6]) | (uint32_t(v[7]) << 16);
+    wtab[(size_t(gidx) * nw + s) * 3 + p] = w;
+  }
+}
+
+__global__ void k_split(const float *__restrict__ x, uint16_t *__restrict__ parts, size_t count, int nparts) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  __bf16 h, l, l2;
+  split_value(x[i], h, l, l2);
+  parts[i] = __builtin_bit_cast(uint16_t, h);
+  if (nparts > 1) parts[count + i] = __builtin_bit_cast(uint16_t, l);
+  if (nparts > 2) parts[2 * count + i] = __builtin_bit_cast(uint16_t, l2);
+}
+
+}  // namespace
+
+int window_entries(int n) { return 2 * n + 151; }
+
+demag_status launch_build_windows(demag_ctx *ctx, demag_factors *f) {
+  for (int d = 0; d < 3; ++d) {
+    if (!f->bfw[d]) continue;
+    const int n = f->n[d];
+    const int nw = window_entries(n);
+    dim3 grid((nw + 127) / 128, F_NTYPES * f->M);
+    k_build_windows<<<grid, 128, 0, ctx->stream>>>(f->bf[d], reinterpret_cast<uint4 *>(f->bfw[d]), n,
+                                                   F_NTYPES * f->M, nw, axis_table_len(f, d));
+    DEMAG_TRY_HIP(hipGetLastError());
+  }
+  return DEMAG_OK;
+}
+
+demag_status launch_left_stage_bf16(demag_ctx *ctx, const demag_factors *f, demag_prec prec, const StagePlan &sp,
+                                    void *const bufp[6], int beta) {
+  Bufs bufs;
+  for (int i = 0; i < 6; ++i) bufs.p[i] = bufp[i];
+  const uint4 *wtab = reinterpret_cast<const uint4 *>(f->bfw[sp.axis]);
+  const int nw = window_entries(f->n[sp.axis]);
+  if (!wtab) {
+    set_error("bfloat16 window table missing (axis longer than the full-format limit)");
+    return DEMAG_E_UNSUPPORTED;
+  }
+  if (prec == DEMAG_BF16X3)
+    return sp.nout == 1 ? launch_bf_n<1, 3>(ctx->stream, sp, wtab, nw, bufs, beta)
+                        : launch_bf_n<2, 3>(ctx->stream, sp, wtab, nw, bufs, beta);
+  return sp.nout == 1 ? launch_bf_n<1, 2>(ctx->stream, sp, wtab, nw, bufs, beta)
+                      : launch_bf_n<2, 2>(ctx->stream, sp, wtab, nw, bufs, beta);
+}
+
+demag_status launch_split(demag_ctx *ctx, const float *x, uint16_t *parts, size_t count, int nparts) {
+  if (count == 0) return DEMAG_OK;
+  k_split<<<unsigned((count + 255) / 256), 256, 0, ctx->stream>>>(x, parts, count, nparts);
+  DEMAG_TRY_HIP(hipGetLastError());
+  return DEMAG_OK;
+}
+
+}  // namespace demag

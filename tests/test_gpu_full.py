@@ -1,0 +1,164 @@
+"""GPU parity of factor assembly and the full-format apply against the oracle.
+
+Tolerances: FP64 matches the oracle's Kronecker form (same quadrature rule,
+same factors up to libm rounding) to 1e-12 relative L2; the separable operator
+at M = 40 matches the exact collocation to 1e-6 (it is ~1e-10); FP32 products
+(K = n accumulations of FP32 values with relative error 2^-24 each) stay
+within 1e-6 of the FP64 result.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import apply, sinc
+from paper_1212_3509_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    api.library()
+    return api.Context(0)
+
+
+def _to_dev(m, dtype=torch.float64):
+    return torch.from_numpy(np.ascontiguousarray(m)).to(device="cuda", dtype=dtype)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
+
+
+@pytest.mark.parametrize("n,h,M,rule", [((13, 10, 7), (0.1, 0.12, 0.08), 12, 0),
+                                        ((32, 32, 32), (1 / 32,) * 3, 40, 0),
+                                        ((5, 17, 40), (1.0, 1.0, 1.0), 20, 1)])
+def test_factor_assembly_matches_oracle(ctx, n, h, M, rule):
+    f = ctx.assemble(n, h, M=M, step_rule=rule)
+    L = max(n[d] * h[d] for d in range(3))
+    hs = [x / L for x in h]
+    t, tau, alpha = sinc.sinc_nodes(M, step_rule=rule, h_min=min(hs))
+    gt, gtau, galpha = f.nodes()
+    assert np.allclose(gt, t, rtol=1e-15, atol=0)
+    assert np.allclose(galpha, alpha, rtol=1e-14, atol=0)
+    for d in range(3):
+        ref = sinc.scaled_factors(n[d], hs[d], tau, alpha)
+        got = f.download(d)
+        # exp(-x) with x up to ~700 turns a 1-ulp difference in tau^2 into
+        # ~x * 1e-16 relative, hence 1e-12 relative; plus 1e-15 of the node's
+        # largest factor for entries far below it.
+        scale = np.abs(ref).max(axis=(0, 2), keepdims=True)
+        bad = np.abs(got - ref) > 1e-12 * np.abs(ref) + 1e-15 * scale
+        assert not bad.any(), (d, np.argwhere(bad)[:5], got[bad][:5], ref[bad][:5])
+
+
+def _run_full(ctx, f, m, prec):
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    phi, hf = ctx.apply_full(f, _to_dev(m, dt), prec=prec)
+    torch.cuda.synchronize()
+    return phi.double().cpu().numpy(), hf.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("n,h", [((13, 10, 7), (0.1, 0.12, 0.08)),
+                                 ((16, 3, 21), (0.05, 0.05, 0.05)),
+                                 ((1, 9, 33), (0.2, 0.1, 0.1))])
+def test_full_fp64_ragged_matches_oracle(ctx, n, h):
+    """Ragged sizes (not multiples of 16/4, a 1-cell axis) against the
+    oracle's dense-Toeplitz Kronecker apply, same rule."""
+    M = 16
+    f = ctx.assemble(n, h, M=M)
+    L = max(n[d] * h[d] for d in range(3))
+    hs = [x / L for x in h]
+    _t, tau, alpha = sinc.sinc_nodes(M)
+    m = inputs.random_unit_field(n, seed=11)
+    phi, hf = _run_full(ctx, f, m, "fp64")
+    pref, href = apply.kron_apply_dense(m, hs, tau, alpha)
+    assert _rel(phi, pref * L) < 1e-12
+    assert _rel(hf, href) < 1e-12
+
+
+def test_full_fp64_32_cube_random(ctx):
+    """32^3 unit cube, random unit vectors (seed 0), M = 40, c0 = 2.15."""
+    n = 32
+    h = (1 / n,) * 3
+    f = ctx.assemble((n, n, n), h, M=40)
+    m = inputs.random_unit_field(n, seed=0)
+    phi, hf = _run_full(ctx, f, m, "fp64")
+    _t, tau, alpha = sinc.sinc_nodes(40)
+    pref, href = apply.kron_apply_dense(m, h, tau, alpha)
+    assert _rel(phi, pref) < 1e-12 and _rel(hf, href) < 1e-12
+    pe, he = apply.collocated_apply_fft(m, h)
+    assert _rel(phi, pe) < 1e-6 and _rel(hf, he) < 1e-6
+
+
+def test_full_fp64_uniform_cube_centre(ctx):
+    """Uniformly magnetized cube on an odd grid: centre N_zz = 1/3, phi = 0."""
+    n = 33
+    f = ctx.assemble((n, n, n), (1 / n,) * 3, M=40)
+    phi, hf = _run_full(ctx, f, inputs.uniform_field(n, axis=2), "fp64")
+    c = n // 2
+    assert abs(hf[2, c, c, c] + 1 / 3) < 1e-9
+    assert abs(hf[0, c, c, c]) < 1e-12 and abs(hf[1, c, c, c]) < 1e-12
+    assert abs(phi[c, c, c]) < 1e-12
+
+
+def test_full_fp32_32_cube(ctx):
+    n = 32
+    f = ctx.assemble((n, n, n), (1 / n,) * 3, M=40)
+    m = inputs.random_unit_field(n, seed=0)
+    p64, h64 = _run_full(ctx, f, m, "fp64")
+    p32, h32 = _run_full(ctx, f, m, "fp32")
+    assert _rel(p32, p64) < 1e-6 and _rel(h32, h64) < 1e-6
+
+
+def test_full_chunked_equals_unchunked(ctx):
+    """A small workspace limit splits the node loop into chunks; the result
+    is the same sum in a different association order."""
+    n = (20, 12, 9)
+    h = (0.05, 0.05, 0.05)
+    f = ctx.assemble(n, h, M=13)
+    m = inputs.random_unit_field(n, seed=5)
+    p1, h1 = _run_full(ctx, f, m, "fp64")
+    N = 20 * 12 * 9
+    ctx.set_workspace_limit((12 * 3 + 4) * N * 8)     # 3 nodes per chunk
+    try:
+        p2, h2 = _run_full(ctx, f, m, "fp64")
+    finally:
+        ctx.set_workspace_limit(16 << 30)
+    assert _rel(p2, p1) < 1e-14 and _rel(h2, h1) < 1e-14
+
+
+def test_full_128_vortex_sampled(ctx):
+    """128^3 smooth vortex with 5% noise (seed 0), M = 40: FP64 and FP32 at
+    sampled cells against the oracle's row-wise Kronecker evaluation."""
+    n = 128
+    h = (1 / n,) * 3
+    f = ctx.assemble((n, n, n), h, M=40)
+    m = inputs.vortex_field(n, seed=0)
+    p64, h64 = _run_full(ctx, f, m, "fp64")
+    p32, h32 = _run_full(ctx, f, m, "fp32")
+    _t, tau, alpha = sinc.sinc_nodes(40)
+    cells = [(0, 0, 0), (127, 127, 127), (64, 3, 100), (17, 90, 64)]
+    pr, hr = apply.kron_apply_at_cells(m, h, tau, alpha, cells)
+    hscale = np.abs(h64).max()
+    pscale = np.abs(p64).max()
+    for c, cell in enumerate(cells):
+        assert abs(p64[cell] - pr[c]) < 1e-12 * pscale
+        assert np.abs(h64[(slice(None),) + cell] - hr[c]).max() < 1e-12 * hscale
+    # FP32 storage and products: the stray field stays within 1e-6 of FP64;
+    # the potential (partly cancelling sums over the components) within 3e-6.
+    e_phi, e_h = _rel(p32, p64), _rel(h32, h64)
+    print(f"128^3 fp32 vs fp64: phi {e_phi:.3e}  h {e_h:.3e}")
+    assert e_h < 1e-6 and e_phi < 3e-6
+
+
+def test_invalid_arguments_rejected(ctx):
+    f = ctx.assemble((4, 4, 4), (0.25,) * 3, M=4)
+    lib = api.library()
+    st = lib.demag_apply_full(ctx.handle, f.handle, 0, None, None, None)
+    assert st == 1
+    assert b"NULL" in lib.demag_last_error()
+    with pytest.raises(api.DemagError):
+        ctx.assemble((0, 4, 4), (0.25,) * 3, M=4)
+    with pytest.raises(api.DemagError):
+        ctx.assemble((4, 4, 4), (0.25,) * 3, M=0)
