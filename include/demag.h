@@ -140,6 +140,81 @@ demag_status demag_factors_download(demag_ctx *ctx, const demag_factors *f, int3
 demag_status demag_apply_full(demag_ctx *ctx, const demag_factors *f, demag_prec prec,
                               const void *m, void *phi, void *h);
 
+/* ---------------------------------------------------------------- batches
+ * Many states on uneven grids (same quadrature rule), FP64 or FP32.  All
+ * states' intermediate products are formed by one persistent launch per
+ * mode-product stage (a fixed, cost-sorted list of tiles walked by a fixed
+ * set of workgroups: no atomics, reproducible), node chunks sized to the
+ * context's workspace limit.  Fields are packed state after state:
+ *   m   = concat_s m_s[3][nz][ny][nx],   phi = concat_s phi_s[nz][ny][nx],
+ *   h   = concat_s h_s[3][nz][ny][nx];
+ * state s starts at 3*off[s] in m and h and at off[s] in phi, with the
+ * cell offsets off[] from demag_batch_offsets.  1 <= n <= 1024 per axis. */
+typedef struct demag_batch demag_batch;
+demag_status demag_batch_create(demag_ctx *ctx, int32_t count, const demag_grid *grids,
+                                const demag_quad *quad, demag_prec prec, demag_batch **out);
+demag_status demag_batch_free(demag_batch *b);
+/* off: host array of count + 1 cell offsets (off[0] = 0, off[count] = total). */
+demag_status demag_batch_offsets(const demag_batch *b, int64_t *off);
+/* Nodes per chunk, persistent workgroups per launch, and the algorithmic
+ * FLOPs of one apply (dense Toeplitz products); any pointer may be NULL. */
+demag_status demag_batch_info(const demag_batch *b, int32_t *node_chunk, int32_t *persistent_groups,
+                              double *flops_per_apply);
+/* Apply to device buffers m, phi, h (element type of the batch precision,
+ * 16-byte aligned).  use_graph != 0: the launch sequence is captured once as a
+ * HIP graph for these buffers and this stream and replayed on later calls. */
+demag_status demag_batch_apply(demag_ctx *ctx, demag_batch *b, const void *m, void *phi, void *h,
+                               int32_t use_graph);
+/* Autotuner: times each candidate row-block shape (16, 32, 64 or 128 rows
+ * per wave) of the stage kernel for every (axis length, outputs) class of the
+ * batch on the device (reps launches each), keeps the fastest and rebuilds
+ * the batch.  With path != NULL the choices are read from and merged into a
+ * JSON object there ({"fp32/n96/nout2": 8, ...}); cached entries are not
+ * re-timed.  Synchronizes the stream. */
+demag_status demag_batch_tune(demag_ctx *ctx, demag_batch *b, const char *path, int32_t reps);
+
+/* ---------------------------------------------------------------- path (b)
+ * Structured inputs (Sec. 2, Eqs. (CP), (tucker_rep); App. C, Eq. (tt_3d_2)).
+ * Applying the Kronecker operator to a structured tensor needs only the
+ * Toeplitz products of its factor columns (Eqs. (kron_eval_cp),
+ * (kron_eval_tuck)), computed here through zero-padded FFTs of length
+ * L = 2^p >= 2 n_d - 1 (Sec. 4, Eq. (fft_pot)), in FP32 with FP64 kernel
+ * spectra.  Axis lengths up to 4096.
+ *
+ * Column sets per axis d, all device FP32, one column contiguous:
+ *   in[d]:  [3 components q][R_d][n_d]
+ *   out[d]: [3 q][2 s][M][R_d][n_d]
+ * Output column (q, s, k, l) = T_{d,type,k} in[d][q][l], where for the
+ * component's own axis (d == q) type = X~ (s = 0) or P~ (s = 1), and on the
+ * other axes type = E~ (s = 0) or Q~ (s = 1).  Slot s = 1 is the factor
+ * differentiated for the field component along d.  The caller owns all
+ * buffers; out must not overlap in. */
+demag_status demag_prepare_structured(demag_ctx *ctx, demag_factors *f);
+demag_status demag_apply_columns(demag_ctx *ctx, demag_factors *f, const int32_t R[3],
+                                 const float *const in[3], float *const out[3]);
+
+/* CP input, rank r per component (weights pass through unchanged):
+ * U[d] = [3 q][r][n_d] holds column l of U^{(q,d)}.  Result: out[d] as above
+ * with R_d = r, and (if table != NULL) the host int32 term table
+ * [4 outputs (phi, h_x, h_y, h_z)][3 M r terms][3 axes]: term (q, k, l),
+ * index (q M + k) r + l, of output o uses column ((q 2 + s) M + k) r + l of
+ * out[d] with s = 1 exactly when o is the field along d.  Output o is
+ * sum over its terms of lambda^q_l out[x][.] o out[y][.] o out[z][.]. */
+demag_status demag_apply_cp(demag_ctx *ctx, demag_factors *f, int32_t r, const float *const U[3],
+                            float *const out[3], int32_t *table);
+/* Tucker input, ranks r[3]: U[d] = [3 q][r_d][n_d].  Result out[d] with
+ * R_d = r_d and the host block table [4][3 M blocks][3 axes]: block (q, k),
+ * index q M + k, of output o is [[C^q; out[x] cols c_x..c_x+r_x-1, ...]]
+ * with first columns c_d = ((q 2 + s) M + k) r_d. */
+demag_status demag_apply_tucker(demag_ctx *ctx, demag_factors *f, const int32_t r[3],
+                                const float *const U[3], float *const out[3], int32_t *table);
+/* TT input with ranks (1, r1, r2, 1): G1 = [3 q][r1][n_x] (columns of G1),
+ * G2 = [3 q][r1][r2][n_y] (fibres G2[a, :, b]), G3 = [3 q][r2][n_z] (rows of
+ * G3).  As Tucker with R = (r1, r1 r2, r2); block table as for Tucker. */
+demag_status demag_apply_tt(demag_ctx *ctx, demag_factors *f, int32_t r1, int32_t r2,
+                            const float *G1, const float *G2, const float *G3,
+                            float *const out[3], int32_t *table);
+
 /* The bfloat16 split used by DEMAG_BF16X2/X3 on the device, exposed for
  * checking: x (device, count floats) -> parts (device, [nparts][count]
  * uint16 bit patterns): hi = bf16(x), lo = bf16(x - hi), lo2 = bf16(x - hi -

@@ -48,6 +48,17 @@ _SIGS = {
     "demag_factors_nodes": (C.c_int, [_P, _P, _P, _P]),
     "demag_factors_download": (C.c_int, [_P, _P, C.c_int32, _P]),
     "demag_apply_full": (C.c_int, [_P, _P, C.c_int, _P, _P, _P]),
+    "demag_batch_create": (C.c_int, [_P, C.c_int32, _P, C.POINTER(Quad), C.c_int, C.POINTER(_P)]),
+    "demag_batch_free": (C.c_int, [_P]),
+    "demag_batch_offsets": (C.c_int, [_P, _P]),
+    "demag_batch_info": (C.c_int, [_P, _P, _P, _P]),
+    "demag_batch_apply": (C.c_int, [_P, _P, _P, _P, _P, C.c_int32]),
+    "demag_batch_tune": (C.c_int, [_P, _P, C.c_char_p, C.c_int32]),
+    "demag_prepare_structured": (C.c_int, [_P, _P]),
+    "demag_apply_columns": (C.c_int, [_P, _P, _P, _P, _P]),
+    "demag_apply_cp": (C.c_int, [_P, _P, C.c_int32, _P, _P, _P]),
+    "demag_apply_tucker": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "demag_apply_tt": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P]),
     "demag_bf16_split": (C.c_int, [_P, _P, _P, C.c_size_t, C.c_int32]),
     "demag_profile_enable": (C.c_int, [_P, C.c_int32]),
     "demag_profile_read": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, C.POINTER(C.c_int32)]),
@@ -126,6 +137,44 @@ class Factors:
             pass
 
 
+class Batch:
+    """Many states on uneven grids (library handle); fields are packed."""
+
+    def __init__(self, ctx: "Context", handle, count):
+        self.ctx, self.handle, self.count = ctx, handle, count
+
+    def offsets(self) -> np.ndarray:
+        off = np.zeros(self.count + 1, dtype=np.int64)
+        _check(library().demag_batch_offsets(self.handle, off.ctypes.data), "demag_batch_offsets")
+        return off
+
+    def info(self):
+        kc, grid, fl = C.c_int32(), C.c_int32(), C.c_double()
+        _check(library().demag_batch_info(self.handle, C.byref(kc), C.byref(grid), C.byref(fl)), "demag_batch_info")
+        return {"node_chunk": kc.value, "persistent_groups": grid.value, "flops": fl.value}
+
+    def tune(self, path=None, reps: int = 3):
+        self.ctx.use_current_stream()
+        _check(library().demag_batch_tune(self.ctx.handle, self.handle, None if path is None else path.encode(), reps),
+               "demag_batch_tune")
+
+    def apply(self, m, phi, h, use_graph: bool = False):
+        self.ctx.use_current_stream()
+        _check(library().demag_batch_apply(self.ctx.handle, self.handle, _ptr(m), _ptr(phi), _ptr(h),
+                                           1 if use_graph else 0), "demag_batch_apply")
+
+    def free(self):
+        if self.handle:
+            library().demag_batch_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
 class Context:
     """Library context bound to a device and (by default) torch's current stream."""
 
@@ -177,6 +226,68 @@ class Context:
         _check(library().demag_apply_full(self.handle, f.handle, PRECISIONS[prec], _ptr(m), _ptr(phi), _ptr(h)),
                "demag_apply_full")
         return phi, h
+
+    def batch(self, grids, M: int = 40, c0: float = 2.15, step_rule: int = 0, prec: str = "fp32") -> Batch:
+        """grids: list of ((nx, ny, nz), (hx, hy, hz))."""
+        arr = (Grid * len(grids))()
+        for i, (n, h) in enumerate(grids):
+            arr[i] = Grid((C.c_int32 * 3)(*n), (C.c_double * 3)(*h))
+        q = Quad(M, c0, step_rule, None, None)
+        out = C.c_void_p()
+        self.use_current_stream()
+        _check(library().demag_batch_create(self.handle, len(grids), arr, C.byref(q), PRECISIONS[prec],
+                                            C.byref(out)), "demag_batch_create")
+        return Batch(self, out, len(grids))
+
+    # ------------------------------------------------------------ structured
+    def _cols_out(self, f: Factors, R, device):
+        import torch
+        M = f.M
+        return [torch.empty((3, 2, M, R[d], f.n[d]), dtype=torch.float32, device=device) for d in range(3)]
+
+    @staticmethod
+    def _ptr3(ts):
+        return (C.c_void_p * 3)(*[t.data_ptr() for t in ts])
+
+    def apply_columns(self, f: Factors, cols_in):
+        """cols_in[d]: float32 CUDA tensor [3][R_d][n_d].  Returns out[d]
+        [3][2][M][R_d][n_d]."""
+        R = [int(c.shape[1]) for c in cols_in]
+        out = self._cols_out(f, R, cols_in[0].device)
+        self.use_current_stream()
+        Ra = (C.c_int32 * 3)(*R)
+        _check(library().demag_apply_columns(self.handle, f.handle, Ra, self._ptr3(cols_in), self._ptr3(out)),
+               "demag_apply_columns")
+        return out
+
+    def apply_cp(self, f: Factors, U):
+        """U[d]: float32 CUDA tensor [3][r][n_d].  Returns (out[3], table)."""
+        r = int(U[0].shape[1])
+        out = self._cols_out(f, [r, r, r], U[0].device)
+        table = np.empty((4, 3 * f.M * r, 3), dtype=np.int32)
+        self.use_current_stream()
+        _check(library().demag_apply_cp(self.handle, f.handle, r, self._ptr3(U), self._ptr3(out),
+                                        table.ctypes.data), "demag_apply_cp")
+        return out, table
+
+    def apply_tucker(self, f: Factors, U):
+        r = [int(u.shape[1]) for u in U]
+        out = self._cols_out(f, r, U[0].device)
+        table = np.empty((4, 3 * f.M, 3), dtype=np.int32)
+        self.use_current_stream()
+        _check(library().demag_apply_tucker(self.handle, f.handle, (C.c_int32 * 3)(*r), self._ptr3(U),
+                                            self._ptr3(out), table.ctypes.data), "demag_apply_tucker")
+        return out, table
+
+    def apply_tt(self, f: Factors, G1, G2, G3):
+        """G1 [3][r1][n_x], G2 [3][r1][r2][n_y], G3 [3][r2][n_z] (float32 CUDA)."""
+        r1, r2 = int(G1.shape[1]), int(G3.shape[1])
+        out = self._cols_out(f, [r1, r1 * r2, r2], G1.device)
+        table = np.empty((4, 3 * f.M, 3), dtype=np.int32)
+        self.use_current_stream()
+        _check(library().demag_apply_tt(self.handle, f.handle, r1, r2, _ptr(G1), _ptr(G2), _ptr(G3),
+                                        self._ptr3(out), table.ctypes.data), "demag_apply_tt")
+        return out, table
 
     def bf16_split(self, x, nparts: int = 3):
         """Device split of a contiguous float32 CUDA tensor into bfloat16 bit

@@ -153,9 +153,13 @@ void build_chunk(const demag_factors *f, int k0, int kc, double phi_scale,
   auto y1 = [N](int kl, int s) { return (int64_t(kl) * 6 + s) * N; };
   auto y2 = y1;
 
-  MPGeom gz{nz, nx * ny, 1, int64_t(nx) * ny, 0, 0, 0, 2 * nz - 1};
-  MPGeom gy{ny, nx, nz, nx, int64_t(nx) * ny, int64_t(nx) * ny, 1, 2 * ny - 1};
-  MPGeom gx{nx, ny, nz, ny, int64_t(nx) * ny, int64_t(nx) * ny, 1, 2 * nx - 1};
+  const int64_t P = int64_t(nx) * ny;   // one z-plane
+  // along z: columns (y, x) contiguous; output [z][y][x]
+  MPGeom gz{nz, int(P), int(P), 2 * nz - 1, P, 0, 0, 1, P};
+  // along y: columns (z, x); input [z][y][x]; output stored transposed [z][x][y]
+  MPGeom gy{ny, nz * nx, nx, 2 * ny - 1, nx, P, P, ny, 1};
+  // along x: columns (z, y); input [z][x][y]; output back in [z][y][x]
+  MPGeom gx{nx, nz * ny, ny, 2 * nx - 1, ny, P, P, nx, 1};
 
   auto add_job = [](StagePlan &sp, std::initializer_list<MPTerm> terms, int ob0, int64_t oo0, double s0,
                     int ob1, int64_t oo1, double s1) {
@@ -178,6 +182,12 @@ void build_chunk(const demag_factors *f, int k0, int kc, double phi_scale,
     t.gen[0] = g0;
     t.gen[1] = g1;
     return t;
+  };
+  // element offsets of the generators in the stage axis' table
+  auto finish = [](StagePlan &sp) {
+    for (auto &t : sp.terms)
+      for (int o = 0; o < 2; ++o) t.gen_off[o] = int64_t(t.gen[o]) * sp.geom.genlen;
+    sp.rb = default_rb(sp.geom.n);
   };
 
   StagePlan s1;
@@ -245,6 +255,7 @@ void build_chunk(const demag_factors *f, int k0, int kc, double phi_scale,
     }
     s3b.jobs.push_back(j);
   }
+  for (StagePlan *sp : {&s1, &s2a, &s2b, &s3a, &s3b}) finish(*sp);
   stages.clear();
   stages.push_back(std::move(s1));
   stages.push_back(std::move(s2a));
@@ -252,6 +263,14 @@ void build_chunk(const demag_factors *f, int k0, int kc, double phi_scale,
   stages.push_back(std::move(s3a));
   stages.push_back(std::move(s3b));
 }
+
+}  // namespace
+
+void build_chunk_plan(const demag_factors *f, int k0, int kc, double phi_scale, std::vector<StagePlan> &stages) {
+  build_chunk(f, k0, kc, phi_scale, stages);
+}
+
+namespace {
 
 demag_status get_plan(demag_ctx *ctx, demag_factors *f, demag_prec prec, FullPlan **out) {
   const size_t esize = (prec == DEMAG_FP64) ? 8 : 4;
@@ -351,6 +370,85 @@ demag_status demag_destroy(demag_ctx *ctx) {
   for (auto e : ctx->prof_pool) (void)hipEventDestroy(e);
   delete ctx;
   return DEMAG_OK;
+}
+
+demag_status demag_prepare_structured(demag_ctx *ctx, demag_factors *f) {
+  DEMAG_REQUIRE(ctx && f, "demag_prepare_structured: NULL argument");
+  DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  return prepare_spectra(ctx, f);
+}
+
+demag_status demag_apply_columns(demag_ctx *ctx, demag_factors *f, const int32_t R[3], const float *const in[3],
+                                 float *const out[3]) {
+  DEMAG_REQUIRE(ctx && f && R && in && out, "demag_apply_columns: NULL argument");
+  for (int d = 0; d < 3; ++d) {
+    DEMAG_REQUIRE(R[d] >= 0 && R[d] <= 65536, "demag_apply_columns: R out of range");
+    DEMAG_REQUIRE(R[d] == 0 || (in[d] && out[d]), "demag_apply_columns: NULL column buffer");
+    DEMAG_REQUIRE(fft_length(f->n[d]) <= 8192, "demag_apply_columns: n <= 4096 per axis");
+  }
+  DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  demag_status st = prepare_spectra(ctx, f);
+  if (st != DEMAG_OK) return st;
+  for (int d = 0; d < 3; ++d) {
+    st = launch_columns(ctx, f, d, R[d], in[d], out[d]);
+    if (st != DEMAG_OK) return st;
+  }
+  return DEMAG_OK;
+}
+
+namespace {
+// Column numbering of the structured results (see demag.h).
+inline int32_t col_index(int q, int s, int k, int l, int M, int R) { return ((q * 2 + s) * M + k) * R + l; }
+inline int slot_of(int o, int d) { return (o == d + 1) ? 1 : 0; }
+}  // namespace
+
+demag_status demag_apply_cp(demag_ctx *ctx, demag_factors *f, int32_t r, const float *const U[3], float *const out[3],
+                            int32_t *table) {
+  DEMAG_REQUIRE(ctx && f && U && out, "demag_apply_cp: NULL argument");
+  DEMAG_REQUIRE(r >= 1, "demag_apply_cp: rank must be >= 1");
+  const int32_t R[3] = {r, r, r};
+  demag_status st = demag_apply_columns(ctx, f, R, U, out);
+  if (st != DEMAG_OK || !table) return st;
+  const int M = f->M;
+  for (int o = 0; o < 4; ++o)
+    for (int q = 0; q < 3; ++q)
+      for (int k = 0; k < M; ++k)
+        for (int l = 0; l < r; ++l) {
+          int32_t *t = table + ((size_t(o) * 3 * M * r) + (size_t(q) * M + k) * r + l) * 3;
+          for (int d = 0; d < 3; ++d) t[d] = col_index(q, slot_of(o, d), k, l, M, r);
+        }
+  return DEMAG_OK;
+}
+
+namespace {
+void block_table(int M, const int32_t R[3], int32_t *table) {
+  for (int o = 0; o < 4; ++o)
+    for (int q = 0; q < 3; ++q)
+      for (int k = 0; k < M; ++k) {
+        int32_t *t = table + ((size_t(o) * 3 * M) + size_t(q) * M + k) * 3;
+        for (int d = 0; d < 3; ++d) t[d] = col_index(q, slot_of(o, d), k, 0, M, R[d]);
+      }
+}
+}  // namespace
+
+demag_status demag_apply_tucker(demag_ctx *ctx, demag_factors *f, const int32_t r[3], const float *const U[3],
+                                float *const out[3], int32_t *table) {
+  DEMAG_REQUIRE(ctx && f && r && U && out, "demag_apply_tucker: NULL argument");
+  DEMAG_REQUIRE(r[0] >= 1 && r[1] >= 1 && r[2] >= 1, "demag_apply_tucker: ranks must be >= 1");
+  demag_status st = demag_apply_columns(ctx, f, r, U, out);
+  if (st == DEMAG_OK && table) block_table(f->M, r, table);
+  return st;
+}
+
+demag_status demag_apply_tt(demag_ctx *ctx, demag_factors *f, int32_t r1, int32_t r2, const float *G1,
+                            const float *G2, const float *G3, float *const out[3], int32_t *table) {
+  DEMAG_REQUIRE(ctx && f && G1 && G2 && G3 && out, "demag_apply_tt: NULL argument");
+  DEMAG_REQUIRE(r1 >= 1 && r2 >= 1, "demag_apply_tt: ranks must be >= 1");
+  const int32_t R[3] = {r1, r1 * r2, r2};
+  const float *const in[3] = {G1, G2, G3};
+  demag_status st = demag_apply_columns(ctx, f, R, in, out);
+  if (st == DEMAG_OK && table) block_table(f->M, R, table);
+  return st;
 }
 
 demag_status demag_bf16_split(demag_ctx *ctx, const float *x, uint16_t *parts, size_t count, int32_t nparts) {
@@ -461,6 +559,8 @@ demag_status demag_factors_free(demag_factors *f) {
     if (f->f32[d]) (void)hipFree(f->f32[d]);
     if (f->bf[d]) (void)hipFree(f->bf[d]);
     if (f->bfw[d]) (void)hipFree(f->bfw[d]);
+    if (f->spec[d]) (void)hipFree(f->spec[d]);
+    if (f->twiddle[d]) (void)hipFree(f->twiddle[d]);
   }
   delete f;
   return DEMAG_OK;

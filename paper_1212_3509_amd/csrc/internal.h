@@ -36,12 +36,15 @@ void set_error(const std::string &msg);
 enum FactorType { F_E = 0, F_X = 1, F_P = 2, F_Q = 3, F_NTYPES = 4 };
 
 // One term of a left Toeplitz product: input tensor (buffer id + element
-// offset) times the Toeplitz matrix of generator gen[o] for each output o.
+// offset) times the Toeplitz matrix of a generator for each output o, given
+// both as an index (type * M + k, used by the bfloat16 window tables) and as
+// an element offset into the launch's generator table.
 struct MPTerm {
   int32_t in_buf;
   int32_t gen[2];
   int32_t pad_;
   int64_t in_off;
+  int64_t gen_off[2];
 };
 
 // One job: NOUT outputs accumulated over terms [term0, term0 + nterms).
@@ -53,17 +56,34 @@ struct MPJob {
   double scale[2];
 };
 
-// Geometry of one stage: out[b][i][c] (or out[b][c][i] when transposed)
-//   = sum_terms sum_j T[i][j] in[b][j][c],  i, j < n,  c < C,  b < B.
+// Geometry of one stage: out[i][c] = sum_terms sum_j T[i][j] in[j][c] with
+// i, j < n and c < C.  The column index splits as c = co * C1 + ci; the input
+// element of (j, c) is at co * in_S1 + ci + j * kstride, the output element
+// of (i, c) at co * out_S1 + ci * out_cs + i * out_is.
 struct MPGeom {
-  int n;              // contraction length = output rows = axis length
-  int C;              // columns per batch
-  int B;              // batches
-  int64_t kstride;    // element stride of j in the input
-  int64_t in_bstride; // element stride of b in the input
-  int64_t out_bstride;
-  int transposed;     // store out[b][c][i] instead of out[b][i][c]
-  int genlen;         // 2n - 1
+  int n;
+  int C;
+  int C1;
+  int genlen;          // 2n - 1
+  int64_t kstride;
+  int64_t in_S1;
+  int64_t out_S1;
+  int64_t out_cs;
+  int64_t out_is;
+};
+
+struct Bufs {
+  void *p[6];
+};
+
+// A tile of the persistent batched launch.
+struct BatchItem {
+  int32_t job;
+  int32_t geom;
+  int32_t ct;
+  int16_t rg;
+  int8_t rb;
+  int8_t nout;
 };
 
 // A stage launch: jobs with the same NOUT and geometry.
@@ -71,6 +91,7 @@ struct StagePlan {
   MPGeom geom;
   int axis;           // axis whose generators are used
   int nout;
+  int rb = 8;         // row blocks of 16 per wave
   std::vector<MPJob> jobs;
   std::vector<MPTerm> terms;
   MPJob *d_jobs = nullptr;
@@ -125,6 +146,9 @@ struct demag_factors {
   float *f32[3] = {nullptr, nullptr, nullptr};
   uint16_t *bf[3] = {nullptr, nullptr, nullptr};  // [3 parts][4][M][2n-1] bf16 bits
   void *bfw[3] = {nullptr, nullptr, nullptr};      // [4][M][2n+151][3 parts] 16-byte windows (n <= 1024)
+  bool spec_ready = false;
+  double *spec[3] = {nullptr, nullptr, nullptr};   // [4][M][L/2+1] real or imaginary parts (structured path)
+  void *twiddle[3] = {nullptr, nullptr, nullptr};  // double2 [L/2]
   std::map<std::pair<int, int>, std::unique_ptr<demag::FullPlan>> plans;  // (prec class, kc)
 };
 
@@ -137,8 +161,18 @@ demag_status launch_assemble(demag_ctx *ctx, demag_factors *f);
 demag_status launch_left_stage(demag_ctx *ctx, const demag_factors *f, demag_prec prec,
                                const StagePlan &sp, void *const bufs[6], int beta);
 int window_entries(int n);
+int default_rb(int n);
+size_t items_lds_bytes(int nmax, bool fp64);
+int items_blocks_per_cu(bool fp64, size_t lds);
+void build_chunk_plan(const demag_factors *f, int k0, int kc, double phi_scale, std::vector<StagePlan> &stages);
+demag_status launch_items(demag_ctx *ctx, demag_prec prec, const BatchItem *items, int nitems, int grid,
+                          const MPJob *jobs, const MPTerm *terms, const MPGeom *geoms, void *const bufp[6],
+                          const void *gens, int nmax, int beta);
 demag_status launch_build_windows(demag_ctx *ctx, demag_factors *f);
 demag_status launch_left_stage_bf16(demag_ctx *ctx, const demag_factors *f, demag_prec prec,
                                     const StagePlan &sp, void *const bufs[6], int beta);
 demag_status launch_split(demag_ctx *ctx, const float *x, uint16_t *parts, size_t count, int nparts);
+int fft_length(int n);
+demag_status prepare_spectra(demag_ctx *ctx, demag_factors *f);
+demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, int d, int R, const float *in, float *out);
 } // namespace demag

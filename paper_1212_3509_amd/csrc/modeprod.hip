@@ -1,11 +1,12 @@
 // Left Toeplitz mode products on the matrix cores (FP64 and FP32).
 //
-// One launch computes, for every job and batch b,
-//   out_o[b][i][c] = scale_o * sum_terms sum_j T_{gen(o,term)}[i][j] * in_term[b][j][c]
-// (or stored transposed as out_o[b][c][i]), with the Toeplitz matrices
-// T[i][j] = g[i - j + n - 1] generated from their length 2n-1 generators
-// (Sec. 4.2) and never materialised.  This is the j-mode product of
-// Eq. (modemul) along the axis whose index is j, batched over the other axes.
+// One launch computes, for every job,
+//   out_o[i][c] = scale_o * sum_terms sum_j T_{gen(o,term)}[i][j] * in_term[j][c]
+// with the Toeplitz matrices T[i][j] = g[i - j + n - 1] generated from their
+// length-(2n-1) generators (Sec. 4.2) and never materialised.  This is the
+// j-mode product of Eq. (modemul) along the axis whose index is j; the other
+// two axes are flattened into the column index c = (co, ci), ci < C1, whose
+// input and output addresses are co * S1 + ci * (inner stride) (MPGeom).
 //
 // Tiling (wave64, CDNA4): a workgroup of 4 waves covers 64 columns; each wave
 // owns 16 columns and 16*RB rows as RB blocks of the 16x16x4 MFMA, for NOUT
@@ -14,6 +15,9 @@
 // lane per K-step; the A operand (Toeplitz) comes from the generator staged
 // in LDS (one ds_read per fragment).  Loads of the next 8 K-steps are issued
 // before the current 8 are multiplied.
+//
+// The same tile routine serves the batched path, where one persistent launch
+// walks a list of (job, geometry, tile) items of many grids.
 #include "internal.h"
 
 namespace demag {
@@ -41,31 +45,26 @@ template <> struct Mfma<float> {
   __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-struct Bufs {
-  void *p[6];
-};
-
 constexpr int kUnroll = 8;  // K-steps (of 4) prefetched ahead
 
-template <class T, int RB, int NOUT, bool TR>
-__global__ __launch_bounds__(256) void k_left(const MPJob *__restrict__ jobs,
-                                              const MPTerm *__restrict__ terms, Bufs bufs,
-                                              const T *__restrict__ gens, MPGeom g, int col_tiles,
-                                              int beta) {
-  extern __shared__ unsigned char smem_raw[];
-  T *sg = reinterpret_cast<T *>(smem_raw);
+__host__ __device__ inline size_t tile_lds_elems(int n, int RB, int NOUT) {
+  return size_t(NOUT) * (2 * n + 16 * RB + 32);
+}
+
+// One 64-column x 16*RB-row tile of one job.  sg: LDS, tile_lds_elems(n, RB, NOUT).
+template <class T, int RB, int NOUT>
+__device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__restrict__ terms, const Bufs &bufs,
+                                          const T *__restrict__ gens, const MPGeom &g, int ct, int rg, int beta,
+                                          T *sg) {
   using Mf = Mfma<T>;
   using acc_t = typename Mf::acc_t;
   const int n = g.n;
   const int glds = 2 * n + 16 * RB + 32;
-  const MPJob job = jobs[blockIdx.z];
-  const int b = blockIdx.y;
-  const int ct = blockIdx.x % col_tiles;
-  const int rg = blockIdx.x / col_tiles;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int kq = lane >> 4;
   const int c = ct * 64 + wave * 16 + (lane & 15);
   const bool cvalid = c < g.C;
+  const int co = cvalid ? c / g.C1 : 0, ci = cvalid ? c % g.C1 : 0;
   const int row0 = rg * 16 * RB;
   // LDS index of T[row0 + (lane & 15)][kq] for j0 = 0; add 16 rb - j0.
   const int ibase = row0 + (lane & 15) - kq + n - 1 + 16;
@@ -81,15 +80,14 @@ __global__ __launch_bounds__(256) void k_left(const MPJob *__restrict__ jobs,
     __syncthreads();
 #pragma unroll
     for (int o = 0; o < NOUT; ++o) {
-      const T *gsrc = gens + size_t(tm.gen[o]) * g.genlen;
+      const T *gsrc = gens + tm.gen_off[o];
       for (int idx = threadIdx.x; idx < glds; idx += 256) {
         const int s = idx - 16;
         sg[o * glds + idx] = (s >= 0 && s < g.genlen) ? gsrc[s] : T(0);
       }
     }
     __syncthreads();
-    const T *in = static_cast<const T *>(bufs.p[tm.in_buf]) + tm.in_off + size_t(b) * g.in_bstride +
-                  (cvalid ? c : 0);
+    const T *in = static_cast<const T *>(bufs.p[tm.in_buf]) + tm.in_off + size_t(co) * g.in_S1 + ci;
     T nxt[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
@@ -123,7 +121,7 @@ __global__ __launch_bounds__(256) void k_left(const MPJob *__restrict__ jobs,
   if (!cvalid) return;
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
-    T *out = static_cast<T *>(bufs.p[job.out_buf[o]]) + job.out_off[o] + size_t(b) * g.out_bstride;
+    T *out = static_cast<T *>(bufs.p[job.out_buf[o]]) + job.out_off[o] + size_t(co) * g.out_S1 + size_t(ci) * g.out_cs;
     const T scale = T(job.scale[o]);
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
@@ -131,7 +129,7 @@ __global__ __launch_bounds__(256) void k_left(const MPJob *__restrict__ jobs,
       for (int r = 0; r < 4; ++r) {
         const int i = row0 + 16 * rb + Mf::row(lane, r);
         if (i < n) {
-          const size_t idx = TR ? size_t(c) * n + i : size_t(i) * g.C + c;
+          const size_t idx = size_t(i) * g.out_is;
           T v = scale * acc[o][rb][r];
           if (beta) v += out[idx];
           out[idx] = v;
@@ -140,28 +138,75 @@ __global__ __launch_bounds__(256) void k_left(const MPJob *__restrict__ jobs,
   }
 }
 
-template <class T, int RB, int NOUT>
-demag_status launch_rb(hipStream_t s, const StagePlan &sp, const T *gens, const Bufs &bufs, int beta) {
+template <class T, int RB, int NOUT, int AXIS>
+__global__ __launch_bounds__(256) void k_left(const MPJob *__restrict__ jobs, const MPTerm *__restrict__ terms,
+                                              Bufs bufs, const T *__restrict__ gens, MPGeom g, int col_tiles,
+                                              int beta) {
+  extern __shared__ unsigned char smem_raw[];
+  const MPJob job = jobs[blockIdx.y];
+  left_tile<T, RB, NOUT>(job, terms, bufs, gens, g, blockIdx.x % col_tiles, blockIdx.x / col_tiles, beta,
+                         reinterpret_cast<T *>(smem_raw));
+}
+
+// Persistent variant: workgroup w processes items w, w + G, w + 2G, ...
+// (static order, no atomics); each item names its job, geometry, tile and
+// the (RB, NOUT) shape chosen for it.
+template <class T>
+__global__ __launch_bounds__(256) void k_left_items(const BatchItem *__restrict__ items, int nitems,
+                                                    const MPJob *__restrict__ jobs, const MPTerm *__restrict__ terms,
+                                                    const MPGeom *__restrict__ geoms, Bufs bufs,
+                                                    const T *__restrict__ gens, int beta) {
+  extern __shared__ unsigned char smem_raw[];
+  T *sg = reinterpret_cast<T *>(smem_raw);
+  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+    const BatchItem item = items[it];
+    const MPJob job = jobs[item.job];
+    const MPGeom g = geoms[item.geom];
+    const int key = item.rb * 4 + item.nout;
+    switch (key) {
+      case 1 * 4 + 1: left_tile<T, 1, 1>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
+      case 1 * 4 + 2: left_tile<T, 1, 2>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
+      case 2 * 4 + 1: left_tile<T, 2, 1>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
+      case 2 * 4 + 2: left_tile<T, 2, 2>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
+      case 4 * 4 + 1: left_tile<T, 4, 1>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
+      case 4 * 4 + 2: left_tile<T, 4, 2>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
+      case 8 * 4 + 1: left_tile<T, 8, 1>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
+      default: left_tile<T, 8, 2>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
+    }
+  }
+}
+
+template <class T, int RB, int NOUT, int AXIS>
+demag_status launch_axis(hipStream_t s, const StagePlan &sp, const T *gens, const Bufs &bufs, int beta) {
   const MPGeom &g = sp.geom;
   const int col_tiles = (g.C + 63) / 64;
   const int row_groups = (g.n + 16 * RB - 1) / (16 * RB);
-  dim3 grid(col_tiles * row_groups, g.B, unsigned(sp.jobs.size()));
-  const size_t lds = size_t(NOUT) * (2 * g.n + 16 * RB + 32) * sizeof(T);
-  if (g.transposed)
-    k_left<T, RB, NOUT, true><<<grid, 256, lds, s>>>(sp.d_jobs, sp.d_terms, bufs, gens, g, col_tiles, beta);
-  else
-    k_left<T, RB, NOUT, false><<<grid, 256, lds, s>>>(sp.d_jobs, sp.d_terms, bufs, gens, g, col_tiles, beta);
+  dim3 grid(col_tiles * row_groups, unsigned(sp.jobs.size()));
+  const size_t lds = tile_lds_elems(g.n, RB, NOUT) * sizeof(T);
+  if (lds > 65536)
+    DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_left<T, RB, NOUT, AXIS>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  k_left<T, RB, NOUT, AXIS><<<grid, 256, lds, s>>>(sp.d_jobs, sp.d_terms, bufs, gens, g, col_tiles, beta);
   DEMAG_TRY_HIP(hipGetLastError());
   return DEMAG_OK;
 }
 
+template <class T, int RB, int NOUT>
+demag_status launch_rb(hipStream_t s, const StagePlan &sp, const T *gens, const Bufs &bufs, int beta) {
+  // one template instance per stage axis, so kernel traces separate the stages
+  if (sp.axis == 0) return launch_axis<T, RB, NOUT, 0>(s, sp, gens, bufs, beta);
+  if (sp.axis == 1) return launch_axis<T, RB, NOUT, 1>(s, sp, gens, bufs, beta);
+  return launch_axis<T, RB, NOUT, 2>(s, sp, gens, bufs, beta);
+}
+
 template <class T, int NOUT>
 demag_status launch_nout(hipStream_t s, const StagePlan &sp, const T *gens, const Bufs &bufs, int beta) {
-  const int n = sp.geom.n;
-  if (n <= 16) return launch_rb<T, 1, NOUT>(s, sp, gens, bufs, beta);
-  if (n <= 32) return launch_rb<T, 2, NOUT>(s, sp, gens, bufs, beta);
-  if (n <= 64) return launch_rb<T, 4, NOUT>(s, sp, gens, bufs, beta);
-  return launch_rb<T, 8, NOUT>(s, sp, gens, bufs, beta);
+  switch (sp.rb) {
+    case 1: return launch_rb<T, 1, NOUT>(s, sp, gens, bufs, beta);
+    case 2: return launch_rb<T, 2, NOUT>(s, sp, gens, bufs, beta);
+    case 4: return launch_rb<T, 4, NOUT>(s, sp, gens, bufs, beta);
+    default: return launch_rb<T, 8, NOUT>(s, sp, gens, bufs, beta);
+  }
 }
 
 template <class T>
@@ -171,6 +216,43 @@ demag_status launch_typed(hipStream_t s, const StagePlan &sp, const T *gens, con
 }
 
 }  // namespace
+
+int default_rb(int n) { return n <= 16 ? 1 : n <= 32 ? 2 : n <= 64 ? 4 : 8; }
+
+size_t items_lds_bytes(int nmax, bool fp64) {
+  return tile_lds_elems(nmax, 8, 2) * (fp64 ? 8 : 4);
+}
+
+int items_blocks_per_cu(bool fp64, size_t lds) {
+  int n = 0;
+  hipError_t e = fp64 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_left_items<double>, 256, lds)
+                      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_left_items<float>, 256, lds);
+  return (e == hipSuccess && n > 0) ? n : 1;
+}
+
+demag_status launch_items(demag_ctx *ctx, demag_prec prec, const BatchItem *items, int nitems, int grid,
+                          const MPJob *jobs, const MPTerm *terms, const MPGeom *geoms, void *const bufp[6],
+                          const void *gens, int nmax, int beta) {
+  if (nitems == 0) return DEMAG_OK;
+  Bufs bufs;
+  for (int i = 0; i < 6; ++i) bufs.p[i] = bufp[i];
+  const size_t lds = items_lds_bytes(nmax, prec == DEMAG_FP64);
+  if (prec == DEMAG_FP64) {
+    if (lds > 65536)
+      DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_left_items<double>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    k_left_items<double><<<grid, 256, lds, ctx->stream>>>(items, nitems, jobs, terms, geoms, bufs,
+                                                           static_cast<const double *>(gens), beta);
+  } else {
+    if (lds > 65536)
+      DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_left_items<float>),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    k_left_items<float><<<grid, 256, lds, ctx->stream>>>(items, nitems, jobs, terms, geoms, bufs,
+                                                          static_cast<const float *>(gens), beta);
+  }
+  DEMAG_TRY_HIP(hipGetLastError());
+  return DEMAG_OK;
+}
 
 demag_status launch_left_stage(demag_ctx *ctx, const demag_factors *f, demag_prec prec,
                                const StagePlan &sp, void *const bufp[6], int beta) {
@@ -196,14 +278,14 @@ demag_status launch_left_stage(demag_ctx *ctx, const demag_factors *f, demag_pre
   if (st != DEMAG_OK) return st;
   if (ev) {
     // Algorithmic work of the launch: each term of each job is a dense
-    // n x n Toeplitz times n x (C B) product per output; compulsory traffic
+    // n x n Toeplitz times n x C product per output; compulsory traffic
     // reads each term's input once and writes (and, when accumulating,
-    // reads) each output once.
+    // reads) each output once.  Split precisions count every bfloat16
+    // product they issue.
     const MPGeom &g = sp.geom;
-    const double slab = double(g.n) * g.C * g.B;
-    double flops = 0, bytes = 0;
-    // split precisions count every bfloat16 product they issue
+    const double slab = double(g.n) * g.C;
     const double mult = (prec == DEMAG_BF16X3) ? 6.0 : (prec == DEMAG_BF16X2) ? 3.0 : 1.0;
+    double flops = 0, bytes = 0;
     for (const auto &j : sp.jobs) {
       flops += mult * 2.0 * g.n * slab * j.nterms * sp.nout;
       bytes += slab * esize * (j.nterms + sp.nout * (beta ? 2 : 1));

@@ -25,10 +25,6 @@ namespace {
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-struct Bufs {
-  void *p[6];
-};
-
 __device__ inline void split_value(float x, __bf16 &h, __bf16 &l, __bf16 &l2) {
   h = __bf16(x);
   const float r = x - float(h);
@@ -42,7 +38,7 @@ union Frag {
   bf8 v;
 };
 
-template <int RB, int CB, int NOUT, bool TR, int PARTS>
+template <int RB, int CB, int NOUT, int PARTS>
 __global__ __launch_bounds__(256) void k_left_bf16(const MPJob *__restrict__ jobs,
                                                    const MPTerm *__restrict__ terms, Bufs bufs,
                                                    const uint4 *__restrict__ wtab, MPGeom g, int nw,
@@ -50,8 +46,7 @@ __global__ __launch_bounds__(256) void k_left_bf16(const MPJob *__restrict__ job
   extern __shared__ uint4 wl[];
   const int n = g.n;
   const int cnt = n + 16 * RB + 23;
-  const MPJob job = jobs[blockIdx.z];
-  const int b = blockIdx.y;
+  const MPJob job = jobs[blockIdx.y];
   const int ct = blockIdx.x % col_tiles;
   const int rg = blockIdx.x / col_tiles;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -61,12 +56,15 @@ __global__ __launch_bounds__(256) void k_left_bf16(const MPJob *__restrict__ job
   // local window entry of this lane for rb = 0, j0 = 0 (see the bound notes:
   // 0 <= sbase - 16 rb + j0 < cnt for every rb < RB and j0 < n)
   const int sbase = 16 * RB - 1 - (lane & 15) + 8 * kq;
-  int cols[CB];
+  int64_t inoff[CB], outoff[CB];
   bool cval[CB];
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb) {
-    cols[cb] = ct * (64 * CB) + wave * (16 * CB) + 16 * cb + (lane & 15);
-    cval[cb] = cols[cb] < g.C;
+    const int c = ct * (64 * CB) + wave * (16 * CB) + 16 * cb + (lane & 15);
+    cval[cb] = c < g.C;
+    const int co = cval[cb] ? c / g.C1 : 0, ci = cval[cb] ? c % g.C1 : 0;
+    inoff[cb] = int64_t(co) * g.in_S1 + ci;
+    outoff[cb] = int64_t(co) * g.out_S1 + int64_t(ci) * g.out_cs;
   }
 
   f4 acc[NOUT][RB][CB];
@@ -89,14 +87,14 @@ __global__ __launch_bounds__(256) void k_left_bf16(const MPJob *__restrict__ job
       }
     }
     __syncthreads();
-    const float *in = static_cast<const float *>(bufs.p[tm.in_buf]) + tm.in_off + size_t(b) * g.in_bstride;
+    const float *in = static_cast<const float *>(bufs.p[tm.in_buf]) + tm.in_off;
     float raw[CB][8];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const int j = 8 * kq + e;
-        raw[cb][e] = (cval[cb] && j < n) ? in[size_t(j) * g.kstride + cols[cb]] : 0.0f;
+        raw[cb][e] = (cval[cb] && j < n) ? in[size_t(j) * g.kstride + inoff[cb]] : 0.0f;
       }
     for (int j0 = 0; j0 < n; j0 += 32) {
       Frag bh[CB], bl[CB], bl2[CB];
@@ -116,7 +114,7 @@ __global__ __launch_bounds__(256) void k_left_bf16(const MPJob *__restrict__ job
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int j = j0 + 32 + 8 * kq + e;
-          raw[cb][e] = (cval[cb] && j < n) ? in[size_t(j) * g.kstride + cols[cb]] : 0.0f;
+          raw[cb][e] = (cval[cb] && j < n) ? in[size_t(j) * g.kstride + inoff[cb]] : 0.0f;
         }
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
@@ -147,19 +145,18 @@ __global__ __launch_bounds__(256) void k_left_bf16(const MPJob *__restrict__ job
 
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
-    float *out = static_cast<float *>(bufs.p[job.out_buf[o]]) + job.out_off[o] + size_t(b) * g.out_bstride;
+    float *out = static_cast<float *>(bufs.p[job.out_buf[o]]) + job.out_off[o];
     const float scale = float(job.scale[o]);
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
       if (!cval[cb]) continue;
-      const int c = cols[cb];
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = row0 + 16 * rb + 4 * kq + r;   // 16x16 output: row 4 (l/16) + r
           if (i < n) {
-            const size_t idx = TR ? size_t(c) * n + i : size_t(i) * g.C + c;
+            const size_t idx = outoff[cb] + size_t(i) * g.out_is;
             float v = scale * acc[o][rb][cb][r];
             if (beta) v += out[idx];
             out[idx] = v;
@@ -175,14 +172,12 @@ demag_status launch_bf(hipStream_t s, const StagePlan &sp, const uint4 *wtab, in
   const MPGeom &g = sp.geom;
   const int col_tiles = (g.C + 64 * CB - 1) / (64 * CB);
   const int row_groups = (g.n + 16 * RB - 1) / (16 * RB);
-  dim3 grid(col_tiles * row_groups, g.B, unsigned(sp.jobs.size()));
+  dim3 grid(col_tiles * row_groups, unsigned(sp.jobs.size()));
   const size_t lds = size_t(NOUT) * PARTS * (g.n + 16 * RB + 23) * sizeof(uint4);
-  if (g.transposed)
-    k_left_bf16<RB, CB, NOUT, true, PARTS>
-        <<<grid, 256, lds, s>>>(sp.d_jobs, sp.d_terms, bufs, wtab, g, nw, col_tiles, beta);
-  else
-    k_left_bf16<RB, CB, NOUT, false, PARTS>
-        <<<grid, 256, lds, s>>>(sp.d_jobs, sp.d_terms, bufs, wtab, g, nw, col_tiles, beta);
+  if (lds > 65536)
+    DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_left_bf16<RB, CB, NOUT, PARTS>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  k_left_bf16<RB, CB, NOUT, PARTS><<<grid, 256, lds, s>>>(sp.d_jobs, sp.d_terms, bufs, wtab, g, nw, col_tiles, beta);
   DEMAG_TRY_HIP(hipGetLastError());
   return DEMAG_OK;
 }
@@ -190,11 +185,12 @@ demag_status launch_bf(hipStream_t s, const StagePlan &sp, const uint4 *wtab, in
 template <int NOUT, int PARTS>
 demag_status launch_bf_n(hipStream_t s, const StagePlan &sp, const uint4 *wtab, int nw, const Bufs &bufs,
                          int beta) {
-  const int n = sp.geom.n;
-  if (n <= 16) return launch_bf<1, 1, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
-  if (n <= 32) return launch_bf<2, 1, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
-  if (n <= 64) return launch_bf<4, 1, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
-  return launch_bf<8, 1, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
+  switch (sp.rb) {
+    case 1: return launch_bf<1, 1, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
+    case 2: return launch_bf<2, 1, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
+    case 4: return launch_bf<4, 1, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
+    default: return launch_bf<8, 1, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
+  }
 }
 
 __global__ void k_build_windows(const uint16_t *__restrict__ bf, uint4 *__restrict__ wtab, int n, int ngen,

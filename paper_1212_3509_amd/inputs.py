@@ -189,3 +189,66 @@ def quad_training_cases(count: int = 20000, seed: int = 3):
     rprime = rng.integers(16, 33, size=count)
     return {"n": n.astype(np.int64), "h": h, "log10_tol": log10_tol,
             "rprime": rprime.astype(np.int64)}
+
+
+# ---------------------------------------------------------------- network inputs
+MLP_SIZES = (6, 64, 64, 64, 65)
+
+
+def mlp_param_count(sizes=MLP_SIZES) -> int:
+    return sum(o * i + o for i, o in zip(sizes[:-1], sizes[1:]))
+
+
+def mlp_init(seed: int = 4, sizes=MLP_SIZES, out_scale: float = 0.0) -> np.ndarray:
+    """Flat float32 parameter vector [W1 (64x6, row = output), b1, W2, b2, W3,
+    b3, W4 (65x64), b4]: hidden weights ~ N(0, 1/fan_in), biases 0, and the
+    output layer scaled by ``out_scale`` (0: the untrained network proposes
+    the unmodified base rule)."""
+    rng = _rng(seed)
+    parts = []
+    layers = list(zip(sizes[:-1], sizes[1:]))
+    for li, (i, o) in enumerate(layers):
+        scale = 1.0 / np.sqrt(i)
+        if li == len(layers) - 1:
+            scale *= out_scale
+        parts.append((rng.standard_normal((o, i)) * scale).ravel())
+        parts.append(np.zeros(o))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def sentinel_offsets(n) -> np.ndarray:
+    """Fixed offsets J = (Jx, Jy, Jz) at which a quadrature rule's kernels are
+    judged on a grid n = (nx, ny, nz): the self cell, its face, edge and corner
+    neighbours, short steps, and offsets spread to the far end of the grid.
+    Returns int32 (S, 3) with 0 <= J_d < n_d (kernels are even/odd in J)."""
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
+    base = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1),
+            (2, 1, 0), (0, 2, 1), (1, 0, 2), (3, 2, 1)]
+    fr = [0.1, 0.3, 0.6, 1.0]
+    far = []
+    for a in fr:
+        far.append((a, 0.0, 0.0))
+        far.append((0.0, a, 0.0))
+        far.append((0.0, 0.0, a))
+        far.append((a, a, a))
+    far += [(1.0, 0.5, 0.25), (0.25, 1.0, 0.5), (0.5, 0.25, 1.0), (0.7, 0.7, 0.0)]
+    out = []
+    for j in base:
+        out.append(tuple(min(j[d], (nx, ny, nz)[d] - 1) for d in range(3)))
+    for f in far:
+        out.append(tuple(int(round(f[d] * ((nx, ny, nz)[d] - 1))) for d in range(3)))
+    return np.array(out, dtype=np.int32)
+
+
+def quad_features(n, h, log10_tol, rprime) -> np.ndarray:
+    """Network input per case (float32, 6 values): the three aspect ratios
+    n_d / n_max, the cell size as log2(1/h)/6 - 1, the tolerance as
+    (log10 tol + 6.5)/2.5 and the requested node count as (R' - 24)/8.
+    Arrays of cases broadcast: n (B, 3), h, log10_tol, rprime (B,)."""
+    n = np.atleast_2d(np.asarray(n, dtype=np.float64))
+    nmax = n.max(axis=1, keepdims=True)
+    h = np.atleast_1d(np.asarray(h, dtype=np.float64))
+    x = np.concatenate([n / nmax, (np.log2(1.0 / h) / 6.0 - 1.0)[:, None],
+                        ((np.atleast_1d(log10_tol) + 6.5) / 2.5)[:, None],
+                        ((np.atleast_1d(rprime).astype(np.float64) - 24.0) / 8.0)[:, None]], axis=1)
+    return x.astype(np.float32)

@@ -1,0 +1,148 @@
+"""GPU checks of the batched apply over uneven grids.
+
+Each output tile of the batched launch is computed by one workgroup with the
+same tile routine and the same accumulation order as the single-state path,
+so in the same precision the batch must reproduce the single-state results
+exactly (whatever the row-block shape).  The single-state path is itself
+checked against the oracle; two states are also checked against the oracle
+directly.  Graph replays are checked against the eager result after eager
+work and synchronizations between replays."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import apply, sinc
+from paper_1212_3509_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+
+GRIDS = [((16, 16, 16), None), ((17, 9, 5), None), ((24, 24, 24), None), ((40, 32, 4), None),
+         ((33, 20, 12), None), ((7, 1, 9), None)]
+
+
+def _grids():
+    out = []
+    for n, _ in GRIDS:
+        h = 1.0 / max(n)
+        out.append((n, (h, h, h)))
+    return out
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    api.library()
+    return api.Context(0)
+
+
+def _pack(fields, dtype):
+    m = np.concatenate([f.reshape(-1) for f in fields])
+    return torch.from_numpy(m).to(device="cuda", dtype=dtype)
+
+
+def _run_batch(ctx, b, fields, dtype, use_graph=False):
+    off = b.offsets()
+    m = _pack(fields, dtype)
+    phi = torch.empty(int(off[-1]), dtype=dtype, device="cuda")
+    h = torch.empty(3 * int(off[-1]), dtype=dtype, device="cuda")
+    b.apply(m, phi, h, use_graph=use_graph)
+    torch.cuda.synchronize()
+    return m, phi, h, off
+
+
+def _unpack(phi, h, off, grids):
+    out = []
+    for s, (n, _h) in enumerate(grids):
+        nx, ny, nz = n
+        p = phi[off[s]:off[s + 1]].reshape(nz, ny, nx)
+        hh = h[3 * off[s]:3 * off[s + 1]].reshape(3, nz, ny, nx)
+        out.append((p.double().cpu().numpy(), hh.double().cpu().numpy()))
+    return out
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_equals_single_state(ctx, prec):
+    dtype = torch.float64 if prec == "fp64" else torch.float32
+    grids = _grids()
+    fields = [inputs.random_unit_field(n, seed=20 + s) for s, (n, _h) in enumerate(grids)]
+    b = ctx.batch(grids, M=12, prec=prec)
+    _m, phi, h, off = _run_batch(ctx, b, fields, dtype)
+    got = _unpack(phi, h, off, grids)
+    for s, (n, hcell) in enumerate(grids):
+        f = ctx.assemble(n, hcell, M=12)
+        p1, h1 = ctx.apply_full(f, torch.from_numpy(fields[s]).to(device="cuda", dtype=dtype), prec=prec)
+        torch.cuda.synchronize()
+        assert np.array_equal(got[s][0], p1.double().cpu().numpy()), s
+        assert np.array_equal(got[s][1], h1.double().cpu().numpy()), s
+
+
+def test_batch_fp64_matches_oracle(ctx):
+    grids = _grids()
+    fields = [inputs.random_unit_field(n, seed=40 + s) for s, (n, _h) in enumerate(grids)]
+    b = ctx.batch(grids, M=12, prec="fp64")
+    _m, phi, h, off = _run_batch(ctx, b, fields, torch.float64)
+    got = _unpack(phi, h, off, grids)
+    _t, tau, alpha = sinc.sinc_nodes(12)
+    for s in (1, 3):
+        n, hcell = grids[s]
+        pr, hr = apply.kron_apply_dense(fields[s], hcell, tau, alpha)   # unit longest edge: L = 1
+        assert apply.rel_l2(got[s][0], pr) < 1e-12 and apply.rel_l2(got[s][1], hr) < 1e-12
+
+
+def test_batch_graph_replays(ctx):
+    grids = _grids()
+    fields = [inputs.random_unit_field(n, seed=60 + s) for s, (n, _h) in enumerate(grids)]
+    b = ctx.batch(grids, M=8, prec="fp32")
+    m, phi, h, off = _run_batch(ctx, b, fields, torch.float32)
+    ref_phi, ref_h = phi.clone(), h.clone()
+    for rep in range(3):
+        phi.fill_(float("nan"))
+        h.zero_()
+        _ = (m * 2.0).sum()                       # unrelated eager work between replays
+        torch.cuda.synchronize()
+        b.apply(m, phi, h, use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(phi, ref_phi) and torch.equal(h, ref_h), rep
+
+
+def test_batch_tuner(ctx, tmp_path):
+    grids = _grids()
+    fields = [inputs.random_unit_field(n, seed=80 + s) for s, (n, _h) in enumerate(grids)]
+    b = ctx.batch(grids, M=6, prec="fp32")
+    _m, phi0, h0, off = _run_batch(ctx, b, fields, torch.float32)
+    path = str(tmp_path / "tune.json")
+    b.tune(path, reps=2)
+    table = json.load(open(path))
+    assert table and all(v in (1, 2, 4, 8) for v in table.values())
+    assert all(k.startswith("fp32/n") for k in table)
+    _m, phi1, h1, _off = _run_batch(ctx, b, fields, torch.float32)
+    assert torch.equal(phi0, phi1) and torch.equal(h0, h1)
+    # cached entries are reused without timing
+    b2 = ctx.batch(grids, M=6, prec="fp32")
+    b2.tune(path, reps=2)
+    assert json.load(open(path)) == table
+    os.remove(path)
+
+
+def test_uneven_batch_recipe_subset(ctx):
+    """First 16 states of the 256-state recipe (cubes 16..96 and two films
+    256x256x{4,8}), FP32: states compared with their single-state applies."""
+    states = inputs.batch_grids(16, seed=2, with_fields=True)
+    grids = [(st.n, st.h) for st in states]
+    ctx.set_workspace_limit(64 << 30)        # one node chunk, as in the single-state applies
+    try:
+        b = ctx.batch(grids, M=40, prec="fp32")
+    finally:
+        ctx.set_workspace_limit(16 << 30)
+    assert b.info()["node_chunk"] == 40
+    _m, phi, h, off = _run_batch(ctx, b, [st.m for st in states], torch.float32)
+    got = _unpack(phi, h, off, grids)
+    for s in (0, 7, 15):
+        n, hcell = grids[s]
+        f = ctx.assemble(n, hcell, M=40)
+        p1, h1 = ctx.apply_full(f, torch.from_numpy(states[s].m).to(device="cuda", dtype=torch.float32), prec="fp32")
+        torch.cuda.synchronize()
+        assert np.array_equal(got[s][0], p1.double().cpu().numpy()), s
+        assert np.array_equal(got[s][1], h1.double().cpu().numpy()), s

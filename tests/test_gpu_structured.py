@@ -1,0 +1,150 @@
+"""GPU parity of the structured (CP / Tucker / TT) apply against the oracle.
+
+Columns are FP32 in and out; the transforms run in FP64, so each output
+column is within FP32 rounding of the oracle's dense-Toeplitz FP64 product:
+the bound is 1e-6 of the column norm plus 1e-12 of the largest column (very
+narrow kernels give columns that underflow FP32).  Term and block tables are
+integer results and must match exactly."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import apply, sinc, structured
+from paper_1212_3509_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    api.library()
+    return api.Context(0)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _check_cols(got, ref, tol=1e-6):
+    """got/ref: lists per axis of arrays [ncols][n]."""
+    big = max(np.linalg.norm(r, axis=1).max() for r in ref)
+    worst = 0.0
+    for g, r in zip(got, ref):
+        err = np.linalg.norm(g - r, axis=1)
+        nrm = np.linalg.norm(r, axis=1)
+        assert np.all(err <= tol * nrm + 1e-12 * big), (err / np.maximum(nrm, 1e-300)).max()
+        ok = nrm > 1e-6 * big
+        if ok.any():
+            worst = max(worst, float((err[ok] / nrm[ok]).max()))
+    return worst
+
+
+def _oracle_rule(n, h, M):
+    L = max(n[d] * h[d] for d in range(3))
+    hs = [x / L for x in h]
+    _t, tau, alpha = sinc.sinc_nodes(M)
+    return hs, tau, alpha
+
+
+N_SMALL = (9, 8, 7)
+H_SMALL = (1 / 9,) * 3
+
+
+def test_cp_small(ctx):
+    M, r = 6, 3
+    f = ctx.assemble(N_SMALL, H_SMALL, M=M)
+    cp = inputs.cp_input(N_SMALL, rank=r, seed=1, dtype=np.float32)
+    U = [_dev(np.stack([cp.U[q][d].T for q in range(3)])) for d in range(3)]
+    out, table = ctx.apply_cp(f, U)
+    torch.cuda.synchronize()
+    hs, tau, alpha = _oracle_rule(N_SMALL, H_SMALL, M)
+    cols, tab_ref = structured.cp_apply(cp, N_SMALL, hs, tau, alpha)
+    got = [o.cpu().numpy().reshape(-1, N_SMALL[d]).astype(np.float64) for d, o in enumerate(out)]
+    worst = _check_cols(got, cols)
+    assert np.array_equal(table, tab_ref)
+    # the structured result densifies to the full-format operator applied to the CP tensor
+    dense = structured.cp_densify(got, table, cp.lam, M, r, N_SMALL)
+    phi, hf = apply.kron_apply_dense(structured.cp_to_full(cp, N_SMALL), hs, tau, alpha)
+    assert apply.rel_l2(dense[0], phi) < 1e-6 and apply.rel_l2(dense[1:], hf) < 1e-6
+    print(f"cp small: worst column rel err {worst:.2e}")
+
+
+def test_tucker_small(ctx):
+    M, ranks = 5, (2, 3, 2)
+    n = (12, 10, 16)
+    h = (1 / 16,) * 3
+    f = ctx.assemble(n, h, M=M)
+    tk = inputs.tucker_input(n, ranks=ranks, seed=1, dtype=np.float32)
+    U = [_dev(np.stack([tk.U[q][d].T for q in range(3)])) for d in range(3)]
+    out, table = ctx.apply_tucker(f, U)
+    torch.cuda.synchronize()
+    hs, tau, alpha = _oracle_rule(n, h, M)
+    cols, tab_ref = structured.tucker_apply(tk, n, hs, tau, alpha)
+    got = [o.cpu().numpy().reshape(-1, n[d]).astype(np.float64) for d, o in enumerate(out)]
+    _check_cols(got, cols)
+    assert np.array_equal(table, tab_ref)
+    dense = structured.tucker_densify(got, table, tk.core, M, n)
+    phi, hf = apply.kron_apply_dense(structured.tucker_to_full(tk, n), hs, tau, alpha)
+    assert apply.rel_l2(dense[0], phi) < 1e-6 and apply.rel_l2(dense[1:], hf) < 1e-6
+
+
+def test_tt_small(ctx):
+    M, r1, r2 = 4, 2, 3
+    n = (7, 13, 5)
+    h = (0.1, 0.1, 0.1)
+    f = ctx.assemble(n, h, M=M)
+    tt = inputs.tt_input(n, ranks=(r1, r2), seed=2, dtype=np.float32)
+    G1 = _dev(np.stack([tt.G1[q].T for q in range(3)]))                    # [q][a][x]
+    G2 = _dev(np.stack([tt.G2[q].transpose(0, 2, 1) for q in range(3)]))   # [q][a][b][y]
+    G3 = _dev(np.stack([tt.G3[q] for q in range(3)]))                      # [q][b][z]
+    out, table = ctx.apply_tt(f, G1, G2, G3)
+    torch.cuda.synchronize()
+    hs, tau, alpha = _oracle_rule(n, h, M)
+    cols, tab_ref = structured.tt_apply(tt, n, hs, tau, alpha)
+    got = [o.cpu().numpy().reshape(-1, n[d]).astype(np.float64) for d, o in enumerate(out)]
+    _check_cols(got, cols)
+    assert np.array_equal(table, tab_ref)
+    dense = structured.tt_densify(got, table, M, n, r1, r2)
+    L = max(n[d] * h[d] for d in range(3))
+    phi, hf = apply.kron_apply_dense(structured.tt_to_full(tt, n), hs, tau, alpha)
+    assert apply.rel_l2(dense[0], phi) < 1e-6 and apply.rel_l2(dense[1:], hf) < 1e-6
+    assert L > 1.0   # the potential of the physical grid is L times the scaled one
+
+
+def test_cp_4096_rank10_sampled(ctx):
+    """n = 4096 per axis, CP rank 10 (seed 1), M = 40: 30 sampled jobs of each
+    axis against direct FP64 convolution with the oracle's generators."""
+    n, M, r = 4096, 40, 10
+    f = ctx.assemble((n, n, n), (1 / n,) * 3, M=M)
+    cp = inputs.cp_input(n, rank=r, seed=1, dtype=np.float32)
+    U = [_dev(np.stack([cp.U[q][d].T for q in range(3)])) for d in range(3)]
+    out, table = ctx.apply_cp(f, U)
+    torch.cuda.synchronize()
+    assert np.array_equal(table, structured.term_table(M, r))
+    _t, tau, alpha = sinc.sinc_nodes(M)
+    F = sinc.scaled_factors(n, 1 / n, tau, alpha)
+    rng = np.random.default_rng(0)
+    got_all = [o.cpu().numpy() for o in out]
+    worst = 0.0
+    for d in range(3):
+        for _ in range(30):
+            q, s, k, l = int(rng.integers(3)), int(rng.integers(2)), int(rng.integers(M)), int(rng.integers(r))
+            t = structured.type_of(q, d, s)
+            u = cp.U[q][d][:, l].astype(np.float64)
+            ref = np.convolve(F[t, k], u)[n - 1:2 * n - 1]
+            got = got_all[d][q, s, k, l].astype(np.float64)
+            nrm = np.linalg.norm(ref)
+            err = np.linalg.norm(got - ref)
+            assert err <= 1e-6 * nrm + 1e-12 * np.abs(F[t, k]).sum() * np.linalg.norm(u), (d, q, s, k, l, err / nrm)
+            if nrm > 0:
+                worst = max(worst, err / nrm)
+    print(f"cp 4096: worst sampled column rel err {worst:.2e}")
+
+
+def test_columns_rejects_bad_arguments(ctx):
+    f = ctx.assemble((8, 8, 8), (0.125,) * 3, M=4)
+    lib = api.library()
+    import ctypes as C
+    R = (C.c_int32 * 3)(-1, 1, 1)
+    null3 = (C.c_void_p * 3)(None, None, None)
+    assert lib.demag_apply_columns(ctx.handle, f.handle, R, null3, null3) == 1
