@@ -1,15 +1,23 @@
 #!/usr/bin/env python3
-"""Throughput of the full-format stray-field apply on one MI355X.
+"""Throughput of the stray-field apply on one MI355X.
 
-Workload: 128^3 cells on [-1/2, 1/2]^3, smooth vortex magnetization with 5%
-seeded noise (seed 0), sinc rule with M = 40 nodes (81-point rule), c0 = 2.15.
-One step = one complete apply: potential and all three field components at
-every cell (23 mode products per node, all nodes).  Inputs and outputs stay
-resident in device memory; the timed region covers only the apply calls.
+Default workload (the headline): 128^3 cells on [-1/2, 1/2]^3, smooth vortex
+magnetization with 5% seeded noise (seed 0).  One step = one complete
+full-format apply: potential and all three field components at every cell.
+Inputs and outputs stay resident in device memory; the timed region covers
+only the apply calls.
 
-Prints one JSON line.  ``value`` is cell-field evaluations per second (1e6
-cells/s) of the FP64 path; the other precisions are reported beside it with
-their relative L2 difference to the FP64 result of the same run.
+  * FP64 plain: sinc rule with M = 40 nodes (81-point rule), c0 = 2.15 -> ``value``.
+  * mixed + learned: the node-proposal network is trained on the GPU (outside
+    the timed region), proposes a shortened rule for this grid at a rule
+    tolerance, and the apply runs with bfloat16 three-part split products;
+    its relative L2 difference to the FP64 plain result of the same run is
+    reported beside its throughput.
+  * FP32, BF16x3 and BF16x2 with the full rule, for reference.
+
+Other workloads (``--workload``): ``cp4096`` (structured CP rank 10, Tucker
+(8,8,8) and TT (1,8,8,1) inputs at n = 4096 per axis) and ``batch`` (256
+magnetization states on uneven grids).  Each prints its own JSON line.
 """
 from __future__ import annotations
 
@@ -25,19 +33,20 @@ if ROOT not in sys.path:
 
 METRIC = "Mcell-field evals/s at 128³, FP64 plain vs mixed+learned R' at rel err 1e-6"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x2": 2500.0, "bf16x3": 2500.0}
+HBM_GBS = 8000.0
 
 
-def _time_apply(ctx, f, m, phi, h, prec, steps, warmup):
+def _timed(ctx, fn, steps, warmup):
     import torch
     for _ in range(warmup):
-        ctx.apply_full(f, m, phi, h, prec=prec)
+        fn()
     torch.cuda.synchronize()
     ctx.profile_enable(True)
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     start.record()
     for _ in range(steps):
-        ctx.apply_full(f, m, phi, h, prec=prec)
+        fn()
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / steps
@@ -55,6 +64,11 @@ def _roofline(prof, prec):
     return {"bound": "mfma", "kernel": label, "achieved": round(achieved, 3), "peak": peak,
             "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
             "flops_per_launch": flops, "avg_launch_ms": round(per_launch_ms, 4)}
+
+
+def _kernels(prof, steps):
+    return {k: {"ms_per_step": round(v["ms"] / steps, 4), "launches_per_step": v["launches"] // steps,
+                "tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3)} for k, v in sorted(prof.items())}
 
 
 def _cpu_baseline(m, n, nodes_sample):
@@ -75,23 +89,15 @@ def _cpu_baseline(m, n, nodes_sample):
                       f"factors), wall {wall:.1f} s, scaled x{40 / nodes_sample:g}"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-nodes", type=int, default=3, help="oracle nodes timed for the CPU baseline (0: skip)")
-    ap.add_argument("--precs", default="fp64,fp32,bf16x3,bf16x2")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py: this library runs on a single GPU; multi-GPU runs are not part of it "
-              "(see DESIGN.md for how the path would shard)", file=sys.stderr)
-        sys.exit(2)
+def _rel(a, b):
+    import torch
+    return float(torch.linalg.norm((a - b).reshape(-1)) / torch.linalg.norm(b.reshape(-1)))
 
-    import numpy as np
+
+def headline(args):
     import torch
 
-    from paper_1212_3509_amd import api, inputs
+    from paper_1212_3509_amd import api, inputs, learned
 
     n = 128
     N = n ** 3
@@ -105,21 +111,40 @@ def main():
         m = torch.from_numpy(m_host).to(device="cuda", dtype=dt)
         phi = torch.empty((n, n, n), dtype=dt, device="cuda")
         h = torch.empty((3, n, n, n), dtype=dt, device="cuda")
-        ms, prof = _time_apply(ctx, f, m, phi, h, prec, args.steps, args.warmup)
-        out = torch.cat([phi.reshape(-1), h.reshape(-1)]).double()
+        ms, prof = _timed(ctx, lambda: ctx.apply_full(f, m, phi, h, prec=prec), args.steps, args.warmup)
         entry = {"ms_per_step": round(ms, 4), "value": round(N / (ms * 1e-3) / 1e6, 3),
-                 "roofline": _roofline(prof, prec),
-                 "kernels": {k: {"ms_per_step": round(v["ms"] / args.steps, 4),
-                                 "launches_per_step": v["launches"] // args.steps,
-                                 "tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3)}
-                             for k, v in sorted(prof.items())}}
+                 "roofline": _roofline(prof, prec), "kernels": _kernels(prof, args.steps)}
         if ref is None:
-            ref = out
+            ref = (phi.double().clone(), h.double().clone())
         else:
-            entry["rel_l2_vs_fp64"] = float(torch.linalg.norm(out - ref) / torch.linalg.norm(ref))
+            entry["rel_l2_vs_fp64"] = {"phi": _rel(phi.double(), ref[0]), "h": _rel(h.double(), ref[1])}
         results[prec] = entry
         del m, phi, h
         torch.cuda.empty_cache()
+
+    mixed = None
+    if args.learned_steps > 0:
+        t0 = time.perf_counter()
+        cases = learned.prepare_cases(args.cases, seed=3)
+        params, loss = learned.train(ctx, cases, steps=args.learned_steps, batch=1024)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        rule = learned.predict(ctx, params, (n, n, n), args.rule_tol)
+        fl = ctx.assemble((n, n, n), (1.0 / n,) * 3, t=rule["t"], alpha=rule["alpha"])
+        m = torch.from_numpy(m_host).to(device="cuda", dtype=torch.float32)
+        phi = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
+        h = torch.empty((3, n, n, n), dtype=torch.float32, device="cuda")
+        prec = args.mixed_prec
+        ms, prof = _timed(ctx, lambda: ctx.apply_full(fl, m, phi, h, prec=prec), args.steps, args.warmup)
+        err = {"phi": _rel(phi.double(), ref[0]), "h": _rel(h.double(), ref[1])}
+        mixed = {"value": round(N / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 4), "dtype": prec,
+                 "nodes": rule["R"], "fell_back": rule["fell_back"], "rule_tol": args.rule_tol,
+                 "judged_kernel_err": rule["judged"], "predicted_log10_err": rule["predicted"],
+                 "rel_l2_vs_fp64_plain": err, "meets_1e-6": max(err.values()) <= 1e-6,
+                 "speedup_vs_fp64_plain": round(results["fp64"]["ms_per_step"] / ms, 3),
+                 "roofline": _roofline(prof, prec), "kernels": _kernels(prof, args.steps),
+                 "training": {"cases": args.cases, "steps": args.learned_steps, "seconds": round(train_s, 2),
+                              "loss_first": float(loss[:10].mean()), "loss_last": float(loss[-10:].mean())}}
 
     head = results["fp64"]
     line = {
@@ -131,11 +156,96 @@ def main():
                                "(81 points), c0=2.15, FP64, potential + field",
                    "cells": N, "nodes": 40},
         "roofline": head["roofline"],
-        "precisions": {k: v for k, v in results.items()},
+        "mixed_learned": mixed,
+        "precisions": results,
     }
     if args.cpu_nodes > 0:
         line["cpu_baseline"] = _cpu_baseline(m_host, n, args.cpu_nodes)
     print(json.dumps(line), flush=True)
+
+
+def structured(args):
+    import numpy as np
+    import torch
+
+    from paper_1212_3509_amd import api, inputs
+
+    n, M = 4096, 40
+    ctx = api.Context(0)
+    f = ctx.assemble((n, n, n), (1.0 / n,) * 3, M=M, c0=2.15)
+    ctx.prepare_structured(f)
+    out = {}
+    cp = inputs.cp_input(n, rank=10, seed=1, dtype=np.float32)
+    U = [torch.from_numpy(np.ascontiguousarray(np.stack([cp.U[q][d].T for q in range(3)]))).cuda() for d in range(3)]
+    tk = inputs.tucker_input(n, ranks=(8, 8, 8), seed=1, dtype=np.float32)
+    V = [torch.from_numpy(np.ascontiguousarray(np.stack([tk.U[q][d].T for q in range(3)]))).cuda() for d in range(3)]
+    tt = inputs.tt_input(n, ranks=(8, 8), seed=1, dtype=np.float32)
+    G1 = torch.from_numpy(np.ascontiguousarray(np.stack([tt.G1[q].T for q in range(3)]))).cuda()
+    G2 = torch.from_numpy(np.ascontiguousarray(np.stack([tt.G2[q].transpose(0, 2, 1) for q in range(3)]))).cuda()
+    G3 = torch.from_numpy(np.ascontiguousarray(np.stack([tt.G3[q] for q in range(3)]))).cuda()
+    cases = {"cp_r10": lambda: ctx.apply_cp(f, U), "tucker_888": lambda: ctx.apply_tucker(f, V),
+             "tt_188_1": lambda: ctx.apply_tt(f, G1, G2, G3)}
+    for name, fn in cases.items():
+        ms, prof = _timed(ctx, fn, args.steps, args.warmup)
+        bytes_ = sum(v["bytes"] for v in prof.values()) / args.steps
+        flops = sum(v["flops"] for v in prof.values()) / args.steps
+        out[name] = {"ms_per_apply": round(ms, 4), "implicit_cells_per_s": n ** 3 / (ms * 1e-3),
+                     "algorithmic_GBps": round(bytes_ / (ms * 1e-3) / 1e9, 1),
+                     "hbm_frac": round(bytes_ / (ms * 1e-3) / 1e9 / HBM_GBS, 4),
+                     "fft_gflops": round(flops / (ms * 1e-3) / 1e9, 1), "kernels": _kernels(prof, args.steps)}
+    print(json.dumps({"workload": "structured apply, n=4096 per axis, M=40, FP32 columns / FP64 transforms",
+                      "n_gpus": 1, "results": out}), flush=True)
+
+
+def batch(args):
+    import numpy as np
+    import torch
+
+    from paper_1212_3509_amd import api, inputs
+
+    states = inputs.batch_grids(256, seed=2, with_fields=True)
+    ctx = api.Context(0)
+    ctx.set_workspace_limit(int(args.batch_ws_gib) << 30)
+    b = ctx.batch([(s.n, s.h) for s in states], M=40, prec="fp32")
+    if args.tune:
+        b.tune(os.path.join(ROOT, "gpurun_out", "batch_tune.json") if os.path.isdir(os.path.join(ROOT, "gpurun_out"))
+               else None, reps=2)
+    off = b.offsets()
+    m = torch.from_numpy(np.concatenate([s.m.reshape(-1) for s in states]).astype(np.float32)).cuda()
+    phi = torch.empty(int(off[-1]), dtype=torch.float32, device="cuda")
+    h = torch.empty(3 * int(off[-1]), dtype=torch.float32, device="cuda")
+    ms, prof = _timed(ctx, lambda: b.apply(m, phi, h, use_graph=True), args.steps, args.warmup)
+    info = b.info()
+    print(json.dumps({"workload": "256 states on uneven grids (cubes 16..96, films 256x256x{4,8,16}), "
+                                  "FP32, M=40, one persistent launch per stage, graph replay",
+                      "n_gpus": 1, "cells": int(off[-1]), "ms_per_batch": round(ms, 3),
+                      "Mcell_per_s": round(off[-1] / (ms * 1e-3) / 1e6, 2),
+                      "tflops": round(info["flops"] / (ms * 1e-3) / 1e12, 2),
+                      "mfma_frac_fp32": round(info["flops"] / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"], 4),
+                      "node_chunk": info["node_chunk"], "persistent_groups": info["persistent_groups"]}),
+          flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="headline", choices=["headline", "cp4096", "batch"])
+    ap.add_argument("--cpu-nodes", type=int, default=3, help="oracle nodes timed for the CPU baseline (0: skip)")
+    ap.add_argument("--precs", default="fp64,fp32,bf16x3,bf16x2")
+    ap.add_argument("--learned-steps", type=int, default=1500)
+    ap.add_argument("--cases", type=int, default=20000)
+    ap.add_argument("--rule-tol", type=float, default=3e-7)
+    ap.add_argument("--mixed-prec", default="bf16x3")
+    ap.add_argument("--batch-ws-gib", type=int, default=32)
+    ap.add_argument("--tune", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this library runs on a single GPU; multi-GPU runs are not part of it "
+              "(see DESIGN.md for how the path would shard)", file=sys.stderr)
+        sys.exit(2)
+    {"headline": headline, "cp4096": structured, "batch": batch}[args.workload](args)
 
 
 if __name__ == "__main__":

@@ -215,6 +215,65 @@ demag_status demag_apply_tt(demag_ctx *ctx, demag_factors *f, int32_t r1, int32_
                             const float *G1, const float *G2, const float *G3,
                             float *const out[3], int32_t *table);
 
+/* ---------------------------------------------------------------- learned rule
+ * A network proposes shortened rules (R' = 16..32 nodes); an FP64 judge
+ * measures their kernel error; the full rule is the fallback.  Not part of
+ * the paper's method: it shortens the sinc rule of Cor. kron_op.
+ *
+ * Network: 6 -> 64 -> 64 -> 64 -> 65, GELU hidden layers, FP32, parameters a
+ * flat device array of demag_mlp_param_count() floats [W1 (64x6, row =
+ * output), b1, W2, b2, W3, b3, W4 (65x64), b4].  Inputs per case (x[b][6]):
+ * n_x/n_max, n_y/n_max, n_z/n_max, log2(1/h)/6 - 1, (log10 tol + 6.5)/2.5,
+ * (R' - 24)/8.  Outputs y[b][65]: 32 node offsets, 32 log-weight offsets, the
+ * predicted log10 kernel error.
+ * Rule from outputs, base = sinc rule with R' nodes and c0 = 2.15:
+ *   t'_k = t_k + 0.45 theta tanh(y_k), alpha'_k = alpha_k exp(tanh(y_{32+k})).
+ * Judge: err = sqrt(mean over sentinel offsets J of |K(J) - K_ref(J)|^2 /
+ * |K_ref(J)|^2) over the nine kernel values [K^x, K^y, K^z, F_xx, F_yy,
+ * F_zz, F_xy, F_xz, F_yz], K_ref from the sinc rule with the step of Thm.
+ * sinc_theo and 96 nodes, on unit-longest-edge grids with cubic cells hmin.
+ * All arrays below are device arrays unless marked host. */
+int32_t demag_mlp_param_count(void);
+/* y[B][65]; z, a (optional, [B][3][64]) hidden pre-activations/activations. */
+demag_status demag_mlp_forward(demag_ctx *ctx, const float *params, const float *x, int32_t B, float *y,
+                               float *z, float *a);
+/* Gradient of sum_b <dy_b, y_b> w.r.t. params (grad[param_count]), summed over
+ * samples in a fixed order; delta[B][3][64] is scratch. */
+demag_status demag_mlp_backward(demag_ctx *ctx, const float *params, const float *x, const float *z,
+                                const float *a, const float *dy, int32_t B, float *delta, float *grad);
+/* One bias-corrected Adam update of count parameters (step >= 1). */
+demag_status demag_adam_step(demag_ctx *ctx, float *params, const float *grad, float *m, float *v,
+                             int32_t count, int32_t step, float lr, float b1, float b2, float eps);
+/* Rules t, alpha [B][32] from outputs y (NULL: the base rules) and R[B]. */
+demag_status demag_quad_rules(demag_ctx *ctx, const float *y, const int32_t *R, int32_t B, double *t,
+                              double *alpha);
+/* Judge B rules (t, alpha [B][KM], R[B] nodes used) on grids [B][3] with
+ * cell sizes hmin[B] at sentinels [B][S][3] (offsets 0 <= J_d < n_d):
+ * err[B]; with dt, dalpha non-NULL also d err / d t_k, d err / d alpha_k
+ * [B][KM].  Synchronizes the stream. */
+demag_status demag_quad_judge(demag_ctx *ctx, int32_t B, const int32_t *grids, const double *hmin,
+                              const int32_t *sentinels, int32_t S, const double *t, const double *alpha,
+                              const int32_t *R, int32_t KM, double *err, double *dt, double *dalpha);
+/* Train in place with Adam for `steps` minibatches of `batch` consecutive
+ * cases (wrapping; shuffle the cases beforehand) on
+ *   mean_b [ ln err_b + lambda (y_64,b - log10 err_b)^2 ];
+ * step0 = Adam steps already taken.  loss_host (host, length steps, may be
+ * NULL) receives each step's mean loss. */
+demag_status demag_quad_train(demag_ctx *ctx, float *params, float *adam_m, float *adam_v, const float *x,
+                              const int32_t *grids, const double *hmin, const int32_t *R,
+                              const int32_t *sentinels, int32_t count, int32_t S, int32_t steps,
+                              int32_t batch, int32_t step0, float lr, float lambda, float *loss_host);
+/* Rule for one grid (n host[3], cell size hmin, sentinels [S][3]) at
+ * tolerance tol: features [17][6] for R' = 16..32 in order; the smallest R'
+ * with predicted log10 error <= log10 tol is judged, and if its error
+ * exceeds tol the sinc rule with the step of Thm. sinc_theo and 64 nodes is
+ * returned instead (*fell_back = 1).  Host outputs: t_out, alpha_out
+ * (capacity 64), *R_out, *judged, *predicted, *fell_back. */
+demag_status demag_quad_predict(demag_ctx *ctx, const float *params, const float *features,
+                                const int32_t n[3], double hmin, const int32_t *sentinels, int32_t S,
+                                double tol, double *t_out, double *alpha_out, int32_t *R_out,
+                                double *judged, double *predicted, int32_t *fell_back);
+
 /* The bfloat16 split used by DEMAG_BF16X2/X3 on the device, exposed for
  * checking: x (device, count floats) -> parts (device, [nparts][count]
  * uint16 bit patterns): hi = bf16(x), lo = bf16(x - hi), lo2 = bf16(x - hi -

@@ -54,6 +54,17 @@ _SIGS = {
     "demag_batch_info": (C.c_int, [_P, _P, _P, _P]),
     "demag_batch_apply": (C.c_int, [_P, _P, _P, _P, _P, C.c_int32]),
     "demag_batch_tune": (C.c_int, [_P, _P, C.c_char_p, C.c_int32]),
+    "demag_mlp_param_count": (C.c_int32, []),
+    "demag_mlp_forward": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P, _P]),
+    "demag_mlp_backward": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int32, _P, _P]),
+    "demag_adam_step": (C.c_int, [_P, _P, _P, _P, _P, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
+                                  C.c_float]),
+    "demag_quad_judge": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.c_int32, _P, _P, _P, C.c_int32, _P, _P, _P]),
+    "demag_quad_rules": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P]),
+    "demag_quad_train": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                   C.c_int32, C.c_float, C.c_float, _P]),
+    "demag_quad_predict": (C.c_int, [_P, _P, _P, _P, C.c_double, _P, C.c_int32, C.c_double, _P, _P, _P, _P, _P,
+                                     _P]),
     "demag_prepare_structured": (C.c_int, [_P, _P]),
     "demag_apply_columns": (C.c_int, [_P, _P, _P, _P, _P]),
     "demag_apply_cp": (C.c_int, [_P, _P, C.c_int32, _P, _P, _P]),
@@ -249,6 +260,10 @@ class Context:
     def _ptr3(ts):
         return (C.c_void_p * 3)(*[t.data_ptr() for t in ts])
 
+    def prepare_structured(self, f: Factors):
+        self.use_current_stream()
+        _check(library().demag_prepare_structured(self.handle, f.handle), "demag_prepare_structured")
+
     def apply_columns(self, f: Factors, cols_in):
         """cols_in[d]: float32 CUDA tensor [3][R_d][n_d].  Returns out[d]
         [3][2][M][R_d][n_d]."""
@@ -288,6 +303,85 @@ class Context:
         _check(library().demag_apply_tt(self.handle, f.handle, r1, r2, _ptr(G1), _ptr(G2), _ptr(G3),
                                         self._ptr3(out), table.ctypes.data), "demag_apply_tt")
         return out, table
+
+    # ------------------------------------------------------------ learned rule
+    def mlp_forward(self, params, x):
+        """params: float32 CUDA [12993]; x: float32 CUDA [B][6].  Returns (y, z, a)."""
+        import torch
+        B = int(x.shape[0])
+        y = torch.empty((B, 65), dtype=torch.float32, device=x.device)
+        z = torch.empty((B, 3, 64), dtype=torch.float32, device=x.device)
+        a = torch.empty((B, 3, 64), dtype=torch.float32, device=x.device)
+        self.use_current_stream()
+        _check(library().demag_mlp_forward(self.handle, _ptr(params), _ptr(x), B, _ptr(y), _ptr(z), _ptr(a)),
+               "demag_mlp_forward")
+        return y, z, a
+
+    def mlp_backward(self, params, x, z, a, dy):
+        import torch
+        B = int(x.shape[0])
+        delta = torch.empty((B, 3, 64), dtype=torch.float32, device=x.device)
+        grad = torch.empty(params.numel(), dtype=torch.float32, device=x.device)
+        self.use_current_stream()
+        _check(library().demag_mlp_backward(self.handle, _ptr(params), _ptr(x), _ptr(z), _ptr(a), _ptr(dy), B,
+                                            _ptr(delta), _ptr(grad)), "demag_mlp_backward")
+        return grad
+
+    def adam_step(self, params, grad, m, v, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        self.use_current_stream()
+        _check(library().demag_adam_step(self.handle, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(),
+                                         step, lr, b1, b2, eps), "demag_adam_step")
+
+    def quad_rules(self, y, R):
+        """Rules from network outputs y (CUDA float32 [B][65], or None for the
+        base rule) and node counts R (CUDA int32 [B]): (t, alpha) [B][32]."""
+        import torch
+        B = int(R.shape[0])
+        t = torch.zeros((B, 32), dtype=torch.float64, device=R.device)
+        a = torch.zeros((B, 32), dtype=torch.float64, device=R.device)
+        self.use_current_stream()
+        _check(library().demag_quad_rules(self.handle, _ptr(y), _ptr(R), B, _ptr(t), _ptr(a)), "demag_quad_rules")
+        return t, a
+
+    def quad_judge(self, grids, hmin, sent, t, alpha, R, grad=False):
+        """grids int32 [B][3], hmin float64 [B], sent int32 [B][S][3], t/alpha
+        float64 [B][KM], R int32 [B] (all CUDA).  Returns err [B] (and the
+        gradients [B][KM] with respect to t and alpha)."""
+        import torch
+        B, S = int(sent.shape[0]), int(sent.shape[1])
+        KM = int(t.shape[1])
+        err = torch.empty(B, dtype=torch.float64, device=t.device)
+        dt = torch.empty((B, KM), dtype=torch.float64, device=t.device) if grad else None
+        da = torch.empty((B, KM), dtype=torch.float64, device=t.device) if grad else None
+        self.use_current_stream()
+        _check(library().demag_quad_judge(self.handle, B, _ptr(grids), _ptr(hmin), _ptr(sent), S, _ptr(t),
+                                          _ptr(alpha), _ptr(R), KM, _ptr(err), _ptr(dt), _ptr(da)),
+               "demag_quad_judge")
+        return (err, dt, da) if grad else err
+
+    def quad_train(self, params, m, v, x, grids, hmin, R, sent, steps, batch, step0=0, lr=1e-3, lam=0.1):
+        loss = np.zeros(max(steps, 1), dtype=np.float32)
+        S = int(sent.shape[1])
+        self.use_current_stream()
+        _check(library().demag_quad_train(self.handle, _ptr(params), _ptr(m), _ptr(v), _ptr(x), _ptr(grids),
+                                          _ptr(hmin), _ptr(R), _ptr(sent), int(x.shape[0]), S, steps, batch, step0,
+                                          lr, lam, loss.ctypes.data), "demag_quad_train")
+        return loss[:steps]
+
+    def quad_predict(self, params, features, n, hmin, sent, tol):
+        """features: CUDA float32 [17][6] for R' = 16..32; sent: CUDA int32
+        [S][3].  Returns dict(t, alpha, R, judged, predicted, fell_back)."""
+        t = np.zeros(64)
+        a = np.zeros(64)
+        R, fb = C.c_int32(), C.c_int32()
+        judged, pred = C.c_double(), C.c_double()
+        n3 = (C.c_int32 * 3)(*n)
+        self.use_current_stream()
+        _check(library().demag_quad_predict(self.handle, _ptr(params), _ptr(features), n3, hmin, _ptr(sent),
+                                            int(sent.shape[0]), tol, t.ctypes.data, a.ctypes.data, C.byref(R),
+                                            C.byref(judged), C.byref(pred), C.byref(fb)), "demag_quad_predict")
+        return {"t": t[:R.value], "alpha": a[:R.value], "R": R.value, "judged": judged.value,
+                "predicted": pred.value, "fell_back": bool(fb.value)}
 
     def bf16_split(self, x, nparts: int = 3):
         """Device split of a contiguous float32 CUDA tensor into bfloat16 bit

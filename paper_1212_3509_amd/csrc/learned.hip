@@ -1,0 +1,605 @@
+// Learned shortened quadrature: a small network proposes R' (16..32) nodes
+// and weights for a grid and tolerance; an FP64 judge measures the kernel
+// error of any rule against an accurate reference rule; the full rule is the
+// fallback.  (Not in the paper: built on its sinc rule, Cor. kron_op, and its
+// separable kernels, Eqs. (sep_integrands), (f_anal).)
+//
+// Network: 6 -> 64 -> 64 -> 64 -> 65, GELU(x) = x Phi(x) on the hidden layers,
+// FP32, parameters flat [W1 (64x6, row = output), b1, W2, b2, W3, b3, W4
+// (65x64), b4].  Inputs per case: aspect ratios n_d/n_max, log2(1/h)/6 - 1,
+// (log10 tol + 6.5)/2.5, (R' - 24)/8.  Outputs: y_0..31 node offsets,
+// y_32..63 log-weight offsets, y_64 predicted log10 error.
+//
+// Rule from outputs (base: the sinc rule with R' nodes, c0 = 2.15):
+//   theta = c0 ln(R')/R', t_k = k theta, alpha_k = 2 theta cosh t_k sinh^2 t_k,
+//   t'_k = t_k + 0.45 theta tanh(y_k),  alpha'_k = alpha_k exp(tanh(y_{32+k})).
+// Judge: at S sentinel offsets J, nine kernel values per rule
+//   [K^x, K^y, K^z, F_xx, F_yy, F_zz, F_xy, F_xz, F_yz]
+//   K^q  = W prod_d f_d with f = X along q, E elsewhere;
+//   F_pq = the same for h_p <- m_q with axis p differentiated (X -> P = -X',
+//          E -> Q = 2 tau^2 X), W = alpha / (2 pi^(3/2)),
+// err = sqrt(mean_J |K - K_ref|^2 / |K_ref|^2), K_ref from the sinc rule with
+// the step of Thm. sinc_theo and 96 nodes.  Training minimises
+//   mean_b [ ln err_b + lambda (y_64,b - log10 err_b)^2 ]   (err_b held fixed in the second term)
+// with Adam; the gradient of err with respect to (t', alpha') uses the
+// closed-form tau-derivatives of the 1D factors:
+//   dE/dtau = (X' - E)/tau,  dX/dtau = (b^2 e_b - a^2 e_a - 2X)/tau,
+//   dX'/dtau = -2 tau (b^3 e_b - a^3 e_a),  e_a = exp(-tau^2 a^2).
+#include "internal.h"
+
+#include <cmath>
+#include <cstring>
+
+namespace demag {
+
+namespace {
+
+constexpr int kIn = 6, kH = 64, kOut = 65, kRmax = 32, kNcomp = 9;
+constexpr int oW1 = 0, oB1 = oW1 + kH * kIn, oW2 = oB1 + kH, oB2 = oW2 + kH * kH, oW3 = oB2 + kH,
+              oB3 = oW3 + kH * kH, oW4 = oB3 + kH, oB4 = oW4 + kOut * kH, kParams = oB4 + kOut;
+static_assert(kParams == 12993, "parameter count");
+constexpr double kPi = 3.141592653589793238462643383279502884;
+constexpr double kC0 = 2.15;
+
+__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ inline float gelu_grad(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+// ------------------------------------------------------------------ network
+// One 64-thread workgroup per sample.  Z, A: [B][3][64] pre-activations and
+// activations of the hidden layers (for the backward pass).
+__global__ __launch_bounds__(64) void k_mlp_forward(const float *__restrict__ P, const float *__restrict__ X, int B,
+                                                    float *__restrict__ Y, float *__restrict__ Z,
+                                                    float *__restrict__ A) {
+  __shared__ float a[kH];
+  __shared__ float x[kIn];
+  const int b = blockIdx.x, j = threadIdx.x;
+  if (b >= B) return;
+  if (j < kIn) x[j] = X[size_t(b) * kIn + j];
+  __syncthreads();
+  float z = P[oB1 + j];
+  for (int i = 0; i < kIn; ++i) z += P[oW1 + j * kIn + i] * x[i];
+  float act = gelu(z);
+  if (Z) Z[(size_t(b) * 3 + 0) * kH + j] = z;
+  if (A) A[(size_t(b) * 3 + 0) * kH + j] = act;
+  a[j] = act;
+  __syncthreads();
+  for (int l = 1; l < 3; ++l) {
+    const int oW = (l == 1) ? oW2 : oW3, oB = (l == 1) ? oB2 : oB3;
+    z = P[oB + j];
+    for (int i = 0; i < kH; ++i) z += P[oW + j * kH + i] * a[i];
+    act = gelu(z);
+    if (Z) Z[(size_t(b) * 3 + l) * kH + j] = z;
+    if (A) A[(size_t(b) * 3 + l) * kH + j] = act;
+    __syncthreads();
+    a[j] = act;
+    __syncthreads();
+  }
+  for (int o = j; o < kOut; o += kH) {
+    float y = P[oB4 + o];
+    for (int i = 0; i < kH; ++i) y += P[oW4 + o * kH + i] * a[i];
+    Y[size_t(b) * kOut + o] = y;
+  }
+}
+
+// Deltas of the hidden pre-activations, D: [B][3][64].
+__global__ __launch_bounds__(64) void k_mlp_delta(const float *__restrict__ P, const float *__restrict__ Z,
+                                                  const float *__restrict__ dY, int B, float *__restrict__ D) {
+  __shared__ float d[kOut];
+  const int b = blockIdx.x, i = threadIdx.x;
+  if (b >= B) return;
+  for (int o = i; o < kOut; o += kH) d[o] = dY[size_t(b) * kOut + o];
+  __syncthreads();
+  float s = 0.0f;
+  for (int o = 0; o < kOut; ++o) s += P[oW4 + o * kH + i] * d[o];
+  float di = s * gelu_grad(Z[(size_t(b) * 3 + 2) * kH + i]);
+  D[(size_t(b) * 3 + 2) * kH + i] = di;
+  __syncthreads();
+  d[i] = di;
+  __syncthreads();
+  for (int l = 1; l >= 0; --l) {
+    const int oW = (l == 1) ? oW3 : oW2;   // weights of layer l+1 (maps layer l to l+1)
+    s = 0.0f;
+    for (int o = 0; o < kH; ++o) s += P[oW + o * kH + i] * d[o];
+    di = s * gelu_grad(Z[(size_t(b) * 3 + l) * kH + i]);
+    D[(size_t(b) * 3 + l) * kH + i] = di;
+    __syncthreads();
+    d[i] = di;
+    __syncthreads();
+  }
+}
+
+// Parameter gradients, one thread per parameter, summed over samples in a
+// fixed order (deterministic).
+__global__ void k_mlp_grad(const float *__restrict__ X, const float *__restrict__ A, const float *__restrict__ D,
+                           const float *__restrict__ dY, int B, float *__restrict__ G) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kParams) return;
+  // locate (layer, row j, column i or bias)
+  int layer, j, i = -1, nin;
+  if (p < oB1) { layer = 0; nin = kIn; j = (p - oW1) / kIn; i = (p - oW1) % kIn; }
+  else if (p < oW2) { layer = 0; nin = kIn; j = p - oB1; }
+  else if (p < oB2) { layer = 1; nin = kH; j = (p - oW2) / kH; i = (p - oW2) % kH; }
+  else if (p < oW3) { layer = 1; nin = kH; j = p - oB2; }
+  else if (p < oB3) { layer = 2; nin = kH; j = (p - oW3) / kH; i = (p - oW3) % kH; }
+  else if (p < oW4) { layer = 2; nin = kH; j = p - oB3; }
+  else if (p < oB4) { layer = 3; nin = kH; j = (p - oW4) / kH; i = (p - oW4) % kH; }
+  else { layer = 3; nin = kH; j = p - oB4; }
+  (void)nin;
+  float s = 0.0f;
+  for (int b = 0; b < B; ++b) {
+    const float delta = (layer == 3) ? dY[size_t(b) * kOut + j] : D[(size_t(b) * 3 + layer) * kH + j];
+    float in = 1.0f;
+    if (i >= 0) in = (layer == 0) ? X[size_t(b) * kIn + i] : A[(size_t(b) * 3 + layer - 1) * kH + i];
+    s += delta * in;
+  }
+  G[p] = s;
+}
+
+__global__ void k_adam(float *__restrict__ P, const float *__restrict__ G, float *__restrict__ m,
+                       float *__restrict__ v, int n, int step, float lr, float b1, float b2, float eps) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n) return;
+  const float g = G[p];
+  const float mm = b1 * m[p] + (1.0f - b1) * g;
+  const float vv = b2 * v[p] + (1.0f - b2) * g * g;
+  m[p] = mm;
+  v[p] = vv;
+  const float mh = mm / (1.0f - powf(b1, float(step)));
+  const float vh = vv / (1.0f - powf(b2, float(step)));
+  P[p] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+// ------------------------------------------------------------------ rules
+// Rules from outputs (or the plain base rule when Y == NULL): t, alpha [B][KM].
+__global__ void k_rules(const float *__restrict__ Y, const int *__restrict__ R, int B, int KM,
+                        double *__restrict__ t, double *__restrict__ alpha) {
+  const int b = blockIdx.x, k = threadIdx.x;
+  if (b >= B || k >= KM) return;
+  const int r = R[b];
+  double tk = 0.0, ak = 0.0;
+  if (k < r) {
+    const double theta = kC0 * log(double(r)) / r;
+    tk = (k + 1) * theta;
+    const double sh = sinh(tk);
+    ak = 2.0 * theta * cosh(tk) * sh * sh;
+    if (Y) {
+      tk += 0.45 * theta * tanh(double(Y[size_t(b) * kOut + k]));
+      ak *= exp(tanh(double(Y[size_t(b) * kOut + kRmax + k])));
+    }
+  }
+  t[size_t(b) * KM + k] = tk;
+  alpha[size_t(b) * KM + k] = ak;
+}
+
+// Reference rules (sinc rule, step of Thm. sinc_theo, M nodes) per case.
+__global__ void k_ref_rules(const double *__restrict__ hmin, int B, int M, double *__restrict__ t,
+                            double *__restrict__ alpha) {
+  const int b = blockIdx.x;
+  for (int k = threadIdx.x; k < M && b < B; k += blockDim.x) {
+    const double a = 2.0, bb = 0.25 * (0.5 * hmin[b]) * (0.5 * hmin[b]);
+    const double theta = log(2.0 * kPi * a * M / bb) / (a * M);
+    const double tk = (k + 1) * theta;
+    const double sh = sinh(tk);
+    t[size_t(b) * M + k] = tk;
+    alpha[size_t(b) * M + k] = 2.0 * theta * cosh(tk) * sh * sh;
+  }
+}
+
+// 1D factors at offset J (any sign) for node tau and cell size h, and their
+// tau-derivatives.  f[0] = E, f[1] = X, f[2] = P = -X', f[3] = Q = 2 tau^2 X.
+__device__ inline void factors_1d(int J, double tau, double h, double f[4], double df[4]) {
+  const int Ja = J < 0 ? -J : J;
+  const double sg = J < 0 ? -1.0 : 1.0;
+  const double a = (Ja - 0.5) * h, b = (Ja + 0.5) * h;
+  const double t2 = tau * tau;
+  const double ea = exp(-t2 * a * a), eb = exp(-t2 * b * b);
+  double E, X;
+  if (Ja == 0) {
+    E = 1.7724538509055160273 / tau * erf(0.5 * tau * h);
+    X = 0.0;
+  } else {
+    const double ta = tau * a, tb = tau * b;
+    const double diff = (ta > 0.5) ? (erfc(ta) - erfc(tb)) : (erf(tb) - erf(ta));
+    E = 1.7724538509055160273 / (2.0 * tau) * diff;
+    X = -ea * expm1(-t2 * (2.0 * Ja * h * h)) / (2.0 * t2);
+  }
+  const double Xp = b * eb - a * ea;
+  const double dE = (Xp - E) / tau;
+  const double dX = (b * b * eb - a * a * ea - 2.0 * X) / tau;
+  const double dXp = -2.0 * tau * (b * b * b * eb - a * a * a * ea);
+  f[0] = E;
+  f[1] = sg * X;
+  f[2] = -Xp;
+  f[3] = sg * 2.0 * t2 * X;
+  df[0] = dE;
+  df[1] = sg * dX;
+  df[2] = -dXp;
+  df[3] = sg * (4.0 * tau * X + 2.0 * t2 * dX);
+}
+
+// factor types per axis (x, y, z) of the nine components
+__constant__ int kTypes[kNcomp][3] = {{1, 0, 0}, {0, 1, 0}, {0, 0, 1},   // K^x, K^y, K^z
+                                      {2, 0, 0}, {0, 2, 0}, {0, 0, 2},   // F_xx, F_yy, F_zz
+                                      {3, 1, 0}, {3, 0, 1}, {0, 3, 1}};  // F_xy, F_xz, F_yz
+
+// Kernel values of each case's rule at its sentinels: K [B][S][9].
+__global__ void k_judge_values(const int *__restrict__ grids, const double *__restrict__ hmin,
+                               const int *__restrict__ sent, int S, const double *__restrict__ t,
+                               const double *__restrict__ alpha, const int *__restrict__ R, int KM, int B,
+                               double *__restrict__ K) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= B * S) return;
+  const int b = idx / S, s = idx % S;
+  const double h = hmin[b];
+  const int *J = sent + (size_t(b) * S + s) * 3;
+  const int r = R ? R[b] : KM;
+  double acc[kNcomp] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+  for (int k = 0; k < r; ++k) {
+    const double tk = t[size_t(b) * KM + k];
+    const double tau = sinh(tk);
+    const double W = alpha[size_t(b) * KM + k] / (2.0 * pow(kPi, 1.5));
+    double f[3][4], df[3][4];
+    for (int d = 0; d < 3; ++d) factors_1d(J[d], tau, h, f[d], df[d]);
+    for (int c = 0; c < kNcomp; ++c)
+      acc[c] += W * f[0][kTypes[c][0]] * f[1][kTypes[c][1]] * f[2][kTypes[c][2]];
+  }
+  for (int c = 0; c < kNcomp; ++c) K[(size_t(b) * S + s) * kNcomp + c] = acc[c];
+}
+
+// err per case and the scaled residuals (K - K_ref)/|K_ref|^2 per sentinel.
+__global__ void k_judge_err(const double *__restrict__ K, const double *__restrict__ Kref, int B, int S,
+                            double *__restrict__ err, double *__restrict__ resid) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  double sum = 0.0;
+  for (int s = 0; s < S; ++s) {
+    const double *k = K + (size_t(b) * S + s) * kNcomp;
+    const double *r = Kref + (size_t(b) * S + s) * kNcomp;
+    double num = 0.0, den = 0.0;
+    for (int c = 0; c < kNcomp; ++c) {
+      num += (k[c] - r[c]) * (k[c] - r[c]);
+      den += r[c] * r[c];
+    }
+    sum += num / den;
+    if (resid)
+      for (int c = 0; c < kNcomp; ++c) resid[(size_t(b) * S + s) * kNcomp + c] = (k[c] - r[c]) / den;
+  }
+  err[b] = sqrt(sum / S);
+}
+
+// d err / d t'_k and d err / d alpha'_k: [B][KM].
+__global__ void k_judge_grad(const int *__restrict__ grids, const double *__restrict__ hmin,
+                             const int *__restrict__ sent, int S, const double *__restrict__ t,
+                             const double *__restrict__ alpha, const int *__restrict__ R, int KM, int B,
+                             const double *__restrict__ resid, const double *__restrict__ err,
+                             double *__restrict__ dt, double *__restrict__ dalpha) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= B * KM) return;
+  const int b = idx / KM, k = idx % KM;
+  double gt = 0.0, ga = 0.0;
+  if (k < R[b]) {
+    const double h = hmin[b];
+    const double tk = t[size_t(b) * KM + k];
+    const double tau = sinh(tk), ch = cosh(tk);
+    const double c = 1.0 / (2.0 * pow(kPi, 1.5));
+    const double W = alpha[size_t(b) * KM + k] * c;
+    for (int s = 0; s < S; ++s) {
+      const int *J = sent + (size_t(b) * S + s) * 3;
+      double f[3][4], df[3][4];
+      for (int d = 0; d < 3; ++d) factors_1d(J[d], tau, h, f[d], df[d]);
+      const double *r = resid + (size_t(b) * S + s) * kNcomp;
+      for (int q = 0; q < kNcomp; ++q) {
+        const int t0 = kTypes[q][0], t1 = kTypes[q][1], t2 = kTypes[q][2];
+        const double prod = f[0][t0] * f[1][t1] * f[2][t2];
+        const double dprod = df[0][t0] * f[1][t1] * f[2][t2] + f[0][t0] * df[1][t1] * f[2][t2] +
+                             f[0][t0] * f[1][t1] * df[2][t2];
+        ga += r[q] * c * prod;
+        gt += r[q] * W * ch * dprod;
+      }
+    }
+    const double scale = 1.0 / (S * err[b]);
+    gt *= scale;
+    ga *= scale;
+  }
+  dt[idx] = gt;
+  dalpha[idx] = ga;
+}
+
+// Output gradients of the training loss and per-case loss values.
+__global__ void k_output_grads(const float *__restrict__ Y, const int *__restrict__ R, int B, int KM,
+                               const double *__restrict__ t, const double *__restrict__ alpha,
+                               const double *__restrict__ dt, const double *__restrict__ dalpha,
+                               const double *__restrict__ err, float lambda, float *__restrict__ dY,
+                               float *__restrict__ loss) {
+  const int b = blockIdx.x, o = threadIdx.x;
+  if (b >= B || o >= kOut) return;
+  const double e = err[b];
+  const float pred = Y[size_t(b) * kOut + 64];
+  const float target = float(log10(e));
+  float g = 0.0f;
+  if (o == 64) {
+    g = 2.0f * lambda * (pred - target) / B;
+    loss[b] = float(log(e)) + lambda * (pred - target) * (pred - target);
+  } else {
+    const int k = o % kRmax;
+    const int r = R[b];
+    if (k < r) {
+      const double theta = kC0 * log(double(r)) / r;
+      const double th = tanh(double(Y[size_t(b) * kOut + o]));
+      if (o < kRmax) g = float(dt[size_t(b) * KM + k] / e * 0.45 * theta * (1.0 - th * th) / B);
+      else g = float(dalpha[size_t(b) * KM + k] * alpha[size_t(b) * KM + k] / e * (1.0 - th * th) / B);
+    }
+  }
+  dY[size_t(b) * kOut + o] = g;
+}
+
+template <class T>
+demag_status dalloc(T **p, size_t n) {
+  DEMAG_TRY_HIP(hipMalloc(p, sizeof(T) * std::max<size_t>(n, 1)));
+  return DEMAG_OK;
+}
+
+struct JudgeBufs {
+  double *t = nullptr, *alpha = nullptr, *K = nullptr, *resid = nullptr, *err = nullptr, *dt = nullptr,
+         *dalpha = nullptr;
+  void release() {
+    for (double *p : {t, alpha, K, resid, err, dt, dalpha})
+      if (p) (void)hipFree(p);
+  }
+};
+
+demag_status reference_values(demag_ctx *ctx, const int *grids, const double *hmin, const int *sent, int S, int B,
+                              double *Kref) {
+  const int M = 96;
+  double *t = nullptr, *a = nullptr;
+  demag_status st = dalloc(&t, size_t(B) * M);
+  if (st == DEMAG_OK) st = dalloc(&a, size_t(B) * M);
+  if (st != DEMAG_OK) return st;
+  k_ref_rules<<<B, 128, 0, ctx->stream>>>(hmin, B, M, t, a);
+  k_judge_values<<<(B * S + 127) / 128, 128, 0, ctx->stream>>>(grids, hmin, sent, S, t, a, nullptr, M, B, Kref);
+  DEMAG_TRY_HIP(hipGetLastError());
+  DEMAG_TRY_HIP(hipStreamSynchronize(ctx->stream));
+  (void)hipFree(t);
+  (void)hipFree(a);
+  return DEMAG_OK;
+}
+
+}  // namespace
+}  // namespace demag
+
+using namespace demag;
+
+extern "C" {
+
+int32_t demag_mlp_param_count(void) { return kParams; }
+
+demag_status demag_mlp_forward(demag_ctx *ctx, const float *params, const float *x, int32_t B, float *y,
+                               float *z, float *a) {
+  DEMAG_REQUIRE(ctx && params && x && y, "demag_mlp_forward: NULL argument");
+  DEMAG_REQUIRE(B >= 1, "demag_mlp_forward: B must be >= 1");
+  DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  k_mlp_forward<<<B, 64, 0, ctx->stream>>>(params, x, B, y, z, a);
+  DEMAG_TRY_HIP(hipGetLastError());
+  return DEMAG_OK;
+}
+
+demag_status demag_mlp_backward(demag_ctx *ctx, const float *params, const float *x, const float *z, const float *a,
+                                const float *dy, int32_t B, float *delta, float *grad) {
+  DEMAG_REQUIRE(ctx && params && x && z && a && dy && delta && grad, "demag_mlp_backward: NULL argument");
+  DEMAG_REQUIRE(B >= 1, "demag_mlp_backward: B must be >= 1");
+  DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  k_mlp_delta<<<B, 64, 0, ctx->stream>>>(params, z, dy, B, delta);
+  k_mlp_grad<<<(kParams + 255) / 256, 256, 0, ctx->stream>>>(x, a, delta, dy, B, grad);
+  DEMAG_TRY_HIP(hipGetLastError());
+  return DEMAG_OK;
+}
+
+demag_status demag_adam_step(demag_ctx *ctx, float *params, const float *grad, float *m, float *v, int32_t count,
+                             int32_t step, float lr, float b1, float b2, float eps) {
+  DEMAG_REQUIRE(ctx && params && grad && m && v, "demag_adam_step: NULL argument");
+  DEMAG_REQUIRE(count >= 1 && step >= 1, "demag_adam_step: count and step must be >= 1");
+  DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  k_adam<<<(count + 255) / 256, 256, 0, ctx->stream>>>(params, grad, m, v, count, step, lr, b1, b2, eps);
+  DEMAG_TRY_HIP(hipGetLastError());
+  return DEMAG_OK;
+}
+
+demag_status demag_quad_judge(demag_ctx *ctx, int32_t B, const int32_t *grids, const double *hmin,
+                              const int32_t *sent, int32_t S, const double *t, const double *alpha, const int32_t *R,
+                              int32_t KM, double *err, double *dt, double *dalpha) {
+  DEMAG_REQUIRE(ctx && grids && hmin && sent && t && alpha && R && err, "demag_quad_judge: NULL argument");
+  DEMAG_REQUIRE(B >= 1 && S >= 1 && KM >= 1 && KM <= 256, "demag_quad_judge: sizes out of range");
+  DEMAG_REQUIRE((dt == nullptr) == (dalpha == nullptr), "demag_quad_judge: give both gradients or neither");
+  DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  double *Kref = nullptr, *K = nullptr, *resid = nullptr;
+  demag_status st = dalloc(&Kref, size_t(B) * S * kNcomp);
+  if (st == DEMAG_OK) st = dalloc(&K, size_t(B) * S * kNcomp);
+  if (st == DEMAG_OK) st = dalloc(&resid, size_t(B) * S * kNcomp);
+  if (st == DEMAG_OK) st = reference_values(ctx, grids, hmin, sent, S, B, Kref);
+  if (st == DEMAG_OK) {
+    k_judge_values<<<(B * S + 127) / 128, 128, 0, ctx->stream>>>(grids, hmin, sent, S, t, alpha, R, KM, B, K);
+    k_judge_err<<<(B + 127) / 128, 128, 0, ctx->stream>>>(K, Kref, B, S, err, resid);
+    if (dt)
+      k_judge_grad<<<(B * KM + 127) / 128, 128, 0, ctx->stream>>>(grids, hmin, sent, S, t, alpha, R, KM, B, resid,
+                                                                 err, dt, dalpha);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      set_error(hipGetErrorString(e));
+      st = DEMAG_E_HIP;
+    } else if (hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      set_error("demag_quad_judge: stream synchronization failed");
+      st = DEMAG_E_HIP;
+    }
+  }
+  for (double *p : {Kref, K, resid})
+    if (p) (void)hipFree(p);
+  return st;
+}
+
+demag_status demag_quad_rules(demag_ctx *ctx, const float *y, const int32_t *R, int32_t B, double *t,
+                              double *alpha) {
+  DEMAG_REQUIRE(ctx && R && t && alpha, "demag_quad_rules: NULL argument");
+  DEMAG_REQUIRE(B >= 1, "demag_quad_rules: B must be >= 1");
+  DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  k_rules<<<B, kRmax, 0, ctx->stream>>>(y, R, B, kRmax, t, alpha);
+  DEMAG_TRY_HIP(hipGetLastError());
+  return DEMAG_OK;
+}
+
+demag_status demag_quad_train(demag_ctx *ctx, float *params, float *adam_m, float *adam_v, const float *x,
+                              const int32_t *grids, const double *hmin, const int32_t *R, const int32_t *sent,
+                              int32_t count, int32_t S, int32_t steps, int32_t batch, int32_t step0, float lr,
+                              float lambda, float *loss_host) {
+  DEMAG_REQUIRE(ctx && params && adam_m && adam_v && x && grids && hmin && R && sent, "demag_quad_train: NULL argument");
+  DEMAG_REQUIRE(count >= 1 && S >= 1 && steps >= 0 && batch >= 1 && batch <= count && step0 >= 0,
+                "demag_quad_train: sizes out of range");
+  DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  const int KM = kRmax;
+  double *Kref = nullptr;
+  demag_status st = dalloc(&Kref, size_t(count) * S * kNcomp);
+  if (st != DEMAG_OK) return st;
+  st = reference_values(ctx, grids, hmin, sent, S, count, Kref);
+  float *Y = nullptr, *Z = nullptr, *A = nullptr, *D = nullptr, *dY = nullptr, *G = nullptr, *loss = nullptr;
+  JudgeBufs jb;
+  for (auto pp : {&Y, &dY}) if (st == DEMAG_OK) st = dalloc(pp, size_t(batch) * kOut);
+  for (auto pp : {&Z, &A, &D}) if (st == DEMAG_OK) st = dalloc(pp, size_t(batch) * 3 * kH);
+  if (st == DEMAG_OK) st = dalloc(&G, kParams);
+  if (st == DEMAG_OK) st = dalloc(&loss, size_t(steps) * batch);
+  for (auto pp : {&jb.t, &jb.alpha, &jb.dt, &jb.dalpha}) if (st == DEMAG_OK) st = dalloc(pp, size_t(batch) * KM);
+  for (auto pp : {&jb.K, &jb.resid}) if (st == DEMAG_OK) st = dalloc(pp, size_t(batch) * S * kNcomp);
+  if (st == DEMAG_OK) st = dalloc(&jb.err, batch);
+  for (int it = 0; st == DEMAG_OK && it < steps; ++it) {
+    // contiguous minibatch of the (caller-shuffled) cases, wrapping around
+    const int first = int((int64_t(it) * batch) % count);
+    const int nb = std::min(batch, count - first);
+    const float *xb = x + size_t(first) * kIn;
+    const int *gb = grids + size_t(first) * 3;
+    const double *hb = hmin + first;
+    const int *Rb = R + first;
+    const int *sb = sent + size_t(first) * S * 3;
+    const double *Kr = Kref + size_t(first) * S * kNcomp;
+    k_mlp_forward<<<nb, 64, 0, ctx->stream>>>(params, xb, nb, Y, Z, A);
+    k_rules<<<nb, kRmax, 0, ctx->stream>>>(Y, Rb, nb, KM, jb.t, jb.alpha);
+    k_judge_values<<<(nb * S + 127) / 128, 128, 0, ctx->stream>>>(gb, hb, sb, S, jb.t, jb.alpha, Rb, KM, nb, jb.K);
+    k_judge_err<<<(nb + 127) / 128, 128, 0, ctx->stream>>>(jb.K, Kr, nb, S, jb.err, jb.resid);
+    k_judge_grad<<<(nb * KM + 127) / 128, 128, 0, ctx->stream>>>(gb, hb, sb, S, jb.t, jb.alpha, Rb, KM, nb,
+                                                                 jb.resid, jb.err, jb.dt, jb.dalpha);
+    k_output_grads<<<nb, 128, 0, ctx->stream>>>(Y, Rb, nb, KM, jb.t, jb.alpha, jb.dt, jb.dalpha, jb.err, lambda, dY,
+                                               loss + size_t(it) * batch);
+    k_mlp_delta<<<nb, 64, 0, ctx->stream>>>(params, Z, dY, nb, D);
+    k_mlp_grad<<<(kParams + 255) / 256, 256, 0, ctx->stream>>>(xb, A, D, dY, nb, G);
+    k_adam<<<(kParams + 255) / 256, 256, 0, ctx->stream>>>(params, G, adam_m, adam_v, kParams, step0 + it + 1, lr,
+                                                          0.9f, 0.999f, 1e-8f);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+      set_error(std::string("demag_quad_train: ") + hipGetErrorString(e));
+      st = DEMAG_E_HIP;
+    }
+    if (loss_host && st == DEMAG_OK) {
+      // mean loss of the step (host copy; the per-case values stay on the device)
+      std::vector<float> lb(nb);
+      if (hipMemcpyAsync(lb.data(), loss + size_t(it) * batch, sizeof(float) * nb, hipMemcpyDeviceToHost,
+                         ctx->stream) != hipSuccess ||
+          hipStreamSynchronize(ctx->stream) != hipSuccess) {
+        set_error("demag_quad_train: loss copy failed");
+        st = DEMAG_E_HIP;
+      } else {
+        double s = 0;
+        for (float v : lb) s += v;
+        loss_host[it] = float(s / nb);
+      }
+    }
+  }
+  (void)hipStreamSynchronize(ctx->stream);
+  for (float *p : {Y, Z, A, D, dY, G, loss})
+    if (p) (void)hipFree(p);
+  jb.release();
+  (void)hipFree(Kref);
+  return st;
+}
+
+// Shortened rule for one grid: try R' = 16..32, take the smallest whose
+// predicted log10 error is <= log10(tol) (else 32), judge it against the
+// reference on the grid's sentinels, and fall back to the sinc rule with the
+// step of Thm. sinc_theo and 64 nodes if the judged error exceeds tol.
+// features: device [17][6] (R' = 16..32 in order); grid n (host), hmin,
+// sentinels (device [S][3]).  Outputs (host): t_out, alpha_out (capacity 64),
+// *R_out, *judged, *predicted (log10), *fell_back.
+demag_status demag_quad_predict(demag_ctx *ctx, const float *params, const float *features, const int32_t n[3],
+                                double hmin, const int32_t *sent, int32_t S, double tol, double *t_out,
+                                double *alpha_out, int32_t *R_out, double *judged, double *predicted,
+                                int32_t *fell_back) {
+  DEMAG_REQUIRE(ctx && params && features && n && sent && t_out && alpha_out && R_out && judged && predicted &&
+                    fell_back,
+                "demag_quad_predict: NULL argument");
+  DEMAG_REQUIRE(tol > 0 && hmin > 0 && S >= 1, "demag_quad_predict: tol, hmin and S must be positive");
+  DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  const int NC = 17;
+  float *Y = nullptr;
+  demag_status st = dalloc(&Y, size_t(NC) * kOut);
+  if (st != DEMAG_OK) return st;
+  k_mlp_forward<<<NC, 64, 0, ctx->stream>>>(params, features, NC, Y, nullptr, nullptr);
+  std::vector<float> yh(size_t(NC) * kOut);
+  DEMAG_TRY_HIP(hipMemcpyAsync(yh.data(), Y, sizeof(float) * yh.size(), hipMemcpyDeviceToHost, ctx->stream));
+  DEMAG_TRY_HIP(hipStreamSynchronize(ctx->stream));
+  int pick = NC - 1;
+  for (int c = 0; c < NC; ++c)
+    if (yh[size_t(c) * kOut + 64] <= std::log10(tol)) {
+      pick = c;
+      break;
+    }
+  const int Rp = 16 + pick;
+  *predicted = yh[size_t(pick) * kOut + 64];
+  // rule of the pick, judged against the reference on the device
+  int32_t *dR = nullptr, *dgrid = nullptr;
+  double *dh = nullptr, *dt = nullptr, *da = nullptr, *derr = nullptr;
+  if (st == DEMAG_OK) st = dalloc(&dR, 1);
+  if (st == DEMAG_OK) st = dalloc(&dgrid, 3);
+  if (st == DEMAG_OK) st = dalloc(&dh, 1);
+  if (st == DEMAG_OK) st = dalloc(&dt, kRmax);
+  if (st == DEMAG_OK) st = dalloc(&da, kRmax);
+  if (st == DEMAG_OK) st = dalloc(&derr, 1);
+  if (st == DEMAG_OK) {
+    DEMAG_TRY_HIP(hipMemcpyAsync(dR, &Rp, sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+    DEMAG_TRY_HIP(hipMemcpyAsync(dgrid, n, sizeof(int32_t) * 3, hipMemcpyHostToDevice, ctx->stream));
+    DEMAG_TRY_HIP(hipMemcpyAsync(dh, &hmin, sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    k_rules<<<1, kRmax, 0, ctx->stream>>>(Y + size_t(pick) * kOut, dR, 1, kRmax, dt, da);
+    DEMAG_TRY_HIP(hipGetLastError());
+    st = demag_quad_judge(ctx, 1, dgrid, dh, sent, S, dt, da, dR, kRmax, derr, nullptr, nullptr);
+  }
+  if (st == DEMAG_OK) {
+    double e = 0;
+    std::vector<double> th(kRmax), ah(kRmax);
+    DEMAG_TRY_HIP(hipMemcpy(&e, derr, sizeof(double), hipMemcpyDeviceToHost));
+    DEMAG_TRY_HIP(hipMemcpy(th.data(), dt, sizeof(double) * kRmax, hipMemcpyDeviceToHost));
+    DEMAG_TRY_HIP(hipMemcpy(ah.data(), da, sizeof(double) * kRmax, hipMemcpyDeviceToHost));
+    *judged = e;
+    if (e <= tol) {
+      *fell_back = 0;
+      *R_out = Rp;
+      for (int k = 0; k < Rp; ++k) {
+        t_out[k] = th[k];
+        alpha_out[k] = ah[k];
+      }
+    } else {
+      // fallback: the sinc rule with the step of Thm. sinc_theo, 64 nodes
+      *fell_back = 1;
+      const int M = 64;
+      const double a = 2.0, bb = 0.25 * (0.5 * hmin) * (0.5 * hmin);
+      const double theta = std::log(2.0 * kPi * a * M / bb) / (a * M);
+      *R_out = M;
+      for (int k = 0; k < M; ++k) {
+        const double tk = (k + 1) * theta, sh = std::sinh(tk);
+        t_out[k] = tk;
+        alpha_out[k] = 2.0 * theta * std::cosh(tk) * sh * sh;
+      }
+    }
+  }
+  for (void *p : {(void *)Y, (void *)dR, (void *)dgrid, (void *)dh, (void *)dt, (void *)da, (void *)derr})
+    if (p) (void)hipFree(p);
+  return st;
+}
+
+}  // extern "C"
