@@ -99,6 +99,11 @@ demag_status demag_set_stream(demag_ctx *ctx, void *hip_stream);
 /* Upper bound in bytes of the internal workspace of demag_apply_full (the
  * node loop is split into chunks that fit).  Default 16 GiB. */
 demag_status demag_set_workspace_limit(demag_ctx *ctx, size_t bytes);
+/* Tile shape of the full-format mode products: `rows` = 16-row blocks per
+ * tile (1, 2, 4 or 8; 0 = chosen from the axis length), `cols` = 64-column
+ * blocks per bfloat16 tile (1 or 2; 0 = automatic).  Results do not depend
+ * on the shape.  DEMAG_E_INVAL for other values. */
+demag_status demag_set_tiles(demag_ctx *ctx, int32_t rows, int32_t cols);
 /* Message of the calling thread's most recent failure ("" if none). */
 const char *demag_last_error(void);
 

@@ -42,6 +42,7 @@ _SIGS = {
     "demag_destroy": (C.c_int, [_P]),
     "demag_set_stream": (C.c_int, [_P, _P]),
     "demag_set_workspace_limit": (C.c_int, [_P, C.c_size_t]),
+    "demag_set_tiles": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "demag_assemble_factors": (C.c_int, [_P, C.POINTER(Grid), C.POINTER(Quad), C.POINTER(_P)]),
     "demag_factors_free": (C.c_int, [_P]),
     "demag_factors_count": (C.c_int, [_P, C.POINTER(C.c_int32)]),
@@ -203,6 +204,10 @@ class Context:
 
     def set_workspace_limit(self, nbytes: int):
         _check(library().demag_set_workspace_limit(self.handle, nbytes), "demag_set_workspace_limit")
+
+    def set_tiles(self, rows: int = 0, cols: int = 0):
+        """Tile shape of the full-format products (0 = automatic)."""
+        _check(library().demag_set_tiles(self.handle, rows, cols), "demag_set_tiles")
 
     def assemble(self, n, h, M: int = 40, c0: float = 2.15, step_rule: int = 0, t=None, alpha=None) -> Factors:
         g = Grid((C.c_int32 * 3)(*n), (C.c_double * 3)(*h))

@@ -503,6 +503,16 @@ demag_status demag_set_workspace_limit(demag_ctx *ctx, size_t bytes) {
   return DEMAG_OK;
 }
 
+demag_status demag_set_tiles(demag_ctx *ctx, int32_t rows, int32_t cols) {
+  DEMAG_REQUIRE(ctx, "demag_set_tiles: ctx is NULL");
+  DEMAG_REQUIRE(rows == 0 || rows == 1 || rows == 2 || rows == 4 || rows == 8,
+                "demag_set_tiles: rows must be 0, 1, 2, 4 or 8");
+  DEMAG_REQUIRE(cols == 0 || cols == 1 || cols == 2, "demag_set_tiles: cols must be 0, 1 or 2");
+  ctx->tile_rows = rows;
+  ctx->tile_cols = cols;
+  return DEMAG_OK;
+}
+
 demag_status demag_assemble_factors(demag_ctx *ctx, const demag_grid *grid, const demag_quad *quad,
                                     demag_factors **out) {
   DEMAG_REQUIRE(ctx && grid && quad && out, "demag_assemble_factors: NULL argument");

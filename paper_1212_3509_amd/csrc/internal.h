@@ -129,6 +129,8 @@ struct demag_ctx {
   void *ws = nullptr;
   size_t ws_bytes = 0;
   size_t ws_limit = size_t(16) << 30;
+  int tile_rows = 0;        // row blocks per full-format tile (0: by grid size)
+  int tile_cols = 0;        // column blocks per bfloat16 tile (0: automatic)
   bool profiling = false;
   std::vector<demag::ProfRecord> prof_pending;
   std::vector<hipEvent_t> prof_pool;

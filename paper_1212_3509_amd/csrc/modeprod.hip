@@ -13,8 +13,16 @@
 // outputs that share the input fragment.  The B operand (input) is read
 // straight from global memory, 16 consecutive columns per row, one value per
 // lane per K-step; the A operand (Toeplitz) comes from the generator staged
-// in LDS (one ds_read per fragment).  Loads of the next 8 K-steps are issued
-// before the current 8 are multiplied.
+// in LDS (one ds_read per fragment).
+//
+// Pipelining: the (term, K-chunk) pairs of a job form one loop; the loads of
+// chunk q + 1 (which may belong to the next term) are in flight while chunk q
+// is multiplied, and the next term's generators are fetched into registers a
+// whole term ahead and written to the second of two LDS buffers, so a term
+// boundary costs one barrier.  Every global load is unconditional (rows past
+// n and columns past C read clamped, in-bounds addresses whose values are
+// zeroed or never stored), so the compiler can count outstanding loads and
+// wait only for the oldest ones.
 //
 // The same tile routine serves the batched path, where one persistent launch
 // walks a list of (job, geometry, tile) items of many grids.
@@ -45,10 +53,25 @@ template <> struct Mfma<float> {
   __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-constexpr int kUnroll = 8;  // K-steps (of 4) prefetched ahead
+constexpr int kUnroll = 8;  // K-steps (of 4) per chunk
+constexpr int kGenPer = 4;  // generator values per thread fetched a term ahead
 
 __host__ __device__ inline size_t tile_lds_elems(int n, int RB, int NOUT) {
-  return size_t(NOUT) * (2 * n + 16 * RB + 32);
+  return 2 * size_t(NOUT) * (2 * n + 16 * RB + 32);  // two generator buffers
+}
+
+// Generator value e of a term's staged block: output o = e / glds, generator
+// index s = e % glds - 16 (zero outside [0, genlen)).  g0, g1: the term's
+// generators of outputs 0 and 1.  Returns an in-bounds address for every e
+// and sets ok when the value is a real generator entry.
+template <class T, int NOUT>
+__device__ __forceinline__ const T *gen_addr(const T *g0, const T *g1, int e, int glds, int gtot, int genlen,
+                                             bool &ok) {
+  const bool second = NOUT > 1 && e >= glds;
+  const int s = e - (second ? glds : 0) - 16;
+  ok = e < gtot && s >= 0 && s < genlen;
+  const int sc = s < 0 ? 0 : (s >= genlen ? genlen - 1 : s);
+  return (second ? g1 : g0) + sc;
 }
 
 // One 64-column x 16*RB-row tile of one job.  sg: LDS, tile_lds_elems(n, RB, NOUT).
@@ -59,15 +82,27 @@ __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__rest
   using Mf = Mfma<T>;
   using acc_t = typename Mf::acc_t;
   const int n = g.n;
+  const int nterms = job.nterms;
+  if (nterms <= 0) return;
   const int glds = 2 * n + 16 * RB + 32;
+  const int gtot = NOUT * glds;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int kq = lane >> 4;
   const int c = ct * 64 + wave * 16 + (lane & 15);
   const bool cvalid = c < g.C;
-  const int co = cvalid ? c / g.C1 : 0, ci = cvalid ? c % g.C1 : 0;
+  // columns past C read column C - 1 and are never stored
+  const int cl = cvalid ? c : g.C - 1;
+  const int co = cl / g.C1, ci = cl % g.C1;
+  const size_t cin = size_t(co) * g.in_S1 + ci;
   const int row0 = rg * 16 * RB;
   // LDS index of T[row0 + (lane & 15)][kq] for j0 = 0; add 16 rb - j0.
   const int ibase = row0 + (lane & 15) - kq + n - 1 + 16;
+  const int nch = (n + 4 * kUnroll - 1) / (4 * kUnroll);
+  const int nq = nterms * nch;
+  auto term_in = [&](int t) -> const T * {
+    const MPTerm &tm = terms[job.term0 + t];
+    return static_cast<const T *>(bufs.p[tm.in_buf]) + tm.in_off + cin;
+  };
 
   acc_t acc[NOUT][RB];
 #pragma unroll
@@ -75,46 +110,95 @@ __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__rest
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) acc[o][rb] = acc_t{0, 0, 0, 0};
 
-  for (int t = 0; t < job.nterms; ++t) {
-    const MPTerm tm = terms[job.term0 + t];
-    __syncthreads();
+  // the previous tile of a persistent workgroup may still read the buffers
+  __syncthreads();
+  auto gen0 = [&](int t) { return gens + terms[job.term0 + t].gen_off[0]; };
+  auto gen1 = [&](int t) { return gens + terms[job.term0 + t].gen_off[NOUT > 1 ? 1 : 0]; };
+  T greg[kGenPer];
+  {
+    const T *g0 = gen0(0), *g1 = gen1(0);
 #pragma unroll
-    for (int o = 0; o < NOUT; ++o) {
-      const T *gsrc = gens + tm.gen_off[o];
-      for (int idx = threadIdx.x; idx < glds; idx += 256) {
-        const int s = idx - 16;
-        sg[o * glds + idx] = (s >= 0 && s < g.genlen) ? gsrc[s] : T(0);
-      }
+    for (int r = 0; r < kGenPer; ++r) {
+      bool ok;
+      greg[r] = *gen_addr<T, NOUT>(g0, g1, threadIdx.x + 256 * r, glds, gtot, g.genlen, ok);
     }
-    __syncthreads();
-    const T *in = static_cast<const T *>(bufs.p[tm.in_buf]) + tm.in_off + size_t(co) * g.in_S1 + ci;
-    T nxt[kUnroll];
+  }
+  T nxt[kUnroll];
+  {
+    const T *in = term_in(0);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int j = 4 * u + kq;
-      nxt[u] = (cvalid && j < n) ? in[size_t(j) * g.kstride] : T(0);
+      const int j = min(4 * u + kq, n - 1);
+      nxt[u] = in[size_t(j) * g.kstride];
     }
-    for (int j0 = 0; j0 < n; j0 += 4 * kUnroll) {
-      T cur[kUnroll];
+  }
+
+  int t = 0, j0 = 0;
+  for (int q = 0; q < nq; ++q) {
+    if (j0 == 0) {
+      // term t starts: its generators (fetched a term ahead) go to buffer t & 1,
+      // last read during term t - 2, which every wave finished before the
+      // barrier of term t - 1
+      T *buf = sg + (t & 1) * gtot;
+      const T *g0 = gen0(t), *g1 = gen1(t);
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) cur[u] = nxt[u];
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int j = j0 + 4 * (kUnroll + u) + kq;
-        nxt[u] = (cvalid && j < n) ? in[size_t(j) * g.kstride] : T(0);
+      for (int r = 0; r < kGenPer; ++r) {
+        const int e = threadIdx.x + 256 * r;
+        bool ok;
+        gen_addr<T, NOUT>(g0, g1, e, glds, gtot, g.genlen, ok);
+        if (e < gtot) buf[e] = ok ? greg[r] : T(0);
       }
+      for (int e0 = 256 * kGenPer; e0 < gtot; e0 += 256) {  // long generators: the rest now
+        const int e = e0 + threadIdx.x;
+        bool ok;
+        const T v = *gen_addr<T, NOUT>(g0, g1, e, glds, gtot, g.genlen, ok);
+        if (e < gtot) buf[e] = ok ? v : T(0);
+      }
+      const int tn = min(t + 1, nterms - 1);
+      const T *n0 = gen0(tn), *n1 = gen1(tn);
+#pragma unroll
+      for (int r = 0; r < kGenPer; ++r) {
+        bool ok;
+        greg[r] = *gen_addr<T, NOUT>(n0, n1, threadIdx.x + 256 * r, glds, gtot, g.genlen, ok);
+      }
+      __syncthreads();
+    }
+    const T *sgen = sg + (t & 1) * gtot;
+    T cur[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) cur[u] = nxt[u];
+    {
+      // chunk q + 1: the next chunk of this term, else the first of the next
+      // term; the last chunk of the job re-reads its own rows
+      int t1 = t, j1 = j0 + 4 * kUnroll;
+      if (j1 >= n) {
+        j1 = (t + 1 < nterms) ? 0 : j0;
+        t1 = min(t + 1, nterms - 1);
+      }
+      const T *in1 = term_in(t1);
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        const int jj = j0 + 4 * u;
-        if (jj < n) {
+        const int j = min(j1 + 4 * u + kq, n - 1);
+        nxt[u] = in1[size_t(j) * g.kstride];
+      }
+    }
 #pragma unroll
-          for (int rb = 0; rb < RB; ++rb) {
-            const int idx = ibase + 16 * rb - jj;
+    for (int u = 0; u < kUnroll; ++u) {
+      const int jj = j0 + 4 * u;
+      if (jj < n) {
+        const T b = (jj + kq < n) ? cur[u] : T(0);
 #pragma unroll
-            for (int o = 0; o < NOUT; ++o) acc[o][rb] = Mf::step(sg[o * glds + idx], cur[u], acc[o][rb]);
-          }
+        for (int rb = 0; rb < RB; ++rb) {
+          const int idx = ibase + 16 * rb - jj;
+#pragma unroll
+          for (int o = 0; o < NOUT; ++o) acc[o][rb] = Mf::step(sgen[o * glds + idx], b, acc[o][rb]);
         }
       }
+    }
+    j0 += 4 * kUnroll;
+    if (j0 >= n) {
+      j0 = 0;
+      ++t;
     }
   }
 
@@ -139,7 +223,7 @@ __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__rest
 }
 
 template <class T, int RB, int NOUT, int AXIS>
-__global__ __launch_bounds__(256) void k_left(const MPJob *__restrict__ jobs, const MPTerm *__restrict__ terms,
+__global__ __launch_bounds__(256, 2) void k_left(const MPJob *__restrict__ jobs, const MPTerm *__restrict__ terms,
                                               Bufs bufs, const T *__restrict__ gens, MPGeom g, int col_tiles,
                                               int beta) {
   extern __shared__ unsigned char smem_raw[];
@@ -152,7 +236,7 @@ __global__ __launch_bounds__(256) void k_left(const MPJob *__restrict__ jobs, co
 // (static order, no atomics); each item names its job, geometry, tile and
 // the (RB, NOUT) shape chosen for it.
 template <class T>
-__global__ __launch_bounds__(256) void k_left_items(const BatchItem *__restrict__ items, int nitems,
+__global__ __launch_bounds__(256, 2) void k_left_items(const BatchItem *__restrict__ items, int nitems,
                                                     const MPJob *__restrict__ jobs, const MPTerm *__restrict__ terms,
                                                     const MPGeom *__restrict__ geoms, Bufs bufs,
                                                     const T *__restrict__ gens, int beta) {
@@ -200,8 +284,8 @@ demag_status launch_rb(hipStream_t s, const StagePlan &sp, const T *gens, const 
 }
 
 template <class T, int NOUT>
-demag_status launch_nout(hipStream_t s, const StagePlan &sp, const T *gens, const Bufs &bufs, int beta) {
-  switch (sp.rb) {
+demag_status launch_nout(hipStream_t s, int rb, const StagePlan &sp, const T *gens, const Bufs &bufs, int beta) {
+  switch (rb) {
     case 1: return launch_rb<T, 1, NOUT>(s, sp, gens, bufs, beta);
     case 2: return launch_rb<T, 2, NOUT>(s, sp, gens, bufs, beta);
     case 4: return launch_rb<T, 4, NOUT>(s, sp, gens, bufs, beta);
@@ -210,9 +294,9 @@ demag_status launch_nout(hipStream_t s, const StagePlan &sp, const T *gens, cons
 }
 
 template <class T>
-demag_status launch_typed(hipStream_t s, const StagePlan &sp, const T *gens, const Bufs &bufs, int beta) {
-  if (sp.nout == 1) return launch_nout<T, 1>(s, sp, gens, bufs, beta);
-  return launch_nout<T, 2>(s, sp, gens, bufs, beta);
+demag_status launch_typed(hipStream_t s, int rb, const StagePlan &sp, const T *gens, const Bufs &bufs, int beta) {
+  if (sp.nout == 1) return launch_nout<T, 1>(s, rb, sp, gens, bufs, beta);
+  return launch_nout<T, 2>(s, rb, sp, gens, bufs, beta);
 }
 
 }  // namespace
@@ -264,12 +348,13 @@ demag_status launch_left_stage(demag_ctx *ctx, const demag_factors *f, demag_pre
   if (st != DEMAG_OK) return st;
   const char *pname = "?";
   size_t esize = 4;
+  const int rb = ctx->tile_rows > 0 ? ctx->tile_rows : sp.rb;
   if (prec == DEMAG_FP64) {
-    st = launch_typed<double>(ctx->stream, sp, f->f64[sp.axis], bufs, beta);
+    st = launch_typed<double>(ctx->stream, rb, sp, f->f64[sp.axis], bufs, beta);
     pname = "fp64";
     esize = 8;
   } else if (prec == DEMAG_FP32) {
-    st = launch_typed<float>(ctx->stream, sp, f->f32[sp.axis], bufs, beta);
+    st = launch_typed<float>(ctx->stream, rb, sp, f->f32[sp.axis], bufs, beta);
     pname = "fp32";
   } else {
     st = launch_left_stage_bf16(ctx, f, prec, sp, bufp, beta);

@@ -38,15 +38,26 @@ union Frag {
   bf8 v;
 };
 
+constexpr int kStageRounds = 3;  // window entries a thread loads per staging round
+
+// Tile: 4 waves x 16*CB columns, 16*RB rows.  The (term, K-step) pairs of a
+// job form one loop whose next step's input loads are in flight while the
+// current one is multiplied; all global loads are unconditional (clamped
+// rows and columns, zeroed or discarded), so the compiler waits only for the
+// loads it needs.  A term's windows are staged in rounds of up to
+// 3 x 256 entries whose loads are all issued before the first LDS store.
 template <int RB, int CB, int NOUT, int PARTS>
-__global__ __launch_bounds__(256) void k_left_bf16(const MPJob *__restrict__ jobs,
+__global__ __launch_bounds__(256, 2) void k_left_bf16(const MPJob *__restrict__ jobs,
                                                    const MPTerm *__restrict__ terms, Bufs bufs,
                                                    const uint4 *__restrict__ wtab, MPGeom g, int nw,
                                                    int col_tiles, int beta) {
   extern __shared__ uint4 wl[];
   const int n = g.n;
   const int cnt = n + 16 * RB + 23;
+  const int tot = NOUT * cnt;
   const MPJob job = jobs[blockIdx.y];
+  const int nterms = job.nterms;
+  if (nterms <= 0) return;
   const int ct = blockIdx.x % col_tiles;
   const int rg = blockIdx.x / col_tiles;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -62,10 +73,15 @@ __global__ __launch_bounds__(256) void k_left_bf16(const MPJob *__restrict__ job
   for (int cb = 0; cb < CB; ++cb) {
     const int c = ct * (64 * CB) + wave * (16 * CB) + 16 * cb + (lane & 15);
     cval[cb] = c < g.C;
-    const int co = cval[cb] ? c / g.C1 : 0, ci = cval[cb] ? c % g.C1 : 0;
+    const int cl = cval[cb] ? c : g.C - 1;  // past the end: read column C - 1, never stored
+    const int co = cl / g.C1, ci = cl % g.C1;
     inoff[cb] = int64_t(co) * g.in_S1 + ci;
     outoff[cb] = int64_t(co) * g.out_S1 + int64_t(ci) * g.out_cs;
   }
+  auto term_in = [&](int t) -> const float * {
+    const MPTerm &tm = terms[job.term0 + t];
+    return static_cast<const float *>(bufs.p[tm.in_buf]) + tm.in_off;
+  };
 
   f4 acc[NOUT][RB][CB];
 #pragma unroll
@@ -75,71 +91,100 @@ __global__ __launch_bounds__(256) void k_left_bf16(const MPJob *__restrict__ job
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) acc[o][rb][cb] = f4{0, 0, 0, 0};
 
-  for (int t = 0; t < job.nterms; ++t) {
-    const MPTerm tm = terms[job.term0 + t];
-    __syncthreads();
+  const int nks = (n + 31) / 32;
+  const int nq = nterms * nks;
+  float raw[CB][8];
+  {
+    const float *in = term_in(0);
 #pragma unroll
-    for (int o = 0; o < NOUT; ++o) {
-      const uint4 *src = wtab + (size_t(tm.gen[o]) * nw + (s0min + 128)) * 3;
-      for (int e = threadIdx.x; e < cnt; e += 256) {
+    for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-        for (int p = 0; p < PARTS; ++p) wl[(o * PARTS + p) * cnt + e] = src[size_t(e) * 3 + p];
+      for (int e = 0; e < 8; ++e) raw[cb][e] = in[size_t(min(8 * kq + e, n - 1)) * g.kstride + inoff[cb]];
+  }
+  int t = 0, j0 = 0;
+  for (int q = 0; q < nq; ++q) {
+    if (j0 == 0) {
+      const MPTerm &tm = terms[job.term0 + t];
+      const int gen0 = tm.gen[0], gen1 = tm.gen[NOUT > 1 ? 1 : 0];
+      __syncthreads();  // every wave is done with the previous term's windows
+      for (int e0 = 0; e0 < tot; e0 += 256 * kStageRounds) {
+        uint4 v[kStageRounds][PARTS];
+#pragma unroll
+        for (int r = 0; r < kStageRounds; ++r) {
+          const int e = min(e0 + 256 * r + int(threadIdx.x), tot - 1);
+          const bool second = NOUT > 1 && e >= cnt;
+          const uint4 *src = wtab + (size_t(second ? gen1 : gen0) * nw + (s0min + 128) + (e - (second ? cnt : 0))) * 3;
+#pragma unroll
+          for (int p = 0; p < PARTS; ++p) v[r][p] = src[p];
+        }
+        // threads past the end rewrite entry tot - 1 with the value they
+        // loaded from it (no branch, so every load is issued before a store)
+#pragma unroll
+        for (int r = 0; r < kStageRounds; ++r) {
+          const int e = min(e0 + 256 * r + int(threadIdx.x), tot - 1);
+          const bool second = NOUT > 1 && e >= cnt;
+          const int o = second ? 1 : 0, el = e - (second ? cnt : 0);
+#pragma unroll
+          for (int p = 0; p < PARTS; ++p) wl[(o * PARTS + p) * cnt + el] = v[r][p];
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
-    const float *in = static_cast<const float *>(bufs.p[tm.in_buf]) + tm.in_off;
-    float raw[CB][8];
+    Frag bh[CB], bl[CB], bl2[CB];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
-        const int j = 8 * kq + e;
-        raw[cb][e] = (cval[cb] && j < n) ? in[size_t(j) * g.kstride + inoff[cb]] : 0.0f;
+        const float x = (j0 + 8 * kq + e < n) ? raw[cb][e] : 0.0f;
+        __bf16 h, l, l2;
+        split_value(x, h, l, l2);
+        bh[cb].v[e] = h;
+        bl[cb].v[e] = l;
+        bl2[cb].v[e] = l2;
       }
-    for (int j0 = 0; j0 < n; j0 += 32) {
-      Frag bh[CB], bl[CB], bl2[CB];
+    {
+      // next K-step: of this term, else the first of the next term; the
+      // last step of the job re-reads its own rows
+      int t1 = t, j1 = j0 + 32;
+      if (j1 >= n) {
+        j1 = (t + 1 < nterms) ? 0 : j0;
+        t1 = min(t + 1, nterms - 1);
+      }
+      const float *in1 = term_in(t1);
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          __bf16 h, l, l2;
-          split_value(raw[cb][e], h, l, l2);
-          bh[cb].v[e] = h;
-          bl[cb].v[e] = l;
-          bl2[cb].v[e] = l2;
-        }
-      // prefetch the next K-step while this one is multiplied
+        for (int e = 0; e < 8; ++e)
+          raw[cb][e] = in1[size_t(min(j1 + 8 * kq + e, n - 1)) * g.kstride + inoff[cb]];
+    }
 #pragma unroll
-      for (int cb = 0; cb < CB; ++cb)
+    for (int rb = 0; rb < RB; ++rb) {
+      const int idx = sbase - 16 * rb + j0;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const int j = j0 + 32 + 8 * kq + e;
-          raw[cb][e] = (cval[cb] && j < n) ? in[size_t(j) * g.kstride + inoff[cb]] : 0.0f;
-        }
+      for (int o = 0; o < NOUT; ++o) {
+        Frag ah, al, al2;
+        ah.u = wl[(o * PARTS + 0) * cnt + idx];
+        al.u = wl[(o * PARTS + 1) * cnt + idx];
+        if (PARTS == 3) al2.u = wl[(o * PARTS + 2) * cnt + idx];
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const int idx = sbase - 16 * rb + j0;
-#pragma unroll
-        for (int o = 0; o < NOUT; ++o) {
-          Frag ah, al, al2;
-          ah.u = wl[(o * PARTS + 0) * cnt + idx];
-          al.u = wl[(o * PARTS + 1) * cnt + idx];
-          if (PARTS == 3) al2.u = wl[(o * PARTS + 2) * cnt + idx];
-#pragma unroll
-          for (int cb = 0; cb < CB; ++cb) {
-            f4 a = acc[o][rb][cb];
-            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah.v, bh[cb].v, a, 0, 0, 0);
-            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah.v, bl[cb].v, a, 0, 0, 0);
-            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al.v, bh[cb].v, a, 0, 0, 0);
-            if (PARTS == 3) {
-              a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah.v, bl2[cb].v, a, 0, 0, 0);
-              a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al2.v, bh[cb].v, a, 0, 0, 0);
-              a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al.v, bl[cb].v, a, 0, 0, 0);
-            }
-            acc[o][rb][cb] = a;
+        for (int cb = 0; cb < CB; ++cb) {
+          f4 a = acc[o][rb][cb];
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah.v, bh[cb].v, a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah.v, bl[cb].v, a, 0, 0, 0);
+          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al.v, bh[cb].v, a, 0, 0, 0);
+          if (PARTS == 3) {
+            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah.v, bl2[cb].v, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al2.v, bh[cb].v, a, 0, 0, 0);
+            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al.v, bl[cb].v, a, 0, 0, 0);
           }
+          acc[o][rb][cb] = a;
         }
       }
+    }
+    j0 += 32;
+    if (j0 >= n) {
+      j0 = 0;
+      ++t;
     }
   }
 
@@ -182,15 +227,22 @@ demag_status launch_bf(hipStream_t s, const StagePlan &sp, const uint4 *wtab, in
   return DEMAG_OK;
 }
 
-template <int NOUT, int PARTS>
-demag_status launch_bf_n(hipStream_t s, const StagePlan &sp, const uint4 *wtab, int nw, const Bufs &bufs,
-                         int beta) {
-  switch (sp.rb) {
-    case 1: return launch_bf<1, 1, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
-    case 2: return launch_bf<2, 1, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
-    case 4: return launch_bf<4, 1, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
-    default: return launch_bf<8, 1, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
+template <int CB, int NOUT, int PARTS>
+demag_status launch_bf_rb(hipStream_t s, int rb, const StagePlan &sp, const uint4 *wtab, int nw, const Bufs &bufs,
+                          int beta) {
+  switch (rb) {
+    case 1: return launch_bf<1, CB, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
+    case 2: return launch_bf<2, CB, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
+    case 4: return launch_bf<4, CB, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
+    default: return launch_bf<8, CB, NOUT, PARTS>(s, sp, wtab, nw, bufs, beta);
   }
+}
+
+template <int NOUT, int PARTS>
+demag_status launch_bf_n(hipStream_t s, int rb, int cb, const StagePlan &sp, const uint4 *wtab, int nw,
+                         const Bufs &bufs, int beta) {
+  if (cb == 2) return launch_bf_rb<2, NOUT, PARTS>(s, rb, sp, wtab, nw, bufs, beta);
+  return launch_bf_rb<1, NOUT, PARTS>(s, rb, sp, wtab, nw, bufs, beta);
 }
 
 __global__ void k_build_windows(const uint16_t *__restrict__ bf, uint4 *__restrict__ wtab, int n, int ngen,
@@ -252,11 +304,15 @@ demag_status launch_left_stage_bf16(demag_ctx *ctx, const demag_factors *f, dema
     set_error("bfloat16 window table missing (axis longer than the full-format limit)");
     return DEMAG_E_UNSUPPORTED;
   }
+  const int rb = ctx->tile_rows > 0 ? ctx->tile_rows : sp.rb;
+  // two column blocks per wave halve the LDS reads per product once the
+  // stage has columns enough to keep every CU busy
+  const int cb = ctx->tile_cols > 0 ? ctx->tile_cols : (sp.geom.C >= 4096 ? 2 : 1);
   if (prec == DEMAG_BF16X3)
-    return sp.nout == 1 ? launch_bf_n<1, 3>(ctx->stream, sp, wtab, nw, bufs, beta)
-                        : launch_bf_n<2, 3>(ctx->stream, sp, wtab, nw, bufs, beta);
-  return sp.nout == 1 ? launch_bf_n<1, 2>(ctx->stream, sp, wtab, nw, bufs, beta)
-                      : launch_bf_n<2, 2>(ctx->stream, sp, wtab, nw, bufs, beta);
+    return sp.nout == 1 ? launch_bf_n<1, 3>(ctx->stream, rb, cb, sp, wtab, nw, bufs, beta)
+                        : launch_bf_n<2, 3>(ctx->stream, rb, cb, sp, wtab, nw, bufs, beta);
+  return sp.nout == 1 ? launch_bf_n<1, 2>(ctx->stream, rb, cb, sp, wtab, nw, bufs, beta)
+                      : launch_bf_n<2, 2>(ctx->stream, rb, cb, sp, wtab, nw, bufs, beta);
 }
 
 demag_status launch_split(demag_ctx *ctx, const float *x, uint16_t *parts, size_t count, int nparts) {

@@ -152,6 +152,27 @@ def test_full_128_vortex_sampled(ctx):
     assert e_h < 1e-6 and e_phi < 3e-6
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_tile_shape_does_not_change_results(ctx, prec):
+    """Every tile shape accumulates each output in the same order, so the
+    results are bitwise equal (ragged grid: partial row blocks and column
+    tiles on every axis)."""
+    n = (45, 38, 71)
+    m = inputs.random_unit_field(n, seed=7)
+    f = ctx.assemble(n, (1.0 / 71,) * 3, M=6)
+    ref = _run_full(ctx, f, m, prec)
+    try:
+        for rows in (1, 2, 4, 8):
+            for cols in ((1, 2) if prec.startswith("bf16") else (0,)):
+                ctx.set_tiles(rows, cols)
+                got = _run_full(ctx, f, m, prec)
+                assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), (rows, cols)
+    finally:
+        ctx.set_tiles(0, 0)
+    with pytest.raises(api.DemagError):
+        ctx.set_tiles(3, 0)
+
+
 def test_invalid_arguments_rejected(ctx):
     f = ctx.assemble((4, 4, 4), (0.25,) * 3, M=4)
     lib = api.library()
