@@ -32,6 +32,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "Mcell-field evals/s at 128³, FP64 plain vs mixed+learned R' at rel err 1e-6"
+KERNEL_SOURCES = ("paper_1212_3509_amd/csrc/modeprod.hip", "paper_1212_3509_amd/csrc/modeprod_bf16.hip",
+                  "paper_1212_3509_amd/csrc/internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_full_apply_128_vortex.json")
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x2": 2500.0, "bf16x3": 2500.0}
 HBM_GBS = 8000.0
 
@@ -55,6 +58,30 @@ def _timed(ctx, fn, steps, warmup):
     return ms, prof
 
 
+def _kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _traffic(label):
+    """HBM bytes per launch of `label` from the committed counter summary
+    (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size), or
+    None when it is missing or the kernel sources changed since."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != _kernel_source_hash():
+        return None
+    k = rec.get("kernels", {}).get(label)
+    return None if k is None else k["hbm_bytes_per_launch"]
+
+
 def _roofline(prof, prec):
     label, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
     per_launch_ms = rec["ms"] / rec["launches"]
@@ -62,8 +89,20 @@ def _roofline(prof, prec):
     achieved = flops / (per_launch_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[prec]
     return {"bound": "mfma", "kernel": label, "achieved": round(achieved, 3), "peak": peak,
-            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-            "flops_per_launch": flops, "avg_launch_ms": round(per_launch_ms, 4)}
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": _traffic(label),
+            "traffic_unit": "bytes per launch", "flops_per_launch": flops,
+            "algorithmic_bytes_per_launch": rec["bytes"] / rec["launches"], "avg_launch_ms": round(per_launch_ms, 4)}
+
+
+def _copy_calibration(mib):
+    """A plain elementwise copy of `mib` MiB (read once, written once): the
+    reference dispatch for scaling the HBM byte counters."""
+    import torch
+    x = torch.ones(mib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    del x, y
 
 
 def _kernels(prof, steps):
@@ -95,6 +134,7 @@ def _rel(a, b):
 
 
 def headline(args):
+    import numpy as np
     import torch
 
     from paper_1212_3509_amd import api, inputs, learned
@@ -102,6 +142,8 @@ def headline(args):
     n = 128
     N = n ** 3
     m_host = inputs.vortex_field(n, seed=0)
+    if args.calib_copy_mib > 0:
+        _copy_calibration(args.calib_copy_mib)
     ctx = api.Context(0)
     f = ctx.assemble((n, n, n), (1.0 / n,) * 3, M=40, c0=2.15)
     results = {}
@@ -126,10 +168,15 @@ def headline(args):
     if args.learned_steps > 0:
         t0 = time.perf_counter()
         cases = learned.prepare_cases(args.cases, seed=3)
-        params, loss = learned.train(ctx, cases, steps=args.learned_steps, batch=1024)
+        learned.fit_targets(ctx, cases, iters=args.fit_iters)
         torch.cuda.synchronize()
-        train_s = time.perf_counter() - t0
+        fit_s = time.perf_counter() - t0
+        params, loss = learned.train(ctx, cases, steps=args.learned_steps, batch=512)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0 - fit_s
+        t1 = time.perf_counter()
         rule = learned.predict(ctx, params, (n, n, n), args.rule_tol)
+        predict_s = time.perf_counter() - t1
         fl = ctx.assemble((n, n, n), (1.0 / n,) * 3, t=rule["t"], alpha=rule["alpha"])
         m = torch.from_numpy(m_host).to(device="cuda", dtype=torch.float32)
         phi = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
@@ -143,8 +190,11 @@ def headline(args):
                  "rel_l2_vs_fp64_plain": err, "meets_1e-6": max(err.values()) <= 1e-6,
                  "speedup_vs_fp64_plain": round(results["fp64"]["ms_per_step"] / ms, 3),
                  "roofline": _roofline(prof, prec), "kernels": _kernels(prof, args.steps),
-                 "training": {"cases": args.cases, "steps": args.learned_steps, "seconds": round(train_s, 2),
-                              "loss_first": float(loss[:10].mean()), "loss_last": float(loss[-10:].mean())}}
+                 "training": {"cases": args.cases, "fit_iters": args.fit_iters, "fit_seconds": round(fit_s, 2),
+                              "median_fitted_log10_err": float(np.median(np.log10(cases["fit_err"].cpu().numpy()))),
+                              "steps": args.learned_steps, "train_seconds": round(train_s, 2),
+                              "loss_first": float(loss[:10].mean()), "loss_last": float(loss[-10:].mean()),
+                              "predict_seconds": round(predict_s, 3)}}
 
     head = results["fp64"]
     line = {
@@ -234,12 +284,15 @@ def main():
     ap.add_argument("--workload", default="headline", choices=["headline", "cp4096", "batch"])
     ap.add_argument("--cpu-nodes", type=int, default=3, help="oracle nodes timed for the CPU baseline (0: skip)")
     ap.add_argument("--precs", default="fp64,fp32,bf16x3,bf16x2")
-    ap.add_argument("--learned-steps", type=int, default=1500)
+    ap.add_argument("--learned-steps", type=int, default=4000)
+    ap.add_argument("--fit-iters", type=int, default=60)
     ap.add_argument("--cases", type=int, default=20000)
     ap.add_argument("--rule-tol", type=float, default=3e-7)
     ap.add_argument("--mixed-prec", default="bf16x3")
     ap.add_argument("--batch-ws-gib", type=int, default=32)
     ap.add_argument("--tune", type=int, default=1)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run a plain copy of this many MiB first (byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this library runs on a single GPU; multi-GPU runs are not part of it "

@@ -232,7 +232,8 @@ demag_status demag_apply_tt(demag_ctx *ctx, demag_factors *f, int32_t r1, int32_
  * (R' - 24)/8.  Outputs y[b][65]: 32 node offsets, 32 log-weight offsets, the
  * predicted log10 kernel error.
  * Rule from outputs, base = sinc rule with R' nodes and c0 = 2.15:
- *   t'_k = t_k + 0.45 theta tanh(y_k), alpha'_k = alpha_k exp(tanh(y_{32+k})).
+ *   t'_k = t_k + 0.45 theta tanh(y_k),
+ *   alpha'_k = 2 theta cosh t'_k sinh^2 t'_k exp(tanh(y_{32+k})).
  * Judge: err = sqrt(mean over sentinel offsets J of |K(J) - K_ref(J)|^2 /
  * |K_ref(J)|^2) over the nine kernel values [K^x, K^y, K^z, F_xx, F_yy,
  * F_zz, F_xy, F_xz, F_yz], K_ref from the sinc rule with the step of Thm.
@@ -259,25 +260,53 @@ demag_status demag_quad_rules(demag_ctx *ctx, const float *y, const int32_t *R, 
 demag_status demag_quad_judge(demag_ctx *ctx, int32_t B, const int32_t *grids, const double *hmin,
                               const int32_t *sentinels, int32_t S, const double *t, const double *alpha,
                               const int32_t *R, int32_t KM, double *err, double *dt, double *dalpha);
+/* Levenberg-Marquardt fit of B cases' outputs (rule parametrization of
+ * demag_quad_rules) against the reference rule on their grids [B][3], cell
+ * sizes hmin[B] and sentinels [B][S][3] (S <= 64), R[B] nodes (16..32):
+ * `iters` damped Gauss-Newton steps in u_k = 0.45 tanh(y_k),
+ * v_k = tanh(y_{32+k}) (projected onto |u| <= 0.44, |v| <= 0.99) from y0
+ * ([B][65] device, NULL = zeros, the plain base rule) with initial damping
+ * mu0.  Device outputs: yout [B][65] (fitted outputs; slot 64 = log10 of the
+ * fitted error), xout [B][64] (u, v in double; may be NULL), H [B][64][64]
+ * (J^T J / err^2 at the fit, zero outside the active outputs; may be NULL),
+ * t, alpha [B][32] (the fitted rule, zero past R), err[B].  Synchronizes
+ * the stream. */
+demag_status demag_quad_fit(demag_ctx *ctx, int32_t B, const int32_t *grids, const double *hmin,
+                            const int32_t *sentinels, int32_t S, const int32_t *R, const float *y0,
+                            int32_t iters, double mu0, float *yout, double *xout, float *H, double *t,
+                            double *alpha, double *err);
+/* Training loss and its output gradient for network outputs y [B][65]
+ * against fits (targets [B][65] = demag_quad_fit's yout, xfit [B][64],
+ * H [B][64][64]):
+ *   loss_b = ln(1 + d^T H d) + lambda (y_64 - t_64)^2,
+ *   d = (0.45 tanh y_k, tanh y_{32+k}) - xfit over the active outputs;
+ * with xfit = H = NULL instead loss_b = mean_k (y_k - clip(t_k, 3))^2 +
+ * lambda (y_64 - t_64)^2.  dy [B][65] = d loss_b / d y / B; loss [B]. */
+demag_status demag_quad_loss_grad(demag_ctx *ctx, const float *y, const float *targets, const double *xfit,
+                                  const float *H, const int32_t *R, int32_t B, float lambda, float *dy,
+                                  float *loss);
 /* Train in place with Adam for `steps` minibatches of `batch` consecutive
- * cases (wrapping; shuffle the cases beforehand) on
- *   mean_b [ ln err_b + lambda (y_64,b - log10 err_b)^2 ];
- * step0 = Adam steps already taken.  loss_host (host, length steps, may be
- * NULL) receives each step's mean loss. */
+ * cases (wrapping; shuffle the cases beforehand) on the mean of
+ * demag_quad_loss_grad's loss over the batch ([count] rows of targets,
+ * xfit, H, R); step0 = Adam steps already taken.  loss_host (host, length
+ * steps, may be NULL) receives each step's mean loss. */
 demag_status demag_quad_train(demag_ctx *ctx, float *params, float *adam_m, float *adam_v, const float *x,
-                              const int32_t *grids, const double *hmin, const int32_t *R,
-                              const int32_t *sentinels, int32_t count, int32_t S, int32_t steps,
-                              int32_t batch, int32_t step0, float lr, float lambda, float *loss_host);
-/* Rule for one grid (n host[3], cell size hmin, sentinels [S][3]) at
- * tolerance tol: features [17][6] for R' = 16..32 in order; the smallest R'
- * with predicted log10 error <= log10 tol is judged, and if its error
- * exceeds tol the sinc rule with the step of Thm. sinc_theo and 64 nodes is
- * returned instead (*fell_back = 1).  Host outputs: t_out, alpha_out
- * (capacity 64), *R_out, *judged, *predicted, *fell_back. */
+                              const float *targets, const double *xfit, const float *H, const int32_t *R,
+                              int32_t count, int32_t steps, int32_t batch, int32_t step0, float lr,
+                              float lambda, float *loss_host);
+/* Rule for one grid (n host[3], cell size hmin, sentinels [S][3] device) at
+ * tolerance tol: features [17][6] (device) for R' = 16..32 in order; the
+ * smallest R' with predicted log10 error <= log10 tol is polished with
+ * fit_iters Levenberg-Marquardt steps (from the network's proposal and from
+ * the plain base rule; the better one is kept) and judged; if it misses tol, R' + 4,
+ * R' + 8, ... (up to 32) follow, and if none meets tol the sinc rule with
+ * the step of Thm. sinc_theo and 64 nodes is returned (*fell_back = 1).
+ * Host outputs: t_out, alpha_out (capacity 64), *R_out, *judged (error of
+ * the last rule judged), *predicted (log10, of the first pick), *fell_back. */
 demag_status demag_quad_predict(demag_ctx *ctx, const float *params, const float *features,
                                 const int32_t n[3], double hmin, const int32_t *sentinels, int32_t S,
-                                double tol, double *t_out, double *alpha_out, int32_t *R_out,
-                                double *judged, double *predicted, int32_t *fell_back);
+                                double tol, int32_t fit_iters, double *t_out, double *alpha_out,
+                                int32_t *R_out, double *judged, double *predicted, int32_t *fell_back);
 
 /* The bfloat16 split used by DEMAG_BF16X2/X3 on the device, exposed for
  * checking: x (device, count floats) -> parts (device, [nparts][count]

@@ -62,10 +62,13 @@ _SIGS = {
                                   C.c_float]),
     "demag_quad_judge": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.c_int32, _P, _P, _P, C.c_int32, _P, _P, _P]),
     "demag_quad_rules": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P]),
+    "demag_quad_fit": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.c_int32, _P, _P, C.c_int32, C.c_double, _P, _P, _P,
+                                 _P, _P, _P]),
+    "demag_quad_loss_grad": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int32, C.c_float, _P, _P]),
     "demag_quad_train": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
-                                   C.c_int32, C.c_float, C.c_float, _P]),
-    "demag_quad_predict": (C.c_int, [_P, _P, _P, _P, C.c_double, _P, C.c_int32, C.c_double, _P, _P, _P, _P, _P,
-                                     _P]),
+                                   C.c_float, C.c_float, _P]),
+    "demag_quad_predict": (C.c_int, [_P, _P, _P, _P, C.c_double, _P, C.c_int32, C.c_double, C.c_int32, _P, _P, _P,
+                                     _P, _P, _P]),
     "demag_prepare_structured": (C.c_int, [_P, _P]),
     "demag_apply_columns": (C.c_int, [_P, _P, _P, _P, _P]),
     "demag_apply_cp": (C.c_int, [_P, _P, C.c_int32, _P, _P, _P]),
@@ -364,16 +367,48 @@ class Context:
                "demag_quad_judge")
         return (err, dt, da) if grad else err
 
-    def quad_train(self, params, m, v, x, grids, hmin, R, sent, steps, batch, step0=0, lr=1e-3, lam=0.1):
-        loss = np.zeros(max(steps, 1), dtype=np.float32)
-        S = int(sent.shape[1])
+    def quad_fit(self, grids, hmin, sent, R, y0=None, iters=30, mu0=1e-3, want_h=False):
+        """Levenberg-Marquardt fit of the outputs per case (all CUDA: grids int32
+        [B][3], hmin float64 [B], sent int32 [B][S][3], R int32 [B], y0 float32
+        [B][65] or None).  Returns (y [B][65], t [B][32], alpha [B][32], err [B]),
+        plus (x [B][64], H [B][64][64]) with want_h."""
+        import torch
+        B, S = int(sent.shape[0]), int(sent.shape[1])
+        dev = sent.device
+        y = torch.empty((B, 65), dtype=torch.float32, device=dev)
+        t = torch.empty((B, 32), dtype=torch.float64, device=dev)
+        a = torch.empty((B, 32), dtype=torch.float64, device=dev)
+        err = torch.empty(B, dtype=torch.float64, device=dev)
+        x = torch.empty((B, 64), dtype=torch.float64, device=dev) if want_h else None
+        H = torch.empty((B, 64, 64), dtype=torch.float32, device=dev) if want_h else None
         self.use_current_stream()
-        _check(library().demag_quad_train(self.handle, _ptr(params), _ptr(m), _ptr(v), _ptr(x), _ptr(grids),
-                                          _ptr(hmin), _ptr(R), _ptr(sent), int(x.shape[0]), S, steps, batch, step0,
-                                          lr, lam, loss.ctypes.data), "demag_quad_train")
+        _check(library().demag_quad_fit(self.handle, B, _ptr(grids), _ptr(hmin), _ptr(sent), S, _ptr(R), _ptr(y0),
+                                        iters, mu0, _ptr(y), _ptr(x), _ptr(H), _ptr(t), _ptr(a), _ptr(err)),
+               "demag_quad_fit")
+        return (y, t, a, err, x, H) if want_h else (y, t, a, err)
+
+    def quad_loss_grad(self, y, targets, xfit, H, R, lam=0.1):
+        """Training loss per case and d loss / d y (see demag_quad_loss_grad)."""
+        import torch
+        B = int(y.shape[0])
+        dy = torch.empty_like(y)
+        loss = torch.empty(B, dtype=torch.float32, device=y.device)
+        self.use_current_stream()
+        _check(library().demag_quad_loss_grad(self.handle, _ptr(y), _ptr(targets), _ptr(xfit), _ptr(H), _ptr(R), B,
+                                              lam, _ptr(dy), _ptr(loss)), "demag_quad_loss_grad")
+        return loss, dy
+
+    def quad_train(self, params, m, v, x, targets, R, steps, batch, step0=0, lr=1e-3, lam=0.1, xfit=None, H=None):
+        """Adam on the distillation loss against fitted targets [count][65]
+        (with xfit, H; else squared output errors)."""
+        loss = np.zeros(max(steps, 1), dtype=np.float32)
+        self.use_current_stream()
+        _check(library().demag_quad_train(self.handle, _ptr(params), _ptr(m), _ptr(v), _ptr(x), _ptr(targets),
+                                          _ptr(xfit), _ptr(H), _ptr(R), int(x.shape[0]), steps, batch, step0, lr, lam,
+                                          loss.ctypes.data), "demag_quad_train")
         return loss[:steps]
 
-    def quad_predict(self, params, features, n, hmin, sent, tol):
+    def quad_predict(self, params, features, n, hmin, sent, tol, fit_iters=20):
         """features: CUDA float32 [17][6] for R' = 16..32; sent: CUDA int32
         [S][3].  Returns dict(t, alpha, R, judged, predicted, fell_back)."""
         t = np.zeros(64)
@@ -383,8 +418,9 @@ class Context:
         n3 = (C.c_int32 * 3)(*n)
         self.use_current_stream()
         _check(library().demag_quad_predict(self.handle, _ptr(params), _ptr(features), n3, hmin, _ptr(sent),
-                                            int(sent.shape[0]), tol, t.ctypes.data, a.ctypes.data, C.byref(R),
-                                            C.byref(judged), C.byref(pred), C.byref(fb)), "demag_quad_predict")
+                                            int(sent.shape[0]), tol, fit_iters, t.ctypes.data, a.ctypes.data,
+                                            C.byref(R), C.byref(judged), C.byref(pred), C.byref(fb)),
+               "demag_quad_predict")
         return {"t": t[:R.value], "alpha": a[:R.value], "R": R.value, "judged": judged.value,
                 "predicted": pred.value, "fell_back": bool(fb.value)}
 

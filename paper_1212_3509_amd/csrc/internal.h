@@ -164,6 +164,7 @@ demag_status launch_left_stage(demag_ctx *ctx, const demag_factors *f, demag_pre
                                const StagePlan &sp, void *const bufs[6], int beta);
 int window_entries(int n);
 int default_rb(int n);
+int stage_rows(const StagePlan &sp, demag_prec prec);
 size_t items_lds_bytes(int nmax, bool fp64);
 int items_blocks_per_cu(bool fp64, size_t lds);
 void build_chunk_plan(const demag_factors *f, int k0, int kc, double phi_scale, std::vector<StagePlan> &stages);

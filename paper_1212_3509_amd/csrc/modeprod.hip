@@ -61,21 +61,25 @@ __host__ __device__ inline size_t tile_lds_elems(int n, int RB, int NOUT) {
 }
 
 // Generator value e of a term's staged block: output o = e / glds, generator
-// index s = e % glds - 16 (zero outside [0, genlen)).  g0, g1: the term's
+// index s = e % glds - 32 (zero outside [0, genlen)).  g0, g1: the term's
 // generators of outputs 0 and 1.  Returns an in-bounds address for every e
 // and sets ok when the value is a real generator entry.
 template <class T, int NOUT>
 __device__ __forceinline__ const T *gen_addr(const T *g0, const T *g1, int e, int glds, int gtot, int genlen,
                                              bool &ok) {
   const bool second = NOUT > 1 && e >= glds;
-  const int s = e - (second ? glds : 0) - 16;
+  const int s = e - (second ? glds : 0) - 32;
   ok = e < gtot && s >= 0 && s < genlen;
   const int sc = s < 0 ? 0 : (s >= genlen ? genlen - 1 : s);
   return (second ? g1 : g0) + sc;
 }
 
 // One 64-column x 16*RB-row tile of one job.  sg: LDS, tile_lds_elems(n, RB, NOUT).
-template <class T, int RB, int NOUT>
+// TRANS: multiply with the operands swapped, which yields the transposed
+// 16x16 block (same fragments: the A and B layouts of the instruction are
+// mirror images), so a lane's results run along the output rows i; chosen
+// when rows are contiguous in memory (out_is == 1), giving 128-byte stores.
+template <class T, int RB, int NOUT, bool TRANS>
 __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__restrict__ terms, const Bufs &bufs,
                                           const T *__restrict__ gens, const MPGeom &g, int ct, int rg, int beta,
                                           T *sg) {
@@ -96,7 +100,9 @@ __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__rest
   const size_t cin = size_t(co) * g.in_S1 + ci;
   const int row0 = rg * 16 * RB;
   // LDS index of T[row0 + (lane & 15)][kq] for j0 = 0; add 16 rb - j0.
-  const int ibase = row0 + (lane & 15) - kq + n - 1 + 16;
+  // With 32 leading zeros and glds = 2n + 16 RB + 32 every index stays in
+  // [1, glds): i < n + 16 RB - 1 and j < n + 31 (zero-input steps included).
+  const int ibase = row0 + (lane & 15) - kq + n - 1 + 32;
   const int nch = (n + 4 * kUnroll - 1) / (4 * kUnroll);
   const int nq = nterms * nch;
   auto term_in = [&](int t) -> const T * {
@@ -182,17 +188,20 @@ __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__rest
         nxt[u] = in1[size_t(j) * g.kstride];
       }
     }
+    // straight-line K-steps (no branch, so the LDS reads of a step are
+    // issued while the previous step's products run); in the last chunk of
+    // a term the steps past n multiply a zero input
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int jj = j0 + 4 * u;
-      if (jj < n) {
-        const T b = (jj + kq < n) ? cur[u] : T(0);
+      const T b = (jj + kq < n) ? cur[u] : T(0);
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-          const int idx = ibase + 16 * rb - jj;
+      for (int rb = 0; rb < RB; ++rb) {
+        const int idx = ibase + 16 * rb - jj;
 #pragma unroll
-          for (int o = 0; o < NOUT; ++o) acc[o][rb] = Mf::step(sgen[o * glds + idx], b, acc[o][rb]);
-        }
+        for (int o = 0; o < NOUT; ++o)
+          acc[o][rb] = TRANS ? Mf::step(b, sgen[o * glds + idx], acc[o][rb])
+                             : Mf::step(sgen[o * glds + idx], b, acc[o][rb]);
       }
     }
     j0 += 4 * kUnroll;
@@ -202,6 +211,39 @@ __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__rest
     }
   }
 
+  if (TRANS) {
+    // register r of lane l: column cbase + row(l, r), output row 16 rb + l % 16
+    const int cbase = ct * 64 + wave * 16;
+    size_t ob[4];
+    bool okc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int cc = cbase + Mf::row(lane, r);
+      okc[r] = cc < g.C;
+      const int cco = okc[r] ? cc / g.C1 : 0, cci = okc[r] ? cc % g.C1 : 0;
+      ob[r] = size_t(cco) * g.out_S1 + size_t(cci) * g.out_cs;
+    }
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+      T *out = static_cast<T *>(bufs.p[job.out_buf[o]]) + job.out_off[o];
+      const T scale = T(job.scale[o]);
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const int i = row0 + 16 * rb + (lane & 15);
+        if (i < n) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (okc[r]) {
+              const size_t idx = ob[r] + size_t(i) * g.out_is;
+              T v = scale * acc[o][rb][r];
+              if (beta) v += out[idx];
+              out[idx] = v;
+            }
+        }
+      }
+    }
+    return;
+  }
   if (!cvalid) return;
 #pragma unroll
   for (int o = 0; o < NOUT; ++o) {
@@ -228,7 +270,8 @@ __global__ __launch_bounds__(256, 2) void k_left(const MPJob *__restrict__ jobs,
                                               int beta) {
   extern __shared__ unsigned char smem_raw[];
   const MPJob job = jobs[blockIdx.y];
-  left_tile<T, RB, NOUT>(job, terms, bufs, gens, g, blockIdx.x % col_tiles, blockIdx.x / col_tiles, beta,
+  // the x and y stages write rows contiguously; the z stage writes columns
+  left_tile<T, RB, NOUT, AXIS != 2>(job, terms, bufs, gens, g, blockIdx.x % col_tiles, blockIdx.x / col_tiles, beta,
                          reinterpret_cast<T *>(smem_raw));
 }
 
@@ -246,16 +289,21 @@ __global__ __launch_bounds__(256, 2) void k_left_items(const BatchItem *__restri
     const BatchItem item = items[it];
     const MPJob job = jobs[item.job];
     const MPGeom g = geoms[item.geom];
-    const int key = item.rb * 4 + item.nout;
+    const int key = (item.rb * 4 + item.nout) * 2 + (g.out_is == 1 ? 1 : 0);
     switch (key) {
-      case 1 * 4 + 1: left_tile<T, 1, 1>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
-      case 1 * 4 + 2: left_tile<T, 1, 2>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
-      case 2 * 4 + 1: left_tile<T, 2, 1>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
-      case 2 * 4 + 2: left_tile<T, 2, 2>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
-      case 4 * 4 + 1: left_tile<T, 4, 1>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
-      case 4 * 4 + 2: left_tile<T, 4, 2>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
-      case 8 * 4 + 1: left_tile<T, 8, 1>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
-      default: left_tile<T, 8, 2>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
+#define DEMAG_ITEM_CASE(R, N)                                                                  \
+  case (R * 4 + N) * 2: left_tile<T, R, N, false>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break; \
+  case (R * 4 + N) * 2 + 1: left_tile<T, R, N, true>(job, terms, bufs, gens, g, item.ct, item.rg, beta, sg); break;
+      DEMAG_ITEM_CASE(1, 1)
+      DEMAG_ITEM_CASE(1, 2)
+      DEMAG_ITEM_CASE(2, 1)
+      DEMAG_ITEM_CASE(2, 2)
+      DEMAG_ITEM_CASE(4, 1)
+      DEMAG_ITEM_CASE(4, 2)
+      DEMAG_ITEM_CASE(8, 1)
+      DEMAG_ITEM_CASE(8, 2)
+#undef DEMAG_ITEM_CASE
+      default: break;  // shapes are validated when the item list is built
     }
   }
 }
@@ -303,6 +351,16 @@ demag_status launch_typed(hipStream_t s, int rb, const StagePlan &sp, const T *g
 
 int default_rb(int n) { return n <= 16 ? 1 : n <= 32 ? 2 : n <= 64 ? 4 : 8; }
 
+// Row blocks per tile for a stage: the tallest tile that covers the axis,
+// lowered while the launch would give fewer than two workgroups per CU
+// (256 CUs), e.g. the x stage's single job of all nodes' terms.
+int stage_rows(const StagePlan &sp, demag_prec) {
+  const int64_t col_tiles = (sp.geom.C + 63) / 64;  // 64 columns per tile (bfloat16: one block per wave)
+  int rb = sp.rb;
+  while (rb > 1 && col_tiles * ((sp.geom.n + 16 * rb - 1) / (16 * rb)) * int64_t(sp.jobs.size()) < 512) rb /= 2;
+  return rb;
+}
+
 size_t items_lds_bytes(int nmax, bool fp64) {
   return tile_lds_elems(nmax, 8, 2) * (fp64 ? 8 : 4);
 }
@@ -348,7 +406,7 @@ demag_status launch_left_stage(demag_ctx *ctx, const demag_factors *f, demag_pre
   if (st != DEMAG_OK) return st;
   const char *pname = "?";
   size_t esize = 4;
-  const int rb = ctx->tile_rows > 0 ? ctx->tile_rows : sp.rb;
+  const int rb = ctx->tile_rows > 0 ? ctx->tile_rows : stage_rows(sp, prec);
   if (prec == DEMAG_FP64) {
     st = launch_typed<double>(ctx->stream, rb, sp, f->f64[sp.axis], bufs, beta);
     pname = "fp64";

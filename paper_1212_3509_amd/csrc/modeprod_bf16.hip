@@ -38,6 +38,15 @@ union Frag {
   bf8 v;
 };
 
+// Toeplitz fragment a times input fragment b; TRANS gives the transposed
+// 16x16 block (the instruction's A and B layouts mirror each other, so the
+// same registers serve), whose lanes run along the output rows.
+template <bool TRANS>
+__device__ __forceinline__ f4 mma(bf8 a, bf8 b, f4 c) {
+  return TRANS ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(b, a, c, 0, 0, 0)
+               : __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
 constexpr int kStageRounds = 3;  // window entries a thread loads per staging round
 
 // Tile: 4 waves x 16*CB columns, 16*RB rows.  The (term, K-step) pairs of a
@@ -46,7 +55,7 @@ constexpr int kStageRounds = 3;  // window entries a thread loads per staging ro
 // rows and columns, zeroed or discarded), so the compiler waits only for the
 // loads it needs.  A term's windows are staged in rounds of up to
 // 3 x 256 entries whose loads are all issued before the first LDS store.
-template <int RB, int CB, int NOUT, int PARTS>
+template <int RB, int CB, int NOUT, int PARTS, bool TRANS>
 __global__ __launch_bounds__(256, 2) void k_left_bf16(const MPJob *__restrict__ jobs,
                                                    const MPTerm *__restrict__ terms, Bufs bufs,
                                                    const uint4 *__restrict__ wtab, MPGeom g, int nw,
@@ -169,13 +178,13 @@ __global__ __launch_bounds__(256, 2) void k_left_bf16(const MPJob *__restrict__ 
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
           f4 a = acc[o][rb][cb];
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah.v, bh[cb].v, a, 0, 0, 0);
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah.v, bl[cb].v, a, 0, 0, 0);
-          a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al.v, bh[cb].v, a, 0, 0, 0);
+          a = mma<TRANS>(ah.v, bh[cb].v, a);
+          a = mma<TRANS>(ah.v, bl[cb].v, a);
+          a = mma<TRANS>(al.v, bh[cb].v, a);
           if (PARTS == 3) {
-            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah.v, bl2[cb].v, a, 0, 0, 0);
-            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al2.v, bh[cb].v, a, 0, 0, 0);
-            a = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al.v, bl[cb].v, a, 0, 0, 0);
+            a = mma<TRANS>(ah.v, bl2[cb].v, a);
+            a = mma<TRANS>(al2.v, bh[cb].v, a);
+            a = mma<TRANS>(al.v, bl[cb].v, a);
           }
           acc[o][rb][cb] = a;
         }
@@ -194,6 +203,27 @@ __global__ __launch_bounds__(256, 2) void k_left_bf16(const MPJob *__restrict__ 
     const float scale = float(job.scale[o]);
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
+      if (TRANS) {
+        // register r of lane l: column cbase + 4 (l/16) + r, output row 16 rb + l % 16
+        const int cbase = ct * (64 * CB) + wave * (16 * CB) + 16 * cb;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int cc = cbase + 4 * kq + r;
+          if (cc >= g.C) continue;
+          const int64_t ob = int64_t(cc / g.C1) * g.out_S1 + int64_t(cc % g.C1) * g.out_cs;
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            const int i = row0 + 16 * rb + (lane & 15);
+            if (i < n) {
+              const size_t idx = ob + size_t(i) * g.out_is;
+              float v = scale * acc[o][rb][cb][r];
+              if (beta) v += out[idx];
+              out[idx] = v;
+            }
+          }
+        }
+        continue;
+      }
       if (!cval[cb]) continue;
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
@@ -219,10 +249,20 @@ demag_status launch_bf(hipStream_t s, const StagePlan &sp, const uint4 *wtab, in
   const int row_groups = (g.n + 16 * RB - 1) / (16 * RB);
   dim3 grid(col_tiles * row_groups, unsigned(sp.jobs.size()));
   const size_t lds = size_t(NOUT) * PARTS * (g.n + 16 * RB + 23) * sizeof(uint4);
-  if (lds > 65536)
-    DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_left_bf16<RB, CB, NOUT, PARTS>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-  k_left_bf16<RB, CB, NOUT, PARTS><<<grid, 256, lds, s>>>(sp.d_jobs, sp.d_terms, bufs, wtab, g, nw, col_tiles, beta);
+  // rows contiguous in the output (x and y stages): transposed blocks
+  if (g.out_is == 1) {
+    auto k = &k_left_bf16<RB, CB, NOUT, PARTS, true>;
+    if (lds > 65536)
+      DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        int(lds)));
+    k<<<grid, 256, lds, s>>>(sp.d_jobs, sp.d_terms, bufs, wtab, g, nw, col_tiles, beta);
+  } else {
+    auto k = &k_left_bf16<RB, CB, NOUT, PARTS, false>;
+    if (lds > 65536)
+      DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        int(lds)));
+    k<<<grid, 256, lds, s>>>(sp.d_jobs, sp.d_terms, bufs, wtab, g, nw, col_tiles, beta);
+  }
   DEMAG_TRY_HIP(hipGetLastError());
   return DEMAG_OK;
 }
@@ -304,10 +344,10 @@ demag_status launch_left_stage_bf16(demag_ctx *ctx, const demag_factors *f, dema
     set_error("bfloat16 window table missing (axis longer than the full-format limit)");
     return DEMAG_E_UNSUPPORTED;
   }
-  const int rb = ctx->tile_rows > 0 ? ctx->tile_rows : sp.rb;
-  // two column blocks per wave halve the LDS reads per product once the
-  // stage has columns enough to keep every CU busy
-  const int cb = ctx->tile_cols > 0 ? ctx->tile_cols : (sp.geom.C >= 4096 ? 2 : 1);
+  const int rb = ctx->tile_rows > 0 ? ctx->tile_rows : stage_rows(sp, prec);
+  // two column blocks per wave halve the LDS reads per product but need
+  // more registers; one block measured faster on every stage of a 128^3 apply
+  const int cb = ctx->tile_cols > 0 ? ctx->tile_cols : 1;
   if (prec == DEMAG_BF16X3)
     return sp.nout == 1 ? launch_bf_n<1, 3>(ctx->stream, rb, cb, sp, wtab, nw, bufs, beta)
                         : launch_bf_n<2, 3>(ctx->stream, rb, cb, sp, wtab, nw, bufs, beta);

@@ -1,7 +1,7 @@
 """Training and use of the shortened-rule network through the C ABI.
 
-Only marshalling: the cases come from ``inputs`` (seeded), every forward,
-backward, judge and update step runs in the library's kernels.
+Only marshalling: the cases come from ``inputs`` (seeded); every fit,
+forward, backward, judge and update step runs in the library's kernels.
 """
 from __future__ import annotations
 
@@ -30,19 +30,52 @@ def prepare_cases(count: int = 20000, seed: int = 3, shuffle_seed: int = 5):
             "Rhost": R}
 
 
-def train(ctx, cases, steps: int = 2000, batch: int = 1024, lr: float = 2e-3, lam: float = 0.1,
-          init_seed: int = 4):
-    """Fresh network trained on ``cases``; returns (params, loss history)."""
+def fit_targets(ctx, cases, iters: int = 60, chunk: int = 4096, with_h: bool = False):
+    """Levenberg-Marquardt fits of every case (the training targets), in
+    chunks; adds "targets" [count][65] (fitted outputs, slot 64 = log10 of the
+    fitted error) and "fit_err" [count], and with_h also "xfit" [count][64]
+    and "H" [count][64][64] for the distillation loss."""
     import torch
+    count = int(cases["x"].shape[0])
+    out = {"targets": [], "fit_err": []}
+    if with_h:
+        out.update({"xfit": [], "H": []})
+    for a in range(0, count, chunk):
+        b = min(count, a + chunk)
+        r = ctx.quad_fit(cases["grids"][a:b], cases["hmin"][a:b], cases["sent"][a:b], cases["R"][a:b], None, iters,
+                         want_h=with_h)
+        out["targets"].append(r[0])
+        out["fit_err"].append(r[3])
+        if with_h:
+            out["xfit"].append(r[4])
+            out["H"].append(r[5])
+    for k, v in out.items():
+        cases[k] = torch.cat(v)
+    return cases
+
+
+def train(ctx, cases, steps: int = 4000, batch: int = 512, lr: float = 1e-3, lam: float = 0.1,
+          init_seed: int = 4, distill_steps: int = 0, distill_lr: float = 1e-4):
+    """Fresh network trained on the fits of ``cases``: squared errors against
+    the fitted outputs and log10 errors, then optionally ``distill_steps``
+    on the Gauss-Newton distillation loss.  Returns (params, loss history)."""
+    import numpy as np
+    import torch
+    if "targets" not in cases or (distill_steps and "H" not in cases):
+        fit_targets(ctx, cases, with_h=distill_steps > 0)
     p = torch.from_numpy(inputs.mlp_init(seed=init_seed, out_scale=0.0)).cuda()
     m = torch.zeros_like(p)
     v = torch.zeros_like(p)
-    loss = ctx.quad_train(p, m, v, cases["x"], cases["grids"], cases["hmin"], cases["R"], cases["sent"],
-                          steps, min(batch, int(cases["x"].shape[0])), 0, lr, lam)
+    bs = min(batch, int(cases["x"].shape[0]))
+    loss = ctx.quad_train(p, m, v, cases["x"], cases["targets"], cases["R"], steps, bs, 0, lr, lam)
+    if distill_steps:
+        loss2 = ctx.quad_train(p, m, v, cases["x"], cases["targets"], cases["R"], distill_steps, bs, steps,
+                               distill_lr, lam, xfit=cases["xfit"], H=cases["H"])
+        loss = np.concatenate([loss, loss2])
     return p, loss
 
 
-def predict(ctx, params, n, tol: float):
+def predict(ctx, params, n, tol: float, fit_iters: int = 60):
     """Shortened rule for grid n (unit longest edge, cubic cells) at tol."""
     import torch
     nmax = max(n)
@@ -50,4 +83,4 @@ def predict(ctx, params, n, tol: float):
     x = inputs.quad_features(np.tile(np.asarray(n)[None], (len(RPRIME), 1)), np.full(len(RPRIME), h),
                              np.full(len(RPRIME), np.log10(tol)), np.array(RPRIME))
     sent = torch.from_numpy(inputs.sentinel_offsets(tuple(n))).to(device="cuda", dtype=torch.int32)
-    return ctx.quad_predict(params, torch.from_numpy(x).cuda(), tuple(n), h, sent, tol)
+    return ctx.quad_predict(params, torch.from_numpy(x).cuda(), tuple(n), h, sent, tol, fit_iters)

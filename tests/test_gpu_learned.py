@@ -1,10 +1,15 @@
-"""GPU checks of the shortened-rule network and its judge against the oracle.
+"""GPU checks of the shortened-rule network, its judge and the per-grid fit
+against the oracle.
 
 Network (FP32 on the GPU, FP64 in the oracle): outputs to 1e-5 relative,
 parameter gradients to 1e-4 relative L2.  Judge (FP64 on both sides, own
 factor code on each): errors to 1e-6 relative, gradients against central
-differences of the oracle judge to 1e-4.  Training must lower the loss and
-give lower judged errors than the unmodified base rule at equal R'."""
+differences of the oracle judge to 1e-4.  Fit: one damped Gauss-Newton step
+(analytic Jacobian on the GPU, central differences in the oracle) to 1e-4 of
+the step; fitted errors must equal the oracle's judge of the returned rule.
+The trained network's error head must predict the fitted error of held-out
+cases, and the learned path must meet a tolerance with fewer nodes than the
+plain sinc rule needs."""
 import numpy as np
 import pytest
 import torch
@@ -86,37 +91,136 @@ def test_rules_and_judge_match_oracle(ctx):
         assert np.linalg.norm(da[b, :R[b]] - ga) <= 1e-4 * np.linalg.norm(ga)
 
 
+def test_fit_step_matches_oracle(ctx):
+    grids = np.array([[24, 20, 16], [32, 40, 36]], dtype=np.int32)
+    R = np.array([16, 21], dtype=np.int32)
+    h = 1.0 / grids.max(axis=1)
+    rng = np.random.default_rng(4)
+    y0 = (0.2 * rng.standard_normal((2, 65))).astype(np.float32)
+    sent = np.stack([inputs.sentinel_offsets(tuple(g)) for g in grids])
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    y1, t1, a1, e1 = ctx.quad_fit(dev(grids), dev(h), dev(sent), dev(R), dev(y0), iters=1, mu0=1e-2)
+    torch.cuda.synchronize()
+    y1, t1, a1, e1 = (x.cpu().numpy() for x in (y1, t1, a1, e1))
+    for b in range(2):
+        n = tuple(int(v) for v in grids[b])
+        hh = (h[b],) * 3
+        Rb = int(R[b])
+        tr, ar = quadrule.reference_rule(h[b])
+        ref = quadrule.kernel_values(n, hh, tr, ar, sent[b])
+        yb = y0[b].astype(np.float64)
+        x0 = np.r_[np.clip(0.45 * np.tanh(yb[:Rb]), -0.44, 0.44), np.clip(np.tanh(yb[32:32 + Rb]), -0.99, 0.99)]
+        xo, e_before, e_after = quadrule.lm_step(n, hh, x0, Rb, ref, sent[b], 1e-2)
+        expect = xo if e_after < e_before else x0
+        yg = y1[b].astype(np.float64)
+        xg = np.r_[0.45 * np.tanh(yg[:Rb]), np.tanh(yg[32:32 + Rb])]
+        assert np.linalg.norm(xg - expect) <= 1e-4 * np.linalg.norm(xo - x0) + 1e-6, b
+        # the reported error is the oracle's judge of the returned rule
+        e_or = quadrule.judge(n, hh, t1[b, :Rb], a1[b, :Rb], ref, sent[b])
+        assert abs(e1[b] - e_or) <= 1e-8 * e_or
+        assert np.all(t1[b, Rb:] == 0)
+
+
+def test_fit_lowers_the_error_of_held_out_cases(ctx):
+    cases = learned.prepare_cases(64, seed=21, shuffle_seed=22)
+    y, t, a, err = ctx.quad_fit(cases["grids"], cases["hmin"], cases["sent"], cases["R"], None, iters=30)
+    t0, a0 = ctx.quad_rules(None, cases["R"])
+    e0 = ctx.quad_judge(cases["grids"], cases["hmin"], cases["sent"], t0, a0, cases["R"])
+    e1 = ctx.quad_judge(cases["grids"], cases["hmin"], cases["sent"], t, a, cases["R"])
+    torch.cuda.synchronize()
+    err, e0, e1 = (x.cpu().numpy() for x in (err, e0, e1))
+    assert np.allclose(err, e1, rtol=1e-9, atol=0)
+    assert np.all(err <= e0)
+    ratio = err / e0
+    print(f"fit: geometric mean error ratio fitted/base {np.exp(np.mean(np.log(ratio))):.3e}")
+    assert np.exp(np.mean(np.log(ratio))) < 0.3
+    # one case checked end to end by the oracle
+    b = 0
+    n = tuple(int(v) for v in cases["n"][b])
+    hh = (float(cases["h"][b]),) * 3
+    tr, ar = quadrule.reference_rule(hh[0])
+    sent = cases["sent"][b].cpu().numpy()
+    ref = quadrule.kernel_values(n, hh, tr, ar, sent)
+    R = int(cases["Rhost"][b])
+    tt, aa = t[b, :R].cpu().numpy(), a[b, :R].cpu().numpy()
+    assert abs(quadrule.judge(n, hh, tt, aa, ref, sent) - err[b]) <= 1e-8 * err[b]
+    to, ao = quadrule.rule_from_outputs(y[b].cpu().numpy().astype(np.float64), R, hh[0])
+    assert np.allclose(to, tt, rtol=1e-6) and np.allclose(ao, aa, rtol=1e-5)
+
+
+def test_loss_grad_matches_oracle(ctx):
+    rng = np.random.default_rng(8)
+    B = 3
+    R = np.array([16, 23, 32], dtype=np.int32)
+    y = (0.5 * rng.standard_normal((B, 65))).astype(np.float32)
+    T = (0.5 * rng.standard_normal((B, 65))).astype(np.float32)
+    xf = np.r_[0.4 * np.tanh(rng.standard_normal(32)), 0.9 * np.tanh(rng.standard_normal(32))][None].repeat(B, 0)
+    G = rng.standard_normal((B, 64, 64))
+    H = (np.einsum("bij,bkj->bik", G, G) * 10.0).astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
+    loss, dy = ctx.quad_loss_grad(dev(y), dev(T), dev(xf), dev(H), dev(R), lam=0.1)
+    torch.cuda.synchronize()
+    loss, dy = loss.cpu().numpy(), dy.cpu().numpy()
+    for b in range(B):
+        f = lambda v: quadrule.distill_loss(v, float(T[b, 64]), xf[b], H[b], int(R[b]), 0.1)  # noqa: E731
+        assert abs(loss[b] - f(y[b])) <= 1e-5 * (1 + abs(f(y[b])))
+        fd = np.zeros(65)
+        for k in range(65):
+            e = np.zeros(65)
+            e[k] = 1e-6
+            fd[k] = (f(y[b].astype(np.float64) + e) - f(y[b].astype(np.float64) - e)) / 2e-6
+        assert np.allclose(dy[b] * B, fd, rtol=1e-4, atol=1e-6 * np.abs(fd).max()), b
+
+
 @pytest.fixture(scope="module")
 def trained(ctx):
     cases = learned.prepare_cases(4096, seed=3)
-    params, loss = learned.train(ctx, cases, steps=400, batch=512)
+    learned.fit_targets(ctx, cases, iters=60)
+    params, loss = learned.train(ctx, cases, steps=3000, batch=512)
     torch.cuda.synchronize()
     return params, loss
 
 
-def test_training_lowers_loss_and_beats_base_rule(ctx, trained):
+def test_training_learns_the_achievable_error(ctx, trained):
+    """The error head predicts, for held-out grids and R', the error a fitted
+    R'-node rule reaches: it is what picks R' for a tolerance."""
     params, loss = trained
     assert np.isfinite(loss).all()
-    assert loss[-20:].mean() < loss[:5].mean() - 1.0        # ln err drops by > e
-    # held-out cases (the recipe's next draws)
+    assert loss[-20:].mean() < 0.2 * loss[:5].mean()
     test = learned.prepare_cases(256, seed=11, shuffle_seed=12)
     y, _z, _a = ctx.mlp_forward(params, test["x"])
-    t1, a1 = ctx.quad_rules(y, test["R"])
-    t0, a0 = ctx.quad_rules(None, test["R"])
-    e1 = ctx.quad_judge(test["grids"], test["hmin"], test["sent"], t1, a1, test["R"])
-    e0 = ctx.quad_judge(test["grids"], test["hmin"], test["sent"], t0, a0, test["R"])
+    _y, _t, _a2, efit = ctx.quad_fit(test["grids"], test["hmin"], test["sent"], test["R"], None, 60)
     torch.cuda.synchronize()
-    ratio = (e1 / e0).cpu().numpy()
-    gmean = float(np.exp(np.mean(np.log(ratio))))
-    print(f"held-out: geometric mean error ratio learned/base {gmean:.3e}, better in {np.mean(ratio < 1):.0%}")
-    assert gmean < 0.5 and np.mean(ratio < 1) > 0.8
+    head = y[:, 64].cpu().numpy()
+    target = np.log10(efit.cpu().numpy())
+    corr = float(np.corrcoef(head, target)[0, 1])
+    mae = float(np.mean(np.abs(head - target)))
+    print(f"held-out: error head correlation {corr:.3f}, mean abs error {mae:.3f} (log10)")
+    assert corr > 0.9 and mae < 0.3
+
+
+def test_learned_rule_beats_sinc_at_equal_nodes(ctx, trained):
+    """At 128^3 and tol 1e-6 the learned path picks R' nodes, meets tol, and
+    the plain sinc rule with the same R' misses it by far; the plain rule
+    needs more nodes (the gain: fewer mode products at equal accuracy)."""
+    params, _loss = trained
+    n = (128, 128, 128)
+    r = learned.predict(ctx, params, n, 1e-6)
+    print("predict 128^3 at 1e-6:", {k: v for k, v in r.items() if k not in ("t", "alpha")})
+    assert not r["fell_back"] and r["judged"] <= 1e-6 and r["R"] <= 30
+    h = 1.0 / 128
+    sent = inputs.sentinel_offsets(n)
+    tr, ar = quadrule.reference_rule(h)
+    ref = quadrule.kernel_values(n, (h,) * 3, tr, ar, sent)
+    assert abs(quadrule.judge(n, (h,) * 3, r["t"], r["alpha"], ref, sent) - r["judged"]) <= 1e-8 * r["judged"]
+    t0, a0, _ = quadrule.base_rule(r["R"])
+    assert quadrule.judge(n, (h,) * 3, t0, a0, ref, sent) > 10 * 1e-6
 
 
 def test_predict_and_fallback(ctx, trained):
     params, _loss = trained
     r = learned.predict(ctx, params, (48, 64, 40), 1e-6)
-    assert 16 <= r["R"] <= 32 or (r["fell_back"] and r["R"] == 64)
-    if not r["fell_back"]:
-        assert r["judged"] <= 1e-6
+    print("predict 48x64x40 at 1e-6:", {k: v for k, v in r.items() if k not in ("t", "alpha")})
+    assert not r["fell_back"] and 16 <= r["R"] <= 32 and r["judged"] <= 1e-6
     r2 = learned.predict(ctx, params, (48, 64, 40), 1e-13)   # unattainable with R' <= 32
     assert r2["fell_back"] and r2["R"] == 64 and r2["judged"] > 1e-13
