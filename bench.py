@@ -287,7 +287,7 @@ def main():
     ap.add_argument("--learned-steps", type=int, default=4000)
     ap.add_argument("--fit-iters", type=int, default=60)
     ap.add_argument("--cases", type=int, default=20000)
-    ap.add_argument("--rule-tol", type=float, default=3e-7)
+    ap.add_argument("--rule-tol", type=float, default=1e-6)
     ap.add_argument("--mixed-prec", default="bf16x3")
     ap.add_argument("--batch-ws-gib", type=int, default=32)
     ap.add_argument("--tune", type=int, default=1)

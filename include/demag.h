@@ -262,7 +262,7 @@ demag_status demag_quad_judge(demag_ctx *ctx, int32_t B, const int32_t *grids, c
                               const int32_t *R, int32_t KM, double *err, double *dt, double *dalpha);
 /* Levenberg-Marquardt fit of B cases' outputs (rule parametrization of
  * demag_quad_rules) against the reference rule on their grids [B][3], cell
- * sizes hmin[B] and sentinels [B][S][3] (S <= 64), R[B] nodes (16..32):
+ * sizes hmin[B] and sentinels [B][S][3] (S <= 256), R[B] nodes (16..32):
  * `iters` damped Gauss-Newton steps in u_k = 0.45 tanh(y_k),
  * v_k = tanh(y_{32+k}) (projected onto |u| <= 0.44, |v| <= 0.99) from y0
  * ([B][65] device, NULL = zeros, the plain base rule) with initial damping
@@ -294,18 +294,19 @@ demag_status demag_quad_train(demag_ctx *ctx, float *params, float *adam_m, floa
                               const float *targets, const double *xfit, const float *H, const int32_t *R,
                               int32_t count, int32_t steps, int32_t batch, int32_t step0, float lr,
                               float lambda, float *loss_host);
-/* Rule for one grid (n host[3], cell size hmin, sentinels [S][3] device) at
- * tolerance tol: features [17][6] (device) for R' = 16..32 in order; the
- * smallest R' with predicted log10 error <= log10 tol is polished with
- * fit_iters Levenberg-Marquardt steps (from the network's proposal and from
- * the plain base rule; the better one is kept) and judged; if it misses tol, R' + 4,
+/* Rule for one grid (n host[3], cell size hmin, fit offsets [S][3] with
+ * S <= 256 and check offsets [Sc][3], device) at tolerance tol: features
+ * [17][6] (device) for R' = 16..32 in order; the smallest R' with predicted
+ * log10 error <= log10 tol is polished with fit_iters Levenberg-Marquardt
+ * steps on the fit offsets (from the network's proposal and from the plain
+ * base rule; the better one is kept) and judged on the check offsets; if it misses tol, R' + 4,
  * R' + 8, ... (up to 32) follow, and if none meets tol the sinc rule with
  * the step of Thm. sinc_theo and 64 nodes is returned (*fell_back = 1).
  * Host outputs: t_out, alpha_out (capacity 64), *R_out, *judged (error of
  * the last rule judged), *predicted (log10, of the first pick), *fell_back. */
 demag_status demag_quad_predict(demag_ctx *ctx, const float *params, const float *features,
                                 const int32_t n[3], double hmin, const int32_t *sentinels, int32_t S,
-                                double tol, int32_t fit_iters, double *t_out, double *alpha_out,
+                                const int32_t *check, int32_t Sc, double tol, int32_t fit_iters, double *t_out, double *alpha_out,
                                 int32_t *R_out, double *judged, double *predicted, int32_t *fell_back);
 
 /* The bfloat16 split used by DEMAG_BF16X2/X3 on the device, exposed for

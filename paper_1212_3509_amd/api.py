@@ -67,8 +67,8 @@ _SIGS = {
     "demag_quad_loss_grad": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int32, C.c_float, _P, _P]),
     "demag_quad_train": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                    C.c_float, C.c_float, _P]),
-    "demag_quad_predict": (C.c_int, [_P, _P, _P, _P, C.c_double, _P, C.c_int32, C.c_double, C.c_int32, _P, _P, _P,
-                                     _P, _P, _P]),
+    "demag_quad_predict": (C.c_int, [_P, _P, _P, _P, C.c_double, _P, C.c_int32, _P, C.c_int32, C.c_double,
+                                     C.c_int32, _P, _P, _P, _P, _P, _P]),
     "demag_prepare_structured": (C.c_int, [_P, _P]),
     "demag_apply_columns": (C.c_int, [_P, _P, _P, _P, _P]),
     "demag_apply_cp": (C.c_int, [_P, _P, C.c_int32, _P, _P, _P]),
@@ -408,9 +408,10 @@ class Context:
                                           loss.ctypes.data), "demag_quad_train")
         return loss[:steps]
 
-    def quad_predict(self, params, features, n, hmin, sent, tol, fit_iters=20):
-        """features: CUDA float32 [17][6] for R' = 16..32; sent: CUDA int32
-        [S][3].  Returns dict(t, alpha, R, judged, predicted, fell_back)."""
+    def quad_predict(self, params, features, n, hmin, sent, check, tol, fit_iters=60):
+        """features: CUDA float32 [17][6] for R' = 16..32; sent, check: CUDA
+        int32 [S][3] fit and check offsets.  Returns dict(t, alpha, R, judged,
+        predicted, fell_back)."""
         t = np.zeros(64)
         a = np.zeros(64)
         R, fb = C.c_int32(), C.c_int32()
@@ -418,7 +419,8 @@ class Context:
         n3 = (C.c_int32 * 3)(*n)
         self.use_current_stream()
         _check(library().demag_quad_predict(self.handle, _ptr(params), _ptr(features), n3, hmin, _ptr(sent),
-                                            int(sent.shape[0]), tol, fit_iters, t.ctypes.data, a.ctypes.data,
+                                            int(sent.shape[0]), _ptr(check), int(check.shape[0]), tol, fit_iters,
+                                            t.ctypes.data, a.ctypes.data,
                                             C.byref(R), C.byref(judged), C.byref(pred), C.byref(fb)),
                "demag_quad_predict")
         return {"t": t[:R.value], "alpha": a[:R.value], "R": R.value, "judged": judged.value,

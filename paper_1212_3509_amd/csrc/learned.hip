@@ -364,7 +364,7 @@ __global__ void k_target_grads(const float *__restrict__ Y, const float *__restr
 // ------------------------------------------------------------------ fit
 constexpr int kFitSB = 8;        // sentinels per pass: 8 x 32 nodes = 256 threads
 constexpr int kNP = 2 * kRmax;   // fitted outputs y_k, y_{32+k}
-constexpr int kMaxS = 64;
+constexpr int kMaxS = 256;
 
 constexpr double kUMax = 0.44, kVMax = 0.99;
 
@@ -866,23 +866,25 @@ demag_status demag_quad_fit(demag_ctx *ctx, int32_t B, const int32_t *grids, con
 // Shortened rule for one grid: the network's predicted-error head picks the
 // smallest R' (16..32) it expects to meet tol; that proposal (and the plain
 // base rule, as a guard) is polished by `fit_iters` Levenberg-Marquardt
-// steps on the grid's own sentinels and the better one is judged; if it misses tol, R' + 4, R' + 8, ... (up to 32) are tried the
+// steps on the grid's fit offsets, and the better one is judged on the
+// check offsets (not seen by the fit); if it misses tol, R' + 4, R' + 8, ... (up to 32) are tried the
 // same way, and if none meets tol the sinc rule with the step of
 // Thm. sinc_theo and 64 nodes is returned (*fell_back = 1).
 demag_status demag_quad_predict(demag_ctx *ctx, const float *params, const float *features, const int32_t n[3],
-                                double hmin, const int32_t *sent, int32_t S, double tol, int32_t fit_iters,
-                                double *t_out, double *alpha_out, int32_t *R_out, double *judged, double *predicted,
-                                int32_t *fell_back) {
-  DEMAG_REQUIRE(ctx && params && features && n && sent && t_out && alpha_out && R_out && judged && predicted &&
-                    fell_back,
+                                double hmin, const int32_t *sent, int32_t S, const int32_t *check, int32_t Sc,
+                                double tol, int32_t fit_iters, double *t_out, double *alpha_out, int32_t *R_out,
+                                double *judged, double *predicted, int32_t *fell_back) {
+  DEMAG_REQUIRE(ctx && params && features && n && sent && check && t_out && alpha_out && R_out && judged &&
+                    predicted && fell_back,
                 "demag_quad_predict: NULL argument");
-  DEMAG_REQUIRE(tol > 0 && hmin > 0 && S >= 1 && S <= kMaxS && fit_iters >= 0,
-                "demag_quad_predict: tol, hmin, S or fit_iters out of range");
+  DEMAG_REQUIRE(tol > 0 && hmin > 0 && S >= 1 && S <= kMaxS && Sc >= 1 && fit_iters >= 0,
+                "demag_quad_predict: tol, hmin, S, Sc or fit_iters out of range");
   DEMAG_TRY_HIP(hipSetDevice(ctx->device));
   const int NC = 17;
   float *Y = nullptr, *yfit = nullptr;
   int32_t *dR = nullptr, *dgrid = nullptr;
-  double *dh = nullptr, *dt = nullptr, *da = nullptr, *derr = nullptr, *Kref = nullptr;
+  double *dh = nullptr, *dt = nullptr, *da = nullptr, *derr = nullptr, *Kref = nullptr, *KrefC = nullptr,
+         *Kc = nullptr;
   demag_status st = dalloc(&Y, size_t(NC) * kOut);
   if (st == DEMAG_OK) st = dalloc(&yfit, kOut);
   if (st == DEMAG_OK) st = dalloc(&dR, 1);
@@ -892,6 +894,8 @@ demag_status demag_quad_predict(demag_ctx *ctx, const float *params, const float
   if (st == DEMAG_OK) st = dalloc(&da, kRmax);
   if (st == DEMAG_OK) st = dalloc(&derr, 1);
   if (st == DEMAG_OK) st = dalloc(&Kref, size_t(S) * kNcomp);
+  if (st == DEMAG_OK) st = dalloc(&KrefC, size_t(Sc) * kNcomp);
+  if (st == DEMAG_OK) st = dalloc(&Kc, size_t(Sc) * kNcomp);
   std::vector<float> yh(size_t(NC) * kOut);
   if (st == DEMAG_OK) {
     k_mlp_forward<<<NC, 64, 0, ctx->stream>>>(params, features, NC, Y, nullptr, nullptr);
@@ -903,6 +907,7 @@ demag_status demag_quad_predict(demag_ctx *ctx, const float *params, const float
     }
   }
   if (st == DEMAG_OK) st = reference_values(ctx, dgrid, dh, sent, S, 1, Kref);
+  if (st == DEMAG_OK) st = reference_values(ctx, dgrid, dh, check, Sc, 1, KrefC);
   int pick = NC - 1;
   if (st == DEMAG_OK) {
     for (int c = 0; c < NC; ++c)
@@ -946,6 +951,22 @@ demag_status demag_quad_predict(demag_ctx *ctx, const float *params, const float
       }
     }
     if (st != DEMAG_OK) break;
+    // judge the kept rule on the check offsets, which the fit never saw
+    if (hipMemcpyAsync(dt, th.data(), sizeof(double) * kRmax, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(da, ah.data(), sizeof(double) * kRmax, hipMemcpyHostToDevice, ctx->stream) != hipSuccess) {
+      set_error("demag_quad_predict: copy failed");
+      st = DEMAG_E_HIP;
+      break;
+    }
+    k_judge_values<<<(Sc + 127) / 128, 128, 0, ctx->stream>>>(dgrid, dh, check, Sc, dt, da, dR, kRmax, 1, Kc);
+    k_judge_err<<<1, 128, 0, ctx->stream>>>(Kc, KrefC, 1, Sc, derr, nullptr);
+    if (hipGetLastError() != hipSuccess ||
+        hipMemcpyAsync(&e, derr, sizeof(double), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      set_error("demag_quad_predict: judge failed");
+      st = DEMAG_E_HIP;
+      break;
+    }
     *judged = e;
     if (e <= tol) {
       done = true;
@@ -971,7 +992,7 @@ demag_status demag_quad_predict(demag_ctx *ctx, const float *params, const float
     }
   }
   for (void *p : {(void *)Y, (void *)yfit, (void *)dR, (void *)dgrid, (void *)dh, (void *)dt, (void *)da,
-                  (void *)derr, (void *)Kref})
+                  (void *)derr, (void *)Kref, (void *)KrefC, (void *)Kc})
     if (p) (void)hipFree(p);
   return st;
 }

