@@ -312,6 +312,9 @@ demag_status get_plan(demag_ctx *ctx, demag_factors *f, demag_prec prec, FullPla
   return DEMAG_OK;
 }
 
+}  // namespace
+
+// Grow the context workspace to at least `bytes` (stream-ordered reuse).
 demag_status ensure_workspace(demag_ctx *ctx, size_t bytes) {
   if (ctx->ws_bytes >= bytes) return DEMAG_OK;
   if (ctx->ws) {
@@ -332,7 +335,6 @@ demag_status ensure_workspace(demag_ctx *ctx, size_t bytes) {
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
-}  // namespace
 }  // namespace demag
 
 using namespace demag;

@@ -20,12 +20,16 @@
 // A real transform of length L is computed through a complex transform of
 // length N = L/2 on z[m] = x[2m] + i x[2m+1], with the usual even/odd
 // unpacking by W_L^f.  The complex transform runs in LDS as Stockham passes
-// of radix 16/8/4/2 (N/R butterflies per pass, 256 threads, twiddles from a
-// precomputed table of W_N^e).  One workgroup owns one input column: it
-// transforms the column once (keeping the spectrum in registers, each
-// thread holding the frequency pairs f, N - f it later needs), then for each
-// of its jobs multiplies by a kernel spectrum, transforms back and writes the
-// n outputs.
+// of radix 16/8/4/2 (N/R butterflies per pass, 256 threads).  Twiddles come
+// from two 64-entry tables in LDS, W_N^e = W_N^(e mod 64) W_N^(64 (e div 64)),
+// so no pass waits on global memory.
+//
+// Two launches per axis: k_fft_fwd transforms every input column once and
+// stores its unpacked spectrum U[0..N] in the workspace; k_fft_jobs gives
+// each workgroup a few jobs of one column: it loads the column's frequency
+// pairs (f, N - f) into registers (from L2: every job group of a column reads
+// the same 64 KB), and per job multiplies by a kernel spectrum, transforms
+// back and writes the n outputs.
 #include "internal.h"
 
 #include <cmath>
@@ -36,7 +40,7 @@ namespace {
 
 constexpr int kThreads = 256;
 
-struct c32 {
+struct alignas(16) c32 {   // 16-byte aligned: one ds_read_b128 / ds_write_b128 per point
   double x, y;
 };
 __device__ inline c32 cadd(c32 a, c32 b) { return {a.x + b.x, a.y + b.y}; }
@@ -111,8 +115,20 @@ template <> __device__ inline void dftR<true, 16>(c32 *v) { dft_split<true, 4, 4
 // One Stockham pass of radix R over N points in LDS (in place: all reads of
 // the pass complete before any write).  Ns = length of the sub-transforms
 // already formed.  tw[e] = W_N^e (forward sign), e < N.
+// LDS slot of point i: one pad slot after every 16 points, so the strided
+// accesses of the Stockham passes (stride R points) spread over the banks.
+__device__ inline int pd(int i) { return i + (i >> 4); }
+__host__ __device__ inline int padded_points(int N) { return N + N / 16 + 1; }
+
+// W_N^e (forward sign) from the two LDS tables: lo[i] = W_N^i (i < 64),
+// hi[i] = W_N^(64 i) (i < N/64).
+__device__ inline c32 twid(int e, const c32 *lo, const c32 *hi) {
+  const c32 a = lo[e & 63];
+  return (e >> 6) ? cmul(a, hi[e >> 6]) : a;
+}
+
 template <bool INV, int R>
-__device__ inline void stockham_pass(c32 *buf, int N, int Ns, const double2 *__restrict__ tw) {
+__device__ inline void stockham_pass(c32 *buf, int N, int Ns, const c32 *tlo, const c32 *thi) {
   const int nb = N / R;
   constexpr int kMaxB = 16 / R > 0 ? (4096 / R + kThreads - 1) / kThreads : 1;
   c32 v[kMaxB][R];
@@ -124,12 +140,17 @@ __device__ inline void stockham_pass(c32 *buf, int N, int Ns, const double2 *__r
     if (j < nb) {
       const int k = j & (Ns - 1);
       const int step = N / (Ns * R);          // W_{Ns R}^{k r} = W_N^{k r step}
+      // twiddles w^r, r = 1..R-1, of w = W_N^{k step}: one table lookup,
+      // then products (a few ulp in FP64)
+      c32 w = twid((k * step) & (N - 1), tlo, thi);
+      if (INV) w = cconj(w);
+      c32 wr = w;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        c32 x = buf[j + r * nb];
-        if (r > 0 && k > 0) {
-          const double2 w = tw[(k * r * step) & (N - 1)];
-          x = cmul(x, INV ? c32{w.x, -w.y} : c32{w.x, w.y});
+        c32 x = buf[pd(j + r * nb)];
+        if (r > 0) {
+          x = cmul(x, wr);
+          wr = cmul(wr, w);
         }
         v[q][r] = x;
       }
@@ -144,7 +165,7 @@ __device__ inline void stockham_pass(c32 *buf, int N, int Ns, const double2 *__r
       const int k = j & (Ns - 1);
       const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[base + r * Ns] = v[q][r];
+      for (int r = 0; r < R; ++r) buf[pd(base + r * Ns)] = v[q][r];
     }
   }
   __syncthreads();
@@ -152,34 +173,46 @@ __device__ inline void stockham_pass(c32 *buf, int N, int Ns, const double2 *__r
 
 // Complex FFT of N (power of 2, N <= 4096) points in LDS.
 template <bool INV>
-__device__ void fft_lds(c32 *buf, int N, const double2 *__restrict__ tw) {
+__device__ void fft_lds(c32 *buf, int N, const c32 *tlo, const c32 *thi) {
   int Ns = 1;
   while (Ns < N) {
     const int left = N / Ns;
     if (left >= 16) {
-      stockham_pass<INV, 16>(buf, N, Ns, tw);
+      stockham_pass<INV, 16>(buf, N, Ns, tlo, thi);
       Ns *= 16;
     } else if (left == 8) {
-      stockham_pass<INV, 8>(buf, N, Ns, tw);
+      stockham_pass<INV, 8>(buf, N, Ns, tlo, thi);
       Ns *= 8;
     } else if (left == 4) {
-      stockham_pass<INV, 4>(buf, N, Ns, tw);
+      stockham_pass<INV, 4>(buf, N, Ns, tlo, thi);
       Ns *= 4;
     } else {
-      stockham_pass<INV, 2>(buf, N, Ns, tw);
+      stockham_pass<INV, 2>(buf, N, Ns, tlo, thi);
       Ns *= 2;
     }
   }
 }
 
 // W_L^f = exp(-2 pi i f / L) for the real-transform unpacking, with L = 2N:
-// W_L^f = W_N^{f/2} for even f; for odd f the table entry at (f-1)/2 times
-// W_L^1 (passed in).
-__device__ inline c32 wl(int f, int N, const double2 *__restrict__ tw, c32 w1) {
-  const double2 a = tw[(f >> 1) & (N - 1)];
-  c32 w{a.x, a.y};
+// W_L^f = W_N^{f/2} for even f; for odd f that times W_L^1 (passed in).
+__device__ inline c32 wl(int f, int N, const c32 *tlo, const c32 *thi, c32 w1) {
+  c32 w = twid((f >> 1) & (N - 1), tlo, thi);
   if (f & 1) w = cmul(w, w1);
   return w;
+}
+
+// Fill the two twiddle tables (LDS, 64 + 64 entries) from the global table
+// tw[e] = W_N^e; callers synchronize before use.
+__device__ inline void load_twiddles(c32 *tlo, c32 *thi, int N, const double2 *__restrict__ tw) {
+  const int t = threadIdx.x;
+  if (t < 64) {
+    const double2 a = tw[t & (N - 1)];
+    tlo[t] = c32{a.x, a.y};
+  } else if (t < 128) {
+    const int i = t - 64;
+    const double2 a = (64 * i < N) ? tw[64 * i] : make_double2(1.0, 0.0);
+    thi[i] = c32{a.x, a.y};
+  }
 }
 
 // ---------------------------------------------------------------- spectra
@@ -224,42 +257,58 @@ __global__ void k_twiddles(double2 *__restrict__ tw, int N) {
 // frequency pairs (f, N - f), f = 0..N/2, per thread at N = 4096: 2049 pairs
 constexpr int kMaxPairs = (4096 / 2 + 1 + kThreads - 1) / kThreads;
 
-// Grid: x = input column (q * R + l), y = job group.  Jobs of a column are
-// its (s, k) pairs, j = s * M + k, in contiguous groups of jobs_per_group.
-__global__ __launch_bounds__(kThreads) void k_toeplitz_fft(const float *__restrict__ in, float *__restrict__ out,
-                                                           const double *__restrict__ spec,
-                                                           const double2 *__restrict__ tw, int n, int L, int M,
-                                                           int R, int axis, int jobs_per_group) {
-  extern __shared__ c32 wk[];   // N points
+// Forward real transform of every column: U[col][f], f = 0..N (N + 1 values).
+__global__ __launch_bounds__(kThreads) void k_fft_fwd(const float *__restrict__ in, c32 *__restrict__ U,
+                                                      const double2 *__restrict__ tw, int n, int L) {
+  extern __shared__ c32 wk[];   // N points (padded), then the twiddle tables
   const int N = L / 2;
-  const int col = blockIdx.x;   // q * R + l
-  const int q = col / R, l = col % R;
-  double sw, cw;
-  sincospi(-1.0 / double(N), &sw, &cw);
-  const c32 w1{cw, sw};         // W_L^1
-
-  // forward transform of the column: z[m] = u[2m] + i u[2m+1]
+  c32 *tlo = wk + padded_points(N), *thi = tlo + 64;
+  const int col = blockIdx.x;
+  load_twiddles(tlo, thi, N, tw);
   const float *u = in + size_t(col) * n;
   for (int m = threadIdx.x; m < N; m += kThreads) {
     const int a = 2 * m, b = 2 * m + 1;
-    wk[m] = c32{a < n ? double(u[a]) : 0.0, b < n ? double(u[b]) : 0.0};
+    wk[pd(m)] = c32{a < n ? double(u[a]) : 0.0, b < n ? double(u[b]) : 0.0};
   }
   __syncthreads();
-  fft_lds<false>(wk, N, tw);
+  fft_lds<false>(wk, N, tlo, thi);
+  double sw, cw;
+  sincospi(-1.0 / double(N), &sw, &cw);
+  const c32 w1{cw, sw};         // W_L^1
+  // X[f] = E + W_L^f O with E = (Z[f] + conj Z[N-f])/2, O = (Z[f] - conj Z[N-f])/(2i)
+  c32 *Uc = U + size_t(col) * (N + 1);
+  for (int f = threadIdx.x; f <= N; f += kThreads) {
+    const c32 zf = wk[pd(f & (N - 1))];
+    const c32 zcc = cconj(wk[pd((N - f) & (N - 1))]);
+    const c32 D{0.5 * (zf.x - zcc.x), 0.5 * (zf.y - zcc.y)};
+    Uc[f] = cadd(c32{0.5 * (zf.x + zcc.x), 0.5 * (zf.y + zcc.y)}, cmul(wl(f, N, tlo, thi, w1), c32{D.y, -D.x}));
+  }
+}
+
+// Grid: x = input column (q * R + l), y = job group.  Jobs of a column are
+// its (s, k) pairs, j = s * M + k, in contiguous groups of jobs_per_group.
+__global__ __launch_bounds__(kThreads) void k_fft_jobs(const c32 *__restrict__ U, float *__restrict__ out,
+                                                       const double *__restrict__ spec,
+                                                       const double2 *__restrict__ tw, int n, int L, int M, int R,
+                                                       int axis, int jobs_per_group) {
+  extern __shared__ c32 wk[];   // N points (padded), then the twiddle tables
+  const int N = L / 2;
+  c32 *tlo = wk + padded_points(N), *thi = tlo + 64;
+  const int col = blockIdx.x;   // q * R + l
+  const int q = col / R, l = col % R;
+  load_twiddles(tlo, thi, N, tw);
+  double sw, cw;
+  sincospi(-1.0 / double(N), &sw, &cw);
+  const c32 w1{cw, sw};         // W_L^1
   // U[f] and U[N - f] for this thread's pairs f = threadIdx.x + p * kThreads <= N/2
+  const c32 *Uc = U + size_t(col) * (N + 1);
   c32 uf[kMaxPairs], uc[kMaxPairs];
 #pragma unroll
   for (int p = 0; p < kMaxPairs; ++p) {
     const int f = threadIdx.x + p * kThreads;
     if (f <= N / 2) {
-      const c32 zf = wk[f & (N - 1)];
-      const c32 zc = wk[(N - f) & (N - 1)];
-      // X[f] = E + W_L^f O with E = (Z[f] + conj Z[N-f])/2, O = (Z[f] - conj Z[N-f])/(2i)
-      const c32 zcc = cconj(zc), zfc = cconj(zf);
-      const c32 D1{0.5 * (zf.x - zcc.x), 0.5 * (zf.y - zcc.y)};
-      const c32 D2{0.5 * (zc.x - zfc.x), 0.5 * (zc.y - zfc.y)};
-      uf[p] = cadd(c32{0.5 * (zf.x + zcc.x), 0.5 * (zf.y + zcc.y)}, cmul(wl(f, N, tw, w1), c32{D1.y, -D1.x}));
-      uc[p] = cadd(c32{0.5 * (zc.x + zfc.x), 0.5 * (zc.y + zfc.y)}, cmul(wl(N - f, N, tw, w1), c32{D2.y, -D2.x}));
+      uf[p] = Uc[f];
+      uc[p] = Uc[N - f];
     }
   }
   __syncthreads();
@@ -289,23 +338,23 @@ __global__ __launch_bounds__(kThreads) void k_toeplitz_fft(const float *__restri
           const c32 ycc = cconj(yc);
           const c32 E{0.5 * (yf.x + ycc.x), 0.5 * (yf.y + ycc.y)};
           const c32 Dm{0.5 * (yf.x - ycc.x), 0.5 * (yf.y - ycc.y)};
-          const c32 O = cmul(Dm, cconj(wl(f, N, tw, w1)));
-          wk[f & (N - 1)] = c32{E.x - O.y, E.y + O.x};
+          const c32 O = cmul(Dm, cconj(wl(f, N, tlo, thi, w1)));
+          wk[pd(f & (N - 1))] = c32{E.x - O.y, E.y + O.x};
         }
         if (fc != f && fc < N) {
           const c32 yfc = cconj(yf);
           const c32 E{0.5 * (yc.x + yfc.x), 0.5 * (yc.y + yfc.y)};
           const c32 Dm{0.5 * (yc.x - yfc.x), 0.5 * (yc.y - yfc.y)};
-          const c32 O = cmul(Dm, cconj(wl(fc, N, tw, w1)));
-          wk[fc] = c32{E.x - O.y, E.y + O.x};
+          const c32 O = cmul(Dm, cconj(wl(fc, N, tlo, thi, w1)));
+          wk[pd(fc)] = c32{E.x - O.y, E.y + O.x};
         }
       }
     }
     __syncthreads();
-    fft_lds<true>(wk, N, tw);
+    fft_lds<true>(wk, N, tlo, thi);
     float *y = out + ((size_t(q) * 2 + s) * M + k) * size_t(R) * n + size_t(l) * n;
     for (int m = threadIdx.x; m < N; m += kThreads) {
-      const c32 z = wk[m];
+      const c32 z = wk[pd(m)];
       const int a = 2 * m, b = 2 * m + 1;
       if (a < n) y[a] = float(z.x * inv_n);
       if (b < n) y[b] = float(z.y * inv_n);
@@ -351,22 +400,28 @@ demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, int d, int R
   const int N = L / 2;
   const int ncols = 3 * R;
   if (ncols == 0) return DEMAG_OK;
+  // column spectra in the workspace
+  demag_status st = ensure_workspace(ctx, sizeof(double2) * size_t(ncols) * (N + 1));
+  if (st != DEMAG_OK) return st;
+  c32 *U = static_cast<c32 *>(ctx->ws);
   // job groups per column: enough workgroups to fill the chip (>= 4 per CU)
   int target = 1;
   const int njobs = 2 * f->M;
   while (ncols * target < 1024 && target < njobs) target *= 2;
   const int per = (njobs + target - 1) / target;
   const int groups = (njobs + per - 1) / per;   // every group owns >= 1 job
-  dim3 grid(ncols, groups);
-  const size_t lds = sizeof(double2) * size_t(N);
-  DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_toeplitz_fft),
+  const size_t lds = sizeof(double2) * (size_t(padded_points(N)) + 128);
+  DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_fwd),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_jobs),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  const double2 *tw = reinterpret_cast<const double2 *>(f->twiddle[d]);
   hipEvent_t ev = nullptr;
-  demag_status st = prof_begin(ctx, &ev);
+  st = prof_begin(ctx, &ev);
   if (st != DEMAG_OK) return st;
-  k_toeplitz_fft<<<grid, kThreads, lds, ctx->stream>>>(in, out, f->spec[d],
-                                                       reinterpret_cast<const double2 *>(f->twiddle[d]), n, L,
-                                                       f->M, R, d, per);
+  k_fft_fwd<<<ncols, kThreads, lds, ctx->stream>>>(in, U, tw, n, L);
+  DEMAG_TRY_HIP(hipGetLastError());
+  k_fft_jobs<<<dim3(ncols, groups), kThreads, lds, ctx->stream>>>(U, out, f->spec[d], tw, n, L, f->M, R, d, per);
   DEMAG_TRY_HIP(hipGetLastError());
   if (ev) {
     const double jobs = double(ncols) * njobs;

@@ -177,5 +177,6 @@ demag_status launch_left_stage_bf16(demag_ctx *ctx, const demag_factors *f, dema
 demag_status launch_split(demag_ctx *ctx, const float *x, uint16_t *parts, size_t count, int nparts);
 int fft_length(int n);
 demag_status prepare_spectra(demag_ctx *ctx, demag_factors *f);
+demag_status ensure_workspace(demag_ctx *ctx, size_t bytes);
 demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, int d, int R, const float *in, float *out);
 } // namespace demag
