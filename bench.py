@@ -289,7 +289,7 @@ def main():
     ap.add_argument("--cases", type=int, default=20000)
     ap.add_argument("--rule-tol", type=float, default=1e-6)
     ap.add_argument("--mixed-prec", default="bf16x3")
-    ap.add_argument("--batch-ws-gib", type=int, default=32)
+    ap.add_argument("--batch-ws-gib", type=int, default=64)
     ap.add_argument("--tune", type=int, default=1)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain copy of this many MiB first (byte-counter calibration)")

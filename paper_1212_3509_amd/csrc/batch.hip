@@ -4,9 +4,9 @@
 // The 23 products per node of each state (see build_chunk in api.hip) are
 // cut into tiles (64 columns x 16*RB rows of one job); all tiles of one
 // stage, over all states, form one list that a single persistent launch
-// walks in a fixed order (workgroup w takes items w, w+G, ...; no atomics,
-// so results are bitwise reproducible).  Items are sorted by decreasing cost
-// so the largest tiles are spread over all workgroups first.  Nodes are
+// works off through a counter (each workgroup draws the next item; the tiles
+// write disjoint outputs, so results are bitwise reproducible).  Items are
+// sorted by decreasing cost, so the draw is a longest-first greedy schedule.  Nodes are
 // processed in chunks sized to the workspace limit; the launch sequence can
 // be captured once as a HIP graph and replayed.
 //
@@ -46,6 +46,7 @@ struct demag_batch {
   demag::MPJob *d_jobs = nullptr;
   demag::MPTerm *d_terms = nullptr;
   demag::MPGeom *d_geoms = nullptr;
+  int *d_counters = nullptr;                      // one item counter per launch
   std::map<std::pair<int, int>, int> rb_choice;   // (n, nout) -> RB
   double flops = 0;                               // algorithmic FLOPs of one apply
   // captured graph
@@ -190,6 +191,7 @@ demag_status build(demag_ctx *ctx, demag_batch *b) {
       DEMAG_TRY_HIP(hipMalloc(&L.d_items, sizeof(BatchItem) * std::max<size_t>(1, sorted.size())));
       DEMAG_TRY_HIP(hipMemcpy(L.d_items, sorted.data(), sizeof(BatchItem) * sorted.size(), hipMemcpyHostToDevice));
     }
+  DEMAG_TRY_HIP(hipMalloc(&b->d_counters, sizeof(int) * size_t(b->nchunks) * 3));
   b->ws_bytes = size_t(12) * kc * Ntot * esize;
   hipError_t e = hipMalloc(&b->ws, b->ws_bytes);
   if (e != hipSuccess) {
@@ -208,6 +210,8 @@ void release_tables(demag_batch *b) {
   if (b->d_jobs) (void)hipFree(b->d_jobs);
   if (b->d_terms) (void)hipFree(b->d_terms);
   if (b->d_geoms) (void)hipFree(b->d_geoms);
+  if (b->d_counters) (void)hipFree(b->d_counters);
+  b->d_counters = nullptr;
   if (b->ws) (void)hipFree(b->ws);
   b->d_jobs = nullptr;
   b->d_terms = nullptr;
@@ -225,12 +229,14 @@ demag_status enqueue(demag_ctx *ctx, demag_batch *b, const void *m, void *phi, v
   void *y1 = ws;
   void *y2 = ws + size_t(6) * b->kc * b->off.back() * esize;
   void *bufs[6] = {const_cast<void *>(m), y1, y2, phi, h, nullptr};
+  demag_status s = launch_reset_counters(ctx, b->d_counters, b->nchunks * 3);
+  if (s != DEMAG_OK) return s;
   for (int c = 0; c < b->nchunks; ++c)
     for (int st = 0; st < 3; ++st) {
       const auto &L = b->launches[c][st];
       const int beta = (st == 2 && c > 0) ? 1 : 0;
-      demag_status s = launch_items(ctx, b->prec, L.d_items, L.nitems, b->grid, b->d_jobs, b->d_terms, b->d_geoms,
-                                    bufs, b->gens, b->nmax, beta);
+      s = launch_items(ctx, b->prec, L.d_items, L.nitems, b->grid, b->d_jobs, b->d_terms, b->d_geoms, bufs, b->gens,
+                       b->nmax, beta, b->d_counters + c * 3 + st);
       if (s != DEMAG_OK) return s;
     }
   return DEMAG_OK;
@@ -374,10 +380,16 @@ demag_status demag_batch_apply(demag_ctx *ctx, demag_batch *b, const void *m, vo
   return DEMAG_OK;
 }
 
-// Autotuner: for every (axis length, outputs) class of the batch, time the
-// per-state stage kernel of a representative state with each RB candidate
-// and keep the fastest; then rebuild the item lists.  If path is non-NULL the
-// table is merged into a JSON object {"fp32/n96/nout2": 8, ...} at path.
+// Autotuner: the row-block shape RB of every item is default_rb(n) shifted
+// by one of {-1, 0, +1} powers of two per axis-length bucket (n <= 32,
+// n <= 96, larger).  Starting from no shift, each bucket's two alternatives
+// are timed in place (the whole batch apply, `reps` repetitions after a
+// warm-up, on scratch fields), keeping a shift when it is faster.  Timing
+// the persistent launch itself matters: a stage launched alone for one
+// state prefers small tiles for parallelism that the batch already has.
+// The resulting table {"fp32/n96/nout2": 8, ...} is merged into the JSON
+// object at path; when the file already holds every class of the batch, it
+// is used without timing.
 demag_status demag_batch_tune(demag_ctx *ctx, demag_batch *b, const char *path, int32_t reps) {
   DEMAG_REQUIRE(ctx && b, "demag_batch_tune: NULL argument");
   DEMAG_REQUIRE(reps >= 1 && reps <= 100, "demag_batch_tune: reps must be in [1, 100]");
@@ -399,85 +411,94 @@ demag_status demag_batch_tune(demag_ctx *ctx, demag_batch *b, const char *path, 
       if (pos == std::string::npos) break;
     }
   }
-  // distinct (n, nout) classes with a representative state and stage
-  struct Cls {
-    int n, nout, state, stage;
-  };
-  std::vector<Cls> classes;
+  // axis lengths of the batch
+  std::vector<int> lens;
   for (int s = 0; s < b->count; ++s)
-    for (int st = 0; st < 3; ++st)
-      for (int nout = 1; nout <= 2; ++nout) {
-        if (st == 0 && nout == 1) continue;
-        const int n = b->factors[s]->n[2 - st];
-        bool seen = false;
-        for (auto &c : classes) seen |= (c.n == n && c.nout == nout);
-        if (!seen) classes.push_back({n, nout, s, st});
-      }
-  hipEvent_t e0, e1;
-  DEMAG_TRY_HIP(hipEventCreate(&e0));
-  DEMAG_TRY_HIP(hipEventCreate(&e1));
+    for (int d = 0; d < 3; ++d)
+      if (std::find(lens.begin(), lens.end(), b->factors[s]->n[d]) == lens.end()) lens.push_back(b->factors[s]->n[d]);
+  bool cached = true;
+  for (int n : lens)
+    for (int nout = 1; nout <= 2; ++nout) cached = cached && cache.count(tune_key(b->prec, n, nout));
+  auto bucket = [](int n) { return n <= 32 ? 0 : n <= 96 ? 1 : 2; };
+  auto shifted = [](int n, int sh) {
+    int rb = default_rb(n);
+    for (; sh > 0 && rb < 8; --sh) rb *= 2;
+    for (; sh < 0 && rb > 1; ++sh) rb /= 2;
+    return rb;
+  };
+  auto apply = [&](const int sh[3]) -> demag_status {
+    b->rb_choice.clear();
+    for (int n : lens)
+      for (int nout = 1; nout <= 2; ++nout) b->rb_choice[{n, nout}] = shifted(n, sh[bucket(n)]);
+    release_tables(b);
+    return build(ctx, b);
+  };
+  if (cached) {
+    b->rb_choice.clear();
+    for (int n : lens)
+      for (int nout = 1; nout <= 2; ++nout) b->rb_choice[{n, nout}] = cache[tune_key(b->prec, n, nout)];
+    release_tables(b);
+    return build(ctx, b);
+  }
+  // scratch fields (inputs zero: the work does not depend on the values)
+  const size_t esize = (b->prec == DEMAG_FP64) ? 8 : 4;
+  const size_t ncell = size_t(b->off.back());
+  void *fields = nullptr;
+  DEMAG_TRY_HIP(hipMalloc(&fields, 7 * ncell * esize));
+  DEMAG_TRY_HIP(hipMemsetAsync(fields, 0, 7 * ncell * esize, ctx->stream));
+  char *fb = static_cast<char *>(fields);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  demag_status st = DEMAG_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    set_error("demag_batch_tune: event creation failed");
+    st = DEMAG_E_HIP;
+  }
   const bool prof = ctx->profiling;
   ctx->profiling = false;
-  for (auto &c : classes) {
-    const std::string key = tune_key(b->prec, c.n, c.nout);
-    if (cache.count(key)) {
-      b->rb_choice[{c.n, c.nout}] = cache[key];
-      continue;
-    }
-    // a per-state plan of the representative state, timed on a one-node chunk
-    demag_factors *f = b->factors[c.state];
-    std::vector<StagePlan> stages;
-    build_chunk_plan(f, 0, 1, f->L, stages);
-    // stage index in build order: 0 z/nout2, 1 y/nout2, 2 y/nout1, 3 x/nout2, 4 x/nout1
-    const int which = c.stage == 0 ? 0 : c.stage == 1 ? (c.nout == 2 ? 1 : 2) : (c.nout == 2 ? 3 : 4);
-    StagePlan &sp = stages[which];
-    DEMAG_TRY_HIP(hipMalloc(&sp.d_jobs, sizeof(MPJob) * sp.jobs.size()));
-    DEMAG_TRY_HIP(hipMemcpy(sp.d_jobs, sp.jobs.data(), sizeof(MPJob) * sp.jobs.size(), hipMemcpyHostToDevice));
-    DEMAG_TRY_HIP(hipMalloc(&sp.d_terms, sizeof(MPTerm) * sp.terms.size()));
-    DEMAG_TRY_HIP(hipMemcpy(sp.d_terms, sp.terms.data(), sizeof(MPTerm) * sp.terms.size(), hipMemcpyHostToDevice));
-    const int64_t N = int64_t(f->n[0]) * f->n[1] * f->n[2];
-    const size_t esize = (b->prec == DEMAG_FP64) ? 8 : 4;
-    void *scratch = nullptr;
-    DEMAG_TRY_HIP(hipMalloc(&scratch, size_t(12 + 7) * N * esize));
-    DEMAG_TRY_HIP(hipMemsetAsync(scratch, 0, size_t(12 + 7) * N * esize, ctx->stream));
-    char *sc = static_cast<char *>(scratch);
-    void *bufs[6] = {sc + 12 * N * esize, sc, sc + 6 * N * esize, sc + 15 * N * esize, sc + 16 * N * esize, nullptr};
-    float best = 1e30f;
-    int best_rb = default_rb(c.n);
-    for (int rb : {1, 2, 4, 8}) {
-      if (16 * rb > 2 * std::max(16, c.n) + 16) continue;   // mostly idle rows
-      sp.rb = rb;
-      demag_status st = launch_left_stage(ctx, f, b->prec, sp, bufs, 0);   // warm-up
-      if (st != DEMAG_OK) return st;
-      DEMAG_TRY_HIP(hipEventRecord(e0, ctx->stream));
-      for (int r = 0; r < reps; ++r) {
-        st = launch_left_stage(ctx, f, b->prec, sp, bufs, 0);
-        if (st != DEMAG_OK) return st;
-      }
-      DEMAG_TRY_HIP(hipEventRecord(e1, ctx->stream));
-      DEMAG_TRY_HIP(hipEventSynchronize(e1));
+  auto time_apply = [&](float &ms) -> demag_status {
+    demag_status s2 = enqueue(ctx, b, fb, fb + 3 * ncell * esize, fb + 4 * ncell * esize);   // warm-up
+    if (s2 != DEMAG_OK) return s2;
+    DEMAG_TRY_HIP(hipEventRecord(e0, ctx->stream));
+    for (int r = 0; r < reps && s2 == DEMAG_OK; ++r)
+      s2 = enqueue(ctx, b, fb, fb + 3 * ncell * esize, fb + 4 * ncell * esize);
+    if (s2 != DEMAG_OK) return s2;
+    DEMAG_TRY_HIP(hipEventRecord(e1, ctx->stream));
+    DEMAG_TRY_HIP(hipEventSynchronize(e1));
+    DEMAG_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+    ms /= reps;
+    return DEMAG_OK;
+  };
+  int best[3] = {0, 0, 0};
+  float best_ms = 0;
+  if (st == DEMAG_OK) st = apply(best);
+  if (st == DEMAG_OK) st = time_apply(best_ms);
+  for (int bk = 0; bk < 3 && st == DEMAG_OK; ++bk) {
+    bool present = false;
+    for (int n : lens) present |= (bucket(n) == bk);
+    if (!present) continue;
+    for (int sh : {-1, 1}) {
+      int trial[3] = {best[0], best[1], best[2]};
+      trial[bk] = sh;
       float ms = 0;
-      DEMAG_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best) {
-        best = ms;
-        best_rb = rb;
+      st = apply(trial);
+      if (st == DEMAG_OK) st = time_apply(ms);
+      if (st != DEMAG_OK) break;
+      if (ms < best_ms) {
+        best_ms = ms;
+        best[bk] = sh;
       }
     }
-    (void)hipFree(scratch);
-    (void)hipFree(sp.d_jobs);
-    (void)hipFree(sp.d_terms);
-    sp.d_jobs = nullptr;
-    sp.d_terms = nullptr;
-    for (auto &other : stages) {
-      other.d_jobs = nullptr;
-      other.d_terms = nullptr;
-    }
-    b->rb_choice[{c.n, c.nout}] = best_rb;
-    cache[key] = best_rb;
   }
   ctx->profiling = prof;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(ctx->stream);
+  (void)hipFree(fields);
+  if (st != DEMAG_OK) return st;
+  st = apply(best);
+  if (st != DEMAG_OK) return st;
+  for (int n : lens)
+    for (int nout = 1; nout <= 2; ++nout) cache[tune_key(b->prec, n, nout)] = shifted(n, best[bucket(n)]);
   if (path) {
     std::ofstream outf(path);
     outf << "{";
@@ -488,8 +509,7 @@ demag_status demag_batch_tune(demag_ctx *ctx, demag_batch *b, const char *path, 
     }
     outf << "}\n";
   }
-  release_tables(b);
-  return build(ctx, b);
+  return DEMAG_OK;
 }
 
 }  // extern "C"

@@ -170,7 +170,8 @@ int items_blocks_per_cu(bool fp64, size_t lds);
 void build_chunk_plan(const demag_factors *f, int k0, int kc, double phi_scale, std::vector<StagePlan> &stages);
 demag_status launch_items(demag_ctx *ctx, demag_prec prec, const BatchItem *items, int nitems, int grid,
                           const MPJob *jobs, const MPTerm *terms, const MPGeom *geoms, void *const bufp[6],
-                          const void *gens, int nmax, int beta);
+                          const void *gens, int nmax, int beta, int *counter);
+demag_status launch_reset_counters(demag_ctx *ctx, int *counters, int count);
 demag_status launch_build_windows(demag_ctx *ctx, demag_factors *f);
 demag_status launch_left_stage_bf16(demag_ctx *ctx, const demag_factors *f, demag_prec prec,
                                     const StagePlan &sp, void *const bufs[6], int beta);

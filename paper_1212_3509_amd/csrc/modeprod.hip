@@ -275,17 +275,26 @@ __global__ __launch_bounds__(256, 2) void k_left(const MPJob *__restrict__ jobs,
                          reinterpret_cast<T *>(smem_raw));
 }
 
-// Persistent variant: workgroup w processes items w, w + G, w + 2G, ...
-// (static order, no atomics); each item names its job, geometry, tile and
-// the (RB, NOUT) shape chosen for it.
+// Persistent variant: workgroups take items from a counter (one atomic add
+// per item, so the cost-sorted list is spread greedily over the chip); each
+// item names its job, geometry, tile and the (RB, NOUT) shape chosen for it.
+// Items write disjoint output tiles, so the result does not depend on which
+// workgroup takes which item.  The counter starts at 0 (k_reset_counters)
+// and every workgroup leaves once it draws an index past the list.
 template <class T>
 __global__ __launch_bounds__(256, 2) void k_left_items(const BatchItem *__restrict__ items, int nitems,
                                                     const MPJob *__restrict__ jobs, const MPTerm *__restrict__ terms,
                                                     const MPGeom *__restrict__ geoms, Bufs bufs,
-                                                    const T *__restrict__ gens, int beta) {
+                                                    const T *__restrict__ gens, int beta, int *counter) {
   extern __shared__ unsigned char smem_raw[];
+  __shared__ int next_item;
   T *sg = reinterpret_cast<T *>(smem_raw);
-  for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+  for (;;) {
+    if (threadIdx.x == 0) next_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = next_item;
+    __syncthreads();   // every thread has read next_item before it is drawn again
+    if (it >= nitems) break;
     const BatchItem item = items[it];
     const MPJob job = jobs[item.job];
     const MPGeom g = geoms[item.geom];
@@ -372,9 +381,21 @@ int items_blocks_per_cu(bool fp64, size_t lds) {
   return (e == hipSuccess && n > 0) ? n : 1;
 }
 
+__global__ void k_reset_counters(int *c, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) c[i] = 0;
+}
+
+demag_status launch_reset_counters(demag_ctx *ctx, int *counters, int count) {
+  if (count <= 0) return DEMAG_OK;
+  k_reset_counters<<<(count + 255) / 256, 256, 0, ctx->stream>>>(counters, count);
+  DEMAG_TRY_HIP(hipGetLastError());
+  return DEMAG_OK;
+}
+
 demag_status launch_items(demag_ctx *ctx, demag_prec prec, const BatchItem *items, int nitems, int grid,
                           const MPJob *jobs, const MPTerm *terms, const MPGeom *geoms, void *const bufp[6],
-                          const void *gens, int nmax, int beta) {
+                          const void *gens, int nmax, int beta, int *counter) {
   if (nitems == 0) return DEMAG_OK;
   Bufs bufs;
   for (int i = 0; i < 6; ++i) bufs.p[i] = bufp[i];
@@ -384,13 +405,13 @@ demag_status launch_items(demag_ctx *ctx, demag_prec prec, const BatchItem *item
       DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_left_items<double>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     k_left_items<double><<<grid, 256, lds, ctx->stream>>>(items, nitems, jobs, terms, geoms, bufs,
-                                                           static_cast<const double *>(gens), beta);
+                                                           static_cast<const double *>(gens), beta, counter);
   } else {
     if (lds > 65536)
       DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_left_items<float>),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     k_left_items<float><<<grid, 256, lds, ctx->stream>>>(items, nitems, jobs, terms, geoms, bufs,
-                                                          static_cast<const float *>(gens), beta);
+                                                          static_cast<const float *>(gens), beta, counter);
   }
   DEMAG_TRY_HIP(hipGetLastError());
   return DEMAG_OK;
