@@ -132,6 +132,17 @@ demag_status demag_factors_nodes(const demag_factors *f, double *t, double *tau,
 demag_status demag_factors_download(demag_ctx *ctx, const demag_factors *f, int32_t d,
                                     double *dst);
 
+/* Full-format apply of the same separable operator by 3D FFT convolution
+ * (Sec. 4.2's route for unstructured tensors): the kernel's 3D spectrum is
+ * the sum over nodes of products of the 1D factor spectra (formed once per
+ * factor set, 9 x Lz x Ly x (Lx/2+1) FP64 values, L_d = 2^p >= 2 n_d - 1);
+ * each apply runs forward real/complex FFTs of m, the pointwise products and
+ * the inverse FFTs, all FP64.  m: device [3][nz][ny][nx] FP64; phi: device
+ * [nz][ny][nx]; h: device [3][nz][ny][nx] (FP64, non-overlapping).  Uses the
+ * context workspace (4 x Lz x Ly x (Lx/2+1) complex values).  n <= 1024 per
+ * axis, else DEMAG_E_INVAL. */
+demag_status demag_apply_fft(demag_ctx *ctx, demag_factors *f, const double *m, double *phi, double *h);
+
 /* Full-format apply, path (a): for every node, the 23 mode products of
  * Eq. (modemul) (6 along z, 9 along y, 8 along x, sharing partial products
  * between outputs), accumulated over nodes into

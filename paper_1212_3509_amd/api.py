@@ -49,6 +49,7 @@ _SIGS = {
     "demag_factors_nodes": (C.c_int, [_P, _P, _P, _P]),
     "demag_factors_download": (C.c_int, [_P, _P, C.c_int32, _P]),
     "demag_apply_full": (C.c_int, [_P, _P, C.c_int, _P, _P, _P]),
+    "demag_apply_fft": (C.c_int, [_P, _P, _P, _P, _P]),
     "demag_batch_create": (C.c_int, [_P, C.c_int32, _P, C.POINTER(Quad), C.c_int, C.POINTER(_P)]),
     "demag_batch_free": (C.c_int, [_P]),
     "demag_batch_offsets": (C.c_int, [_P, _P]),
@@ -244,6 +245,20 @@ class Context:
         self.use_current_stream()
         _check(library().demag_apply_full(self.handle, f.handle, PRECISIONS[prec], _ptr(m), _ptr(phi), _ptr(h)),
                "demag_apply_full")
+        return phi, h
+
+    def apply_fft(self, f: Factors, m, phi=None, h=None):
+        """Same operator as apply_full, by 3D FFT convolution (FP64 only)."""
+        import torch
+        nx, ny, nz = f.n
+        if m.dtype != torch.float64 or not m.is_cuda or not m.is_contiguous() or tuple(m.shape) != (3, nz, ny, nx):
+            raise ValueError(f"m must be a contiguous float64 CUDA tensor of shape {(3, nz, ny, nx)}")
+        if phi is None:
+            phi = torch.empty((nz, ny, nx), dtype=torch.float64, device=m.device)
+        if h is None:
+            h = torch.empty((3, nz, ny, nx), dtype=torch.float64, device=m.device)
+        self.use_current_stream()
+        _check(library().demag_apply_fft(self.handle, f.handle, _ptr(m), _ptr(phi), _ptr(h)), "demag_apply_fft")
         return phi, h
 
     def batch(self, grids, M: int = 40, c0: float = 2.15, step_rule: int = 0, prec: str = "fp32") -> Batch:

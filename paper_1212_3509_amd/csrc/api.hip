@@ -574,6 +574,7 @@ demag_status demag_factors_free(demag_factors *f) {
     if (f->spec[d]) (void)hipFree(f->spec[d]);
     if (f->twiddle[d]) (void)hipFree(f->twiddle[d]);
   }
+  if (f->k3) (void)hipFree(f->k3);
   delete f;
   return DEMAG_OK;
 }
@@ -634,6 +635,18 @@ demag_status demag_apply_full(demag_ctx *ctx, const demag_factors *fc, demag_pre
     }
   }
   return DEMAG_OK;
+}
+
+demag_status demag_apply_fft(demag_ctx *ctx, demag_factors *f, const double *m, double *phi, double *h) {
+  DEMAG_REQUIRE(ctx && f && m && phi && h, "demag_apply_fft: NULL argument");
+  for (int d = 0; d < 3; ++d)
+    DEMAG_REQUIRE(f->n[d] <= 1024, "demag_apply_fft: n <= 1024 per axis");
+  DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  demag_status st = prepare_fft3d(ctx, f);
+  if (st != DEMAG_OK) return st;
+  st = ensure_workspace(ctx, fft3d_workspace_bytes(f));
+  if (st != DEMAG_OK) return st;
+  return launch_fft3d(ctx, f, m, phi, h, ctx->ws);
 }
 
 }  // extern "C"

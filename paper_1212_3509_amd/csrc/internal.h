@@ -151,6 +151,7 @@ struct demag_factors {
   bool spec_ready = false;
   double *spec[3] = {nullptr, nullptr, nullptr};   // [4][M][L/2+1] real or imaginary parts (structured path)
   void *twiddle[3] = {nullptr, nullptr, nullptr};  // double2 [L/2]
+  double *k3 = nullptr;    // 3D kernel spectra [9][Lz][Ly][Lx/2+1] (FFT apply)
   std::map<std::pair<int, int>, std::unique_ptr<demag::FullPlan>> plans;  // (prec class, kc)
 };
 
@@ -179,5 +180,9 @@ demag_status launch_split(demag_ctx *ctx, const float *x, uint16_t *parts, size_
 int fft_length(int n);
 demag_status prepare_spectra(demag_ctx *ctx, demag_factors *f);
 demag_status ensure_workspace(demag_ctx *ctx, size_t bytes);
+demag_status prepare_fft3d(demag_ctx *ctx, demag_factors *f);
+size_t fft3d_workspace_bytes(const demag_factors *f);
+demag_status launch_fft3d(demag_ctx *ctx, const demag_factors *f, const double *m, double *phi, double *h,
+                          void *ws);
 demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, int d, int R, const float *in, float *out);
 } // namespace demag
