@@ -9,16 +9,19 @@
 // G_z(fz), with G the 1D spectra of the structured path (real for E and P,
 // imaginary for X and Q).  With one odd factor (potential kernels) the 3D
 // spectrum is imaginary, with none (F_pp) real, with two (F_pq) real and
-// negated; it is stored as one real array per component.
+// negated; it is stored as one real array per component, and since each 1D
+// spectrum is even or odd in f, only the octant fy <= Ly/2, fz <= Lz/2.
 //
 // Layout of a spectrum: [fz < Lz][fy < Ly][fx <= Lx/2] complex FP64 (real
-// transform along x).  Passes, all FP64 in LDS (Stockham radix 16/8/4/2,
-// several lines per workgroup, 4096 points at most per workgroup):
+// transform along x), rows padded to a multiple of 8 points (128 B).
+// Passes, all FP64 in LDS (Stockham radix 16/8/4/2, several lines per
+// workgroup):
 //   x: real rows (z < nz, y < ny) -> half spectra;  y: lines along y for
-//   z < nz (rows y >= ny are zero, not read);  z: lines along z for all
-//   (fy, fx) (planes z >= nz are zero, not read);  pointwise products with
-//   the nine kernel spectra; then the inverse passes, each storing only the
-//   part of the next input that is needed (z < nz, then y < ny, then x < nx).
+//   z < nz (rows y >= ny are zero, not read);  z, fused with the products:
+//   per column group, forward transforms of the three magnetization spectra
+//   (planes z >= nz zero, not read), pointwise products with the kernel
+//   spectra, inverse transforms of the four outputs, stored for z < nz; then
+//   the inverse y pass (stores y < ny) and the inverse real x pass (x < nx).
 #include "internal.h"
 
 #include <cmath>
@@ -26,9 +29,6 @@
 namespace demag {
 
 namespace {
-
-constexpr int kT = 256;          // threads per workgroup
-constexpr int kPts = 4096;       // points per workgroup
 
 struct alignas(16) cplx {
   double x, y;
@@ -44,12 +44,15 @@ template <bool INV> __device__ inline cplx mul_mi(cplx a) { return INV ? cplx{-a
 // accesses within a line and accesses across lines (the transposed global
 // loads of the strided passes) both spread over the banks.
 __device__ inline int pd(int i) { return i + (i >> 4); }
-__host__ __device__ inline int line_stride(int N) { return (N + (N - 1) / 16 + 1) | 1; }
-constexpr int kCap = kPts + kPts / 16 + 64;   // LDS points per workgroup
-// lines per workgroup for lines of N points
-__host__ __device__ inline int lines_per_wg(int N) {
-  int nl = kPts / N;
-  while (nl > 1 && nl * line_stride(N) > kCap) nl /= 2;
+__host__ __device__ constexpr int line_stride(int N) { return (N + (N - 1) / 16 + 1) | 1; }
+__host__ __device__ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+// LDS points of a workgroup of shape <KT threads, KP points> (KP / KT = 16:
+// one radix-16 butterfly per thread and pass)
+__host__ __device__ constexpr int cap(int KP) { return KP + KP / 16 + 64; }
+// lines of N points (N <= KP) per workgroup
+__host__ __device__ inline int lines_per_wg(int N, int KP) {
+  int nl = KP / N;
+  while (nl > 1 && nl * line_stride(N) > cap(KP)) nl /= 2;
   return nl;
 }
 
@@ -119,45 +122,44 @@ __device__ inline cplx twid(int e, const cplx *lo, const cplx *hi) {
   return (e >> 6) ? cmul(a, hi[e >> 6]) : a;
 }
 __device__ inline void make_twiddles(cplx *lo, cplx *hi, int N) {
-  const int t = threadIdx.x;
-  double s, c;
-  if (t < 64) {
-    sincospi(-2.0 * double(t) / double(N), &s, &c);
-    lo[t] = cplx{c, s};
-  } else if (t < 128) {
-    sincospi(-2.0 * double(64 * (t - 64)) / double(N), &s, &c);
-    hi[t - 64] = cplx{c, s};
+  for (int t = threadIdx.x; t < 128; t += blockDim.x) {
+    double s, c;
+    sincospi(-2.0 * double(t < 64 ? t : 64 * (t - 64)) / double(N), &s, &c);
+    (t < 64 ? lo[t] : hi[t - 64]) = cplx{c, s};
   }
 }
 
-// One Stockham pass of radix R over nl lines of N points.  Butterfly g:
-// line g % nl, index g / nl (lines fastest across threads).
-template <bool INV, int R>
-__device__ inline void pass(cplx *buf, int N, int nl, int LS, int Ns, const cplx *tlo, const cplx *thi) {
-  const int per = N / R;                 // butterflies per line
-  const int nb = nl * per;
-  constexpr int kMaxB = (kPts / R + kT - 1) / kT;
+// One Stockham pass of radix R over narr arrays of nl = 2^lnl lines of N
+// points (array a, line b at LDS line a * nl + b; input sub-transform length
+// Ns).  Butterfly g: array g / (nl N / R), then line fastest across threads.
+// The first pass (Ns = 1) has no twiddles.
+template <bool INV, int R, int KT, int KP, int N, int Ns>
+__device__ inline void pass(cplx *buf, int lnl, int narr, const cplx *tlo, const cplx *thi) {
+  constexpr int LS = line_stride(N);
+  constexpr int per = N / R;             // butterflies per line
+  constexpr int lper = ilog2(per);
+  constexpr int kMaxB = (KP / R + KT - 1) / KT;
+  const int nb = (narr * per) << lnl;
+  const int lmask = (1 << lnl) - 1, amask = (per << lnl) - 1;
   cplx v[kMaxB][R];
-  int jj[kMaxB];
 #pragma unroll
   for (int q = 0; q < kMaxB; ++q) {
-    const int g = threadIdx.x + q * kT;
-    jj[q] = g;
+    const int g = threadIdx.x + q * KT;
     if (g < nb) {
-      const int j = g / nl, line = g - j * nl;
-      cplx *lb = buf + line * LS;
-      const int k = j & (Ns - 1);
-      cplx w = twid((k * (N / (Ns * R))) & (N - 1), tlo, thi);
-      if (INV) w = cconj(w);
-      cplx wr = w;
+      const int ga = g & amask, j = ga >> lnl, line = ((g >> (lnl + lper)) << lnl) + (ga & lmask);
+      const cplx *lb = buf + line * LS;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        cplx x = lb[pd(j + r * per)];
-        if (r > 0) {
-          x = cmul(x, wr);
-          wr = cmul(wr, w);
+      for (int r = 0; r < R; ++r) v[q][r] = lb[pd(j + r * per)];
+      if constexpr (Ns > 1) {
+        const int k = j & (Ns - 1);
+        cplx w = twid(k * (N / (Ns * R)), tlo, thi);
+        if (INV) w = cconj(w);
+        cplx wr = w;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          v[q][r] = cmul(v[q][r], wr);
+          if (r + 1 < R) wr = cmul(wr, w);
         }
-        v[q][r] = x;
       }
       dftR<INV, R>(v[q]);
     }
@@ -165,9 +167,9 @@ __device__ inline void pass(cplx *buf, int N, int nl, int LS, int Ns, const cplx
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < kMaxB; ++q) {
-    const int g = jj[q];
+    const int g = threadIdx.x + q * KT;
     if (g < nb) {
-      const int j = g / nl, line = g - j * nl;
+      const int ga = g & amask, j = ga >> lnl, line = ((g >> (lnl + lper)) << lnl) + (ga & lmask);
       const int k = j & (Ns - 1);
       const int o = (j / Ns) * Ns * R + k;
       cplx *lb = buf + line * LS;
@@ -178,26 +180,30 @@ __device__ inline void pass(cplx *buf, int N, int nl, int LS, int Ns, const cplx
   __syncthreads();
 }
 
-// Complex FFTs of nl lines of N points (power of 2) in LDS.
-template <bool INV>
-__device__ void fft_lines(cplx *buf, int N, int nl, const cplx *tlo, const cplx *thi) {
-  const int LS = line_stride(N);
-  int Ns = 1;
-  while (Ns < N) {
-    const int left = N / Ns;
-    if (left >= 16) {
-      pass<INV, 16>(buf, N, nl, LS, Ns, tlo, thi);
-      Ns *= 16;
-    } else if (left == 8) {
-      pass<INV, 8>(buf, N, nl, LS, Ns, tlo, thi);
-      Ns *= 8;
-    } else if (left == 4) {
-      pass<INV, 4>(buf, N, nl, LS, Ns, tlo, thi);
-      Ns *= 4;
-    } else {
-      pass<INV, 2>(buf, N, nl, LS, Ns, tlo, thi);
-      Ns *= 2;
-    }
+// Complex FFTs of narr arrays of nl = 2^lnl lines of N points (power of 2, N <= 2048) in
+// LDS: a fixed pass plan per length (radix 16 first), each pass inlined with
+// its sizes known at compile time, so that the register allocation and the
+// index arithmetic are per pass.
+template <bool INV, int KT, int KP, int N, int Ns, int R0, int... Rs>
+__device__ inline void run_passes(cplx *buf, int lnl, int narr, const cplx *tlo, const cplx *thi) {
+  pass<INV, R0, KT, KP, N, Ns>(buf, lnl, narr, tlo, thi);
+  if constexpr (sizeof...(Rs) > 0) run_passes<INV, KT, KP, N, Ns * R0, Rs...>(buf, lnl, narr, tlo, thi);
+}
+template <bool INV, int KT, int KP>
+__device__ void fft_lines(cplx *buf, int N, int lnl, int narr, const cplx *tlo, const cplx *thi) {
+  switch (N) {
+    case 2: run_passes<INV, KT, KP, 2, 1, 2>(buf, lnl, narr, tlo, thi); break;
+    case 4: run_passes<INV, KT, KP, 4, 1, 4>(buf, lnl, narr, tlo, thi); break;
+    case 8: run_passes<INV, KT, KP, 8, 1, 8>(buf, lnl, narr, tlo, thi); break;
+    case 16: run_passes<INV, KT, KP, 16, 1, 16>(buf, lnl, narr, tlo, thi); break;
+    case 32: run_passes<INV, KT, KP, 32, 1, 16, 2>(buf, lnl, narr, tlo, thi); break;
+    case 64: run_passes<INV, KT, KP, 64, 1, 16, 4>(buf, lnl, narr, tlo, thi); break;
+    case 128: run_passes<INV, KT, KP, 128, 1, 16, 8>(buf, lnl, narr, tlo, thi); break;
+    case 256: run_passes<INV, KT, KP, 256, 1, 16, 16>(buf, lnl, narr, tlo, thi); break;
+    case 512: run_passes<INV, KT, KP, 512, 1, 16, 16, 2>(buf, lnl, narr, tlo, thi); break;
+    case 1024: run_passes<INV, KT, KP, 1024, 1, 16, 16, 4>(buf, lnl, narr, tlo, thi); break;
+    case 2048: run_passes<INV, KT, KP, 2048, 1, 16, 16, 8>(buf, lnl, narr, tlo, thi); break;
+    default: break;   // N = 1: identity
   }
 }
 
@@ -209,22 +215,34 @@ __device__ inline cplx wl(int f, int N, const cplx *tlo, const cplx *thi, cplx w
 }
 
 // ---------------------------------------------------------------- x pass
+// Work index of a workgroup: the hardware places workgroup lin on XCD
+// lin % 8; this gives the workgroups of one XCD consecutive work indices, so
+// that neighbouring column tiles (which share cache lines) meet in one L2.
+__device__ inline unsigned xcd_work_index(unsigned lin, unsigned total) {
+  const unsigned x = lin & 7u, slot = lin >> 3;
+  const unsigned per = total >> 3, rem = total & 7u;
+  return x * per + min(x, rem) + slot;
+}
+
 // Real rows r = z * ny + y (z < nz, y < ny) of in[3][nz][ny][nx] (component
-// c = blockIdx.y) -> S_c[z][y][0..Lx/2].  nl rows per workgroup.
-__global__ __launch_bounds__(kT) void k_x_fwd(const double *__restrict__ in, cplx *__restrict__ S, int nx, int ny,
-                                              int nz, int Lx, int Ly, int Lz, int nl) {
+// c = blockIdx.y) -> S_c[z][y][0..Lx/2] (row pitch P).  2^lnl rows per
+// workgroup.
+template <int KT, int KP>
+__global__ __launch_bounds__(KT) void k_x_fwd(const double *__restrict__ in, cplx *__restrict__ S, size_t astride,
+                                              int nx, int ny, int nz, int Lx, int Ly, int P, int lnl) {
   extern __shared__ cplx sm[];
-  cplx *buf = sm, *tlo = sm + kCap, *thi = tlo + 64;
-  const int N = Lx / 2, H = N + 1;
+  cplx *buf = sm, *tlo = sm + cap(KP), *thi = tlo + 64;
+  const int N = Lx / 2, H = N + 1, lN = __builtin_ctz(N);
+  const int nl = 1 << lnl;
   const int comp = blockIdx.y;
   const int rows = ny * nz;
-  const int r0 = blockIdx.x * nl;
+  const int r0 = blockIdx.x << lnl;
   const int nr = min(nl, rows - r0);
   make_twiddles(tlo, thi, N);
   const double *src = in + size_t(comp) * nx * ny * nz;
   const int LS = line_stride(N);
-  for (int i = threadIdx.x; i < nl * N; i += kT) {
-    const int line = i / N, m = i - line * N;
+  for (int i = threadIdx.x; i < nl * N; i += KT) {
+    const int line = i >> lN, m = i & (N - 1);
     cplx v{0.0, 0.0};
     if (line < nr) {
       const double *row = src + size_t(r0 + line) * nx;
@@ -234,67 +252,69 @@ __global__ __launch_bounds__(kT) void k_x_fwd(const double *__restrict__ in, cpl
     buf[line * LS + pd(m)] = v;
   }
   __syncthreads();
-  fft_lines<false>(buf, N, nl, tlo, thi);
+  fft_lines<false, KT, KP>(buf, N, lnl, 1, tlo, thi);
   double sw, cw;
   sincospi(-1.0 / double(N), &sw, &cw);
   const cplx w1{cw, sw};
-  cplx *dst = S + size_t(comp) * Lz * Ly * H;
-  for (int i = threadIdx.x; i < nl * H; i += kT) {
-    const int line = i / H, f = i - line * H;
+  cplx *dst = S + size_t(comp) * astride;
+  // X[f] = (Z[f] + conj Z[N-f]) / 2 - i W_L^f (Z[f] - conj Z[N-f]) / 2 for
+  // f < N; the thread of f = 0 also writes f = N (same two points, W_L^N = -1)
+  for (int i = threadIdx.x; i < nl * N; i += KT) {
+    const int line = i >> lN, f = i & (N - 1);
     if (line >= nr) continue;
     const int r = r0 + line, z = r / ny, y = r - z * ny;
-    const cplx zf = buf[line * LS + pd(f & (N - 1))];
+    cplx *drow = dst + (size_t(z) * Ly + y) * P;
+    const cplx zf = buf[line * LS + pd(f)];
     const cplx zcc = cconj(buf[line * LS + pd((N - f) & (N - 1))]);
+    const cplx Sm{0.5 * (zf.x + zcc.x), 0.5 * (zf.y + zcc.y)};
     const cplx D{0.5 * (zf.x - zcc.x), 0.5 * (zf.y - zcc.y)};
-    dst[(size_t(z) * Ly + y) * H + f] =
-        cadd(cplx{0.5 * (zf.x + zcc.x), 0.5 * (zf.y + zcc.y)}, cmul(wl(f, N, tlo, thi, w1), cplx{D.y, -D.x}));
+    drow[f] = cadd(Sm, cmul(wl(f, N, tlo, thi, w1), cplx{D.y, -D.x}));
+    if (f == 0) drow[N] = cplx{Sm.x - D.y, Sm.y + D.x};
   }
 }
 
-// ---------------------------------------------------------------- y, z passes
-// Complex FFTs of length N along a strided axis, in place: workgroup
-// (blockIdx.x = fx tile, blockIdx.y = outer index o, blockIdx.z = array)
-// handles nl lines fx = fx0 .. fx0 + nl - 1 of elements
-//   A[arr][o * so + i * si + fx],  i < N,
+// ---------------------------------------------------------------- y pass
+// Complex FFTs of length N along y, in place, for the planes z < nz: the
+// workgroup with work index w (XCD-grouped) handles array w / (tiles nz),
+// plane z, and the 2^lnl lines fx = fx0 .. (fx < H) of elements
+//   A[arr][(z Ly + i) P + fx],  i < N,
 // reading only i < nin (the rest is zero) and writing only i < nout.
-template <bool INV>
-__global__ __launch_bounds__(kT) void k_lines(cplx *__restrict__ A, size_t arr_stride, int N, int H, size_t so,
-                                              size_t si, int nin, int nout, int nl) {
+template <bool INV, int KT, int KP>
+__global__ __launch_bounds__(KT) void k_lines(cplx *__restrict__ A, size_t astride, int N, int H, int P, int nz,
+                                              int nin, int nout, int lnl) {
   extern __shared__ cplx sm[];
-  cplx *buf = sm, *tlo = sm + kCap, *thi = tlo + 64;
-  const int fx0 = blockIdx.x * nl;
+  cplx *buf = sm, *tlo = sm + cap(KP), *thi = tlo + 64;
+  const int nl = 1 << lnl;
+  const int tiles = (H + nl - 1) >> lnl;
+  const unsigned w = xcd_work_index(blockIdx.x, gridDim.x);
+  const int tile = int(w % unsigned(tiles)), rest = int(w / unsigned(tiles));
+  const int z = rest % nz, arr = rest / nz;
+  const int fx0 = tile << lnl;
   const int nf = min(nl, H - fx0);
-  cplx *base = A + size_t(blockIdx.z) * arr_stride + size_t(blockIdx.y) * so + fx0;
+  cplx *base = A + size_t(arr) * astride + size_t(z) * N * P + fx0;
   make_twiddles(tlo, thi, N);
   // global accesses run along fx (coalesced); line stride LS is odd
   const int LS = line_stride(N);
-  for (int e = threadIdx.x; e < nl * N; e += kT) {
-    const int i = e / nl, b = e - i * nl;
+  for (int e = threadIdx.x; e < nl * N; e += KT) {
+    const int i = e >> lnl, b = e & (nl - 1);
     cplx v{0.0, 0.0};
-    if (i < nin && b < nf) v = base[size_t(i) * si + b];
+    if (i < nin && b < nf) v = base[size_t(i) * P + b];
     buf[b * LS + pd(i)] = v;
   }
   __syncthreads();
-  fft_lines<INV>(buf, N, nl, tlo, thi);
-  for (int e = threadIdx.x; e < nl * nout; e += kT) {
-    const int i = e / nl, b = e - i * nl;
-    if (b < nf) base[size_t(i) * si + b] = buf[b * LS + pd(i)];
+  fft_lines<INV, KT, KP>(buf, N, lnl, 1, tlo, thi);
+  for (int e = threadIdx.x; e < nl * nout; e += KT) {
+    const int i = e >> lnl, b = e & (nl - 1);
+    if (b < nf) base[size_t(i) * P + b] = buf[b * LS + pd(i)];
   }
 }
 
 // ---------------------------------------------------------------- kernel spectra
-// Kspec[c][fz][fy][fx] (real; component c: 0..2 potential K^q, 3..8 field
-// (0,0) (1,1) (2,2) (0,1) (0,2) (1,2)) = sign_c * sum_k s_x(fx) s_y(fy) s_z(fz),
-// s the stored 1D spectra ([type][M][L/2+1], the imaginary part for odd
-// types; s(L - f) = s(f) for even, -s(f) for odd types).
-__device__ inline double spec1(const double *sp, int type, int k, int M, int L, int f) {
-  const bool odd = (type == F_X || type == F_Q);
-  const int h = L / 2;
-  const double *s = sp + size_t(type * M + k) * (h + 1);
-  if (f <= h) return s[f];
-  return odd ? -s[L - f] : s[L - f];
-}
-
+// 1D spectra s(f) of the factors ([type][M][L/2+1], the imaginary part for
+// odd types): s(L - f) = s(f) for even, -s(f) for odd types.  The 3D kernel
+// spectra inherit this per axis, so only the octant fy <= Ly/2, fz <= Lz/2 is
+// stored: Kspec[c][fz][fy][fx] (row pitch P; component c: 0..2 potential K^q,
+// 3..8 field (0,0) (1,1) (2,2) (0,1) (0,2) (1,2)) = sign_c sum_k s_x s_y s_z.
 __device__ inline void comp_types(int c, int t[3]) {
   // potential K^q: X along q, E elsewhere; field h_p <- m_q: differentiate along p
   const int p = c < 3 ? -1 : (c < 6 ? c - 3 : (c == 6 ? 0 : (c == 7 ? 0 : 1)));
@@ -302,94 +322,153 @@ __device__ inline void comp_types(int c, int t[3]) {
   for (int d = 0; d < 3; ++d) t[d] = (d == q) ? F_X : F_E;
   if (p >= 0) t[p] = (t[p] == F_X) ? F_P : F_Q;
 }
+__host__ __device__ constexpr bool odd_type(int t) { return t == F_X || t == F_Q; }
 
 __global__ void k_kernel_spectra(const double *__restrict__ sx, const double *__restrict__ sy,
                                  const double *__restrict__ sz, double *__restrict__ K, int M, int Lx, int Ly,
-                                 int Lz) {
-  const int H = Lx / 2 + 1;
-  const size_t np = size_t(Lz) * Ly * H;
+                                 int Lz, int P) {
+  const int H = Lx / 2 + 1, hy = Ly / 2 + 1, hz = Lz / 2 + 1;
+  const size_t npk = size_t(hz) * hy * P;
   const size_t idx = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (idx >= np) return;
-  const int fx = int(idx % H);
-  const int fy = int((idx / H) % Ly);
-  const int fz = int(idx / (size_t(H) * Ly));
+  if (idx >= npk) return;
+  const int fx = int(idx % P);
+  const int fy = int((idx / P) % hy);
+  const int fz = int(idx / (size_t(P) * hy));
   double acc[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
-  for (int k = 0; k < M; ++k) {
-    double vx[4], vy[4], vz[4];
+  if (fx < H) {
+    for (int k = 0; k < M; ++k) {
+      double vx[4], vy[4], vz[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      vx[t] = spec1(sx, t, k, M, Lx, fx);
-      vy[t] = spec1(sy, t, k, M, Ly, fy);
-      vz[t] = spec1(sz, t, k, M, Lz, fz);
+      for (int t = 0; t < 4; ++t) {
+        vx[t] = sx[size_t(t * M + k) * H + fx];
+        vy[t] = sy[size_t(t * M + k) * hy + fy];
+        vz[t] = sz[size_t(t * M + k) * hz + fz];
+      }
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        int t[3];
+        comp_types(c, t);
+        acc[c] += vx[t[0]] * vy[t[1]] * vz[t[2]];
+      }
     }
+  }
+#pragma unroll
+  for (int c = 0; c < 9; ++c) K[size_t(c) * npk + idx] = (c >= 6) ? -acc[c] : acc[c];
+}
+
+// ---------------------------------------------------------------- z pass + products
+// For the columns (fx0 .. fx0 + nl - 1, fy), nl = 2^lnl: forward transforms
+// along z of m^_0..2 (planes z >= nz are zero), products with the kernel
+// spectra (phi^ = i sum_q K^q m^_q, h^_p = sum_q F_pq m^_q, scaled by
+// 1 / (Lx Ly Lz) and the length scale for phi), inverse transforms along z
+// of the four outputs, stored for z < nz only: S[0..2] <- h^, S[3] <- phi^.
+// LDS holds 4 nl lines: array a, column b at line a * nl + b.  Work order
+// (XCD-grouped): fy = 0, Ly/2, 1, Ly - 1, 2, Ly - 2, ..., fx tiles fastest,
+// so that fy and Ly - fy, which read the same kernel spectra, run together.
+template <int KT, int KP>
+__global__ __launch_bounds__(KT) void k_z_conv(cplx *__restrict__ S, size_t astride, const double *__restrict__ K,
+                                               int Lz, int nz, int Ly, int P, int H, int lnl, double scale,
+                                               double phi_scale) {
+  extern __shared__ cplx sm[];
+  cplx *buf = sm, *tlo = sm + cap(KP), *thi = tlo + 64;
+  const int nl = 1 << lnl;
+  const int tiles = (H + nl - 1) >> lnl;
+  const unsigned w = xcd_work_index(blockIdx.x, gridDim.x);
+  const int tile = int(w % unsigned(tiles)), q = int(w / unsigned(tiles));
+  const int fy = q == 0 ? 0 : (q == 1 ? Ly / 2 : ((q & 1) ? Ly - (q - 1) / 2 : q / 2));
+  const int fx0 = tile << lnl;
+  const int nf = min(nl, H - fx0);
+  make_twiddles(tlo, thi, Lz);
+  const int LS = line_stride(Lz);
+  const size_t col = size_t(fy) * P + fx0;      // offset of (z = 0, fy, fx0)
+  const size_t zs = size_t(Ly) * P;             // z stride
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    for (int e = threadIdx.x; e < nl * Lz; e += KT) {
+      const int i = e >> lnl, b = e & (nl - 1);
+      cplx v{0.0, 0.0};
+      if (i < nz && b < nf) v = S[size_t(a) * astride + i * zs + col + b];
+      buf[(a * nl + b) * LS + pd(i)] = v;
+    }
+  }
+  __syncthreads();
+  fft_lines<false, KT, KP>(buf, Lz, lnl, 3, tlo, thi);
+  // kernel spectra octant index and per-component signs for this fy
+  const int hy = Ly / 2 + 1, hz = Lz / 2 + 1;
+  const size_t npk = size_t(hz) * hy * P;
+  const bool fy_hi = fy >= hy;
+  const int fyk = fy_hi ? Ly - fy : fy;
+  const double ps = scale * phi_scale;
+  for (int e = threadIdx.x; e < nl * Lz; e += KT) {
+    const int i = e >> lnl, b = e & (nl - 1);
+    if (b >= nf) continue;
+    const bool fz_hi = i >= hz;
+    const int fzk = fz_hi ? Lz - i : i;
+    const double *kp = K + (size_t(fzk) * hy + fyk) * P + fx0 + b;
+    double kv[9];
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       int t[3];
       comp_types(c, t);
-      acc[c] += vx[t[0]] * vy[t[1]] * vz[t[2]];
+      const bool neg = (fy_hi && odd_type(t[1])) != (fz_hi && odd_type(t[2]));
+      const double k = kp[size_t(c) * npk];
+      kv[c] = neg ? -k : k;
+    }
+    const cplx m0 = buf[(0 * nl + b) * LS + pd(i)];
+    const cplx m1 = buf[(1 * nl + b) * LS + pd(i)];
+    const cplx m2 = buf[(2 * nl + b) * LS + pd(i)];
+    // potential: i (K^0 m0 + K^1 m1 + K^2 m2)
+    const double pr = kv[0] * m0.x + kv[1] * m1.x + kv[2] * m2.x;
+    const double pi = kv[0] * m0.y + kv[1] * m1.y + kv[2] * m2.y;
+    buf[(3 * nl + b) * LS + pd(i)] = cplx{-ps * pi, ps * pr};
+    // field: symmetric F with pairs 3..8 = (0,0) (1,1) (2,2) (0,1) (0,2) (1,2)
+    const double F[3][3] = {{kv[3], kv[6], kv[7]}, {kv[6], kv[4], kv[8]}, {kv[7], kv[8], kv[5]}};
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+      buf[(p * nl + b) * LS + pd(i)] = cplx{scale * (F[p][0] * m0.x + F[p][1] * m1.x + F[p][2] * m2.x),
+                                           scale * (F[p][0] * m0.y + F[p][1] * m1.y + F[p][2] * m2.y)};
+  }
+  __syncthreads();
+  fft_lines<true, KT, KP>(buf, Lz, lnl, 4, tlo, thi);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    for (int e = threadIdx.x; e < nl * nz; e += KT) {
+      const int i = e >> lnl, b = e & (nl - 1);
+      if (b < nf) S[size_t(a) * astride + i * zs + col + b] = buf[(a * nl + b) * LS + pd(i)];
     }
   }
-#pragma unroll
-  for (int c = 0; c < 9; ++c) K[size_t(c) * np + idx] = (c >= 6) ? -acc[c] : acc[c];
-}
-
-// ---------------------------------------------------------------- products
-// S[0..2] = m^ (x, y, z); writes phi^ to S[3] and h^_p to S[p] (in place),
-// scaled by 1/(Lx Ly Lz) (and the length scale for phi).  Potential kernels
-// are imaginary (times i), field kernels real.
-__global__ void k_products(cplx *__restrict__ S, const double *__restrict__ K, size_t np, double scale,
-                           double phi_scale) {
-  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i >= np) return;
-  const cplx m0 = S[i], m1 = S[np + i], m2 = S[2 * np + i];
-  const cplx mq[3] = {m0, m1, m2};
-  double kv[9];
-#pragma unroll
-  for (int c = 0; c < 9; ++c) kv[c] = K[size_t(c) * np + i];
-  // phi^ = i sum_q K^q m^_q
-  cplx ph{0.0, 0.0};
-#pragma unroll
-  for (int q = 0; q < 3; ++q) ph = cadd(ph, cplx{-kv[q] * mq[q].y, kv[q] * mq[q].x});
-  // field: symmetric pairs 3..8 = (0,0) (1,1) (2,2) (0,1) (0,2) (1,2)
-  const double F[3][3] = {{kv[3], kv[6], kv[7]}, {kv[6], kv[4], kv[8]}, {kv[7], kv[8], kv[5]}};
-#pragma unroll
-  for (int p = 0; p < 3; ++p) {
-    cplx hp{0.0, 0.0};
-#pragma unroll
-    for (int q = 0; q < 3; ++q) hp = cadd(hp, cplx{F[p][q] * mq[q].x, F[p][q] * mq[q].y});
-    S[size_t(p) * np + i] = cplx{scale * hp.x, scale * hp.y};
-  }
-  S[3 * np + i] = cplx{scale * phi_scale * ph.x, scale * phi_scale * ph.y};
 }
 
 // ---------------------------------------------------------------- x inverse
 // Half spectra S[a][z][y][0..Lx/2] (z < nz, y < ny) -> real rows out[a] (x < nx),
 // output a = blockIdx.y: 0..2 field components to h[a], 3 potential to phi.
-__global__ __launch_bounds__(kT) void k_x_inv(const cplx *__restrict__ S, double *__restrict__ phi,
+template <int KT, int KP>
+__global__ __launch_bounds__(KT) void k_x_inv(const cplx *__restrict__ S, size_t astride, double *__restrict__ phi,
                                               double *__restrict__ hout, int nx, int ny, int nz, int Lx, int Ly,
-                                              int Lz, int nl) {
+                                              int P, int lnl) {
   extern __shared__ cplx sm[];
-  cplx *buf = sm, *tlo = sm + kCap, *thi = tlo + 64;
-  const int N = Lx / 2, H = N + 1;
+  cplx *buf = sm, *tlo = sm + cap(KP), *thi = tlo + 64;
+  const int N = Lx / 2, lN = __builtin_ctz(N);
+  const int nl = 1 << lnl;
   const int a = blockIdx.y;
   const int rows = ny * nz;
-  const int r0 = blockIdx.x * nl;
+  const int r0 = blockIdx.x << lnl;
   const int nr = min(nl, rows - r0);
   make_twiddles(tlo, thi, N);
   double sw, cw;
   sincospi(-1.0 / double(N), &sw, &cw);
   const cplx w1{cw, sw};
-  const cplx *src = S + size_t(a) * Lz * Ly * H;
+  const cplx *src = S + size_t(a) * astride;
   // pack Z[f] = E[f] + i O[f] from X[f], X[N - f]: E = X[f] + conj X[N-f],
   // O = (X[f] - conj X[N-f]) conj(W_L^f); the unnormalized inverse complex
   // transform of Z then holds Lx x[2m] + i Lx x[2m+1]
   const int LS = line_stride(N);
-  for (int i = threadIdx.x; i < nl * N; i += kT) {
-    const int line = i / N, f = i - line * N;
+  for (int i = threadIdx.x; i < nl * N; i += KT) {
+    const int line = i >> lN, f = i & (N - 1);
     cplx v{0.0, 0.0};
     if (line < nr) {
       const int r = r0 + line, z = r / ny, y = r - z * ny;
-      const cplx *row = src + (size_t(z) * Ly + y) * H;
+      const cplx *row = src + (size_t(z) * Ly + y) * P;
       const cplx xf = row[f], xcc = cconj(row[N - f]);
       const cplx E = cadd(xf, xcc);
       const cplx O = cmul(csub(xf, xcc), cconj(wl(f, N, tlo, thi, w1)));
@@ -398,10 +477,10 @@ __global__ __launch_bounds__(kT) void k_x_inv(const cplx *__restrict__ S, double
     buf[line * LS + pd(f)] = v;
   }
   __syncthreads();
-  fft_lines<true>(buf, N, nl, tlo, thi);
+  fft_lines<true, KT, KP>(buf, N, lnl, 1, tlo, thi);
   double *dst = (a < 3) ? hout + size_t(a) * nx * ny * nz : phi;
-  for (int i = threadIdx.x; i < nl * N; i += kT) {
-    const int line = i / N, m = i - line * N;
+  for (int i = threadIdx.x; i < nl * N; i += KT) {
+    const int line = i >> lN, m = i & (N - 1);
     if (line >= nr) continue;
     const cplx v = buf[line * LS + pd(m)];
     double *row = dst + size_t(r0 + line) * nx;
@@ -411,6 +490,56 @@ __global__ __launch_bounds__(kT) void k_x_inv(const cplx *__restrict__ S, double
   }
 }
 
+// Row pitch of the half spectra: Lx/2 + 1 rounded up to 8 points (128 B).
+int pitch(int Lx) { return (Lx / 2 + 1 + 7) & ~7; }
+
+template <typename Kern> demag_status allow_lds(Kern k, size_t lds) {
+  DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    int(lds)));
+  return DEMAG_OK;
+}
+
+// Passes along x and y with workgroups of shape <KT, KP>.
+template <int KT, int KP> struct xy_passes {
+  static constexpr size_t lds = sizeof(cplx) * (cap(KP) + 128);
+  static demag_status fwd(hipStream_t s, const double *m, cplx *S, size_t as, int nx, int ny, int nz, int Lx,
+                          int Ly, int P) {
+    demag_status st = allow_lds(k_x_fwd<KT, KP>, lds);
+    if (st == DEMAG_OK) st = allow_lds(k_lines<false, KT, KP>, lds);
+    if (st != DEMAG_OK) return st;
+    const int H = Lx / 2 + 1, rows = ny * nz;
+    const int lx = ilog2(lines_per_wg(Lx / 2, KP)), ly = ilog2(lines_per_wg(Ly, KP));
+    const unsigned ytiles = unsigned((H + (1 << ly) - 1) >> ly);
+    k_x_fwd<KT, KP><<<dim3((rows + (1 << lx) - 1) >> lx, 3), KT, lds, s>>>(m, S, as, nx, ny, nz, Lx, Ly, P, lx);
+    k_lines<false, KT, KP><<<ytiles * nz * 3, KT, lds, s>>>(S, as, Ly, H, P, nz, ny, Ly, ly);
+    return DEMAG_OK;
+  }
+  static demag_status inv(hipStream_t s, cplx *S, size_t as, double *phi, double *h, int nx, int ny, int nz,
+                          int Lx, int Ly, int P) {
+    demag_status st = allow_lds(k_x_inv<KT, KP>, lds);
+    if (st == DEMAG_OK) st = allow_lds(k_lines<true, KT, KP>, lds);
+    if (st != DEMAG_OK) return st;
+    const int H = Lx / 2 + 1, rows = ny * nz;
+    const int lx = ilog2(lines_per_wg(Lx / 2, KP)), ly = ilog2(lines_per_wg(Ly, KP));
+    const unsigned ytiles = unsigned((H + (1 << ly) - 1) >> ly);
+    k_lines<true, KT, KP><<<ytiles * nz * 4, KT, lds, s>>>(S, as, Ly, H, P, nz, Ly, ny, ly);
+    k_x_inv<KT, KP><<<dim3((rows + (1 << lx) - 1) >> lx, 4), KT, lds, s>>>(S, as, phi, h, nx, ny, nz, Lx, Ly, P, lx);
+    return DEMAG_OK;
+  }
+};
+
+template <int KT, int KP>
+demag_status z_conv(hipStream_t s, cplx *S, size_t as, const double *K, int Lz, int nz, int Ly, int P, int H,
+                    double scale, double phi_scale) {
+  constexpr size_t lds = sizeof(cplx) * (cap(KP) + 128);
+  demag_status st = allow_lds(k_z_conv<KT, KP>, lds);
+  if (st != DEMAG_OK) return st;
+  const int l = ilog2(lines_per_wg(Lz, KP) / 4);
+  const unsigned tiles = unsigned((H + (1 << l) - 1) >> l);
+  k_z_conv<KT, KP><<<tiles * Ly, KT, lds, s>>>(S, as, K, Lz, nz, Ly, P, H, l, scale, phi_scale);
+  return DEMAG_OK;
+}
+
 }  // namespace
 
 demag_status prepare_fft3d(demag_ctx *ctx, demag_factors *f) {
@@ -418,58 +547,52 @@ demag_status prepare_fft3d(demag_ctx *ctx, demag_factors *f) {
   demag_status st = prepare_spectra(ctx, f);
   if (st != DEMAG_OK) return st;
   const int Lx = fft_length(f->n[0]), Ly = fft_length(f->n[1]), Lz = fft_length(f->n[2]);
-  const size_t np = size_t(Lz) * Ly * (Lx / 2 + 1);
-  DEMAG_TRY_HIP(hipMalloc(&f->k3, 9 * np * sizeof(double)));
-  k_kernel_spectra<<<unsigned((np + 255) / 256), 256, 0, ctx->stream>>>(f->spec[0], f->spec[1], f->spec[2], f->k3,
-                                                                       f->M, Lx, Ly, Lz);
+  const size_t npk = size_t(Lz / 2 + 1) * (Ly / 2 + 1) * pitch(Lx);
+  DEMAG_TRY_HIP(hipMalloc(&f->k3, 9 * npk * sizeof(double)));
+  k_kernel_spectra<<<unsigned((npk + 255) / 256), 256, 0, ctx->stream>>>(f->spec[0], f->spec[1], f->spec[2], f->k3,
+                                                                        f->M, Lx, Ly, Lz, pitch(Lx));
   DEMAG_TRY_HIP(hipGetLastError());
   return DEMAG_OK;
 }
 
 size_t fft3d_workspace_bytes(const demag_factors *f) {
   const int Lx = fft_length(f->n[0]), Ly = fft_length(f->n[1]), Lz = fft_length(f->n[2]);
-  return 4 * size_t(Lz) * Ly * (Lx / 2 + 1) * sizeof(cplx);
+  return 4 * size_t(Lz) * Ly * pitch(Lx) * sizeof(cplx);
 }
 
 demag_status launch_fft3d(demag_ctx *ctx, const demag_factors *f, const double *m, double *phi, double *h,
                           void *ws) {
   const int nx = f->n[0], ny = f->n[1], nz = f->n[2];
   const int Lx = fft_length(nx), Ly = fft_length(ny), Lz = fft_length(nz);
-  const int Nx = Lx / 2, H = Nx + 1;
-  const size_t np = size_t(Lz) * Ly * H;
+  const int H = Lx / 2 + 1, P = pitch(Lx);
+  const size_t as = size_t(Lz) * Ly * P;        // array stride
   cplx *S = static_cast<cplx *>(ws);
-  const size_t lds = sizeof(cplx) * (kCap + 128);
-  for (const void *k : {reinterpret_cast<const void *>(&k_x_fwd), reinterpret_cast<const void *>(&k_x_inv),
-                        reinterpret_cast<const void *>(&k_lines<false>), reinterpret_cast<const void *>(&k_lines<true>)})
-    DEMAG_TRY_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  hipStream_t s = ctx->stream;
   hipEvent_t ev = nullptr;
   demag_status st = prof_begin(ctx, &ev);
   if (st != DEMAG_OK) return st;
-  const int rows = ny * nz;
-  const int nlx = lines_per_wg(Nx);                // real rows per workgroup
-  const int nly = lines_per_wg(Ly), nlz = lines_per_wg(Lz);   // strided lines per workgroup
-  // forward: x (real rows), y (z < nz), z (all fy)
-  k_x_fwd<<<dim3((rows + nlx - 1) / nlx, 3), kT, lds, ctx->stream>>>(m, S, nx, ny, nz, Lx, Ly, Lz, nlx);
-  k_lines<false><<<dim3((H + nly - 1) / nly, nz, 3), kT, lds, ctx->stream>>>(S, np, Ly, H, size_t(Ly) * H, H, ny,
-                                                                             Ly, nly);
-  k_lines<false><<<dim3((H + nlz - 1) / nlz, Ly, 3), kT, lds, ctx->stream>>>(S, np, Lz, H, H, size_t(Ly) * H, nz,
-                                                                             Lz, nlz);
-  // products with the kernel spectra (4 outputs), normalization folded in
-  k_products<<<unsigned((np + 255) / 256), 256, 0, ctx->stream>>>(S, f->k3, np, 1.0 / (double(Lx) * Ly * Lz), f->L);
-  // inverse: z (keep z < nz), y (z < nz, keep y < ny), x (rows -> real, x < nx)
-  k_lines<true><<<dim3((H + nlz - 1) / nlz, Ly, 4), kT, lds, ctx->stream>>>(S, np, Lz, H, H, size_t(Ly) * H, Lz, nz,
-                                                                            nlz);
-  k_lines<true><<<dim3((H + nly - 1) / nly, nz, 4), kT, lds, ctx->stream>>>(S, np, Ly, H, size_t(Ly) * H, H, Ly, ny,
-                                                                            nly);
-  k_x_inv<<<dim3((rows + nlx - 1) / nlx, 4), kT, lds, ctx->stream>>>(S, phi, h, nx, ny, nz, Lx, Ly, Lz, nlx);
+  // x and y lines: up to 1024 points per line in one-wave workgroups, longer
+  // lines (2048) in 4096-point workgroups; z: four lines per column group
+  const bool big = (Lx / 2 > 1024) || Ly > 1024;
+  const double scale = 1.0 / (double(Lx) * Ly * Lz);
+  st = big ? xy_passes<256, 4096>::fwd(s, m, S, as, nx, ny, nz, Lx, Ly, P)
+           : xy_passes<64, 1024>::fwd(s, m, S, as, nx, ny, nz, Lx, Ly, P);
+  if (st == DEMAG_OK)
+    st = Lz > 1024 ? z_conv<512, 8192>(s, S, as, f->k3, Lz, nz, Ly, P, H, scale, f->L)
+                   : z_conv<256, 4096>(s, S, as, f->k3, Lz, nz, Ly, P, H, scale, f->L);
+  if (st == DEMAG_OK)
+    st = big ? xy_passes<256, 4096>::inv(s, S, as, phi, h, nx, ny, nz, Lx, Ly, P)
+             : xy_passes<64, 1024>::inv(s, S, as, phi, h, nx, ny, nz, Lx, Ly, P);
+  if (st != DEMAG_OK) return st;
   DEMAG_TRY_HIP(hipGetLastError());
   if (ev) {
-    // real FFTs ~2.5 L log2 L per line point... counted per 3D transform as
-    // 2.5 Lx Ly Lz log2(Lx Ly Lz) (half for the real direction) x 7 transforms
+    // FFT flops 2.5 L log2 L per complex line of L points (half for the real
+    // x transforms): 3 forward and 4 inverse 3D transforms; 18 flops per
+    // frequency and component pair in the products
     const double vol = double(Lx) * Ly * Lz;
-    const double flops = 7.0 * 2.5 * vol * std::log2(vol) / 2.0 + np * (9.0 * 8.0);
-    // compulsory traffic: m, the nine kernel spectra, the outputs
-    const double bytes = 8.0 * (7.0 * nx * ny * nz) + 8.0 * 9.0 * np;
+    const double flops = 7.0 * 2.5 * vol * std::log2(vol) / 2.0 + double(Lz) * Ly * H * 36.0;
+    // compulsory traffic: m, the nine kernel spectra (one octant), the outputs
+    const double bytes = 8.0 * (7.0 * nx * ny * nz) + 8.0 * 9.0 * double(Lz / 2 + 1) * (Ly / 2 + 1) * H;
     st = prof_end(ctx, ev, "fft3d/fp64", flops, bytes);
   }
   return st;
