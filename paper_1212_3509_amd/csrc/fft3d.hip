@@ -25,6 +25,7 @@
 #include "internal.h"
 
 #include <cmath>
+#include <cstdint>
 
 namespace demag {
 
@@ -40,19 +41,27 @@ __device__ inline cplx cconj(cplx a) { return {a.x, -a.y}; }
 template <bool INV> __device__ inline cplx mul_mi(cplx a) { return INV ? cplx{-a.y, a.x} : cplx{a.y, -a.x}; }
 
 // LDS slot of point i of line b: b * LS + pd(i), with one pad slot after
-// every 16 points and an odd line stride LS, so that stride-R butterfly
-// accesses within a line and accesses across lines (the transposed global
-// loads of the strided passes) both spread over the banks.
+// every 16 points.  16-byte LDS accesses are served eight lanes at a time,
+// conflict-free when those lanes hit distinct slots modulo 8.  Butterflies
+// run along a line across lanes (consecutive points: distinct, thanks to the
+// pad for the Stockham stride-R stores); the transposed accesses of the
+// strided passes put nl lines across lanes (fx fastest, then the point), and
+// are conflict-free for a line stride LS = 8 / min(nl, 8) modulo 8.
 __device__ inline int pd(int i) { return i + (i >> 4); }
-__host__ __device__ constexpr int line_stride(int N) { return (N + (N - 1) / 16 + 1) | 1; }
+__host__ __device__ constexpr int line_stride(int N, int nl) {
+  const int base = N + (N - 1) / 16;                  // pd(N - 1) + 1
+  const int t = nl >= 8 ? 1 : 8 / nl;                 // wanted residue modulo 8
+  return nl == 1 ? base : base + ((t - base % 8) + 8) % 8;
+}
 __host__ __device__ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 // LDS points of a workgroup of shape <KT threads, KP points> (KP / KT = 16:
 // one radix-16 butterfly per thread and pass)
-__host__ __device__ constexpr int cap(int KP) { return KP + KP / 16 + 64; }
-// lines of N points (N <= KP) per workgroup
-__host__ __device__ inline int lines_per_wg(int N, int KP) {
-  int nl = KP / N;
-  while (nl > 1 && nl * line_stride(N) > cap(KP)) nl /= 2;
+__host__ __device__ constexpr int cap(int KP) { return KP + KP / 16 + 128; }
+// lines of N points (N <= KP) per workgroup, in groups of g lines that share
+// a column (g = 1, or 4 for the fused z pass); returns the lines per group
+__host__ __device__ inline int lines_per_wg(int N, int KP, int g = 1) {
+  int nl = KP / (N * g);
+  while (nl > 1 && g * nl * line_stride(N, nl) > cap(KP)) nl /= 2;
   return nl;
 }
 
@@ -129,24 +138,21 @@ __device__ inline void make_twiddles(cplx *lo, cplx *hi, int N) {
   }
 }
 
-// One Stockham pass of radix R over narr arrays of nl = 2^lnl lines of N
-// points (array a, line b at LDS line a * nl + b; input sub-transform length
-// Ns).  Butterfly g: array g / (nl N / R), then line fastest across threads.
-// The first pass (Ns = 1) has no twiddles.
+// One Stockham pass of radix R over nlines lines of N points at line stride
+// LS (input sub-transform length Ns).  Butterfly g: line g / (N / R), index
+// g % (N / R).  The first pass (Ns = 1) has no twiddles.
 template <bool INV, int R, int KT, int KP, int N, int Ns>
-__device__ inline void pass(cplx *buf, int lnl, int narr, const cplx *tlo, const cplx *thi) {
-  constexpr int LS = line_stride(N);
+__device__ inline void pass(cplx *buf, int LS, int nlines, const cplx *tlo, const cplx *thi) {
   constexpr int per = N / R;             // butterflies per line
   constexpr int lper = ilog2(per);
   constexpr int kMaxB = (KP / R + KT - 1) / KT;
-  const int nb = (narr * per) << lnl;
-  const int lmask = (1 << lnl) - 1, amask = (per << lnl) - 1;
+  const int nb = nlines << lper;
   cplx v[kMaxB][R];
 #pragma unroll
   for (int q = 0; q < kMaxB; ++q) {
     const int g = threadIdx.x + q * KT;
     if (g < nb) {
-      const int ga = g & amask, j = ga >> lnl, line = ((g >> (lnl + lper)) << lnl) + (ga & lmask);
+      const int j = g & (per - 1), line = g >> lper;
       const cplx *lb = buf + line * LS;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = lb[pd(j + r * per)];
@@ -154,12 +160,28 @@ __device__ inline void pass(cplx *buf, int lnl, int narr, const cplx *tlo, const
         const int k = j & (Ns - 1);
         cplx w = twid(k * (N / (Ns * R)), tlo, thi);
         if (INV) w = cconj(w);
-        cplx wr = w;
-#pragma unroll
-        for (int r = 1; r < R; ++r) {
-          v[q][r] = cmul(v[q][r], wr);
-          if (r + 1 < R) wr = cmul(wr, w);
+        // powers w^r, r < R, as w^(4a + b) = (w^4)^a w^b: dependency depth 5
+        cplx wp[R];
+        wp[1] = w;
+        if constexpr (R > 2) {
+          wp[2] = cmul(w, w);
+          wp[3] = cmul(wp[2], w);
         }
+        if constexpr (R > 4) {
+          wp[4] = cmul(wp[2], wp[2]);
+#pragma unroll
+          for (int r = 5; r < 8; ++r) wp[r] = cmul(wp[4], wp[r - 4]);
+        }
+        if constexpr (R > 8) {
+          wp[8] = cmul(wp[4], wp[4]);
+          wp[12] = cmul(wp[8], wp[4]);
+#pragma unroll
+          for (int r = 9; r < 12; ++r) wp[r] = cmul(wp[8], wp[r - 8]);
+#pragma unroll
+          for (int r = 13; r < 16; ++r) wp[r] = cmul(wp[12], wp[r - 12]);
+        }
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], wp[r]);
       }
       dftR<INV, R>(v[q]);
     }
@@ -169,7 +191,7 @@ __device__ inline void pass(cplx *buf, int lnl, int narr, const cplx *tlo, const
   for (int q = 0; q < kMaxB; ++q) {
     const int g = threadIdx.x + q * KT;
     if (g < nb) {
-      const int ga = g & amask, j = ga >> lnl, line = ((g >> (lnl + lper)) << lnl) + (ga & lmask);
+      const int j = g & (per - 1), line = g >> lper;
       const int k = j & (Ns - 1);
       const int o = (j / Ns) * Ns * R + k;
       cplx *lb = buf + line * LS;
@@ -180,29 +202,29 @@ __device__ inline void pass(cplx *buf, int lnl, int narr, const cplx *tlo, const
   __syncthreads();
 }
 
-// Complex FFTs of narr arrays of nl = 2^lnl lines of N points (power of 2, N <= 2048) in
+// Complex FFTs of nlines lines of N points at line stride LS (power of 2, N <= 2048) in
 // LDS: a fixed pass plan per length (radix 16 first), each pass inlined with
 // its sizes known at compile time, so that the register allocation and the
 // index arithmetic are per pass.
 template <bool INV, int KT, int KP, int N, int Ns, int R0, int... Rs>
-__device__ inline void run_passes(cplx *buf, int lnl, int narr, const cplx *tlo, const cplx *thi) {
-  pass<INV, R0, KT, KP, N, Ns>(buf, lnl, narr, tlo, thi);
-  if constexpr (sizeof...(Rs) > 0) run_passes<INV, KT, KP, N, Ns * R0, Rs...>(buf, lnl, narr, tlo, thi);
+__device__ inline void run_passes(cplx *buf, int LS, int nlines, const cplx *tlo, const cplx *thi) {
+  pass<INV, R0, KT, KP, N, Ns>(buf, LS, nlines, tlo, thi);
+  if constexpr (sizeof...(Rs) > 0) run_passes<INV, KT, KP, N, Ns * R0, Rs...>(buf, LS, nlines, tlo, thi);
 }
 template <bool INV, int KT, int KP>
-__device__ void fft_lines(cplx *buf, int N, int lnl, int narr, const cplx *tlo, const cplx *thi) {
+__device__ void fft_lines(cplx *buf, int N, int LS, int nlines, const cplx *tlo, const cplx *thi) {
   switch (N) {
-    case 2: run_passes<INV, KT, KP, 2, 1, 2>(buf, lnl, narr, tlo, thi); break;
-    case 4: run_passes<INV, KT, KP, 4, 1, 4>(buf, lnl, narr, tlo, thi); break;
-    case 8: run_passes<INV, KT, KP, 8, 1, 8>(buf, lnl, narr, tlo, thi); break;
-    case 16: run_passes<INV, KT, KP, 16, 1, 16>(buf, lnl, narr, tlo, thi); break;
-    case 32: run_passes<INV, KT, KP, 32, 1, 16, 2>(buf, lnl, narr, tlo, thi); break;
-    case 64: run_passes<INV, KT, KP, 64, 1, 16, 4>(buf, lnl, narr, tlo, thi); break;
-    case 128: run_passes<INV, KT, KP, 128, 1, 16, 8>(buf, lnl, narr, tlo, thi); break;
-    case 256: run_passes<INV, KT, KP, 256, 1, 16, 16>(buf, lnl, narr, tlo, thi); break;
-    case 512: run_passes<INV, KT, KP, 512, 1, 16, 16, 2>(buf, lnl, narr, tlo, thi); break;
-    case 1024: run_passes<INV, KT, KP, 1024, 1, 16, 16, 4>(buf, lnl, narr, tlo, thi); break;
-    case 2048: run_passes<INV, KT, KP, 2048, 1, 16, 16, 8>(buf, lnl, narr, tlo, thi); break;
+    case 2: run_passes<INV, KT, KP, 2, 1, 2>(buf, LS, nlines, tlo, thi); break;
+    case 4: run_passes<INV, KT, KP, 4, 1, 4>(buf, LS, nlines, tlo, thi); break;
+    case 8: run_passes<INV, KT, KP, 8, 1, 8>(buf, LS, nlines, tlo, thi); break;
+    case 16: run_passes<INV, KT, KP, 16, 1, 16>(buf, LS, nlines, tlo, thi); break;
+    case 32: run_passes<INV, KT, KP, 32, 1, 16, 2>(buf, LS, nlines, tlo, thi); break;
+    case 64: run_passes<INV, KT, KP, 64, 1, 16, 4>(buf, LS, nlines, tlo, thi); break;
+    case 128: run_passes<INV, KT, KP, 128, 1, 16, 8>(buf, LS, nlines, tlo, thi); break;
+    case 256: run_passes<INV, KT, KP, 256, 1, 16, 16>(buf, LS, nlines, tlo, thi); break;
+    case 512: run_passes<INV, KT, KP, 512, 1, 16, 16, 2>(buf, LS, nlines, tlo, thi); break;
+    case 1024: run_passes<INV, KT, KP, 1024, 1, 16, 16, 4>(buf, LS, nlines, tlo, thi); break;
+    case 2048: run_passes<INV, KT, KP, 2048, 1, 16, 16, 8>(buf, LS, nlines, tlo, thi); break;
     default: break;   // N = 1: identity
   }
 }
@@ -240,19 +262,35 @@ __global__ __launch_bounds__(KT) void k_x_fwd(const double *__restrict__ in, cpl
   const int nr = min(nl, rows - r0);
   make_twiddles(tlo, thi, N);
   const double *src = in + size_t(comp) * nx * ny * nz;
-  const int LS = line_stride(N);
-  for (int i = threadIdx.x; i < nl * N; i += KT) {
+  const int LS = line_stride(N, nl);
+  // all loads of a thread in flight before the LDS stores (nl N <= KP)
+  constexpr int kE = KP / KT;
+  // (x, x + 1) pairs are 16-byte aligned for an even row length and base
+  const bool even = (nx & 1) == 0 && (reinterpret_cast<uintptr_t>(in) & 15) == 0;
+  cplx v[kE];
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int i = threadIdx.x + q * KT;
     const int line = i >> lN, m = i & (N - 1);
-    cplx v{0.0, 0.0};
-    if (line < nr) {
+    v[q] = cplx{0.0, 0.0};
+    if (i < nl * N && line < nr) {
       const double *row = src + size_t(r0 + line) * nx;
       const int a = 2 * m, b = 2 * m + 1;
-      v = cplx{a < nx ? row[a] : 0.0, b < nx ? row[b] : 0.0};
+      if (even && b < nx) {
+        const double2 t = *reinterpret_cast<const double2 *>(row + a);
+        v[q] = cplx{t.x, t.y};
+      } else {
+        v[q] = cplx{a < nx ? row[a] : 0.0, b < nx ? row[b] : 0.0};
+      }
     }
-    buf[line * LS + pd(m)] = v;
+  }
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int i = threadIdx.x + q * KT;
+    if (i < nl * N) buf[(i >> lN) * LS + pd(i & (N - 1))] = v[q];
   }
   __syncthreads();
-  fft_lines<false, KT, KP>(buf, N, lnl, 1, tlo, thi);
+  fft_lines<false, KT, KP>(buf, N, LS, nl, tlo, thi);
   double sw, cw;
   sincospi(-1.0 / double(N), &sw, &cw);
   const cplx w1{cw, sw};
@@ -293,16 +331,25 @@ __global__ __launch_bounds__(KT) void k_lines(cplx *__restrict__ A, size_t astri
   const int nf = min(nl, H - fx0);
   cplx *base = A + size_t(arr) * astride + size_t(z) * N * P + fx0;
   make_twiddles(tlo, thi, N);
-  // global accesses run along fx (coalesced); line stride LS is odd
-  const int LS = line_stride(N);
-  for (int e = threadIdx.x; e < nl * N; e += KT) {
+  // global accesses run along fx (coalesced)
+  const int LS = line_stride(N, nl);
+  // all loads of a thread in flight before the LDS stores (nl N <= KP)
+  constexpr int kE = KP / KT;
+  cplx v[kE];
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int e = threadIdx.x + q * KT;
     const int i = e >> lnl, b = e & (nl - 1);
-    cplx v{0.0, 0.0};
-    if (i < nin && b < nf) v = base[size_t(i) * P + b];
-    buf[b * LS + pd(i)] = v;
+    v[q] = cplx{0.0, 0.0};
+    if (e < nl * N && i < nin && b < nf) v[q] = base[size_t(i) * P + b];
+  }
+#pragma unroll
+  for (int q = 0; q < kE; ++q) {
+    const int e = threadIdx.x + q * KT;
+    if (e < nl * N) buf[(e & (nl - 1)) * LS + pd(e >> lnl)] = v[q];
   }
   __syncthreads();
-  fft_lines<INV, KT, KP>(buf, N, lnl, 1, tlo, thi);
+  fft_lines<INV, KT, KP>(buf, N, LS, nl, tlo, thi);
   for (int e = threadIdx.x; e < nl * nout; e += KT) {
     const int i = e >> lnl, b = e & (nl - 1);
     if (b < nf) base[size_t(i) * P + b] = buf[b * LS + pd(i)];
@@ -313,8 +360,9 @@ __global__ __launch_bounds__(KT) void k_lines(cplx *__restrict__ A, size_t astri
 // 1D spectra s(f) of the factors ([type][M][L/2+1], the imaginary part for
 // odd types): s(L - f) = s(f) for even, -s(f) for odd types.  The 3D kernel
 // spectra inherit this per axis, so only the octant fy <= Ly/2, fz <= Lz/2 is
-// stored: Kspec[c][fz][fy][fx] (row pitch P; component c: 0..2 potential K^q,
-// 3..8 field (0,0) (1,1) (2,2) (0,1) (0,2) (1,2)) = sign_c sum_k s_x s_y s_z.
+// stored: Kspec[fz][fy][fx][c] (row pitch P, kKC = 10 doubles per frequency,
+// 16-byte aligned; component c: 0..2 potential K^q, 3..8 field (0,0) (1,1)
+// (2,2) (0,1) (0,2) (1,2), 9 unused) = sign_c sum_k s_x s_y s_z.
 __device__ inline void comp_types(int c, int t[3]) {
   // potential K^q: X along q, E elsewhere; field h_p <- m_q: differentiate along p
   const int p = c < 3 ? -1 : (c < 6 ? c - 3 : (c == 6 ? 0 : (c == 7 ? 0 : 1)));
@@ -323,6 +371,7 @@ __device__ inline void comp_types(int c, int t[3]) {
   if (p >= 0) t[p] = (t[p] == F_X) ? F_P : F_Q;
 }
 __host__ __device__ constexpr bool odd_type(int t) { return t == F_X || t == F_Q; }
+constexpr int kKC = 10;   // doubles per frequency of the kernel spectra
 
 __global__ void k_kernel_spectra(const double *__restrict__ sx, const double *__restrict__ sy,
                                  const double *__restrict__ sz, double *__restrict__ K, int M, int Lx, int Ly,
@@ -352,8 +401,10 @@ __global__ void k_kernel_spectra(const double *__restrict__ sx, const double *__
       }
     }
   }
+  double *out = K + idx * kKC;
 #pragma unroll
-  for (int c = 0; c < 9; ++c) K[size_t(c) * npk + idx] = (c >= 6) ? -acc[c] : acc[c];
+  for (int c = 0; c < 9; ++c) out[c] = (c >= 6) ? -acc[c] : acc[c];
+  out[9] = 0.0;
 }
 
 // ---------------------------------------------------------------- z pass + products
@@ -379,40 +430,74 @@ __global__ __launch_bounds__(KT) void k_z_conv(cplx *__restrict__ S, size_t astr
   const int fx0 = tile << lnl;
   const int nf = min(nl, H - fx0);
   make_twiddles(tlo, thi, Lz);
-  const int LS = line_stride(Lz);
+  const int LS = line_stride(Lz, nl);
   const size_t col = size_t(fy) * P + fx0;      // offset of (z = 0, fy, fx0)
   const size_t zs = size_t(Ly) * P;             // z stride
+  // all loads of a thread in flight before the LDS stores (4 nl Lz <= KP)
+  constexpr int kE = KP / 4 / KT;
+  {
+    cplx v[3][kE];
 #pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    for (int e = threadIdx.x; e < nl * Lz; e += KT) {
-      const int i = e >> lnl, b = e & (nl - 1);
-      cplx v{0.0, 0.0};
-      if (i < nz && b < nf) v = S[size_t(a) * astride + i * zs + col + b];
-      buf[(a * nl + b) * LS + pd(i)] = v;
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int q = 0; q < kE; ++q) {
+        const int e = threadIdx.x + q * KT;
+        const int i = e >> lnl, b = e & (nl - 1);
+        v[a][q] = cplx{0.0, 0.0};
+        if (e < nl * Lz && i < nz && b < nf) v[a][q] = S[size_t(a) * astride + i * zs + col + b];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+#pragma unroll
+      for (int q = 0; q < kE; ++q) {
+        const int e = threadIdx.x + q * KT;
+        if (e < nl * Lz) buf[(a * nl + (e & (nl - 1))) * LS + pd(e >> lnl)] = v[a][q];
+      }
     }
   }
   __syncthreads();
-  fft_lines<false, KT, KP>(buf, Lz, lnl, 3, tlo, thi);
+  fft_lines<false, KT, KP>(buf, Lz, LS, 3 * nl, tlo, thi);
   // kernel spectra octant index and per-component signs for this fy
   const int hy = Ly / 2 + 1, hz = Lz / 2 + 1;
-  const size_t npk = size_t(hz) * hy * P;
   const bool fy_hi = fy >= hy;
   const int fyk = fy_hi ? Ly - fy : fy;
   const double ps = scale * phi_scale;
-  for (int e = threadIdx.x; e < nl * Lz; e += KT) {
-    const int i = e >> lnl, b = e & (nl - 1);
-    if (b >= nf) continue;
-    const bool fz_hi = i >= hz;
-    const int fzk = fz_hi ? Lz - i : i;
-    const double *kp = K + (size_t(fzk) * hy + fyk) * P + fx0 + b;
-    double kv[9];
+  // Frequencies fz and Lz - fz share one stored kernel entry: item (p, b)
+  // handles fz = p and Lz - p for 0 < p < Lz/2, item (0, b) handles fz = 0
+  // and Lz/2.  The kernel spectra of all the thread's items are in flight at
+  // once.
+  constexpr int kI = (kE + 1) / 2;   // items per thread (nl Lz / 2 <= kI KT)
+  double2 kr[kI][kKC / 2], k2[kKC / 2];
+#pragma unroll
+  for (int q = 0; q < kI; ++q) {
+    const int e = threadIdx.x + q * KT;
+    const int p = e >> lnl, b = e & (nl - 1);
+    if (e < nl * (Lz / 2) && b < nf) {
+      const double2 *kp = reinterpret_cast<const double2 *>(K + ((size_t(p) * hy + fyk) * P + fx0 + b) * kKC);
+#pragma unroll
+      for (int c = 0; c < kKC / 2; ++c) kr[q][c] = kp[c];
+    }
+  }
+  if (int(threadIdx.x) < nf && Lz > 1) {   // items (0, b) also need fz = Lz/2
+    const double2 *kp =
+        reinterpret_cast<const double2 *>(K + ((size_t(Lz / 2) * hy + fyk) * P + fx0 + threadIdx.x) * kKC);
+#pragma unroll
+    for (int c = 0; c < kKC / 2; ++c) k2[c] = kp[c];
+  }
+  // products at point (i, b) with the kernel entry kr (fz_hi: i > Lz/2)
+  auto product = [&](int i, int b, const double2 *kraw, bool fz_hi) {
+    double kv[kKC];
+#pragma unroll
+    for (int c = 0; c < kKC / 2; ++c) {
+      kv[2 * c] = kraw[c].x;
+      kv[2 * c + 1] = kraw[c].y;
+    }
 #pragma unroll
     for (int c = 0; c < 9; ++c) {
       int t[3];
       comp_types(c, t);
-      const bool neg = (fy_hi && odd_type(t[1])) != (fz_hi && odd_type(t[2]));
-      const double k = kp[size_t(c) * npk];
-      kv[c] = neg ? -k : k;
+      if ((fy_hi && odd_type(t[1])) != (fz_hi && odd_type(t[2]))) kv[c] = -kv[c];
     }
     const cplx m0 = buf[(0 * nl + b) * LS + pd(i)];
     const cplx m1 = buf[(1 * nl + b) * LS + pd(i)];
@@ -424,12 +509,21 @@ __global__ __launch_bounds__(KT) void k_z_conv(cplx *__restrict__ S, size_t astr
     // field: symmetric F with pairs 3..8 = (0,0) (1,1) (2,2) (0,1) (0,2) (1,2)
     const double F[3][3] = {{kv[3], kv[6], kv[7]}, {kv[6], kv[4], kv[8]}, {kv[7], kv[8], kv[5]}};
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
-      buf[(p * nl + b) * LS + pd(i)] = cplx{scale * (F[p][0] * m0.x + F[p][1] * m1.x + F[p][2] * m2.x),
-                                           scale * (F[p][0] * m0.y + F[p][1] * m1.y + F[p][2] * m2.y)};
+    for (int a = 0; a < 3; ++a)
+      buf[(a * nl + b) * LS + pd(i)] = cplx{scale * (F[a][0] * m0.x + F[a][1] * m1.x + F[a][2] * m2.x),
+                                           scale * (F[a][0] * m0.y + F[a][1] * m1.y + F[a][2] * m2.y)};
+  };
+#pragma unroll
+  for (int q = 0; q < kI; ++q) {
+    const int e = threadIdx.x + q * KT;
+    const int p = e >> lnl, b = e & (nl - 1);
+    if (e >= nl * (Lz / 2) || b >= nf) continue;
+    product(p, b, kr[q], false);
+    if (p > 0) product(Lz - p, b, kr[q], true);
+    else if (Lz > 1) product(Lz / 2, b, k2, false);
   }
   __syncthreads();
-  fft_lines<true, KT, KP>(buf, Lz, lnl, 4, tlo, thi);
+  fft_lines<true, KT, KP>(buf, Lz, LS, 4 * nl, tlo, thi);
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
     for (int e = threadIdx.x; e < nl * nz; e += KT) {
@@ -455,6 +549,7 @@ __global__ __launch_bounds__(KT) void k_x_inv(const cplx *__restrict__ S, size_t
   const int r0 = blockIdx.x << lnl;
   const int nr = min(nl, rows - r0);
   make_twiddles(tlo, thi, N);
+  __syncthreads();   // the unpacking below reads the twiddle tables
   double sw, cw;
   sincospi(-1.0 / double(N), &sw, &cw);
   const cplx w1{cw, sw};
@@ -462,31 +557,52 @@ __global__ __launch_bounds__(KT) void k_x_inv(const cplx *__restrict__ S, size_t
   // pack Z[f] = E[f] + i O[f] from X[f], X[N - f]: E = X[f] + conj X[N-f],
   // O = (X[f] - conj X[N-f]) conj(W_L^f); the unnormalized inverse complex
   // transform of Z then holds Lx x[2m] + i Lx x[2m+1]
-  const int LS = line_stride(N);
-  for (int i = threadIdx.x; i < nl * N; i += KT) {
-    const int line = i >> lN, f = i & (N - 1);
-    cplx v{0.0, 0.0};
-    if (line < nr) {
-      const int r = r0 + line, z = r / ny, y = r - z * ny;
-      const cplx *row = src + (size_t(z) * Ly + y) * P;
-      const cplx xf = row[f], xcc = cconj(row[N - f]);
-      const cplx E = cadd(xf, xcc);
-      const cplx O = cmul(csub(xf, xcc), cconj(wl(f, N, tlo, thi, w1)));
-      v = cplx{E.x - O.y, E.y + O.x};
+  const int LS = line_stride(N, nl);
+  // two batches of kE / 2 points per thread, all their loads in flight at once
+  constexpr int kE = KP / KT, kB = kE / 2;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    cplx xf[kB], xc[kB];
+#pragma unroll
+    for (int q = 0; q < kB; ++q) {
+      const int i = threadIdx.x + (h * kB + q) * KT;
+      const int line = i >> lN, f = i & (N - 1);
+      xf[q] = xc[q] = cplx{0.0, 0.0};
+      if (i < nl * N && line < nr) {
+        const int r = r0 + line, z = r / ny, y = r - z * ny;
+        const cplx *row = src + (size_t(z) * Ly + y) * P;
+        xf[q] = row[f];
+        xc[q] = row[N - f];
+      }
     }
-    buf[line * LS + pd(f)] = v;
+#pragma unroll
+    for (int q = 0; q < kB; ++q) {
+      const int i = threadIdx.x + (h * kB + q) * KT;
+      if (i >= nl * N) continue;
+      const int f = i & (N - 1);
+      const cplx xcc = cconj(xc[q]);
+      const cplx E = cadd(xf[q], xcc);
+      const cplx O = cmul(csub(xf[q], xcc), cconj(wl(f, N, tlo, thi, w1)));
+      buf[(i >> lN) * LS + pd(f)] = cplx{E.x - O.y, E.y + O.x};
+    }
   }
   __syncthreads();
-  fft_lines<true, KT, KP>(buf, N, lnl, 1, tlo, thi);
+  fft_lines<true, KT, KP>(buf, N, LS, nl, tlo, thi);
   double *dst = (a < 3) ? hout + size_t(a) * nx * ny * nz : phi;
+  // (x, x + 1) pairs are 16-byte aligned for an even row length and base
+  const bool even = (nx & 1) == 0 && (reinterpret_cast<uintptr_t>(dst) & 15) == 0;
   for (int i = threadIdx.x; i < nl * N; i += KT) {
     const int line = i >> lN, m = i & (N - 1);
     if (line >= nr) continue;
     const cplx v = buf[line * LS + pd(m)];
     double *row = dst + size_t(r0 + line) * nx;
     const int xa = 2 * m, xb = 2 * m + 1;
-    if (xa < nx) row[xa] = v.x;
-    if (xb < nx) row[xb] = v.y;
+    if (even && xb < nx) {
+      *reinterpret_cast<double2 *>(row + xa) = make_double2(v.x, v.y);
+    } else {
+      if (xa < nx) row[xa] = v.x;
+      if (xb < nx) row[xb] = v.y;
+    }
   }
 }
 
@@ -534,7 +650,7 @@ demag_status z_conv(hipStream_t s, cplx *S, size_t as, const double *K, int Lz, 
   constexpr size_t lds = sizeof(cplx) * (cap(KP) + 128);
   demag_status st = allow_lds(k_z_conv<KT, KP>, lds);
   if (st != DEMAG_OK) return st;
-  const int l = ilog2(lines_per_wg(Lz, KP) / 4);
+  const int l = ilog2(lines_per_wg(Lz, KP, 4));
   const unsigned tiles = unsigned((H + (1 << l) - 1) >> l);
   k_z_conv<KT, KP><<<tiles * Ly, KT, lds, s>>>(S, as, K, Lz, nz, Ly, P, H, l, scale, phi_scale);
   return DEMAG_OK;
@@ -548,7 +664,7 @@ demag_status prepare_fft3d(demag_ctx *ctx, demag_factors *f) {
   if (st != DEMAG_OK) return st;
   const int Lx = fft_length(f->n[0]), Ly = fft_length(f->n[1]), Lz = fft_length(f->n[2]);
   const size_t npk = size_t(Lz / 2 + 1) * (Ly / 2 + 1) * pitch(Lx);
-  DEMAG_TRY_HIP(hipMalloc(&f->k3, 9 * npk * sizeof(double)));
+  DEMAG_TRY_HIP(hipMalloc(&f->k3, kKC * npk * sizeof(double)));
   k_kernel_spectra<<<unsigned((npk + 255) / 256), 256, 0, ctx->stream>>>(f->spec[0], f->spec[1], f->spec[2], f->k3,
                                                                         f->M, Lx, Ly, Lz, pitch(Lx));
   DEMAG_TRY_HIP(hipGetLastError());
@@ -571,18 +687,14 @@ demag_status launch_fft3d(demag_ctx *ctx, const demag_factors *f, const double *
   hipEvent_t ev = nullptr;
   demag_status st = prof_begin(ctx, &ev);
   if (st != DEMAG_OK) return st;
-  // x and y lines: up to 1024 points per line in one-wave workgroups, longer
-  // lines (2048) in 4096-point workgroups; z: four lines per column group
-  const bool big = (Lx / 2 > 1024) || Ly > 1024;
+  // x and y lines in 4096-point workgroups; the fused z pass in column groups
+  // of at least four lines (8192-point workgroups beyond Lz = 256)
   const double scale = 1.0 / (double(Lx) * Ly * Lz);
-  st = big ? xy_passes<256, 4096>::fwd(s, m, S, as, nx, ny, nz, Lx, Ly, P)
-           : xy_passes<64, 1024>::fwd(s, m, S, as, nx, ny, nz, Lx, Ly, P);
+  st = xy_passes<256, 4096>::fwd(s, m, S, as, nx, ny, nz, Lx, Ly, P);
   if (st == DEMAG_OK)
-    st = Lz > 1024 ? z_conv<512, 8192>(s, S, as, f->k3, Lz, nz, Ly, P, H, scale, f->L)
-                   : z_conv<256, 4096>(s, S, as, f->k3, Lz, nz, Ly, P, H, scale, f->L);
-  if (st == DEMAG_OK)
-    st = big ? xy_passes<256, 4096>::inv(s, S, as, phi, h, nx, ny, nz, Lx, Ly, P)
-             : xy_passes<64, 1024>::inv(s, S, as, phi, h, nx, ny, nz, Lx, Ly, P);
+    st = Lz > 256 ? z_conv<512, 8192>(s, S, as, f->k3, Lz, nz, Ly, P, H, scale, f->L)
+                  : z_conv<256, 4096>(s, S, as, f->k3, Lz, nz, Ly, P, H, scale, f->L);
+  if (st == DEMAG_OK) st = xy_passes<256, 4096>::inv(s, S, as, phi, h, nx, ny, nz, Lx, Ly, P);
   if (st != DEMAG_OK) return st;
   DEMAG_TRY_HIP(hipGetLastError());
   if (ev) {

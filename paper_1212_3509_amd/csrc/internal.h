@@ -151,7 +151,7 @@ struct demag_factors {
   bool spec_ready = false;
   double *spec[3] = {nullptr, nullptr, nullptr};   // [4][M][L/2+1] real or imaginary parts (structured path)
   void *twiddle[3] = {nullptr, nullptr, nullptr};  // double2 [L/2]
-  double *k3 = nullptr;    // 3D kernel spectra [9][Lz][Ly][Lx/2+1] (FFT apply)
+  double *k3 = nullptr;    // 3D kernel spectra, octant [Lz/2+1][Ly/2+1][pitch][10] (FFT apply)
   std::map<std::pair<int, int>, std::unique_ptr<demag::FullPlan>> plans;  // (prec class, kc)
 };
 

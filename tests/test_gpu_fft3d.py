@@ -56,6 +56,19 @@ def test_fft_apply_equals_mode_products(ctx, n):
     assert rel(p1, p2) < 1e-12 and rel(h1, h2) < 1e-12, (rel(p1, p2), rel(h1, h2))
 
 
+@pytest.mark.parametrize("n", [(6, 600, 3), (5, 3, 700), (1100 // 2, 2, 3)])
+def test_fft_apply_long_axes(ctx, n):
+    """Lines of 2048 points along y or z (multi-wave workgroups, four-line
+    column groups of the fused z pass) and real rows of 2048 points along x."""
+    m = _dev(inputs.random_unit_field(n, seed=8))
+    f = ctx.assemble(n, (1.0 / max(n),) * 3, M=12)
+    p1, h1 = ctx.apply_fft(f, m)
+    p2, h2 = ctx.apply_full(f, m, prec="fp64")
+    torch.cuda.synchronize()
+    rel = lambda a, b: float(torch.linalg.norm((a - b).reshape(-1)) / torch.linalg.norm(b.reshape(-1)))  # noqa: E731
+    assert rel(p1, p2) < 1e-12 and rel(h1, h2) < 1e-12, (rel(p1, p2), rel(h1, h2))
+
+
 def test_fft_apply_128_vortex(ctx):
     n = 128
     m = _dev(inputs.vortex_field(n, seed=0))
