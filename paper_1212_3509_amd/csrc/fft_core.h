@@ -1,0 +1,218 @@
+// FP64 complex FFTs in LDS shared by the structured apply and the 3D FFT
+// route: radix 16/8/4/2 Stockham passes over one or several lines, with
+// sizes known at compile time per line length.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace demag {
+namespace fftc {
+
+struct alignas(16) cplx {
+  double x, y;
+};
+__device__ inline cplx cadd(cplx a, cplx b) { return {a.x + b.x, a.y + b.y}; }
+__device__ inline cplx csub(cplx a, cplx b) { return {a.x - b.x, a.y - b.y}; }
+__device__ inline cplx cmul(cplx a, cplx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ inline cplx cconj(cplx a) { return {a.x, -a.y}; }
+template <bool INV> __device__ inline cplx mul_mi(cplx a) { return INV ? cplx{-a.y, a.x} : cplx{a.y, -a.x}; }
+
+// LDS slot of point i of line b: b * LS + pd(i), with one pad slot after
+// every 16 points.  16-byte LDS accesses are served eight lanes at a time,
+// conflict-free when those lanes hit distinct slots modulo 8.  Butterflies
+// run along a line across lanes (consecutive points: distinct, thanks to the
+// pad for the Stockham stride-R stores); the transposed accesses of the
+// strided passes put nl lines across lanes (fx fastest, then the point), and
+// are conflict-free for a line stride LS = 8 / min(nl, 8) modulo 8.
+__device__ inline int pd(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int line_stride(int N, int nl) {
+  const int base = N + (N - 1) / 16;                  // pd(N - 1) + 1
+  const int t = nl >= 8 ? 1 : 8 / nl;                 // wanted residue modulo 8
+  return nl == 1 ? base : base + ((t - base % 8) + 8) % 8;
+}
+__host__ __device__ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+// LDS points of a workgroup of shape <KT threads, KP points> (KP / KT = 16:
+// one radix-16 butterfly per thread and pass)
+__host__ __device__ constexpr int cap(int KP) { return KP + KP / 16 + 128; }
+// lines of N points (N <= KP) per workgroup, in groups of g lines that share
+// a column (g = 1, or 4 for the fused z pass); returns the lines per group
+__host__ __device__ inline int lines_per_wg(int N, int KP, int g = 1) {
+  int nl = KP / (N * g);
+  while (nl > 1 && g * nl * line_stride(N, nl) > cap(KP)) nl /= 2;
+  return nl;
+}
+
+template <bool INV> __device__ inline void dft2(cplx *v) {
+  const cplx t = v[0];
+  v[0] = cadd(t, v[1]);
+  v[1] = csub(t, v[1]);
+}
+template <bool INV> __device__ inline void dft4(cplx *v) {
+  const cplx s0 = cadd(v[0], v[2]), d0 = csub(v[0], v[2]);
+  const cplx s1 = cadd(v[1], v[3]), d1 = mul_mi<INV>(csub(v[1], v[3]));
+  v[0] = cadd(s0, s1);
+  v[2] = csub(s0, s1);
+  v[1] = cadd(d0, d1);
+  v[3] = csub(d0, d1);
+}
+// cos and sin of 2 pi e / 16 (compile-time constants after unrolling)
+__device__ constexpr double cos16(int e) {
+  constexpr double c[16] = {1.0, 0.92387953251128675613, 0.70710678118654752440, 0.38268343236508977173,
+                            0.0, -0.38268343236508977173, -0.70710678118654752440, -0.92387953251128675613,
+                            -1.0, -0.92387953251128675613, -0.70710678118654752440, -0.38268343236508977173,
+                            0.0, 0.38268343236508977173, 0.70710678118654752440, 0.92387953251128675613};
+  return c[e & 15];
+}
+__device__ constexpr double sin16(int e) { return cos16(e + 12); }   // sin x = cos(x - pi/2)
+
+// radix 8 = 4 x 2 and 16 = 4 x 4 (Cooley-Tukey split with constant twiddles)
+template <bool INV, int R1, int R2> __device__ inline void dft_split(cplx *v) {
+  cplx t[R1 * R2];
+#pragma unroll
+  for (int b = 0; b < R2; ++b) {
+    cplx col[R1];
+#pragma unroll
+    for (int a = 0; a < R1; ++a) col[a] = v[R2 * a + b];
+    dft4<INV>(col);
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) {
+      if (b * k1 == 0) {
+        t[b * R1 + k1] = col[k1];
+      } else {
+        const int e = (b * k1 * (16 / (R1 * R2))) & 15;   // angle 2 pi e / 16
+        t[b * R1 + k1] = cmul(col[k1], cplx{cos16(e), INV ? sin16(e) : -sin16(e)});
+      }
+    }
+  }
+#pragma unroll
+  for (int k1 = 0; k1 < R1; ++k1) {
+    cplx row[R2];
+#pragma unroll
+    for (int b = 0; b < R2; ++b) row[b] = t[b * R1 + k1];
+    if (R2 == 2) dft2<INV>(row);
+    else dft4<INV>(row);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = row[k2];
+  }
+}
+template <bool INV, int R> __device__ inline void dftR(cplx *v) {
+  if (R == 2) dft2<INV>(v);
+  else if (R == 4) dft4<INV>(v);
+  else if (R == 8) dft_split<INV, 4, 2>(v);
+  else dft_split<INV, 4, 4>(v);
+}
+
+// W_N^e (forward sign) from two LDS tables: lo[i] = W_N^i, hi[i] = W_N^(64 i).
+__device__ inline cplx twid(int e, const cplx *lo, const cplx *hi) {
+  const cplx a = lo[e & 63];
+  return (e >> 6) ? cmul(a, hi[e >> 6]) : a;
+}
+__device__ inline void make_twiddles(cplx *lo, cplx *hi, int N) {
+  for (int t = threadIdx.x; t < 128; t += blockDim.x) {
+    double s, c;
+    sincospi(-2.0 * double(t < 64 ? t : 64 * (t - 64)) / double(N), &s, &c);
+    (t < 64 ? lo[t] : hi[t - 64]) = cplx{c, s};
+  }
+}
+
+// One Stockham pass of radix R over nlines lines of N points at line stride
+// LS (input sub-transform length Ns).  Butterfly g: line g / (N / R), index
+// g % (N / R).  The first pass (Ns = 1) has no twiddles.
+template <bool INV, int R, int KT, int KP, int N, int Ns>
+__device__ inline void pass(cplx *buf, int LS, int nlines, const cplx *tlo, const cplx *thi) {
+  constexpr int per = N / R;             // butterflies per line
+  constexpr int lper = ilog2(per);
+  constexpr int kMaxB = (KP / R + KT - 1) / KT;
+  const int nb = nlines << lper;
+  cplx v[kMaxB][R];
+#pragma unroll
+  for (int q = 0; q < kMaxB; ++q) {
+    const int g = threadIdx.x + q * KT;
+    if (g < nb) {
+      const int j = g & (per - 1), line = g >> lper;
+      const cplx *lb = buf + line * LS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = lb[pd(j + r * per)];
+      if constexpr (Ns > 1) {
+        const int k = j & (Ns - 1);
+        cplx w = twid(k * (N / (Ns * R)), tlo, thi);
+        if (INV) w = cconj(w);
+        // powers w^r, r < R, as w^(4a + b) = (w^4)^a w^b: dependency depth 5
+        cplx wp[R];
+        wp[1] = w;
+        if constexpr (R > 2) {
+          wp[2] = cmul(w, w);
+          wp[3] = cmul(wp[2], w);
+        }
+        if constexpr (R > 4) {
+          wp[4] = cmul(wp[2], wp[2]);
+#pragma unroll
+          for (int r = 5; r < 8; ++r) wp[r] = cmul(wp[4], wp[r - 4]);
+        }
+        if constexpr (R > 8) {
+          wp[8] = cmul(wp[4], wp[4]);
+          wp[12] = cmul(wp[8], wp[4]);
+#pragma unroll
+          for (int r = 9; r < 12; ++r) wp[r] = cmul(wp[8], wp[r - 8]);
+#pragma unroll
+          for (int r = 13; r < 16; ++r) wp[r] = cmul(wp[12], wp[r - 12]);
+        }
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = cmul(v[q][r], wp[r]);
+      }
+      dftR<INV, R>(v[q]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kMaxB; ++q) {
+    const int g = threadIdx.x + q * KT;
+    if (g < nb) {
+      const int j = g & (per - 1), line = g >> lper;
+      const int k = j & (Ns - 1);
+      const int o = (j / Ns) * Ns * R + k;
+      cplx *lb = buf + line * LS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lb[pd(o + r * Ns)] = v[q][r];
+    }
+  }
+  __syncthreads();
+}
+
+// Complex FFTs of nlines lines of N points at line stride LS (power of 2, N <= 4096) in
+// LDS: a fixed pass plan per length (radix 16 first), each pass inlined with
+// its sizes known at compile time, so that the register allocation and the
+// index arithmetic are per pass.
+template <bool INV, int KT, int KP, int N, int Ns, int R0, int... Rs>
+__device__ inline void run_passes(cplx *buf, int LS, int nlines, const cplx *tlo, const cplx *thi) {
+  pass<INV, R0, KT, KP, N, Ns>(buf, LS, nlines, tlo, thi);
+  if constexpr (sizeof...(Rs) > 0) run_passes<INV, KT, KP, N, Ns * R0, Rs...>(buf, LS, nlines, tlo, thi);
+}
+template <bool INV, int KT, int KP>
+__device__ __noinline__ void fft_lines(cplx *buf, int N, int LS, int nlines, const cplx *tlo, const cplx *thi) {
+  switch (N) {
+    case 2: run_passes<INV, KT, KP, 2, 1, 2>(buf, LS, nlines, tlo, thi); break;
+    case 4: run_passes<INV, KT, KP, 4, 1, 4>(buf, LS, nlines, tlo, thi); break;
+    case 8: run_passes<INV, KT, KP, 8, 1, 8>(buf, LS, nlines, tlo, thi); break;
+    case 16: run_passes<INV, KT, KP, 16, 1, 16>(buf, LS, nlines, tlo, thi); break;
+    case 32: run_passes<INV, KT, KP, 32, 1, 16, 2>(buf, LS, nlines, tlo, thi); break;
+    case 64: run_passes<INV, KT, KP, 64, 1, 16, 4>(buf, LS, nlines, tlo, thi); break;
+    case 128: run_passes<INV, KT, KP, 128, 1, 16, 8>(buf, LS, nlines, tlo, thi); break;
+    case 256: run_passes<INV, KT, KP, 256, 1, 16, 16>(buf, LS, nlines, tlo, thi); break;
+    case 512: run_passes<INV, KT, KP, 512, 1, 16, 16, 2>(buf, LS, nlines, tlo, thi); break;
+    case 1024: run_passes<INV, KT, KP, 1024, 1, 16, 16, 4>(buf, LS, nlines, tlo, thi); break;
+    case 2048: run_passes<INV, KT, KP, 2048, 1, 16, 16, 8>(buf, LS, nlines, tlo, thi); break;
+    case 4096: run_passes<INV, KT, KP, 4096, 1, 16, 16, 16>(buf, LS, nlines, tlo, thi); break;
+    default: break;   // N = 1: identity
+  }
+}
+
+// W_L^f for the real-transform (un)packing, L = 2N: W_N^(f/2), times W_L^1 for odd f.
+__device__ inline cplx wl(int f, int N, const cplx *tlo, const cplx *thi, cplx w1) {
+  cplx w = twid((f >> 1) & (N - 1), tlo, thi);
+  if (f & 1) w = cmul(w, w1);
+  return w;
+}
+
+}  // namespace fftc
+}  // namespace demag
