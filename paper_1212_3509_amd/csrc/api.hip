@@ -391,11 +391,7 @@ demag_status demag_apply_columns(demag_ctx *ctx, demag_factors *f, const int32_t
   DEMAG_TRY_HIP(hipSetDevice(ctx->device));
   demag_status st = prepare_spectra(ctx, f);
   if (st != DEMAG_OK) return st;
-  for (int d = 0; d < 3; ++d) {
-    st = launch_columns(ctx, f, d, R[d], in[d], out[d]);
-    if (st != DEMAG_OK) return st;
-  }
-  return DEMAG_OK;
+  return launch_columns(ctx, f, R, in, out);
 }
 
 namespace {

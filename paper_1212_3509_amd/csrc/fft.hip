@@ -24,15 +24,16 @@
 // from two 64-entry tables in LDS, W_N^e = W_N^(e mod 64) W_N^(64 (e div 64)),
 // so no pass waits on global memory.
 //
-// Two launches per axis: k_fft_fwd transforms every input column once and
-// stores its unpacked spectrum U[0..N] in the workspace; k_fft_jobs gives
-// each workgroup a few jobs of one column: it loads the column's frequency
-// pairs (f, N - f) into registers (from L2: every job group of a column reads
-// the same 64 KB), and per job multiplies by a kernel spectrum, transforms
-// back and writes the n outputs.
+// Two launches per apply, covering the three axes: k_fft_fwd transforms
+// every input column once and stores its unpacked spectrum U[0..N] in the
+// workspace; k_fft_jobs gives each workgroup a few jobs of one column: per
+// job it reads the column's frequency pairs (f, N - f) and the kernel
+// spectrum (from L2: every job group of a column reads the same 64 KB),
+// multiplies, transforms back and writes the n outputs.
 #include "fft_core.h"
 #include "internal.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace demag {
@@ -102,15 +103,40 @@ __global__ void k_twiddles(double2 *__restrict__ tw, int N) {
 // frequency pairs (f, N - f), f = 0..N/2, per thread at N = 4096: 2049 pairs
 constexpr int kMaxPairs = (kPoints / 2 + 1 + kThreads - 1) / kThreads;
 
+// The three axes of one structured apply run in the same two launches; a
+// workgroup finds its axis from the first column / workgroup of each.
+struct ColAxis {
+  const float *in;
+  float *out;
+  const double *spec;
+  const double2 *tw;
+  size_t u_off;              // first spectrum of this axis in U (points)
+  int n, L, R;
+  int col0, wg0;             // first column, first jobs workgroup
+  int per, groups;           // jobs per group, groups per column
+};
+struct ColAxes {
+  ColAxis a[3];
+  int M;
+};
+__device__ inline int axis_of(const ColAxes &P, int idx, bool wg) {
+  int d = 0;
+  for (int e = 1; e < 3; ++e)
+    if (idx >= (wg ? P.a[e].wg0 : P.a[e].col0)) d = e;
+  return d;
+}
+
 // Forward real transform of every column: U[col][f], f = 0..N (N + 1 values).
-__global__ __launch_bounds__(kThreads) void k_fft_fwd(const float *__restrict__ in, cplx *__restrict__ U,
-                                                      const double2 *__restrict__ tw, int n, int L) {
+__global__ __launch_bounds__(kThreads) void k_fft_fwd(const ColAxes P, cplx *__restrict__ Uall, int lds_points) {
   extern __shared__ cplx wk[];   // N points (padded), then the twiddle tables
-  const int N = L / 2;
-  cplx *tlo = wk + padded_points(N), *thi = tlo + 64;
-  const int col = blockIdx.x;
-  load_twiddles(tlo, thi, N, tw);
-  const float *u = in + size_t(col) * n;
+  const int d = axis_of(P, blockIdx.x, false);
+  const ColAxis &A = P.a[d];
+  const int n = A.n, L = A.L, N = L / 2;
+  cplx *tlo = wk + lds_points, *thi = tlo + 64;
+  const int col = blockIdx.x - A.col0;
+  load_twiddles(tlo, thi, N, A.tw);
+  cplx *U = Uall + A.u_off;
+  const float *u = A.in + size_t(col) * n;
   // all loads of a thread in flight before the LDS stores
   constexpr int kE = kPoints / kThreads;
   cplx v[kE];
@@ -140,29 +166,32 @@ __global__ __launch_bounds__(kThreads) void k_fft_fwd(const float *__restrict__ 
   }
 }
 
-// Grid: x = input column (q * R + l), y = job group.  Jobs of a column are
-// its (s, k) pairs, j = s * M + k, in contiguous groups of jobs_per_group.
+// Workgroup = (axis, input column q * R + l, job group).  Jobs of a column
+// are its (s, k) pairs, j = s * M + k, in contiguous groups of A.per.
 // Per job the column spectrum is read again (from L2) rather than held in
 // registers, which keeps two workgroups resident per CU.
-__global__ __launch_bounds__(kThreads) void k_fft_jobs(const cplx *__restrict__ U, float *__restrict__ out,
-                                                       const double *__restrict__ spec,
-                                                       const double2 *__restrict__ tw, int n, int L, int M, int R,
-                                                       int axis, int jobs_per_group) {
+__global__ __launch_bounds__(kThreads) void k_fft_jobs(const ColAxes P, const cplx *__restrict__ Uall,
+                                                       int lds_points) {
   extern __shared__ cplx wk[];   // N points (padded), then the twiddle tables
-  const int N = L / 2;
-  cplx *tlo = wk + padded_points(N), *thi = tlo + 64;
-  const int col = blockIdx.x;   // q * R + l
+  const int axis = axis_of(P, blockIdx.x, true);
+  const ColAxis &A = P.a[axis];
+  const int n = A.n, L = A.L, N = L / 2, R = A.R, M = P.M;
+  cplx *tlo = wk + lds_points, *thi = tlo + 64;
+  const int local = blockIdx.x - A.wg0;
+  const int col = local / A.groups, grp = local - col * A.groups;   // col = q * R + l
   const int q = col / R, l = col % R;
-  load_twiddles(tlo, thi, N, tw);
+  load_twiddles(tlo, thi, N, A.tw);
   double sw, cw;
   sincospi(-1.0 / double(N), &sw, &cw);
   const cplx w1{cw, sw};         // W_L^1
-  const cplx *Uc = U + size_t(col) * (N + 1);
+  const cplx *Uc = Uall + A.u_off + size_t(col) * (N + 1);
+  const double *spec = A.spec;
+  float *out = A.out;
   __syncthreads();
 
   const int njobs = 2 * M;
-  const int j0 = blockIdx.y * jobs_per_group;
-  const int j1 = min(njobs, j0 + jobs_per_group);
+  const int j0 = grp * A.per;
+  const int j1 = min(njobs, j0 + A.per);
   const double inv_n = 1.0 / double(N);
   for (int j = j0; j < j1; ++j) {
     const int s = j / M, k = j % M;
@@ -258,44 +287,65 @@ demag_status prepare_spectra(demag_ctx *ctx, demag_factors *f) {
   return DEMAG_OK;
 }
 
-demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, int d, int R, const float *in, float *out) {
-  const int n = f->n[d];
-  const int L = fft_length(n);
-  const int N = L / 2;
-  const int ncols = 3 * R;
-  if (ncols == 0) return DEMAG_OK;
-  // column spectra in the workspace
-  demag_status st = ensure_workspace(ctx, sizeof(double2) * size_t(ncols) * (N + 1));
-  if (st != DEMAG_OK) return st;
-  cplx *U = static_cast<cplx *>(ctx->ws);
+demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, const int32_t R[3], const float *const in[3],
+                            float *const out[3]) {
+  ColAxes P{};
+  P.M = f->M;
+  const int njobs = 2 * f->M;
+  int ncols_all = 0, maxN = 1;
+  size_t u_points = 0;
+  double flops = 0.0, bytes = 0.0;
+  for (int d = 0; d < 3; ++d) ncols_all += 3 * R[d];
+  if (ncols_all == 0) return DEMAG_OK;
   // job groups per column: enough workgroups to fill the chip (>= 4 per CU)
   int target = 1;
-  const int njobs = 2 * f->M;
-  while (ncols * target < 1024 && target < njobs) target *= 2;
+  while (ncols_all * target < 1024 && target < njobs) target *= 2;
   const int per = (njobs + target - 1) / target;
   const int groups = (njobs + per - 1) / per;   // every group owns >= 1 job
-  const size_t lds = sizeof(double2) * (size_t(padded_points(N)) + 128);
+  int col0 = 0, wg0 = 0;
+  for (int d = 0; d < 3; ++d) {
+    ColAxis &A = P.a[d];
+    const int ncols = 3 * R[d];
+    A.in = in[d];
+    A.out = out[d];
+    A.spec = f->spec[d];
+    A.tw = reinterpret_cast<const double2 *>(f->twiddle[d]);
+    A.n = f->n[d];
+    A.L = fft_length(f->n[d]);
+    A.R = R[d];
+    A.col0 = col0;
+    A.wg0 = wg0;
+    A.per = per;
+    A.groups = groups;
+    A.u_off = u_points;
+    col0 += ncols;
+    wg0 += ncols * groups;
+    u_points += size_t(ncols) * (A.L / 2 + 1);
+    if (ncols > 0) maxN = std::max(maxN, A.L / 2);
+    // real FFT of length L ~ 2.5 L log2 L flops, forward once per column
+    const double jobs = double(ncols) * njobs, lg = std::log2(double(A.L));
+    flops += (jobs + ncols) * 2.5 * A.L * lg;
+    // compulsory traffic: input columns, spectra, output columns
+    bytes += 4.0 * (double(ncols) * A.n + jobs * A.n) + 8.0 * double(F_NTYPES) * f->M * (A.L / 2 + 1);
+  }
+  // column spectra of all three axes in the workspace
+  demag_status st = ensure_workspace(ctx, sizeof(double2) * u_points);
+  if (st != DEMAG_OK) return st;
+  cplx *U = static_cast<cplx *>(ctx->ws);
+  const int lds_points = padded_points(maxN);
+  const size_t lds = sizeof(double2) * (size_t(lds_points) + 128);
   DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_fwd),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_jobs),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-  const double2 *tw = reinterpret_cast<const double2 *>(f->twiddle[d]);
   hipEvent_t ev = nullptr;
   st = prof_begin(ctx, &ev);
   if (st != DEMAG_OK) return st;
-  k_fft_fwd<<<ncols, kThreads, lds, ctx->stream>>>(in, U, tw, n, L);
+  k_fft_fwd<<<ncols_all, kThreads, lds, ctx->stream>>>(P, U, lds_points);
   DEMAG_TRY_HIP(hipGetLastError());
-  k_fft_jobs<<<dim3(ncols, groups), kThreads, lds, ctx->stream>>>(U, out, f->spec[d], tw, n, L, f->M, R, d, per);
+  k_fft_jobs<<<wg0, kThreads, lds, ctx->stream>>>(P, U, lds_points);
   DEMAG_TRY_HIP(hipGetLastError());
-  if (ev) {
-    const double jobs = double(ncols) * njobs;
-    // real FFT of length L ~ 2.5 L log2 L flops, forward once per column
-    const double lg = std::log2(double(L));
-    const double flops = (jobs + ncols) * 2.5 * L * lg;
-    // compulsory traffic: input columns, spectra, output columns
-    const double bytes = 4.0 * (double(ncols) * n + jobs * n) + 8.0 * double(F_NTYPES) * f->M * (N + 1);
-    st = prof_end(ctx, ev, std::string("fft/") + "xyz"[d], flops, bytes);
-  }
+  if (ev) st = prof_end(ctx, ev, "fft/xyz", flops, bytes);
   return st;
 }
 

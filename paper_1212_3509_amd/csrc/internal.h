@@ -184,5 +184,6 @@ demag_status prepare_fft3d(demag_ctx *ctx, demag_factors *f);
 size_t fft3d_workspace_bytes(const demag_factors *f);
 demag_status launch_fft3d(demag_ctx *ctx, const demag_factors *f, const double *m, double *phi, double *h,
                           void *ws);
-demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, int d, int R, const float *in, float *out);
+demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, const int32_t R[3], const float *const in[3],
+                            float *const out[3]);
 } // namespace demag
