@@ -166,6 +166,18 @@ __global__ __launch_bounds__(kThreads) void k_fft_fwd(const ColAxes P, cplx *__r
   }
 }
 
+// Output of the inverse transform: point m of z holds x[2m] + i x[2m+1].
+struct OutSink {
+  float *y;
+  int n;
+  double inv_n;
+  __device__ void operator()(int, int m, cplx z) const {
+    const int a = 2 * m, b = 2 * m + 1;
+    if (a < n) y[a] = float(z.x * inv_n);
+    if (b < n) y[b] = float(z.y * inv_n);
+  }
+};
+
 // Workgroup = (axis, input column q * R + l, job group).  Jobs of a column
 // are its (s, k) pairs, j = s * M + k, in contiguous groups of A.per.
 // Per job the column spectrum is read again (from L2) rather than held in
@@ -244,14 +256,11 @@ __global__ __launch_bounds__(kThreads) void k_fft_jobs(const ColAxes P, const cp
       }
     }
     __syncthreads();
-    fft_lines<true, kThreads, kPoints>(wk, N, padded_points(N), 1, tlo, thi);
+    // inverse transform; the last pass writes the n outputs (x[2m], x[2m+1]
+    // = Re, Im z[m] / N) straight from registers
     float *y = out + ((size_t(q) * 2 + s) * M + k) * size_t(R) * n + size_t(l) * n;
-    for (int m = threadIdx.x; m < N; m += kThreads) {
-      const cplx z = wk[pd(m)];
-      const int a = 2 * m, b = 2 * m + 1;
-      if (a < n) y[a] = float(z.x * inv_n);
-      if (b < n) y[b] = float(z.y * inv_n);
-    }
+    fft_lines_to<true, kThreads, kPoints>(wk, N, padded_points(N), 1, tlo, thi,
+                                          OutSink{y, n, inv_n});
     __syncthreads();
   }
 }

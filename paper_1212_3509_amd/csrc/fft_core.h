@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace demag {
 namespace fftc {
 
@@ -118,8 +120,13 @@ __device__ inline void make_twiddles(cplx *lo, cplx *hi, int N) {
 // One Stockham pass of radix R over nlines lines of N points at line stride
 // LS (input sub-transform length Ns).  Butterfly g: line g / (N / R), index
 // g % (N / R).  The first pass (Ns = 1) has no twiddles.
-template <bool INV, int R, int KT, int KP, int N, int Ns>
-__device__ inline void pass(cplx *buf, int LS, int nlines, const cplx *tlo, const cplx *thi) {
+// Destination of the results of a pass: the LDS lines (ToLds), or, for the
+// last pass of a transform, a functor sink(line, index, value).
+struct ToLds {};
+
+template <bool INV, int R, int KT, int KP, int N, int Ns, typename Sink = ToLds>
+__device__ inline void pass(cplx *buf, int LS, int nlines, const cplx *tlo, const cplx *thi,
+                            const Sink &sink = Sink{}) {
   constexpr int per = N / R;             // butterflies per line
   constexpr int lper = ilog2(per);
   constexpr int kMaxB = (KP / R + KT - 1) / KT;
@@ -163,48 +170,77 @@ __device__ inline void pass(cplx *buf, int LS, int nlines, const cplx *tlo, cons
       dftR<INV, R>(v[q]);
     }
   }
-  __syncthreads();
+  if constexpr (std::is_same_v<Sink, ToLds>) {
+    __syncthreads();
 #pragma unroll
-  for (int q = 0; q < kMaxB; ++q) {
-    const int g = threadIdx.x + q * KT;
-    if (g < nb) {
-      const int j = g & (per - 1), line = g >> lper;
-      const int k = j & (Ns - 1);
-      const int o = (j / Ns) * Ns * R + k;
-      cplx *lb = buf + line * LS;
+    for (int q = 0; q < kMaxB; ++q) {
+      const int g = threadIdx.x + q * KT;
+      if (g < nb) {
+        const int j = g & (per - 1), line = g >> lper;
+        const int k = j & (Ns - 1);
+        const int o = (j / Ns) * Ns * R + k;
+        cplx *lb = buf + line * LS;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lb[pd(o + r * Ns)] = v[q][r];
+        for (int r = 0; r < R; ++r) lb[pd(o + r * Ns)] = v[q][r];
+      }
+    }
+    __syncthreads();
+  } else {
+    // no LDS writes: callers synchronize before reusing the lines
+#pragma unroll
+    for (int q = 0; q < kMaxB; ++q) {
+      const int g = threadIdx.x + q * KT;
+      if (g < nb) {
+        const int j = g & (per - 1), line = g >> lper;
+        const int k = j & (Ns - 1);
+        const int o = (j / Ns) * Ns * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) sink(line, o + r * Ns, v[q][r]);
+      }
     }
   }
-  __syncthreads();
 }
 
 // Complex FFTs of nlines lines of N points at line stride LS (power of 2, N <= 4096) in
 // LDS: a fixed pass plan per length (radix 16 first), each pass inlined with
 // its sizes known at compile time, so that the register allocation and the
 // index arithmetic are per pass.
-template <bool INV, int KT, int KP, int N, int Ns, int R0, int... Rs>
-__device__ inline void run_passes(cplx *buf, int LS, int nlines, const cplx *tlo, const cplx *thi) {
-  pass<INV, R0, KT, KP, N, Ns>(buf, LS, nlines, tlo, thi);
-  if constexpr (sizeof...(Rs) > 0) run_passes<INV, KT, KP, N, Ns * R0, Rs...>(buf, LS, nlines, tlo, thi);
+template <bool INV, int KT, int KP, int N, int Ns, typename Sink, int R0, int... Rs>
+__device__ inline void run_passes(cplx *buf, int LS, int nlines, const cplx *tlo, const cplx *thi, const Sink &sink) {
+  if constexpr (sizeof...(Rs) > 0) {
+    pass<INV, R0, KT, KP, N, Ns>(buf, LS, nlines, tlo, thi);
+    run_passes<INV, KT, KP, N, Ns * R0, Sink, Rs...>(buf, LS, nlines, tlo, thi, sink);
+  } else {
+    pass<INV, R0, KT, KP, N, Ns, Sink>(buf, LS, nlines, tlo, thi, sink);
+  }
+}
+// Transforms whose last pass hands its results to sink (ToLds: in place).
+template <bool INV, int KT, int KP, typename Sink>
+__device__ __noinline__ void fft_lines_to(cplx *buf, int N, int LS, int nlines, const cplx *tlo, const cplx *thi,
+                                          Sink sink) {
+  switch (N) {
+    case 2: run_passes<INV, KT, KP, 2, 1, Sink, 2>(buf, LS, nlines, tlo, thi, sink); break;
+    case 4: run_passes<INV, KT, KP, 4, 1, Sink, 4>(buf, LS, nlines, tlo, thi, sink); break;
+    case 8: run_passes<INV, KT, KP, 8, 1, Sink, 8>(buf, LS, nlines, tlo, thi, sink); break;
+    case 16: run_passes<INV, KT, KP, 16, 1, Sink, 16>(buf, LS, nlines, tlo, thi, sink); break;
+    case 32: run_passes<INV, KT, KP, 32, 1, Sink, 16, 2>(buf, LS, nlines, tlo, thi, sink); break;
+    case 64: run_passes<INV, KT, KP, 64, 1, Sink, 16, 4>(buf, LS, nlines, tlo, thi, sink); break;
+    case 128: run_passes<INV, KT, KP, 128, 1, Sink, 16, 8>(buf, LS, nlines, tlo, thi, sink); break;
+    case 256: run_passes<INV, KT, KP, 256, 1, Sink, 16, 16>(buf, LS, nlines, tlo, thi, sink); break;
+    case 512: run_passes<INV, KT, KP, 512, 1, Sink, 16, 16, 2>(buf, LS, nlines, tlo, thi, sink); break;
+    case 1024: run_passes<INV, KT, KP, 1024, 1, Sink, 16, 16, 4>(buf, LS, nlines, tlo, thi, sink); break;
+    case 2048: run_passes<INV, KT, KP, 2048, 1, Sink, 16, 16, 8>(buf, LS, nlines, tlo, thi, sink); break;
+    case 4096: run_passes<INV, KT, KP, 4096, 1, Sink, 16, 16, 16>(buf, LS, nlines, tlo, thi, sink); break;
+    default:   // N = 1: identity
+      if constexpr (!std::is_same_v<Sink, ToLds>) {
+        for (int line = threadIdx.x; line < nlines; line += KT) sink(line, 0, buf[line * LS]);
+      }
+      break;
+  }
 }
 template <bool INV, int KT, int KP>
-__device__ __noinline__ void fft_lines(cplx *buf, int N, int LS, int nlines, const cplx *tlo, const cplx *thi) {
-  switch (N) {
-    case 2: run_passes<INV, KT, KP, 2, 1, 2>(buf, LS, nlines, tlo, thi); break;
-    case 4: run_passes<INV, KT, KP, 4, 1, 4>(buf, LS, nlines, tlo, thi); break;
-    case 8: run_passes<INV, KT, KP, 8, 1, 8>(buf, LS, nlines, tlo, thi); break;
-    case 16: run_passes<INV, KT, KP, 16, 1, 16>(buf, LS, nlines, tlo, thi); break;
-    case 32: run_passes<INV, KT, KP, 32, 1, 16, 2>(buf, LS, nlines, tlo, thi); break;
-    case 64: run_passes<INV, KT, KP, 64, 1, 16, 4>(buf, LS, nlines, tlo, thi); break;
-    case 128: run_passes<INV, KT, KP, 128, 1, 16, 8>(buf, LS, nlines, tlo, thi); break;
-    case 256: run_passes<INV, KT, KP, 256, 1, 16, 16>(buf, LS, nlines, tlo, thi); break;
-    case 512: run_passes<INV, KT, KP, 512, 1, 16, 16, 2>(buf, LS, nlines, tlo, thi); break;
-    case 1024: run_passes<INV, KT, KP, 1024, 1, 16, 16, 4>(buf, LS, nlines, tlo, thi); break;
-    case 2048: run_passes<INV, KT, KP, 2048, 1, 16, 16, 8>(buf, LS, nlines, tlo, thi); break;
-    case 4096: run_passes<INV, KT, KP, 4096, 1, 16, 16, 16>(buf, LS, nlines, tlo, thi); break;
-    default: break;   // N = 1: identity
-  }
+__device__ inline void fft_lines(cplx *buf, int N, int LS, int nlines, const cplx *tlo, const cplx *thi) {
+  fft_lines_to<INV, KT, KP>(buf, N, LS, nlines, tlo, thi, ToLds{});
 }
 
 // W_L^f for the real-transform (un)packing, L = 2N: W_N^(f/2), times W_L^1 for odd f.
