@@ -231,6 +231,33 @@ demag_status demag_apply_tt(demag_ctx *ctx, demag_factors *f, int32_t r1, int32_
                             const float *G1, const float *G2, const float *G3,
                             float *const out[3], int32_t *table);
 
+/* ---------------------------------------------------------------- recompression
+ * Tolerance-controlled recompression of a CP tensor to Tucker form by HOOI
+ * (Sec. 2.2, Alg. HOOI), for the CP results of demag_apply_cp: the tensor
+ *   X = sum_t lam[t] c0[table[t][0]] o c1[table[t][1]] o c2[table[t][2]]
+ * (mode p column sets cols[p] = [ncols[p]][n[p]] FP32, device; table int32
+ * [T][3] and lam FP64 [T], device) becomes [[core; U0, U1, U2]] with
+ * orthonormal factor rows U_p [ranks[p]][n[p]] and core [r0][r1][r2]
+ * (index (a r1 + b) r2 + c), FP64, device buffers of capacity rmax rows and
+ * rmax^3.  Rank rule per mode and sweep: the smallest r whose discarded
+ * singular values of the projected unfolding have a norm of at most
+ * eps / sqrt(3) of all of them, capped at rmax (1..64).  Sweeps stop when the
+ * squared core norm changes by at most 1e-13 relative, or after max_sweeps.
+ * Singular subspaces come from a randomized range finder with K = rmax + 8
+ * candidates: omega = three Gaussian test matrices [K][n_p] one after another
+ * (initial factors, Khatri-Rao test vectors), gmat = a Gaussian [K*K][K]
+ * matrix (sweeps), FP64 device, supplied by the caller.  Host outputs: ranks,
+ * *rel_err = |X - [[core; U]]|_F / |X|_F (computed without cancellation),
+ * *sweeps.  Synchronizes the stream; uses the context workspace (about
+ * 8 (T (n0 + n1 + n2) + 6 T^2) bytes).  Errors: DEMAG_E_INVAL for NULL
+ * pointers, sizes out of range, table entries outside the column sets or a
+ * zero tensor. */
+demag_status demag_recompress_cp(demag_ctx *ctx, const int32_t n[3], int32_t T, const float *const cols[3],
+                                 const int32_t ncols[3], const int32_t *table, const double *lam, double eps,
+                                 int32_t rmax, int32_t max_sweeps, const double *omega, const double *gmat,
+                                 double *const U[3], double *core, int32_t ranks[3], double *rel_err,
+                                 int32_t *sweeps);
+
 /* ---------------------------------------------------------------- learned rule
  * A network proposes shortened rules (R' = 16..32 nodes); an FP64 judge
  * measures their kernel error; the full rule is the fallback.  Not part of

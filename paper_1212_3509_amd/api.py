@@ -75,6 +75,8 @@ _SIGS = {
     "demag_apply_cp": (C.c_int, [_P, _P, C.c_int32, _P, _P, _P]),
     "demag_apply_tucker": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "demag_apply_tt": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P]),
+    "demag_recompress_cp": (C.c_int, [_P, _P, C.c_int32, _P, _P, _P, _P, C.c_double, C.c_int32, C.c_int32, _P,
+                                      _P, _P, _P, _P, _P, _P]),
     "demag_bf16_split": (C.c_int, [_P, _P, _P, C.c_size_t, C.c_int32]),
     "demag_profile_enable": (C.c_int, [_P, C.c_int32]),
     "demag_profile_read": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, C.POINTER(C.c_int32)]),
@@ -326,6 +328,33 @@ class Context:
         _check(library().demag_apply_tt(self.handle, f.handle, r1, r2, _ptr(G1), _ptr(G2), _ptr(G3),
                                         self._ptr3(out), table.ctypes.data), "demag_apply_tt")
         return out, table
+
+    def recompress_cp(self, n, cols, table, lam, eps, rmax=32, max_sweeps=10, seed=7):
+        """HOOI recompression of the CP tensor sum_t lam[t] cols[0][table[t,0]] o
+        cols[1][table[t,1]] o cols[2][table[t,2]] (cols: float32 CUDA [ncols][n_p];
+        table int32 [T][3], lam float64 [T], CUDA) to Tucker form.  The
+        Gaussian test matrices come from inputs.recompress_test_matrices(seed).
+        Returns dict(U [3] (r_p x n_p), core (r0, r1, r2), ranks, rel_err, sweeps)."""
+        import torch
+        from . import inputs
+        T = int(lam.shape[0])
+        dev = lam.device
+        omega, gmat = inputs.recompress_test_matrices(tuple(n), rmax, seed)
+        om = torch.from_numpy(omega).to(dev)
+        gm = torch.from_numpy(gmat).to(dev)
+        U = [torch.empty((rmax, n[p]), dtype=torch.float64, device=dev) for p in range(3)]
+        core = torch.empty(rmax ** 3, dtype=torch.float64, device=dev)
+        ranks = (C.c_int32 * 3)()
+        err, sweeps = C.c_double(), C.c_int32()
+        n3 = (C.c_int32 * 3)(*n)
+        nc = (C.c_int32 * 3)(*[int(c.shape[0]) for c in cols])
+        self.use_current_stream()
+        _check(library().demag_recompress_cp(self.handle, n3, T, self._ptr3(cols), nc, _ptr(table), _ptr(lam), eps,
+                                             rmax, max_sweeps, _ptr(om), _ptr(gm), self._ptr3(U), _ptr(core),
+                                             ranks, C.byref(err), C.byref(sweeps)), "demag_recompress_cp")
+        r = [ranks[p] for p in range(3)]
+        return {"U": [U[p][:r[p]] for p in range(3)], "core": core[:r[0] * r[1] * r[2]].reshape(r),
+                "ranks": tuple(r), "rel_err": err.value, "sweeps": sweeps.value}
 
     # ------------------------------------------------------------ learned rule
     def mlp_forward(self, params, x):

@@ -268,3 +268,14 @@ def quad_features(n, h, log10_tol, rprime) -> np.ndarray:
                         ((np.atleast_1d(log10_tol) + 6.5) / 2.5)[:, None],
                         ((np.atleast_1d(rprime).astype(np.float64) - 24.0) / 8.0)[:, None]], axis=1)
     return x.astype(np.float32)
+
+
+def recompress_test_matrices(n, rmax: int, seed: int = 7):
+    """Gaussian test matrices of the randomized range finder of the HOOI
+    recompression, K = rmax + 8 candidates: omega = [K][n_p] for p = 0, 1, 2
+    one after another, gmat = [K * K][K] (float64)."""
+    K = rmax + 8
+    rng = _rng(seed)
+    omega = np.concatenate([rng.standard_normal((K, int(n[p]))).ravel() for p in range(3)])
+    gmat = rng.standard_normal((K * K, K))
+    return omega, np.ascontiguousarray(gmat.ravel())
