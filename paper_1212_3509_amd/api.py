@@ -331,7 +331,8 @@ class Context:
 
     def recompress_cp(self, n, cols, table, lam, eps, rmax=32, max_sweeps=10, seed=7):
         """HOOI recompression of the CP tensor sum_t lam[t] cols[0][table[t,0]] o
-        cols[1][table[t,1]] o cols[2][table[t,2]] (cols: float32 CUDA [ncols][n_p];
+        cols[1][table[t,1]] o cols[2][table[t,2]] (cols: contiguous float32 CUDA
+        column sets, ncols x n_p values, e.g. the outputs of apply_cp;
         table int32 [T][3], lam float64 [T], CUDA) to Tucker form.  The
         Gaussian test matrices come from inputs.recompress_test_matrices(seed).
         Returns dict(U [3] (r_p x n_p), core (r0, r1, r2), ranks, rel_err, sweeps)."""
@@ -347,7 +348,7 @@ class Context:
         ranks = (C.c_int32 * 3)()
         err, sweeps = C.c_double(), C.c_int32()
         n3 = (C.c_int32 * 3)(*n)
-        nc = (C.c_int32 * 3)(*[int(c.shape[0]) for c in cols])
+        nc = (C.c_int32 * 3)(*[int(cols[p].numel() // n[p]) for p in range(3)])   # columns of n_p values
         self.use_current_stream()
         _check(library().demag_recompress_cp(self.handle, n3, T, self._ptr3(cols), nc, _ptr(table), _ptr(lam), eps,
                                              rmax, max_sweeps, _ptr(om), _ptr(gm), self._ptr3(U), _ptr(core),
