@@ -119,6 +119,13 @@ struct ColAxes {
   ColAxis a[3];
   int M;
 };
+// The hardware places workgroup lin on XCD lin % 8; this gives the
+// workgroups of one XCD consecutive work indices.
+__device__ inline unsigned xcd_work_index(unsigned lin, unsigned total) {
+  const unsigned x = lin & 7u, slot = lin >> 3;
+  const unsigned per = total >> 3, rem = total & 7u;
+  return x * per + min(x, rem) + slot;
+}
 __device__ inline int axis_of(const ColAxes &P, int idx, bool wg) {
   int d = 0;
   for (int e = 1; e < 3; ++e)
@@ -185,11 +192,14 @@ struct OutSink {
 __global__ __launch_bounds__(kThreads) void k_fft_jobs(const ColAxes P, const cplx *__restrict__ Uall,
                                                        int lds_points) {
   extern __shared__ cplx wk[];   // N points (padded), then the twiddle tables
-  const int axis = axis_of(P, blockIdx.x, true);
+  // work index, XCD-grouped: the job groups of one column run on one XCD, so
+  // its spectrum U is fetched into that L2 once
+  const int w = int(xcd_work_index(blockIdx.x, gridDim.x));
+  const int axis = axis_of(P, w, true);
   const ColAxis &A = P.a[axis];
   const int n = A.n, L = A.L, N = L / 2, R = A.R, M = P.M;
   cplx *tlo = wk + lds_points, *thi = tlo + 64;
-  const int local = blockIdx.x - A.wg0;
+  const int local = w - A.wg0;
   const int col = local / A.groups, grp = local - col * A.groups;   // col = q * R + l
   const int q = col / R, l = col % R;
   load_twiddles(tlo, thi, N, A.tw);
