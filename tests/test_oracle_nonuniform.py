@@ -1,0 +1,69 @@
+"""Pins of the oracle's non-uniform grid factors and apply (CPU)."""
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import apply, nonuniform as nu, sinc
+from paper_1212_3509_amd import inputs
+
+
+def _graded(n, ratio, length=1.0):
+    w = ratio ** np.arange(n)
+    e = np.concatenate([[0.0], np.cumsum(w)])
+    return e / e[-1] * length
+
+
+def test_uniform_edges_give_the_toeplitz_factors():
+    n, h = 9, 1.0 / 9
+    _t, tau, alpha = sinc.sinc_nodes(12)
+    dense = nu.dense_factors(np.arange(n + 1) * h, tau, alpha)
+    gens = sinc.scaled_factors(n, h, tau, alpha)
+    for t in range(4):
+        for k in range(len(tau)):
+            ref = sinc.toeplitz(gens[t, k])
+            # the same integrals; edge and centre arithmetic differ in the last bits
+            assert np.allclose(dense[t, k], ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("tau", [0.7, 9.0, 140.0])
+def test_factors_equal_numerical_integrals(tau):
+    edges = _graded(6, 1.4)
+    xi = nu.centres(edges)
+    E, X, Xp = nu.factor_E(tau, edges), nu.factor_X(tau, edges), nu.factor_Xp(tau, edges)
+    for i in range(6):
+        for j in range(6):
+            lo, hi = edges[j], edges[j + 1]
+            f = lambda y: np.exp(-tau ** 2 * (xi[i] - y) ** 2)  # noqa: E731
+            g = lambda y: (xi[i] - y) * np.exp(-tau ** 2 * (xi[i] - y) ** 2)  # noqa: E731
+            e_ref = integrate.quad(f, lo, hi, epsabs=1e-16, epsrel=1e-13, points=[xi[i]] if lo < xi[i] < hi else None)[0]
+            x_ref = integrate.quad(g, lo, hi, epsabs=1e-16, epsrel=1e-13, points=[xi[i]] if lo < xi[i] < hi else None)[0]
+            assert abs(E[i, j] - e_ref) <= 1e-12 * max(abs(e_ref), 1e-300) + 1e-16
+            assert abs(X[i, j] - x_ref) <= 1e-10 * max(abs(x_ref), 1e-300) + 1e-16
+            # X' (Leibniz: f(b) - f(a) for f(u) = u exp(-tau^2 u^2)) as the
+            # integral of f' over the same interval of u = xi_i - y
+            ua, ub = xi[i] - hi, xi[i] - lo
+            fp = lambda u: (1.0 - 2.0 * tau ** 2 * u * u) * np.exp(-tau ** 2 * u * u)  # noqa: E731
+            xp_ref = integrate.quad(fp, ua, ub, epsabs=1e-16, epsrel=1e-13, points=[0.0] if ua < 0 < ub else None)[0]
+            assert abs(Xp[i, j] - xp_ref) <= 1e-10 * max(abs(xp_ref), 1e-300) + 1e-15
+
+
+def test_exact_direct_on_uniform_edges_equals_the_uniform_oracle():
+    n = (5, 4, 3)
+    h = (0.2, 0.25, 0.3)
+    m = inputs.random_unit_field(n, seed=2)
+    edges = [np.arange(n[d] + 1) * h[d] for d in range(3)]
+    p1, h1 = nu.exact_direct(m, edges)
+    p2, h2 = apply.collocated_apply_direct(m, h)
+    assert apply.rel_l2(p1, p2) < 1e-12 and apply.rel_l2(h1, h2) < 1e-12
+
+
+def test_kron_apply_approximates_exact_collocation_on_a_graded_grid():
+    """M = 40 sinc rule with the theorem step for the smallest cell."""
+    edges = [_graded(6, 1.3), _graded(5, 0.8, 0.8), _graded(4, 1.5, 0.6)]
+    n = tuple(len(e) - 1 for e in edges)
+    m = inputs.random_unit_field(n, seed=4)
+    hmin = min(np.diff(e).min() for e in edges)
+    _t, tau, alpha = sinc.sinc_nodes(60, step_rule=1, h_min=hmin)
+    p1, h1 = nu.kron_apply(m, edges, tau, alpha)
+    p0, h0 = nu.exact_direct(m, edges)
+    assert apply.rel_l2(p1, p0) < 1e-7 and apply.rel_l2(h1, h0) < 1e-7, (apply.rel_l2(p1, p0), apply.rel_l2(h1, h0))
