@@ -120,6 +120,19 @@ const char *demag_last_error(void);
  * assembly is enqueued on the context's stream. */
 demag_status demag_assemble_factors(demag_ctx *ctx, const demag_grid *grid,
                                     const demag_quad *quad, demag_factors **out);
+/* Factors of a non-uniform tensor-product grid (collocation at cell centres
+ * and Lemma sinc_mumag hold for any partition; the factors lose the Toeplitz
+ * structure).  edges[d]: n[d] + 1 strictly increasing cell boundaries
+ * (host, physical units), 1 <= n[d] <= 1024.  The grid is scaled so that its
+ * longest extent is 1 (the potential is scaled back); the theorem-step rule
+ * uses the smallest scaled cell.  Factors are dense n x n matrices per type
+ * and node, entry (i, j) integrating over source cell j seen from the centre
+ * of cell i: E, X, P = -X', Q = 2 tau^2 X as for uniform grids.  Such
+ * factors serve demag_apply_full in FP64 only (dense FP64 mode products);
+ * the FFT, structured and batched paths need uniform grids and reject them.
+ * demag_factors_download returns [4][M][n][n]. */
+demag_status demag_assemble_factors_grid(demag_ctx *ctx, const int32_t n[3], const double *const edges[3],
+                                         const demag_quad *quad, demag_factors **out);
 demag_status demag_factors_free(demag_factors *f);
 /* Number of nodes M of an assembled rule. */
 demag_status demag_factors_count(const demag_factors *f, int32_t *M);

@@ -45,6 +45,7 @@ _SIGS = {
     "demag_set_tiles": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "demag_assemble_factors": (C.c_int, [_P, C.POINTER(Grid), C.POINTER(Quad), C.POINTER(_P)]),
     "demag_factors_free": (C.c_int, [_P]),
+    "demag_assemble_factors_grid": (C.c_int, [_P, _P, _P, C.POINTER(Quad), C.POINTER(_P)]),
     "demag_factors_count": (C.c_int, [_P, C.POINTER(C.c_int32)]),
     "demag_factors_nodes": (C.c_int, [_P, _P, _P, _P]),
     "demag_factors_download": (C.c_int, [_P, _P, C.c_int32, _P]),
@@ -120,6 +121,8 @@ def _current_stream(device: int):
 class Factors:
     """Assembled 1D factors of one grid and quadrature rule (library handle)."""
 
+    dense = False
+
     def __init__(self, ctx: "Context", handle, n, h):
         self.ctx, self.handle, self.n, self.h = ctx, handle, tuple(n), tuple(h)
 
@@ -137,8 +140,10 @@ class Factors:
         return t, tau, alpha
 
     def download(self, d: int) -> np.ndarray:
-        """FP64 factor table of axis d as [4][M][2 n_d - 1]."""
-        out = np.empty((4, self.M, 2 * self.n[d] - 1))
+        """FP64 factor table of axis d as [4][M][2 n_d - 1] (non-uniform
+        grids: dense [4][M][n_d][n_d])."""
+        n = self.n[d]
+        out = np.empty((4, self.M, n, n) if self.dense else (4, self.M, 2 * n - 1))
         _check(library().demag_factors_download(self.ctx.handle, self.handle, d, out.ctypes.data),
                "demag_factors_download")
         return out
@@ -231,6 +236,21 @@ class Context:
         _check(library().demag_assemble_factors(self.handle, C.byref(g), C.byref(q), C.byref(out)),
                "demag_assemble_factors")
         return Factors(self, out, n, h)
+
+    def assemble_grid(self, edges, M: int = 40, c0: float = 2.15, step_rule: int = 0) -> Factors:
+        """Factors of a non-uniform tensor-product grid: edges[d] = the n_d + 1
+        cell boundaries of axis d (x, y, z)."""
+        ed = [np.ascontiguousarray(e, dtype=np.float64) for e in edges]
+        n = tuple(len(e) - 1 for e in ed)
+        ptrs = (C.c_void_p * 3)(*[e.ctypes.data for e in ed])
+        q = Quad(M, c0, step_rule, None, None)
+        out = C.c_void_p()
+        self.use_current_stream()
+        _check(library().demag_assemble_factors_grid(self.handle, (C.c_int32 * 3)(*n), ptrs, C.byref(q),
+                                                     C.byref(out)), "demag_assemble_factors_grid")
+        f = Factors(self, out, n, tuple(float(np.min(np.diff(e))) for e in ed))
+        f.dense = True
+        return f
 
     def apply_full(self, f: Factors, m, phi=None, h=None, prec: str = "fp64"):
         """m: [3][nz][ny][nx] contiguous device tensor (float64 for fp64, else

@@ -184,9 +184,11 @@ void build_chunk(const demag_factors *f, int k0, int kc, double phi_scale,
     return t;
   };
   // element offsets of the generators in the stage axis' table
-  auto finish = [](StagePlan &sp) {
+  const bool dense = f->dense;   // dense tables hold one n x n matrix per generator
+  auto finish = [dense](StagePlan &sp) {
+    const int64_t stride = dense ? int64_t(sp.geom.n) * sp.geom.n : int64_t(sp.geom.genlen);
     for (auto &t : sp.terms)
-      for (int o = 0; o < 2; ++o) t.gen_off[o] = int64_t(t.gen[o]) * sp.geom.genlen;
+      for (int o = 0; o < 2; ++o) t.gen_off[o] = int64_t(t.gen[o]) * stride;
     sp.rb = default_rb(sp.geom.n);
   };
 
@@ -376,6 +378,7 @@ demag_status demag_destroy(demag_ctx *ctx) {
 
 demag_status demag_prepare_structured(demag_ctx *ctx, demag_factors *f) {
   DEMAG_REQUIRE(ctx && f, "demag_prepare_structured: NULL argument");
+  DEMAG_REQUIRE(!f->dense, "demag_prepare_structured: needs a uniform grid (Toeplitz factors)");
   DEMAG_TRY_HIP(hipSetDevice(ctx->device));
   return prepare_spectra(ctx, f);
 }
@@ -383,6 +386,7 @@ demag_status demag_prepare_structured(demag_ctx *ctx, demag_factors *f) {
 demag_status demag_apply_columns(demag_ctx *ctx, demag_factors *f, const int32_t R[3], const float *const in[3],
                                  float *const out[3]) {
   DEMAG_REQUIRE(ctx && f && R && in && out, "demag_apply_columns: NULL argument");
+  DEMAG_REQUIRE(!f->dense, "demag_apply_columns: needs a uniform grid (Toeplitz factors)");
   for (int d = 0; d < 3; ++d) {
     DEMAG_REQUIRE(R[d] >= 0 && R[d] <= 65536, "demag_apply_columns: R out of range");
     DEMAG_REQUIRE(R[d] == 0 || (in[d] && out[d]), "demag_apply_columns: NULL column buffer");
@@ -559,6 +563,53 @@ demag_status demag_assemble_factors(demag_ctx *ctx, const demag_grid *grid, cons
   return DEMAG_OK;
 }
 
+demag_status demag_assemble_factors_grid(demag_ctx *ctx, const int32_t n[3], const double *const edges[3],
+                                         const demag_quad *quad, demag_factors **out) {
+  DEMAG_REQUIRE(ctx && n && edges && quad && out, "demag_assemble_factors_grid: NULL argument");
+  DEMAG_REQUIRE(quad->M >= 1 && quad->M <= 256, "quad: M must be in [1, 256]");
+  double L = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    DEMAG_REQUIRE(n[d] >= 1 && n[d] <= 1024 && edges[d], "grid: n must be in [1, 1024] with n + 1 edges");
+    for (int i = 0; i < n[d]; ++i)
+      DEMAG_REQUIRE(std::isfinite(edges[d][i]) && std::isfinite(edges[d][i + 1]) && edges[d][i + 1] > edges[d][i],
+                    "grid: edges must increase strictly");
+    L = std::max(L, edges[d][n[d]] - edges[d][0]);
+  }
+  DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  auto f = std::make_unique<demag_factors>();
+  f->L = L;
+  f->dense = true;
+  std::vector<double> scaled[3];
+  double hmin = 1e300;
+  for (int d = 0; d < 3; ++d) {
+    f->n[d] = n[d];
+    scaled[d].resize(size_t(n[d]) + 1);
+    for (int i = 0; i <= n[d]; ++i) scaled[d][i] = (edges[d][i] - edges[d][0]) / L;
+    double hm = 1e300;
+    for (int i = 0; i < n[d]; ++i) hm = std::min(hm, scaled[d][i + 1] - scaled[d][i]);
+    f->hs[d] = hm;            // smallest scaled cell of the axis
+    f->h[d] = hm * L;
+    hmin = std::min(hmin, hm);
+  }
+  demag_status st = make_nodes(quad, hmin, f.get());
+  if (st != DEMAG_OK) return st;
+  for (int d = 0; d < 3; ++d) {
+    const size_t cnt = size_t(F_NTYPES) * f->M * size_t(n[d]) * n[d];
+    if (hipMalloc(&f->f64[d], cnt * sizeof(double)) != hipSuccess) {
+      set_error("dense factor tables: device allocation failed");
+      demag_factors_free(f.release());
+      return DEMAG_E_NOMEM;
+    }
+  }
+  st = launch_assemble_dense(ctx, f.get(), scaled);
+  if (st != DEMAG_OK) {
+    demag_factors_free(f.release());
+    return st;
+  }
+  *out = f.release();
+  return DEMAG_OK;
+}
+
 demag_status demag_factors_free(demag_factors *f) {
   if (!f) return DEMAG_OK;
   (void)hipDeviceSynchronize();
@@ -606,6 +657,7 @@ demag_status demag_apply_full(demag_ctx *ctx, const demag_factors *fc, demag_pre
   DEMAG_REQUIRE(prec == DEMAG_FP64 || prec == DEMAG_FP32 || prec == DEMAG_BF16X2 || prec == DEMAG_BF16X3,
                 "demag_apply_full: unknown precision");
   DEMAG_REQUIRE(aligned16(m) && aligned16(phi) && aligned16(h), "demag_apply_full: buffers must be 16-byte aligned");
+  DEMAG_REQUIRE(!fc->dense || prec == DEMAG_FP64, "demag_apply_full: non-uniform grids are applied in FP64");
   for (int d = 0; d < 3; ++d)
     DEMAG_REQUIRE(fc->n[d] <= 1024, "demag_apply_full: full format supports n <= 1024 per axis");
   auto *f = const_cast<demag_factors *>(fc);
@@ -635,6 +687,7 @@ demag_status demag_apply_full(demag_ctx *ctx, const demag_factors *fc, demag_pre
 
 demag_status demag_apply_fft(demag_ctx *ctx, demag_factors *f, const double *m, double *phi, double *h) {
   DEMAG_REQUIRE(ctx && f && m && phi && h, "demag_apply_fft: NULL argument");
+  DEMAG_REQUIRE(!f->dense, "demag_apply_fft: needs a uniform grid (Toeplitz factors)");
   for (int d = 0; d < 3; ++d)
     DEMAG_REQUIRE(f->n[d] <= 1024, "demag_apply_fft: n <= 1024 per axis");
   DEMAG_TRY_HIP(hipSetDevice(ctx->device));

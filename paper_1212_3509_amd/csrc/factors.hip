@@ -59,6 +59,39 @@ __global__ void k_assemble_axis(double *__restrict__ out, int n, int M, double h
   row[F_Q * plane + im] = -2.0 * t2 * wk * X;
 }
 
+// Dense factors of a non-uniform axis: for target cell i (centre xi_i) and
+// source cell j = [x_j, x_{j+1}] the integration interval in u = xi_i - y is
+// [a, b] = [xi_i - x_{j+1}, xi_i - x_j]; E, X and X' as in the Toeplitz case
+// (erfc differences for intervals away from 0 on either side; X through
+// expm1 anchored at the endpoint nearer 0).  out[((type M + k) n + i) n + j].
+__global__ void k_assemble_dense(double *__restrict__ out, const double *__restrict__ edges, int n, int M,
+                                 const double *__restrict__ tau, const double *__restrict__ w) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  if (e >= n * n || k >= M) return;
+  const int i = e / n, j = e - i * n;
+  const double t = tau[k], wk = w[k], t2 = t * t;
+  const double xi = 0.5 * (edges[i] + edges[i + 1]);
+  const double a = xi - edges[j + 1], b = xi - edges[j];
+  const double sqrt_pi = 1.7724538509055160273;
+  const double ta = t * a, tb = t * b;
+  double diff;
+  if (ta > 0.5) diff = erfc(ta) - erfc(tb);
+  else if (tb < -0.5) diff = erfc(-tb) - erfc(-ta);
+  else diff = erf(tb) - erf(ta);
+  const double E = sqrt_pi / (2.0 * t) * diff;
+  const double d2 = (b - a) * (b + a);   // b^2 - a^2
+  const double X = (d2 >= 0.0) ? -exp(-t2 * a * a) * expm1(-t2 * d2) / (2.0 * t2)
+                               : exp(-t2 * b * b) * expm1(t2 * d2) / (2.0 * t2);
+  const double Xp = b * exp(-t2 * b * b) - a * exp(-t2 * a * a);
+  const size_t nn = size_t(n) * n, plane = size_t(M) * nn;
+  const size_t o = size_t(k) * nn + e;
+  out[F_E * plane + o] = wk * E;
+  out[F_X * plane + o] = wk * X;
+  out[F_P * plane + o] = -wk * Xp;
+  out[F_Q * plane + o] = 2.0 * t2 * wk * X;
+}
+
 // FP32 copy and bfloat16 split (round to nearest even by integer arithmetic)
 // of the FP32 value: hi = bf16(x), lo = bf16(x - hi), lo2 = bf16(x - hi - lo).
 __device__ inline uint16_t bf16_rne_bits(float x) {
@@ -87,7 +120,8 @@ __global__ void k_convert(const double *__restrict__ src, float *__restrict__ f3
 }  // namespace
 
 size_t axis_table_len(const demag_factors *f, int d) {
-  return size_t(F_NTYPES) * f->M * (2 * size_t(f->n[d]) - 1);
+  const size_t n = size_t(f->n[d]);
+  return size_t(F_NTYPES) * f->M * (f->dense ? n * n : 2 * n - 1);
 }
 
 demag_status launch_assemble(demag_ctx *ctx, demag_factors *f) {
@@ -108,6 +142,32 @@ demag_status launch_assemble(demag_ctx *ctx, demag_factors *f) {
   // The host vectors are copied before these frees run (stream order).
   DEMAG_TRY_HIP(hipFreeAsync(d_tau, ctx->stream));
   DEMAG_TRY_HIP(hipFreeAsync(d_w, ctx->stream));
+  return DEMAG_OK;
+}
+
+demag_status launch_assemble_dense(demag_ctx *ctx, demag_factors *f, const std::vector<double> edges[3]) {
+  double *d_tau = nullptr, *d_w = nullptr, *d_edges = nullptr;
+  const size_t ne = edges[0].size() + edges[1].size() + edges[2].size();
+  DEMAG_TRY_HIP(hipMallocAsync(&d_tau, sizeof(double) * f->M, ctx->stream));
+  DEMAG_TRY_HIP(hipMallocAsync(&d_w, sizeof(double) * f->M, ctx->stream));
+  DEMAG_TRY_HIP(hipMallocAsync(&d_edges, sizeof(double) * ne, ctx->stream));
+  DEMAG_TRY_HIP(hipMemcpyAsync(d_tau, f->tau.data(), sizeof(double) * f->M, hipMemcpyHostToDevice, ctx->stream));
+  DEMAG_TRY_HIP(hipMemcpyAsync(d_w, f->w.data(), sizeof(double) * f->M, hipMemcpyHostToDevice, ctx->stream));
+  size_t off = 0;
+  for (int d = 0; d < 3; ++d) {
+    DEMAG_TRY_HIP(hipMemcpyAsync(d_edges + off, edges[d].data(), sizeof(double) * edges[d].size(),
+                                 hipMemcpyHostToDevice, ctx->stream));
+    const int n = f->n[d];
+    dim3 grid(unsigned((size_t(n) * n + 255) / 256), unsigned(f->M));
+    k_assemble_dense<<<grid, 256, 0, ctx->stream>>>(f->f64[d], d_edges + off, n, f->M, d_tau, d_w);
+    DEMAG_TRY_HIP(hipGetLastError());
+    off += edges[d].size();
+  }
+  // the host vectors are copied before these frees run (stream order); the
+  // pageable copies above complete before they return
+  DEMAG_TRY_HIP(hipFreeAsync(d_tau, ctx->stream));
+  DEMAG_TRY_HIP(hipFreeAsync(d_w, ctx->stream));
+  DEMAG_TRY_HIP(hipFreeAsync(d_edges, ctx->stream));
   return DEMAG_OK;
 }
 

@@ -152,6 +152,7 @@ struct demag_factors {
   double *spec[3] = {nullptr, nullptr, nullptr};   // [4][M][L/2+1] real or imaginary parts (structured path)
   void *twiddle[3] = {nullptr, nullptr, nullptr};  // double2 [L/2]
   double *k3 = nullptr;    // 3D kernel spectra, octant [Lz/2+1][Ly/2+1][pitch][10] (FFT apply)
+  bool dense = false;      // non-uniform grid: f64[d] holds dense factors [4][M][n][n] (FP64 only)
   std::map<std::pair<int, int>, std::unique_ptr<demag::FullPlan>> plans;  // (prec class, kc)
 };
 
@@ -159,7 +160,7 @@ namespace demag {
 // Record-start / record-stop helpers (no-ops unless profiling is on).
 demag_status prof_begin(demag_ctx *ctx, hipEvent_t *ev);
 demag_status prof_end(demag_ctx *ctx, hipEvent_t start, const std::string &label, double flops, double bytes);
-size_t axis_table_len(const demag_factors *f, int d);  // 4 * M * (2n_d - 1)
+size_t axis_table_len(const demag_factors *f, int d);  // 4 * M * (2n_d - 1), dense: 4 * M * n_d^2
 demag_status launch_assemble(demag_ctx *ctx, demag_factors *f);
 demag_status launch_left_stage(demag_ctx *ctx, const demag_factors *f, demag_prec prec,
                                const StagePlan &sp, void *const bufs[6], int beta);
@@ -174,6 +175,9 @@ demag_status launch_items(demag_ctx *ctx, demag_prec prec, const BatchItem *item
                           const void *gens, int nmax, int beta, int *counter);
 demag_status launch_reset_counters(demag_ctx *ctx, int *counters, int count);
 demag_status launch_build_windows(demag_ctx *ctx, demag_factors *f);
+// non-uniform grids: dense factors from the scaled cell edges (host, n_d + 1 per axis)
+demag_status launch_assemble_dense(demag_ctx *ctx, demag_factors *f, const std::vector<double> edges[3]);
+demag_status launch_dense_stage(hipStream_t s, const StagePlan &sp, const double *mats, const Bufs &bufs, int beta);
 demag_status launch_left_stage_bf16(demag_ctx *ctx, const demag_factors *f, demag_prec prec,
                                     const StagePlan &sp, void *const bufs[6], int beta);
 demag_status launch_split(demag_ctx *ctx, const float *x, uint16_t *parts, size_t count, int nparts);

@@ -428,7 +428,11 @@ demag_status launch_left_stage(demag_ctx *ctx, const demag_factors *f, demag_pre
   const char *pname = "?";
   size_t esize = 4;
   const int rb = ctx->tile_rows > 0 ? ctx->tile_rows : stage_rows(sp, prec);
-  if (prec == DEMAG_FP64) {
+  if (f->dense) {
+    st = launch_dense_stage(ctx->stream, sp, f->f64[sp.axis], bufs, beta);
+    pname = "dense64";
+    esize = 8;
+  } else if (prec == DEMAG_FP64) {
     st = launch_typed<double>(ctx->stream, rb, sp, f->f64[sp.axis], bufs, beta);
     pname = "fp64";
     esize = 8;

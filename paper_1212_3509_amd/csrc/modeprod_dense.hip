@@ -1,0 +1,122 @@
+// Mode products with dense (non-Toeplitz) factor matrices: the full-format
+// apply on non-uniform tensor-product grids (the collocation and Lemma
+// sinc_mumag hold for any partition; only the Toeplitz structure is lost).
+//
+// out[i][c] = sum_terms sum_j A_term[i][j] in[j][c] in FP64 on the matrix
+// cores (v_mfma_f64_16x16x4), with the same jobs, terms and stage geometry
+// as the Toeplitz path; A_term is the n x n matrix of one factor type and
+// node, at element offset gen_off in the axis' dense table [4][M][n][n].
+// Tile: 64 rows x 64 columns per workgroup (4 waves x 16 columns, 4 row
+// blocks each); per chunk of 16 K values the A tiles of the NOUT outputs and
+// the input tile go through LDS.
+#include "internal.h"
+
+namespace demag {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <int NOUT>
+__global__ __launch_bounds__(256) void k_dense_left(const MPJob *__restrict__ jobs, const MPTerm *__restrict__ terms,
+                                                    Bufs bufs, const double *__restrict__ mats, MPGeom g,
+                                                    int col_tiles, int beta) {
+  __shared__ double As[NOUT][64][17];
+  __shared__ double Bs[16][65];
+  const MPJob job = jobs[blockIdx.y];
+  if (job.nterms <= 0) return;
+  const int ct = blockIdx.x % col_tiles, rg = blockIdx.x / col_tiles;
+  const int n = g.n;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63, kq = lane >> 4;
+  const int row0 = rg * 64;
+  // input staging: this thread's column of the tile (columns past C read C - 1)
+  const int cB = tid & 63;
+  const int cs = ct * 64 + cB;
+  const int cl = cs < g.C ? cs : g.C - 1;
+  const size_t cin = size_t(cl / g.C1) * g.in_S1 + size_t(cl % g.C1);
+  d4 acc[NOUT][4];
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) acc[o][rb] = d4{0, 0, 0, 0};
+  for (int t = 0; t < job.nterms; ++t) {
+    const MPTerm tm = terms[job.term0 + t];
+    const double *in = static_cast<const double *>(bufs.p[tm.in_buf]) + tm.in_off + cin;
+    const double *A[2] = {mats + tm.gen_off[0], mats + tm.gen_off[NOUT > 1 ? 1 : 0]};
+    for (int j0 = 0; j0 < n; j0 += 16) {
+      double bv[4], av[NOUT][4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = j0 + (tid >> 6) + 4 * r;
+        bv[r] = j < n ? in[size_t(j) * g.kstride] : 0.0;
+      }
+#pragma unroll
+      for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = tid + 256 * r;
+          const int i = row0 + (e >> 4), j = j0 + (e & 15);
+          av[o][r] = (i < n && j < n) ? A[o][size_t(i) * n + j] : 0.0;
+        }
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Bs[(tid >> 6) + 4 * r][cB] = bv[r];
+#pragma unroll
+      for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int e = tid + 256 * r;
+          As[o][e >> 4][e & 15] = av[o][r];
+        }
+      __syncthreads();
+#pragma unroll
+      for (int k4 = 0; k4 < 4; ++k4) {
+        const double b = Bs[4 * k4 + kq][wave * 16 + (lane & 15)];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+          for (int o = 0; o < NOUT; ++o)
+            acc[o][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[o][16 * rb + (lane & 15)][4 * k4 + kq], b,
+                                                              acc[o][rb], 0, 0, 0);
+      }
+      __syncthreads();
+    }
+  }
+  // register r of lane l holds row (l >> 4) + 4 r of the 16 x 16 block, column l % 16
+  const int cc = ct * 64 + wave * 16 + (lane & 15);
+  if (cc >= g.C) return;
+  const size_t ocol = size_t(cc / g.C1) * g.out_S1 + size_t(cc % g.C1) * g.out_cs;
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    double *out = static_cast<double *>(bufs.p[job.out_buf[o]]) + job.out_off[o] + ocol;
+    const double scale = job.scale[o];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = row0 + 16 * rb + (lane >> 4) + 4 * r;
+        if (i < n) {
+          const size_t idx = size_t(i) * g.out_is;
+          double v = scale * acc[o][rb][r];
+          if (beta) v += out[idx];
+          out[idx] = v;
+        }
+      }
+  }
+}
+
+}  // namespace
+
+demag_status launch_dense_stage(hipStream_t s, const StagePlan &sp, const double *mats, const Bufs &bufs, int beta) {
+  const MPGeom &g = sp.geom;
+  const int col_tiles = (g.C + 63) / 64;
+  const int row_groups = (g.n + 63) / 64;
+  dim3 grid(unsigned(col_tiles * row_groups), unsigned(sp.jobs.size()));
+  if (sp.nout == 2)
+    k_dense_left<2><<<grid, 256, 0, s>>>(sp.d_jobs, sp.d_terms, bufs, mats, g, col_tiles, beta);
+  else
+    k_dense_left<1><<<grid, 256, 0, s>>>(sp.d_jobs, sp.d_terms, bufs, mats, g, col_tiles, beta);
+  DEMAG_TRY_HIP(hipGetLastError());
+  return DEMAG_OK;
+}
+
+}  // namespace demag

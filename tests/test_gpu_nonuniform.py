@@ -1,0 +1,85 @@
+"""GPU parity of the full-format apply on non-uniform tensor-product grids
+(dense FP64 factors and mode products) with the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import apply, nonuniform as nu
+from paper_1212_3509_amd import api, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    api.library()
+    return api.Context(0)
+
+
+def _graded(n, ratio, length=1.0):
+    w = ratio ** np.arange(n)
+    e = np.concatenate([[0.0], np.cumsum(w)])
+    return e / e[-1] * length
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=torch.float64)
+
+
+def test_uniform_edges_equal_the_toeplitz_apply(ctx):
+    n = (45, 38, 71)
+    h = 1.0 / 71
+    m = _dev(inputs.random_unit_field(n, seed=7))
+    fu = ctx.assemble(n, (h,) * 3, M=12)
+    fd = ctx.assemble_grid([np.arange(n[d] + 1) * h for d in range(3)], M=12)
+    p1, h1 = ctx.apply_full(fu, m, prec="fp64")
+    p2, h2 = ctx.apply_full(fd, m, prec="fp64")
+    torch.cuda.synchronize()
+    rel = lambda a, b: float(torch.linalg.norm((a - b).reshape(-1)) / torch.linalg.norm(b.reshape(-1)))  # noqa: E731
+    assert rel(p2, p1) < 1e-12 and rel(h2, h1) < 1e-12, (rel(p2, p1), rel(h2, h1))
+
+
+def test_graded_grid_matches_oracle(ctx):
+    edges = [_graded(37, 1.03, 1.2), _graded(29, 0.97, 0.9), _graded(21, 1.08, 0.7)]
+    n = tuple(len(e) - 1 for e in edges)
+    m = inputs.random_unit_field(n, seed=8)
+    f = ctx.assemble_grid(edges, M=20, step_rule=1)
+    L = max(e[-1] - e[0] for e in edges)
+    scaled = [(e - e[0]) / L for e in edges]
+    _t, tau, alpha = f.nodes()
+    for d in range(3):   # the factors themselves
+        ref = nu.dense_factors(scaled[d], tau, alpha)
+        got = f.download(d)
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    phi, hf = ctx.apply_full(f, _dev(m), prec="fp64")
+    torch.cuda.synchronize()
+    pref, href = nu.kron_apply(m, scaled, tau, alpha)
+    assert apply.rel_l2(phi.cpu().numpy(), L * pref) < 1e-12
+    assert apply.rel_l2(hf.cpu().numpy(), href) < 1e-12
+
+
+def test_graded_grid_approximates_exact_collocation(ctx):
+    """The theorem-step rule with 60 nodes against the closed-form box
+    kernels summed directly (physical units)."""
+    edges = [_graded(9, 1.25, 0.9), _graded(7, 0.85, 0.7), _graded(6, 1.4, 0.5)]
+    n = tuple(len(e) - 1 for e in edges)
+    m = inputs.random_unit_field(n, seed=9)
+    f = ctx.assemble_grid(edges, M=60, step_rule=1)
+    phi, hf = ctx.apply_full(f, _dev(m), prec="fp64")
+    torch.cuda.synchronize()
+    p0, h0 = nu.exact_direct(m, edges)
+    assert apply.rel_l2(phi.cpu().numpy(), p0) < 1e-7 and apply.rel_l2(hf.cpu().numpy(), h0) < 1e-7
+
+
+def test_dense_factors_are_rejected_elsewhere(ctx):
+    edges = [_graded(8, 1.1) for _ in range(3)]
+    f = ctx.assemble_grid(edges, M=4)
+    m64 = torch.zeros((3, 8, 8, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(api.DemagError):
+        ctx.apply_full(f, m64.float(), prec="fp32")
+    with pytest.raises(api.DemagError):
+        ctx.apply_fft(f, m64)
+    with pytest.raises(api.DemagError):
+        ctx.prepare_structured(f)
+    with pytest.raises(api.DemagError):
+        ctx.assemble_grid([np.array([0.0, 1.0, 1.0]), edges[1], edges[2]], M=4)   # edges must increase
