@@ -261,6 +261,25 @@ def headline(args):
         del m, phi, h
         torch.cuda.empty_cache()
 
+    # the same operator on a non-uniform grid (graded cells, dense factors)
+    nonuni = None
+    if args.nonuniform:
+        edges = []
+        for r in (1.01, 0.99, 1.005):
+            w = r ** np.arange(n)
+            e = np.concatenate([[0.0], np.cumsum(w)])
+            edges.append(e / e[-1] - 0.5)
+        fn = ctx.assemble_grid(edges, M=40, c0=2.15)
+        m = torch.from_numpy(m_host).to(device="cuda", dtype=torch.float64)
+        phi = torch.empty((n, n, n), dtype=torch.float64, device="cuda")
+        h = torch.empty((3, n, n, n), dtype=torch.float64, device="cuda")
+        ms, prof = _timed(ctx, lambda: ctx.apply_full(fn, m, phi, h, prec="fp64"), max(2, args.steps // 2), 1)
+        nonuni = {"value": round(N / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 4), "dtype": "f64",
+                  "grid": "128^3 graded cells (width ratios 1.01, 0.99, 1.005 per cell), M=40",
+                  "roofline": _roofline(prof, "fp64"), "kernels": _kernels(prof, max(2, args.steps // 2))}
+        del m, phi, h, fn
+        torch.cuda.empty_cache()
+
     mixed = None
     if args.learned_steps > 0:
         t0 = time.perf_counter()
@@ -310,6 +329,7 @@ def headline(args):
         "mixed_learned": mixed,
         "learned_eval": learned_eval,
         "fft3d_route": fft3d,
+        "nonuniform_grid": nonuni,
         "precisions": results,
     }
     if args.cpu_nodes > 0:
@@ -425,6 +445,7 @@ def main():
     ap.add_argument("--batch-ws-gib", type=int, default=64)
     ap.add_argument("--tune", type=int, default=1)
     ap.add_argument("--fft3d", type=int, default=1, help="also time the 3D-FFT route of the same operator")
+    ap.add_argument("--nonuniform", type=int, default=1, help="also time the apply on a graded non-uniform grid")
     ap.add_argument("--learned-eval", type=int, default=1,
                     help="evaluate the trained network at 256^3 full format and 1024^3 CP rank 10")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
