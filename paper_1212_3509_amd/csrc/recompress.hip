@@ -9,7 +9,7 @@
 //   A_p^T diag(lam) KR,  KR[t][(a, b)] = (A_q U_q^T)[t][a] (A_s U_s^T)[t][b].
 // It is never formed.  A randomized range finder (test matrix G given by the
 // caller) gives K = rmax + 8 candidate directions Yg = Y_(p) G, orthonormalised
-// by Gram-Schmidt with reorthogonalisation (dependent ones dropped); the small
+// by block Gram-Schmidt with reorthogonalisation (dependent ones dropped); the small
 // matrix B = Q Y_(p) (K x r_q r_s) then has the leading singular values and,
 // through the eigenvectors of B B^T, the leading singular vectors of Y_(p).
 // The rank follows the tolerance rule on those singular values (capped at
@@ -17,8 +17,8 @@
 // unfoldings, with Khatri-Rao test vectors (Omega_q[j] kron Omega_s[j]).
 //
 // All arithmetic is FP64.  Symmetric eigenproblems (K <= 72) run as a
-// parallel cyclic Jacobi iteration in one workgroup's LDS, the Gram-Schmidt
-// in one workgroup (mode sizes up to 8192); the long
+// parallel cyclic Jacobi iteration in one workgroup's LDS, Gram-Schmidt
+// within blocks of 8 rows in one workgroup (mode sizes up to 8192); the long
 // contractions are plain tiled kernels (this is a set-up computation, not on
 // the apply's hot path).  The relative error is computed without the
 // cancellation of |X|^2 - |core|^2: the residual splits into the orthogonal
@@ -259,8 +259,9 @@ __global__ __launch_bounds__(256) void k_jacobi(const double *__restrict__ W, in
 
 // Orthonormal rows Q (returned count *kout) spanning the k rows of Y
 // (length n <= 8192): classical Gram-Schmidt with one reorthogonalisation
-// per row; a row whose norm falls below drop times its original norm is
-// dependent and dropped.  One workgroup; thread tid owns the points
+// per row; a row whose norm falls below drop times its reference norm (ref2:
+// squared norms before earlier projections, else its own) is dependent and
+// dropped.  One workgroup; thread tid owns the points
 // x = tid + 256 e, so the rows it writes are the rows it reads back.
 constexpr int kCgsPer = 32;
 __device__ inline double wave_sum(double x) {
@@ -268,7 +269,7 @@ __device__ inline double wave_sum(double x) {
   return x;
 }
 __global__ __launch_bounds__(256) void k_cgs2(const double *__restrict__ Y, int k, int n, double *__restrict__ Q,
-                                              int *__restrict__ kout, double drop) {
+                                              int *__restrict__ kout, double drop, const double *__restrict__ ref2) {
   __shared__ double part[4][kMaxK + 1];
   __shared__ double coef[kMaxK];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -290,7 +291,8 @@ __global__ __launch_bounds__(256) void k_cgs2(const double *__restrict__ Y, int 
       v[e] = x < n ? Y[size_t(j) * n + x] : 0.0;
       sq += v[e] * v[e];
     }
-    const double nrm0 = block_sum(sq);
+    const double own = block_sum(sq);
+    const double nrm0 = ref2 ? ref2[j] : own;   // reference: the row before any projection
     for (int pass = 0; pass < 2; ++pass) {
       for (int i = 0; i < kept; ++i) {
         double d = 0.0;
@@ -329,6 +331,21 @@ __global__ __launch_bounds__(256) void k_cgs2(const double *__restrict__ Y, int 
     }
   }
   if (tid == 0) *kout = kept;
+}
+
+// ref2[j] = |Y[j]|^2 (one workgroup per row).
+__global__ __launch_bounds__(256) void k_rownorm2(const double *__restrict__ Y, int n, double *__restrict__ ref2) {
+  __shared__ double red[4];
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    const double y = Y[size_t(j) * n + i];
+    s += y * y;
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) ref2[j] = red[0] + red[1] + red[2] + red[3];
 }
 
 size_t jacobi_lds(int K) {
@@ -420,14 +437,38 @@ struct Rc {
     DEMAG_TRY_HIP(hipStreamSynchronize(st));
     return DEMAG_OK;
   }
-  // rows of Yin (k x len) -> orthonormal rows Qout spanning them (count kout)
+  // rows of Yin (k x len) -> orthonormal rows Qout spanning them (count
+  // kout): block Gram-Schmidt, blocks of 8 rows projected twice against the
+  // rows kept so far (two tiled products each), then Gram-Schmidt within the
+  // block in one workgroup; dependence is judged against each row's norm
+  // before any projection
   demag_status orthonormalize(const double *Yin, int k, int len, double *Qout, int &kout) {
-    k_cgs2<<<1, 256, 0, st>>>(Yin, k, len, Qout, icount, 1e-13);
+    constexpr int kBlk = 8;
+    k_rownorm2<<<k, 256, 0, st>>>(Yin, len, d);
     DEMAG_TRY_HIP(hipGetLastError());
-    int h = 0;
-    DEMAG_TRY_HIP(hipMemcpyAsync(&h, icount, sizeof(int), hipMemcpyDeviceToHost, st));
-    DEMAG_TRY_HIP(hipStreamSynchronize(st));
-    kout = h;
+    double *Ta = Q1, *Tb = Q1 + size_t(kBlk) * len;
+    int kept = 0;
+    for (int b0 = 0; b0 < k; b0 += kBlk) {
+      const int nb = std::min(kBlk, k - b0);
+      const double *src = Yin + size_t(b0) * len;
+      if (kept > 0) {
+        for (int pass = 0; pass < 2; ++pass) {
+          double *dst = pass == 0 ? Ta : Tb;
+          demag_status s = xty(src, len, Qout, len, nb, kept, len, W, kMaxK);
+          if (s != DEMAG_OK) return s;
+          s = ztx(W, 1, kMaxK, Qout, len, kept, nb, len, dst, len, src, len);
+          if (s != DEMAG_OK) return s;
+          src = dst;
+        }
+      }
+      k_cgs2<<<1, 256, 0, st>>>(src, nb, len, Qout + size_t(kept) * len, icount, 1e-13, d + b0);
+      DEMAG_TRY_HIP(hipGetLastError());
+      int h = 0;
+      DEMAG_TRY_HIP(hipMemcpyAsync(&h, icount, sizeof(int), hipMemcpyDeviceToHost, st));
+      DEMAG_TRY_HIP(hipStreamSynchronize(st));
+      kept += h;
+    }
+    kout = kept;
     return DEMAG_OK;
   }
   demag_status quadform(const double *G0, const double *G1, const double *G2, double &out) {
