@@ -7,8 +7,9 @@
 // as the Toeplitz path; A_term is the n x n matrix of one factor type and
 // node, at element offset gen_off in the axis' dense table [4][M][n][n].
 // Tile: 64 rows x 64 columns per workgroup (4 waves x 16 columns, 4 row
-// blocks each); per chunk of 16 K values the A tiles of the NOUT outputs and
-// the input tile go through LDS.
+// blocks each); per chunk of 32 K values the A tiles of the NOUT outputs and
+// the input tile go through LDS, the next chunk's tiles loaded into registers
+// while the current one is multiplied.
 #include "internal.h"
 
 namespace demag {
@@ -21,8 +22,11 @@ template <int NOUT>
 __global__ __launch_bounds__(256) void k_dense_left(const MPJob *__restrict__ jobs, const MPTerm *__restrict__ terms,
                                                     Bufs bufs, const double *__restrict__ mats, MPGeom g,
                                                     int col_tiles, int beta) {
-  __shared__ double As[NOUT][64][17];
-  __shared__ double Bs[16][65];
+  constexpr int KC = 32;               // K values per chunk
+  constexpr int kBr = KC * 64 / 256;   // input tile values per thread
+  constexpr int kAr = 64 * KC / 256;   // A tile values per thread and output
+  __shared__ double As[NOUT][64][KC + 1];
+  __shared__ double Bs[KC][65];
   const MPJob job = jobs[blockIdx.y];
   if (job.nterms <= 0) return;
   const int ct = blockIdx.x % col_tiles, rg = blockIdx.x / col_tiles;
@@ -39,47 +43,55 @@ __global__ __launch_bounds__(256) void k_dense_left(const MPJob *__restrict__ jo
   for (int o = 0; o < NOUT; ++o)
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) acc[o][rb] = d4{0, 0, 0, 0};
-  for (int t = 0; t < job.nterms; ++t) {
-    const MPTerm tm = terms[job.term0 + t];
+  // (term, K chunk) pairs in one loop; the next pair's tiles are loaded into
+  // registers while the current one is multiplied
+  const int nch = (n + KC - 1) / KC;
+  const int nq = job.nterms * nch;
+  double bv[kBr], av[NOUT][kAr];
+  auto load = [&](int q) {
+    const int t = q / nch, j0 = (q - t * nch) * KC;
+    const MPTerm &tm = terms[job.term0 + t];
     const double *in = static_cast<const double *>(bufs.p[tm.in_buf]) + tm.in_off + cin;
-    const double *A[2] = {mats + tm.gen_off[0], mats + tm.gen_off[NOUT > 1 ? 1 : 0]};
-    for (int j0 = 0; j0 < n; j0 += 16) {
-      double bv[4], av[NOUT][4];
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = j0 + (tid >> 6) + 4 * r;
-        bv[r] = j < n ? in[size_t(j) * g.kstride] : 0.0;
-      }
-#pragma unroll
-      for (int o = 0; o < NOUT; ++o)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int e = tid + 256 * r;
-          const int i = row0 + (e >> 4), j = j0 + (e & 15);
-          av[o][r] = (i < n && j < n) ? A[o][size_t(i) * n + j] : 0.0;
-        }
-#pragma unroll
-      for (int r = 0; r < 4; ++r) Bs[(tid >> 6) + 4 * r][cB] = bv[r];
-#pragma unroll
-      for (int o = 0; o < NOUT; ++o)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int e = tid + 256 * r;
-          As[o][e >> 4][e & 15] = av[o][r];
-        }
-      __syncthreads();
-#pragma unroll
-      for (int k4 = 0; k4 < 4; ++k4) {
-        const double b = Bs[4 * k4 + kq][wave * 16 + (lane & 15)];
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-          for (int o = 0; o < NOUT; ++o)
-            acc[o][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[o][16 * rb + (lane & 15)][4 * k4 + kq], b,
-                                                              acc[o][rb], 0, 0, 0);
-      }
-      __syncthreads();
+    for (int r = 0; r < kBr; ++r) {
+      const int j = j0 + (tid >> 6) + 4 * r;
+      bv[r] = j < n ? in[size_t(j) * g.kstride] : 0.0;
     }
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+      const double *A = mats + tm.gen_off[o];
+#pragma unroll
+      for (int r = 0; r < kAr; ++r) {
+        const int e = tid + 256 * r;
+        const int i = row0 + e / KC, j = j0 + e % KC;
+        av[o][r] = (i < n && j < n) ? A[size_t(i) * n + j] : 0.0;
+      }
+    }
+  };
+  load(0);
+  for (int q = 0; q < nq; ++q) {
+#pragma unroll
+    for (int r = 0; r < kBr; ++r) Bs[(tid >> 6) + 4 * r][cB] = bv[r];
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+      for (int r = 0; r < kAr; ++r) {
+        const int e = tid + 256 * r;
+        As[o][e / KC][e % KC] = av[o][r];
+      }
+    __syncthreads();
+    if (q + 1 < nq) load(q + 1);
+#pragma unroll
+    for (int k4 = 0; k4 < KC / 4; ++k4) {
+      const double b = Bs[4 * k4 + kq][wave * 16 + (lane & 15)];
+#pragma unroll
+      for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int o = 0; o < NOUT; ++o)
+          acc[o][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[o][16 * rb + (lane & 15)][4 * k4 + kq], b,
+                                                            acc[o][rb], 0, 0, 0);
+    }
+    __syncthreads();
   }
   // register r of lane l holds row (l >> 4) + 4 r of the 16 x 16 block, column l % 16
   const int cc = ct * 64 + wave * 16 + (lane & 15);
