@@ -18,7 +18,7 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <int NOUT>
+template <int NOUT, bool TRANS>
 __global__ __launch_bounds__(256) void k_dense_left(const MPJob *__restrict__ jobs, const MPTerm *__restrict__ terms,
                                                     Bufs bufs, const double *__restrict__ mats, MPGeom g,
                                                     int col_tiles, int beta) {
@@ -88,10 +88,40 @@ __global__ __launch_bounds__(256) void k_dense_left(const MPJob *__restrict__ jo
       for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int o = 0; o < NOUT; ++o)
-          acc[o][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(As[o][16 * rb + (lane & 15)][4 * k4 + kq], b,
-                                                            acc[o][rb], 0, 0, 0);
+          acc[o][rb] = TRANS ? __builtin_amdgcn_mfma_f64_16x16x4f64(b, As[o][16 * rb + (lane & 15)][4 * k4 + kq],
+                                                                     acc[o][rb], 0, 0, 0)
+                             : __builtin_amdgcn_mfma_f64_16x16x4f64(As[o][16 * rb + (lane & 15)][4 * k4 + kq], b,
+                                                                     acc[o][rb], 0, 0, 0);
     }
     __syncthreads();
+  }
+  if (TRANS) {
+    // operands swapped: register r of lane l holds column (l >> 4) + 4 r of
+    // the block and output row l % 16, so 16 lanes store 128 contiguous bytes
+    // of a row-contiguous output
+    const int cbase = ct * 64 + wave * 16;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int cc = cbase + (lane >> 4) + 4 * r;
+      if (cc >= g.C) continue;
+      const size_t ocol = size_t(cc / g.C1) * g.out_S1 + size_t(cc % g.C1) * g.out_cs;
+#pragma unroll
+      for (int o = 0; o < NOUT; ++o) {
+        double *out = static_cast<double *>(bufs.p[job.out_buf[o]]) + job.out_off[o] + ocol;
+        const double scale = job.scale[o];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+          const int i = row0 + 16 * rb + (lane & 15);
+          if (i < n) {
+            const size_t idx = size_t(i) * g.out_is;
+            double v = scale * acc[o][rb][r];
+            if (beta) v += out[idx];
+            out[idx] = v;
+          }
+        }
+      }
+    }
+    return;
   }
   // register r of lane l holds row (l >> 4) + 4 r of the 16 x 16 block, column l % 16
   const int cc = ct * 64 + wave * 16 + (lane & 15);
@@ -123,10 +153,15 @@ demag_status launch_dense_stage(hipStream_t s, const StagePlan &sp, const double
   const int col_tiles = (g.C + 63) / 64;
   const int row_groups = (g.n + 63) / 64;
   dim3 grid(unsigned(col_tiles * row_groups), unsigned(sp.jobs.size()));
-  if (sp.nout == 2)
-    k_dense_left<2><<<grid, 256, 0, s>>>(sp.d_jobs, sp.d_terms, bufs, mats, g, col_tiles, beta);
-  else
-    k_dense_left<1><<<grid, 256, 0, s>>>(sp.d_jobs, sp.d_terms, bufs, mats, g, col_tiles, beta);
+  // rows contiguous in the output (x and y stages): transposed blocks
+  const bool tr = g.out_is == 1;
+  if (sp.nout == 2) {
+    if (tr) k_dense_left<2, true><<<grid, 256, 0, s>>>(sp.d_jobs, sp.d_terms, bufs, mats, g, col_tiles, beta);
+    else k_dense_left<2, false><<<grid, 256, 0, s>>>(sp.d_jobs, sp.d_terms, bufs, mats, g, col_tiles, beta);
+  } else {
+    if (tr) k_dense_left<1, true><<<grid, 256, 0, s>>>(sp.d_jobs, sp.d_terms, bufs, mats, g, col_tiles, beta);
+    else k_dense_left<1, false><<<grid, 256, 0, s>>>(sp.d_jobs, sp.d_terms, bufs, mats, g, col_tiles, beta);
+  }
   DEMAG_TRY_HIP(hipGetLastError());
   return DEMAG_OK;
 }
