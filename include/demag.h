@@ -165,7 +165,8 @@ demag_status demag_apply_fft(demag_ctx *ctx, demag_factors *f, const double *m, 
  * phi: device [nz][ny][nx] or NULL; h: device [3][nz][ny][nx] or NULL (at
  * least one non-NULL), same element type as m.  Buffers must not overlap and
  * must be 16-byte aligned.  The grid is the one the factors were assembled
- * for. */
+ * for; n <= 1024 per axis (the bfloat16 factor windows and the LDS-staged
+ * factor rows are sized for it), else DEMAG_E_INVAL. */
 demag_status demag_apply_full(demag_ctx *ctx, const demag_factors *f, demag_prec prec,
                               const void *m, void *phi, void *h);
 
