@@ -16,6 +16,8 @@
 // entries in decreasing order, so the factors are stored as "windows": entry s
 // of a window table holds R[s..s+7] of the reversed generator R[u] = g[2n-2-u]
 // (zero outside), and a fragment is one aligned 16-byte LDS read.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace demag {
@@ -24,6 +26,8 @@ namespace {
 
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
 
 __device__ inline void split_value(float x, __bf16 &h, __bf16 &l, __bf16 &l2) {
   h = __bf16(x);
@@ -36,7 +40,19 @@ __device__ inline void split_value(float x, __bf16 &h, __bf16 &l, __bf16 &l2) {
 union Frag {
   uint4 u;
   bf8 v;
+  bf2 p[4];
 };
+
+// Two values at a time: one packed conversion per part (round to nearest
+// even), the bf16 -> FP32 widening is a shift or a mask.
+__device__ inline void split_pair(float x0, float x1, bf2 &h, bf2 &l, bf2 &l2) {
+  const f2 x = {x0, x1};
+  h = __builtin_convertvector(x, bf2);
+  const f2 r = x - __builtin_convertvector(h, f2);
+  l = __builtin_convertvector(r, bf2);
+  const f2 r2 = r - __builtin_convertvector(l, f2);
+  l2 = __builtin_convertvector(r2, bf2);
+}
 
 // Toeplitz fragment a times input fragment b; TRANS gives the transposed
 // 16x16 block (the instruction's A and B layouts mirror each other, so the
@@ -49,17 +65,35 @@ __device__ __forceinline__ f4 mma(bf8 a, bf8 b, f4 c) {
 
 constexpr int kStageRounds = 3;  // window entries a thread loads per staging round
 
+// LDS slots per window entry: the NOUT x PARTS windows of one entry side by
+// side, padded to an odd count so that 8 lanes reading consecutive entries
+// hit 8 different 16-byte bank groups.
+template <int NOUT, int PARTS>
+constexpr int window_slots() {
+  return (NOUT * PARTS) | 1;
+}
+
+template <int NOUT, int PARTS>
+size_t window_lds_bytes(int n, int rb) {
+  return size_t(window_slots<NOUT, PARTS>()) * (n + 16 * rb + 23) * sizeof(uint4);
+}
+
 // Tile: 4 waves x 16*CB columns, 16*RB rows.  The (term, K-step) pairs of a
-// job form one loop whose next step's input loads are in flight while the
-// current one is multiplied; all global loads are unconditional (clamped
-// rows and columns, zeroed or discarded), so the compiler waits only for the
-// loads it needs.  A term's windows are staged in rounds of up to
-// 3 x 256 entries whose loads are all issued before the first LDS store.
-template <int RB, int CB, int NOUT, int PARTS, bool TRANS>
+// job form one loop whose next step's input loads are issued right after the
+// current step's inputs are split, so they are in flight while it is
+// multiplied.  WHOLE (n a multiple of 32): every K-step lies inside the n
+// rows and loads from a uniform row pointer plus a per-lane 32-bit byte
+// offset; otherwise rows are clamped to n - 1 and the values past n of the
+// last step are zeroed.  A term's windows are staged in
+// rounds of up to 3 x 256 entries whose loads are all issued before the
+// first LDS store; fragments are read at compile-time offsets from one
+// per-lane address per K-step.
+template <int RB, int CB, int NOUT, int PARTS, bool TRANS, bool WHOLE>
 __global__ __launch_bounds__(256, 2) void k_left_bf16(const MPJob *__restrict__ jobs,
                                                    const MPTerm *__restrict__ terms, Bufs bufs,
                                                    const uint4 *__restrict__ wtab, MPGeom g, int nw,
                                                    int col_tiles, int beta) {
+  constexpr int SL = window_slots<NOUT, PARTS>();
   extern __shared__ uint4 wl[];
   const int n = g.n;
   const int cnt = n + 16 * RB + 23;
@@ -73,10 +107,12 @@ __global__ __launch_bounds__(256, 2) void k_left_bf16(const MPJob *__restrict__ 
   const int kq = lane >> 4;
   const int row0 = rg * 16 * RB;
   const int s0min = n - row0 - 16 * RB;
-  // local window entry of this lane for rb = 0, j0 = 0 (see the bound notes:
-  // 0 <= sbase - 16 rb + j0 < cnt for every rb < RB and j0 < n)
-  const int sbase = 16 * RB - 1 - (lane & 15) + 8 * kq;
+  // local window entry of this lane for rb = RB - 1, j0 = 0; row block rb
+  // at K-step j0 reads entry lbase + 16 (RB - 1 - rb) + j0, which lies in
+  // [0, cnt) for every rb < RB and j0 < n
+  const int lbase = 15 - (lane & 15) + 8 * kq;
   int64_t inoff[CB], outoff[CB];
+  uint32_t inb[CB];
   bool cval[CB];
 #pragma unroll
   for (int cb = 0; cb < CB; ++cb) {
@@ -86,10 +122,32 @@ __global__ __launch_bounds__(256, 2) void k_left_bf16(const MPJob *__restrict__ 
     const int co = cl / g.C1, ci = cl % g.C1;
     inoff[cb] = int64_t(co) * g.in_S1 + ci;
     outoff[cb] = int64_t(co) * g.out_S1 + int64_t(ci) * g.out_cs;
+    // byte offset of (row 8 kq, this column); used only in whole K-steps,
+    // where the row is < n and the offset lies inside the input (< 4 GiB for
+    // n <= 1024 per axis)
+    inb[cb] = uint32_t((int64_t(8 * kq) * g.kstride + inoff[cb]) * 4);
   }
   auto term_in = [&](int t) -> const float * {
     const MPTerm &tm = terms[job.term0 + t];
     return static_cast<const float *>(bufs.p[tm.in_buf]) + tm.in_off;
+  };
+  float raw[CB][8];
+  auto load_step = [&](const float *in, int j) {
+    if (WHOLE) {
+      // rows j .. j + 31, all < n: uniform row pointers
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const char *rowp = reinterpret_cast<const char *>(in + (int64_t(j) + e) * g.kstride);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) raw[cb][e] = *reinterpret_cast<const float *>(rowp + inb[cb]);
+      }
+    } else {
+      // rows clamped to n - 1 (the values past n are zeroed when split)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) raw[cb][e] = in[size_t(min(j + 8 * kq + e, n - 1)) * g.kstride + inoff[cb]];
+    }
   };
 
   f4 acc[NOUT][RB][CB];
@@ -102,14 +160,7 @@ __global__ __launch_bounds__(256, 2) void k_left_bf16(const MPJob *__restrict__ 
 
   const int nks = (n + 31) / 32;
   const int nq = nterms * nks;
-  float raw[CB][8];
-  {
-    const float *in = term_in(0);
-#pragma unroll
-    for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-      for (int e = 0; e < 8; ++e) raw[cb][e] = in[size_t(min(8 * kq + e, n - 1)) * g.kstride + inoff[cb]];
-  }
+  load_step(term_in(0), 0);
   int t = 0, j0 = 0;
   for (int q = 0; q < nq; ++q) {
     if (j0 == 0) {
@@ -134,23 +185,24 @@ __global__ __launch_bounds__(256, 2) void k_left_bf16(const MPJob *__restrict__ 
           const bool second = NOUT > 1 && e >= cnt;
           const int o = second ? 1 : 0, el = e - (second ? cnt : 0);
 #pragma unroll
-          for (int p = 0; p < PARTS; ++p) wl[(o * PARTS + p) * cnt + el] = v[r][p];
+          for (int p = 0; p < PARTS; ++p) wl[el * SL + o * PARTS + p] = v[r][p];
         }
       }
       __syncthreads();
     }
     Frag bh[CB], bl[CB], bl2[CB];
+    if (!WHOLE && j0 + 32 > n) {
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (j0 + 8 * kq + e >= n) raw[cb][e] = 0.0f;
+    }
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const float x = (j0 + 8 * kq + e < n) ? raw[cb][e] : 0.0f;
-        __bf16 h, l, l2;
-        split_value(x, h, l, l2);
-        bh[cb].v[e] = h;
-        bl[cb].v[e] = l;
-        bl2[cb].v[e] = l2;
-      }
+      for (int e = 0; e < 4; ++e)
+        split_pair(raw[cb][2 * e], raw[cb][2 * e + 1], bh[cb].p[e], bl[cb].p[e], bl2[cb].p[e]);
     {
       // next K-step: of this term, else the first of the next term; the
       // last step of the job re-reads its own rows
@@ -159,22 +211,20 @@ __global__ __launch_bounds__(256, 2) void k_left_bf16(const MPJob *__restrict__ 
         j1 = (t + 1 < nterms) ? 0 : j0;
         t1 = min(t + 1, nterms - 1);
       }
-      const float *in1 = term_in(t1);
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          raw[cb][e] = in1[size_t(min(j1 + 8 * kq + e, n - 1)) * g.kstride + inoff[cb]];
+      load_step(term_in(t1), j1);
     }
+    // keep the loads ahead of the products
+    __builtin_amdgcn_sched_barrier(0);
+    const uint4 *wp = wl + (lbase + j0) * SL;
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
-      const int idx = sbase - 16 * rb + j0;
 #pragma unroll
       for (int o = 0; o < NOUT; ++o) {
+        const uint4 *w = wp + 16 * (RB - 1 - rb) * SL + o * PARTS;
         Frag ah, al, al2;
-        ah.u = wl[(o * PARTS + 0) * cnt + idx];
-        al.u = wl[(o * PARTS + 1) * cnt + idx];
-        if (PARTS == 3) al2.u = wl[(o * PARTS + 2) * cnt + idx];
+        ah.u = w[0];
+        al.u = w[1];
+        if (PARTS == 3) al2.u = w[2];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
           f4 a = acc[o][rb][cb];
@@ -197,47 +247,84 @@ __global__ __launch_bounds__(256, 2) void k_left_bf16(const MPJob *__restrict__ 
     }
   }
 
+  // beta (accumulate into the output) and whole row groups are uniform:
+  // one branch picks the epilogue.  With beta the old values of a row block
+  // (or column) are all loaded before its stores.
+  auto epilogue = [&](auto beta_c, auto whole_c) {
+    constexpr bool BETA = decltype(beta_c)::value;
+    constexpr bool WROWS = decltype(whole_c)::value;
 #pragma unroll
-  for (int o = 0; o < NOUT; ++o) {
-    float *out = static_cast<float *>(bufs.p[job.out_buf[o]]) + job.out_off[o];
-    const float scale = float(job.scale[o]);
+    for (int o = 0; o < NOUT; ++o) {
+      float *out = static_cast<float *>(bufs.p[job.out_buf[o]]) + job.out_off[o];
+      const float scale = float(job.scale[o]);
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      if (TRANS) {
-        // register r of lane l: column cbase + 4 (l/16) + r, output row 16 rb + l % 16
-        const int cbase = ct * (64 * CB) + wave * (16 * CB) + 16 * cb;
+      for (int cb = 0; cb < CB; ++cb) {
+        if (TRANS) {
+          // register r of lane l: column cbase + 4 (l/16) + r, output row
+          // 16 rb + l % 16; rows are contiguous in the output (out_is = 1)
+          const int cbase = ct * (64 * CB) + wave * (16 * CB) + 16 * cb;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int cc = cbase + 4 * kq + r;
-          if (cc >= g.C) continue;
-          const int64_t ob = int64_t(cc / g.C1) * g.out_S1 + int64_t(cc % g.C1) * g.out_cs;
+          for (int r = 0; r < 4; ++r) {
+            const int cc = cbase + 4 * kq + r;
+            if (cc >= g.C) continue;
+            float *col = out + int64_t(cc / g.C1) * g.out_S1 + int64_t(cc % g.C1) * g.out_cs + row0 + (lane & 15);
+            float old[RB];
+            if (BETA) {
 #pragma unroll
-          for (int rb = 0; rb < RB; ++rb) {
-            const int i = row0 + 16 * rb + (lane & 15);
-            if (i < n) {
-              const size_t idx = ob + size_t(i) * g.out_is;
+              for (int rb = 0; rb < RB; ++rb)
+                old[rb] = (WROWS || row0 + 16 * rb + (lane & 15) < n) ? col[16 * rb] : 0.0f;
+            }
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+              if (WROWS || row0 + 16 * rb + (lane & 15) < n) {
+                float v = scale * acc[o][rb][cb][r];
+                if (BETA) v += old[rb];
+                col[16 * rb] = v;
+              }
+            }
+          }
+          continue;
+        }
+        if (!cval[cb]) continue;
+        // 16x16 output block: register r of lane l is row 4 (l/16) + r
+        const uint32_t ob = uint32_t((outoff[cb] + int64_t(4 * kq) * g.out_is) * 4);
+        auto dst = [&](int rb, int r) -> float * {
+          if (WROWS) {
+            char *rowp = reinterpret_cast<char *>(out + (int64_t(row0) + 16 * rb + r) * g.out_is);
+            return reinterpret_cast<float *>(rowp + ob);
+          }
+          return out + outoff[cb] + size_t(row0 + 16 * rb + 4 * kq + r) * g.out_is;
+        };
+        auto ok = [&](int rb, int r) { return WROWS || row0 + 16 * rb + 4 * kq + r < n; };
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          float old[4];
+          if (BETA) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) old[r] = ok(rb, r) ? *dst(rb, r) : 0.0f;
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            if (ok(rb, r)) {
               float v = scale * acc[o][rb][cb][r];
-              if (beta) v += out[idx];
-              out[idx] = v;
+              if (BETA) v += old[r];
+              *dst(rb, r) = v;
             }
           }
         }
-        continue;
       }
-      if (!cval[cb]) continue;
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = row0 + 16 * rb + 4 * kq + r;   // 16x16 output: row 4 (l/16) + r
-          if (i < n) {
-            const size_t idx = outoff[cb] + size_t(i) * g.out_is;
-            float v = scale * acc[o][rb][cb][r];
-            if (beta) v += out[idx];
-            out[idx] = v;
-          }
-        }
     }
+  };
+  if (row0 + 16 * RB <= n) {
+    if (beta)
+      epilogue(std::true_type{}, std::true_type{});
+    else
+      epilogue(std::false_type{}, std::true_type{});
+  } else {
+    if (beta)
+      epilogue(std::true_type{}, std::false_type{});
+    else
+      epilogue(std::false_type{}, std::false_type{});
   }
 }
 
@@ -248,21 +335,15 @@ demag_status launch_bf(hipStream_t s, const StagePlan &sp, const uint4 *wtab, in
   const int col_tiles = (g.C + 64 * CB - 1) / (64 * CB);
   const int row_groups = (g.n + 16 * RB - 1) / (16 * RB);
   dim3 grid(col_tiles * row_groups, unsigned(sp.jobs.size()));
-  const size_t lds = size_t(NOUT) * PARTS * (g.n + 16 * RB + 23) * sizeof(uint4);
+  const size_t lds = window_lds_bytes<NOUT, PARTS>(g.n, RB);
   // rows contiguous in the output (x and y stages): transposed blocks
-  if (g.out_is == 1) {
-    auto k = &k_left_bf16<RB, CB, NOUT, PARTS, true>;
-    if (lds > 65536)
-      DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        int(lds)));
-    k<<<grid, 256, lds, s>>>(sp.d_jobs, sp.d_terms, bufs, wtab, g, nw, col_tiles, beta);
-  } else {
-    auto k = &k_left_bf16<RB, CB, NOUT, PARTS, false>;
-    if (lds > 65536)
-      DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        int(lds)));
-    k<<<grid, 256, lds, s>>>(sp.d_jobs, sp.d_terms, bufs, wtab, g, nw, col_tiles, beta);
-  }
+  const bool trans = g.out_is == 1, whole = g.n % 32 == 0;
+  auto k = trans ? (whole ? &k_left_bf16<RB, CB, NOUT, PARTS, true, true> : &k_left_bf16<RB, CB, NOUT, PARTS, true, false>)
+                 : (whole ? &k_left_bf16<RB, CB, NOUT, PARTS, false, true> : &k_left_bf16<RB, CB, NOUT, PARTS, false, false>);
+  if (lds > 65536)
+    DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      int(lds)));
+  k<<<grid, 256, lds, s>>>(sp.d_jobs, sp.d_terms, bufs, wtab, g, nw, col_tiles, beta);
   DEMAG_TRY_HIP(hipGetLastError());
   return DEMAG_OK;
 }
