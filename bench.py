@@ -105,6 +105,31 @@ def _copy_calibration(mib):
     del x, y
 
 
+def _vendor_gemm():
+    """Context for the matrix-core figures: torch.matmul (the vendor GEMM
+    library) on square contiguous matrices, FP64 / FP32 / BF16, TFLOP/s of
+    the best of three timed calls."""
+    import torch
+    out = {}
+    for name, dt, size in (("fp64", torch.float64, 8192), ("fp32", torch.float32, 8192), ("bf16", torch.bfloat16, 16384)):
+        a = torch.rand((size, size), dtype=dt, device="cuda")
+        b = torch.rand((size, size), dtype=dt, device="cuda")
+        c = torch.matmul(a, b)
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            torch.matmul(a, b, out=c)
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        out[name] = {"n": size, "tflops": round(2.0 * size ** 3 / (best * 1e-3) / 1e12, 1)}
+        del a, b, c
+        torch.cuda.empty_cache()
+    return out
+
+
 def _kernels(prof, steps):
     return {k: {"ms_per_step": round(v["ms"] / steps, 4), "launches_per_step": v["launches"] // steps,
                 "tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3)} for k, v in sorted(prof.items())}
@@ -332,6 +357,8 @@ def headline(args):
         "nonuniform_grid": nonuni,
         "precisions": results,
     }
+    if args.vendor_gemm:
+        line["vendor_gemm"] = _vendor_gemm()
     if args.cpu_nodes > 0:
         line["cpu_baseline"] = _cpu_baseline(m_host, n, args.cpu_nodes)
     print(json.dumps(line), flush=True)
@@ -448,6 +475,8 @@ def main():
     ap.add_argument("--nonuniform", type=int, default=1, help="also time the apply on a graded non-uniform grid")
     ap.add_argument("--learned-eval", type=int, default=1,
                     help="evaluate the trained network at 256^3 full format and 1024^3 CP rank 10")
+    ap.add_argument("--vendor-gemm", type=int, default=1,
+                    help="also time torch.matmul at FP64/FP32/BF16 as context for the matrix-core figures")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain copy of this many MiB first (byte-counter calibration)")
     args = ap.parse_args()

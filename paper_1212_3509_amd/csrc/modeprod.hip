@@ -79,7 +79,7 @@ __device__ __forceinline__ const T *gen_addr(const T *g0, const T *g1, int e, in
 // 16x16 block (same fragments: the A and B layouts of the instruction are
 // mirror images), so a lane's results run along the output rows i; chosen
 // when rows are contiguous in memory (out_is == 1), giving 128-byte stores.
-template <class T, int RB, int NOUT, bool TRANS>
+template <class T, int RB, int NOUT, bool TRANS, bool WHOLE = false>
 __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__restrict__ terms, const Bufs &bufs,
                                           const T *__restrict__ gens, const MPGeom &g, int ct, int rg, int beta,
                                           T *sg) {
@@ -98,6 +98,10 @@ __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__rest
   const int cl = cvalid ? c : g.C - 1;
   const int co = cl / g.C1, ci = cl % g.C1;
   const size_t cin = size_t(co) * g.in_S1 + ci;
+  // WHOLE (n a multiple of 4 kUnroll): every chunk lies inside the n rows,
+  // so its loads need no clamping and its inputs no masking; row j0 + 4 u +
+  // kq is a uniform row pointer plus this lane's offset kq kstride + cin
+  const size_t clane = size_t(kq) * g.kstride + cin;
   const int row0 = rg * 16 * RB;
   // LDS index of T[row0 + (lane & 15)][kq] for j0 = 0; add 16 rb - j0.
   // With 32 leading zeros and glds = 2n + 16 RB + 32 every index stays in
@@ -130,14 +134,22 @@ __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__rest
     }
   }
   T nxt[kUnroll];
-  {
-    const T *in = term_in(0);
+  auto load_chunk = [&](int t1, int j1) {
+    if (WHOLE) {
+      const MPTerm &tm = terms[job.term0 + t1];
+      const T *base = static_cast<const T *>(bufs.p[tm.in_buf]) + tm.in_off;
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int j = min(4 * u + kq, n - 1);
-      nxt[u] = in[size_t(j) * g.kstride];
+      for (int u = 0; u < kUnroll; ++u) nxt[u] = (base + int64_t(j1 + 4 * u) * g.kstride)[clane];
+    } else {
+      const T *in1 = term_in(t1);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int j = min(j1 + 4 * u + kq, n - 1);
+        nxt[u] = in1[size_t(j) * g.kstride];
+      }
     }
-  }
+  };
+  load_chunk(0, 0);
 
   int t = 0, j0 = 0;
   for (int q = 0; q < nq; ++q) {
@@ -181,20 +193,17 @@ __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__rest
         j1 = (t + 1 < nterms) ? 0 : j0;
         t1 = min(t + 1, nterms - 1);
       }
-      const T *in1 = term_in(t1);
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int j = min(j1 + 4 * u + kq, n - 1);
-        nxt[u] = in1[size_t(j) * g.kstride];
-      }
+      load_chunk(t1, j1);
     }
+    // keep the next chunk's loads ahead of this chunk's products
+    __builtin_amdgcn_sched_barrier(0);
     // straight-line K-steps (no branch, so the LDS reads of a step are
     // issued while the previous step's products run); in the last chunk of
     // a term the steps past n multiply a zero input
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int jj = j0 + 4 * u;
-      const T b = (jj + kq < n) ? cur[u] : T(0);
+      const T b = (WHOLE || jj + kq < n) ? cur[u] : T(0);
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
         const int idx = ibase + 16 * rb - jj;
@@ -264,15 +273,15 @@ __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__rest
   }
 }
 
-template <class T, int RB, int NOUT, int AXIS>
+template <class T, int RB, int NOUT, int AXIS, bool WHOLE>
 __global__ __launch_bounds__(256, 2) void k_left(const MPJob *__restrict__ jobs, const MPTerm *__restrict__ terms,
                                               Bufs bufs, const T *__restrict__ gens, MPGeom g, int col_tiles,
                                               int beta) {
   extern __shared__ unsigned char smem_raw[];
   const MPJob job = jobs[blockIdx.y];
   // the x and y stages write rows contiguously; the z stage writes columns
-  left_tile<T, RB, NOUT, AXIS != 2>(job, terms, bufs, gens, g, blockIdx.x % col_tiles, blockIdx.x / col_tiles, beta,
-                         reinterpret_cast<T *>(smem_raw));
+  left_tile<T, RB, NOUT, AXIS != 2, WHOLE>(job, terms, bufs, gens, g, blockIdx.x % col_tiles, blockIdx.x / col_tiles,
+                                           beta, reinterpret_cast<T *>(smem_raw));
 }
 
 // Persistent variant: workgroups take items from a counter (one atomic add
@@ -324,10 +333,11 @@ demag_status launch_axis(hipStream_t s, const StagePlan &sp, const T *gens, cons
   const int row_groups = (g.n + 16 * RB - 1) / (16 * RB);
   dim3 grid(col_tiles * row_groups, unsigned(sp.jobs.size()));
   const size_t lds = tile_lds_elems(g.n, RB, NOUT) * sizeof(T);
+  auto k = (g.n % (4 * kUnroll) == 0) ? &k_left<T, RB, NOUT, AXIS, true> : &k_left<T, RB, NOUT, AXIS, false>;
   if (lds > 65536)
-    DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_left<T, RB, NOUT, AXIS>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-  k_left<T, RB, NOUT, AXIS><<<grid, 256, lds, s>>>(sp.d_jobs, sp.d_terms, bufs, gens, g, col_tiles, beta);
+    DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      int(lds)));
+  k<<<grid, 256, lds, s>>>(sp.d_jobs, sp.d_terms, bufs, gens, g, col_tiles, beta);
   DEMAG_TRY_HIP(hipGetLastError());
   return DEMAG_OK;
 }
