@@ -105,12 +105,17 @@ __global__ __launch_bounds__(256, 2) void k_left_bf16(const MPJob *__restrict__ 
   const int rg = blockIdx.x / col_tiles;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int kq = lane >> 4;
+  // K rows of lane group kq within a step: 8 kp .. 8 kp + 7 with kp = 0, 2,
+  // 1, 3 for kq = 0..3 (the same K order for A and B).  With the plain
+  // order the window reads of lane groups 0 and 2 (and 1 and 3) fall into
+  // the same LDS banks; this order makes them conflict-free.
+  const int kp = ((kq & 1) << 1) | (kq >> 1);
   const int row0 = rg * 16 * RB;
   const int s0min = n - row0 - 16 * RB;
   // local window entry of this lane for rb = RB - 1, j0 = 0; row block rb
   // at K-step j0 reads entry lbase + 16 (RB - 1 - rb) + j0, which lies in
   // [0, cnt) for every rb < RB and j0 < n
-  const int lbase = 15 - (lane & 15) + 8 * kq;
+  const int lbase = 15 - (lane & 15) + 8 * kp;
   int64_t inoff[CB], outoff[CB];
   uint32_t inb[CB];
   bool cval[CB];
@@ -122,10 +127,10 @@ __global__ __launch_bounds__(256, 2) void k_left_bf16(const MPJob *__restrict__ 
     const int co = cl / g.C1, ci = cl % g.C1;
     inoff[cb] = int64_t(co) * g.in_S1 + ci;
     outoff[cb] = int64_t(co) * g.out_S1 + int64_t(ci) * g.out_cs;
-    // byte offset of (row 8 kq, this column); used only in whole K-steps,
+    // byte offset of (row 8 kp, this column); used only in whole K-steps,
     // where the row is < n and the offset lies inside the input (< 4 GiB for
     // n <= 1024 per axis)
-    inb[cb] = uint32_t((int64_t(8 * kq) * g.kstride + inoff[cb]) * 4);
+    inb[cb] = uint32_t((int64_t(8 * kp) * g.kstride + inoff[cb]) * 4);
   }
   auto term_in = [&](int t) -> const float * {
     const MPTerm &tm = terms[job.term0 + t];
@@ -146,7 +151,7 @@ __global__ __launch_bounds__(256, 2) void k_left_bf16(const MPJob *__restrict__ 
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-        for (int e = 0; e < 8; ++e) raw[cb][e] = in[size_t(min(j + 8 * kq + e, n - 1)) * g.kstride + inoff[cb]];
+        for (int e = 0; e < 8; ++e) raw[cb][e] = in[size_t(min(j + 8 * kp + e, n - 1)) * g.kstride + inoff[cb]];
     }
   };
 
@@ -196,7 +201,7 @@ __global__ __launch_bounds__(256, 2) void k_left_bf16(const MPJob *__restrict__ 
       for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
         for (int e = 0; e < 8; ++e)
-          if (j0 + 8 * kq + e >= n) raw[cb][e] = 0.0f;
+          if (j0 + 8 * kp + e >= n) raw[cb][e] = 0.0f;
     }
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
