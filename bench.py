@@ -147,10 +147,41 @@ def _cpu_baseline(m, n, nodes_sample):
     wall = time.perf_counter() - w0
     cpu = time.process_time() - c0
     per_apply = wall * 40 / nodes_sample
-    return {"value": round(n ** 3 / per_apply / 1e6, 6), "unit": "Mcell-field evals/s",
-            "cores": max(1, round(cpu / wall)), "kind": "oracle",
-            "sample": f"{nodes_sample} of 40 nodes of the 128^3 vortex apply (FP64 NumPy, dense Toeplitz "
-                      f"factors), wall {wall:.1f} s, scaled x{40 / nodes_sample:g}"}
+    out = {"value": round(n ** 3 / per_apply / 1e6, 6), "unit": "Mcell-field evals/s",
+           "cores": max(1, round(cpu / wall)), "kind": "oracle",
+           "sample": f"{nodes_sample} of 40 nodes of the 128^3 vortex apply (FP64 NumPy, dense Toeplitz "
+                     f"factors), wall {wall:.1f} s, scaled x{40 / nodes_sample:g}"}
+    out["host"] = _host_info()
+    # the exact collocation (closed-form cell kernels + FFT convolution) on
+    # the 32^3 random-field case, as the oracle computes it
+    from paper_1212_3509_amd import inputs
+    m32 = inputs.random_unit_field(32, seed=0)
+    c0 = time.process_time()
+    w0 = time.perf_counter()
+    apply.collocated_apply_fft(m32, (1.0 / 32,) * 3)
+    wall = time.perf_counter() - w0
+    cpu = time.process_time() - c0
+    out["exact_fft_32"] = {"value": round(32 ** 3 / wall / 1e6, 6), "unit": "Mcell-field evals/s",
+                           "seconds": round(wall, 3), "cores": max(1, round(cpu / wall))}
+    return out
+
+
+def _host_info():
+    """Host cores and BLAS threading of the process that timed the oracle."""
+    import os
+    info = {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
+    try:
+        with open("/proc/cpuinfo") as fh:
+            info["cpu_model"] = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), None)
+    except OSError:
+        info["cpu_model"] = None
+    try:
+        import threadpoolctl
+        info["blas"] = [{"api": d.get("internal_api"), "threads": d.get("num_threads")}
+                        for d in threadpoolctl.threadpool_info()]
+    except ImportError:
+        info["blas"] = None
+    return info
 
 
 def _rel(a, b):
