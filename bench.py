@@ -402,6 +402,8 @@ def structured(args):
     from paper_1212_3509_amd import api, inputs
 
     n, M = 4096, 40
+    if args.calib_copy_mib > 0:
+        _copy_calibration(args.calib_copy_mib)
     ctx = api.Context(0)
     f = ctx.assemble((n, n, n), (1.0 / n,) * 3, M=M, c0=2.15)
     ctx.prepare_structured(f)
@@ -436,7 +438,8 @@ def structured(args):
     rng = np.random.default_rng(9)
     smooth = [np.stack([np.stack([np.cos(np.pi * (l + 1) * rng.uniform(0.5, 1.5) * x + rng.uniform(0, 3))
                                   for l in range(10)]) for _q in range(3)]).astype(np.float32) for _d in range(3)]
-    for name, cols_in in (("cp_r10_random", U), ("cp_r10_smooth", [torch.from_numpy(c).cuda() for c in smooth])):
+    for name, cols_in in (("cp_r10_random", U), ("cp_r10_smooth", [torch.from_numpy(c).cuda() for c in smooth])
+                          ) if args.recompress else ():
         out_cols, table = ctx.apply_cp(f, cols_in)
         T = table.shape[1]
         tab = torch.from_numpy(np.ascontiguousarray(table[0])).cuda()
@@ -506,6 +509,7 @@ def main():
     ap.add_argument("--nonuniform", type=int, default=1, help="also time the apply on a graded non-uniform grid")
     ap.add_argument("--learned-eval", type=int, default=1,
                     help="evaluate the trained network at 256^3 full format and 1024^3 CP rank 10")
+    ap.add_argument("--recompress", type=int, default=1, help="cp4096: also time the HOOI recompression")
     ap.add_argument("--vendor-gemm", type=int, default=1,
                     help="also time torch.matmul at FP64/FP32/BF16 as context for the matrix-core figures")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
