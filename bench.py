@@ -472,8 +472,7 @@ def batch(args):
     ctx.set_workspace_limit(int(args.batch_ws_gib) << 30)
     b = ctx.batch([(s.n, s.h) for s in states], M=40, prec="fp32")
     if args.tune:
-        b.tune(os.path.join(ROOT, "gpurun_out", "batch_tune.json") if os.path.isdir(os.path.join(ROOT, "gpurun_out"))
-               else None, reps=2)
+        b.tune(args.tune_cache or None, reps=2)
     off = b.offsets()
     m = torch.from_numpy(np.concatenate([s.m.reshape(-1) for s in states]).astype(np.float32)).cuda()
     phi = torch.empty(int(off[-1]), dtype=torch.float32, device="cuda")
@@ -505,6 +504,7 @@ def main():
     ap.add_argument("--mixed-prec", default="bf16x3")
     ap.add_argument("--batch-ws-gib", type=int, default=64)
     ap.add_argument("--tune", type=int, default=1)
+    ap.add_argument("--tune-cache", default="", help="batch: JSON file of tuned tile shapes to read and extend")
     ap.add_argument("--fft3d", type=int, default=1, help="also time the 3D-FFT route of the same operator")
     ap.add_argument("--nonuniform", type=int, default=1, help="also time the apply on a graded non-uniform grid")
     ap.add_argument("--learned-eval", type=int, default=1,
@@ -516,8 +516,8 @@ def main():
                     help="run a plain copy of this many MiB first (byte-counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this library runs on a single GPU; multi-GPU runs are not part of it "
-              "(see DESIGN.md for how the path would shard)", file=sys.stderr)
+        print("bench.py: this library runs on a single GPU; multi-GPU runs (sharding the quadrature nodes, "
+              "states or structured jobs over ranks) are not implemented", file=sys.stderr)
         sys.exit(2)
     {"headline": headline, "cp4096": structured, "batch": batch}[args.workload](args)
 

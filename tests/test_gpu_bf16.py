@@ -3,7 +3,7 @@
 The split itself is integer work and must match the oracle's bit operations
 exactly.  The applies are compared with the FP64 GPU result: three-part
 splits carry 24 significant bits like FP32 (same bound as FP32), two-part
-splits 16 bits (the survey's probe: ~4e-6 on the potential)."""
+splits 16 bits (about 4e-6 on the potential at 128^3)."""
 import numpy as np
 import pytest
 import torch
