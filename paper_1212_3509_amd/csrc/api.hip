@@ -144,8 +144,12 @@ enum Buf { B_M = 0, B_Y1 = 1, B_Y2 = 2, B_PHI = 3, B_H = 4 };
 // Each output's triple of factor types is then that of the potential kernel
 // K^q (X along q, E elsewhere) or its derivative along the field axis p
 // (X -> P = -X', E -> Q = -E').  6 + 9 + 8 = 23 products per node.
+// xsplit > 1: the x stage's sums over the chunk's nodes are cut into xsplit
+// jobs of consecutive terms each, which write unscaled partial sums to the
+// (then dead) Y1 region, partial s of output o (phi, h_x, h_y, h_z) at
+// (4 s + o) N; launch_reduce_partials forms the outputs from them.
 void build_chunk(const demag_factors *f, int k0, int kc, double phi_scale,
-                 std::vector<StagePlan> &stages) {
+                 std::vector<StagePlan> &stages, int xsplit) {
   const int nx = f->n[0], ny = f->n[1], nz = f->n[2];
   const int64_t N = int64_t(nx) * ny * nz;
   const int M = f->M;
@@ -225,37 +229,61 @@ void build_chunk(const demag_factors *f, int k0, int kc, double phi_scale,
   s3b.geom = gx;
   s3b.axis = 0;
   s3b.nout = 1;
-  {
+  // terms [t0, t1) of the 2 kc terms of an x-stage sum: job s of xsplit
+  auto part = [kc, xsplit](int s, int &t0, int &t1) {
+    const int per = (2 * kc + xsplit - 1) / xsplit;
+    t0 = std::min(2 * kc, s * per);
+    t1 = std::min(2 * kc, t0 + per);
+  };
+  for (int kl = 0; kl < kc; ++kl) {
+    const int k = k0 + kl;
+    s3a.terms.push_back(term(B_Y2, y2(kl, 0), gen(F_E, k), gen(F_Q, k)));
+    s3a.terms.push_back(term(B_Y2, y2(kl, 2), gen(F_X, k), gen(F_P, k)));
+  }
+  for (int sp = 0; sp < xsplit; ++sp) {
+    int t0, t1;
+    part(sp, t0, t1);
+    if (t1 <= t0) continue;
     MPJob j{};
-    j.term0 = 0;
-    j.nterms = 2 * kc;
-    j.out_buf[0] = B_PHI;
-    j.out_off[0] = 0;
-    j.scale[0] = phi_scale;
-    j.out_buf[1] = B_H;
-    j.out_off[1] = 0;
-    j.scale[1] = 1.0;
-    for (int kl = 0; kl < kc; ++kl) {
-      const int k = k0 + kl;
-      s3a.terms.push_back(term(B_Y2, y2(kl, 0), gen(F_E, k), gen(F_Q, k)));
-      s3a.terms.push_back(term(B_Y2, y2(kl, 2), gen(F_X, k), gen(F_P, k)));
+    j.term0 = t0;
+    j.nterms = t1 - t0;
+    if (xsplit > 1) {
+      j.out_buf[0] = B_Y1;
+      j.out_off[0] = (int64_t(4) * sp + 0) * N;
+      j.scale[0] = 1.0;
+      j.out_buf[1] = B_Y1;
+      j.out_off[1] = (int64_t(4) * sp + 1) * N;
+      j.scale[1] = 1.0;
+    } else {
+      j.out_buf[0] = B_PHI;
+      j.out_off[0] = 0;
+      j.scale[0] = phi_scale;
+      j.out_buf[1] = B_H;
+      j.out_off[1] = 0;
+      j.scale[1] = 1.0;
     }
     s3a.jobs.push_back(j);
   }
   for (int p = 1; p <= 2; ++p) {
-    MPJob j{};
-    j.term0 = int32_t(s3b.terms.size());
-    j.nterms = 2 * kc;
-    j.out_buf[0] = B_H;
-    j.out_off[0] = p * N;
-    j.scale[0] = 1.0;
+    const int base = int(s3b.terms.size());
     const int su = (p == 1) ? 1 : 4, sv = (p == 1) ? 3 : 5;
     for (int kl = 0; kl < kc; ++kl) {
       const int k = k0 + kl;
       s3b.terms.push_back(term(B_Y2, y2(kl, su), gen(F_E, k), 0));
       s3b.terms.push_back(term(B_Y2, y2(kl, sv), gen(F_X, k), 0));
     }
-    s3b.jobs.push_back(j);
+    for (int sp = 0; sp < xsplit; ++sp) {
+      int t0, t1;
+      part(sp, t0, t1);
+      if (t1 <= t0) continue;
+      MPJob j{};
+      j.term0 = base + t0;
+      j.nterms = t1 - t0;
+      j.out_buf[0] = (xsplit > 1) ? B_Y1 : B_H;
+      j.out_off[0] = (xsplit > 1) ? (int64_t(4) * sp + 1 + p) * N : p * N;
+      j.scale[0] = 1.0;
+      s3b.jobs.push_back(j);
+    }
   }
   for (StagePlan *sp : {&s1, &s2a, &s2b, &s3a, &s3b}) finish(*sp);
   stages.clear();
@@ -269,7 +297,7 @@ void build_chunk(const demag_factors *f, int k0, int kc, double phi_scale,
 }  // namespace
 
 void build_chunk_plan(const demag_factors *f, int k0, int kc, double phi_scale, std::vector<StagePlan> &stages) {
-  build_chunk(f, k0, kc, phi_scale, stages);
+  build_chunk(f, k0, kc, phi_scale, stages, 1);
 }
 
 namespace {
@@ -286,7 +314,13 @@ demag_status get_plan(demag_ctx *ctx, demag_factors *f, demag_prec prec, FullPla
     return DEMAG_E_NOMEM;
   }
   while (kc > 1 && fixed + per_node * kc > ctx->ws_limit) kc = (kc + 1) / 2;
-  const int key_prec = (prec == DEMAG_FP64) ? 0 : 1;
+  // bfloat16 splits: the x stage's sums over nodes run as kXSplit jobs of
+  // partial sums (more workgroups for a stage that otherwise has one or two
+  // jobs), when the chunk's Y1 region holds the 4 kXSplit partial outputs
+  constexpr int kXSplit = 4;
+  const bool bf = (prec == DEMAG_BF16X2 || prec == DEMAG_BF16X3);
+  const int xsplit = (bf && 6 * kc >= 4 * kXSplit) ? kXSplit : 1;
+  const int key_prec = (prec == DEMAG_FP64) ? 0 : bf ? 2 : 1;
   auto key = std::make_pair(key_prec, kc);
   auto it = f->plans.find(key);
   if (it != f->plans.end()) {
@@ -295,13 +329,14 @@ demag_status get_plan(demag_ctx *ctx, demag_factors *f, demag_prec prec, FullPla
   }
   auto plan = std::make_unique<FullPlan>();
   plan->kc = kc;
+  plan->xsplit = xsplit;
   plan->nchunks = (f->M + kc - 1) / kc;
   plan->ws_elems = size_t(12) * kc * N + size_t(4) * N;
   plan->chunks.resize(plan->nchunks);
   for (int c = 0; c < plan->nchunks; ++c) {
     const int k0 = c * kc;
     const int kcc = std::min(kc, f->M - k0);
-    build_chunk(f, k0, kcc, f->L, plan->chunks[c]);
+    build_chunk(f, k0, kcc, f->L, plan->chunks[c], xsplit);
     for (auto &sp : plan->chunks[c]) {
       demag_status st = upload(sp.jobs, &sp.d_jobs);
       if (st != DEMAG_OK) return st;
@@ -677,8 +712,14 @@ demag_status demag_apply_full(demag_ctx *ctx, const demag_factors *fc, demag_pre
   for (int c = 0; c < plan->nchunks; ++c) {
     const auto &stages = plan->chunks[c];
     for (size_t s = 0; s < stages.size(); ++s) {
-      const int beta = (s >= 3 && c > 0) ? 1 : 0;
+      // later chunks accumulate into the outputs (partial sums never do)
+      const int beta = (s >= 3 && c > 0 && plan->xsplit == 1) ? 1 : 0;
       st = launch_left_stage(ctx, f, prec, stages[s], bufs, beta);
+      if (st != DEMAG_OK) return st;
+    }
+    if (plan->xsplit > 1) {
+      st = launch_reduce_partials(ctx, prec, reinterpret_cast<const float *>(y1), plan->xsplit, N,
+                                  static_cast<float *>(bufs[3]), static_cast<float *>(bufs[4]), f->L, c > 0);
       if (st != DEMAG_OK) return st;
     }
   }
