@@ -67,3 +67,28 @@ def test_bf16x3_128_vortex(ctx):
     e_phi, e_h = _rel(p3, p64), _rel(h3, h64)
     print(f"128^3 bf16x3 vs fp64: phi {e_phi:.3e}  h {e_h:.3e}")
     assert e_h < 1e-6 and e_phi < 3e-6
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x2"])
+def test_x_stage_partial_sums(ctx, prec):
+    """The x stage's sums over nodes run as four partial-sum jobs when a node
+    chunk has at least 3 nodes, as single jobs otherwise (1-node chunks, set
+    through the workspace limit, or M = 2): all agree with FP64 to the split
+    precision, and with each other to FP32 summation order."""
+    n = (24, 20, 36)
+    h = (1 / 36,) * 3
+    m = inputs.random_unit_field(n, seed=5)
+    tol = 1e-6 if prec == "bf16x3" else 3e-5
+    for M in (2, 12):
+        f = ctx.assemble(n, h, M=M)
+        p64, h64 = _apply(ctx, f, m, "fp64")
+        ps, hs = _apply(ctx, f, m, prec)                 # one chunk of M nodes
+        N = n[0] * n[1] * n[2]
+        ctx.set_workspace_limit(4 * N * 4 + 12 * N * 4)  # one node per chunk: single jobs
+        try:
+            p1, h1 = _apply(ctx, f, m, prec)
+        finally:
+            ctx.set_workspace_limit(16 << 30)
+        for p, hh in ((ps, hs), (p1, h1)):
+            assert _rel(p, p64) < tol and _rel(hh, h64) < tol, (M, _rel(p, p64), _rel(hh, h64))
+        assert _rel(ps, p1) < 1e-6 and _rel(hs, h1) < 1e-6
