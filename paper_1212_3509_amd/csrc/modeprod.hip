@@ -197,20 +197,50 @@ __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__rest
     }
     // keep the next chunk's loads ahead of this chunk's products
     __builtin_amdgcn_sched_barrier(0);
-    // straight-line K-steps (no branch, so the LDS reads of a step are
-    // issued while the previous step's products run); in the last chunk of
-    // a term the steps past n multiply a zero input
+    // one output: the Toeplitz fragments of step u + 1 are read from LDS
+    // into a second register set before step u's products are issued (with
+    // two outputs the second set costs a wave per SIMD in FP32 and does not
+    // fit in FP64)
+    constexpr bool kABuf = WHOLE && NOUT == 1;
+    if constexpr (kABuf) {
+      T a[2][NOUT][RB];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int jj = j0 + 4 * u;
-      const T b = (WHOLE || jj + kq < n) ? cur[u] : T(0);
+      for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const int idx = ibase + 16 * rb - jj;
+        for (int o = 0; o < NOUT; ++o) a[0][o][rb] = sgen[o * glds + ibase + 16 * rb - j0];
 #pragma unroll
-        for (int o = 0; o < NOUT; ++o)
-          acc[o][rb] = TRANS ? Mf::step(b, sgen[o * glds + idx], acc[o][rb])
-                             : Mf::step(sgen[o * glds + idx], b, acc[o][rb]);
+      for (int u = 0; u < kUnroll; ++u) {
+        if (u + 1 < kUnroll) {
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int o = 0; o < NOUT; ++o)
+              a[(u + 1) & 1][o][rb] = sgen[o * glds + ibase + 16 * rb - (j0 + 4 * (u + 1))];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const T b = cur[u];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int o = 0; o < NOUT; ++o)
+            acc[o][rb] = TRANS ? Mf::step(b, a[u & 1][o][rb], acc[o][rb]) : Mf::step(a[u & 1][o][rb], b, acc[o][rb]);
+      }
+    } else {
+      // straight-line K-steps (no branch, so the LDS reads of a step are
+      // issued while the previous step's products run); in the last chunk
+      // of a term the steps past n multiply a zero input
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int jj = j0 + 4 * u;
+        const T b = (WHOLE || jj + kq < n) ? cur[u] : T(0);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const int idx = ibase + 16 * rb - jj;
+#pragma unroll
+          for (int o = 0; o < NOUT; ++o)
+            acc[o][rb] = TRANS ? Mf::step(b, sgen[o * glds + idx], acc[o][rb])
+                               : Mf::step(sgen[o * glds + idx], b, acc[o][rb]);
+        }
       }
     }
     j0 += 4 * kUnroll;
