@@ -53,7 +53,7 @@ template <> struct Mfma<float> {
   __device__ static inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-constexpr int kUnroll = 8;  // K-steps (of 4) per chunk
+constexpr int kChunkSteps = 8;  // K-steps (of 4) per chunk
 constexpr int kGenPer = 4;  // generator values per thread fetched a term ahead
 
 __host__ __device__ inline size_t tile_lds_elems(int n, int RB, int NOUT) {
@@ -85,6 +85,9 @@ __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__rest
                                           T *sg) {
   using Mf = Mfma<T>;
   using acc_t = typename Mf::acc_t;
+  // K-steps per chunk: FP32 on ragged axes takes chunks of 16 rows, which
+  // halves the zero rows of a term's last chunk
+  constexpr int kUnroll = (!WHOLE && sizeof(T) == 4) ? 4 : kChunkSteps;
   const int n = g.n;
   const int nterms = job.nterms;
   if (nterms <= 0) return;
@@ -98,7 +101,7 @@ __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__rest
   const int cl = cvalid ? c : g.C - 1;
   const int co = cl / g.C1, ci = cl % g.C1;
   const size_t cin = size_t(co) * g.in_S1 + ci;
-  // WHOLE (n a multiple of 4 kUnroll): every chunk lies inside the n rows,
+  // WHOLE (n a multiple of 4 kChunkSteps): every chunk lies inside the n rows,
   // so its loads need no clamping and its inputs no masking; row j0 + 4 u +
   // kq is a uniform row pointer plus this lane's offset kq kstride + cin
   const size_t clane = size_t(kq) * g.kstride + cin;
@@ -363,7 +366,7 @@ demag_status launch_axis(hipStream_t s, const StagePlan &sp, const T *gens, cons
   const int row_groups = (g.n + 16 * RB - 1) / (16 * RB);
   dim3 grid(col_tiles * row_groups, unsigned(sp.jobs.size()));
   const size_t lds = tile_lds_elems(g.n, RB, NOUT) * sizeof(T);
-  auto k = (g.n % (4 * kUnroll) == 0) ? &k_left<T, RB, NOUT, AXIS, true> : &k_left<T, RB, NOUT, AXIS, false>;
+  auto k = (g.n % (4 * kChunkSteps) == 0) ? &k_left<T, RB, NOUT, AXIS, true> : &k_left<T, RB, NOUT, AXIS, false>;
   if (lds > 65536)
     DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                       int(lds)));
