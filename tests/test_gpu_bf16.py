@@ -73,7 +73,8 @@ def test_bf16x3_128_vortex(ctx):
 def test_x_stage_partial_sums(ctx, prec):
     """The x stage's sums over nodes run as four partial-sum jobs when a node
     chunk has at least 3 nodes, as single jobs otherwise (1-node chunks, set
-    through the workspace limit, or M = 2): all agree with FP64 to the split
+    through the workspace limit, or M = 2); with 3-node chunks the partial
+    sums of several chunks accumulate.  All agree with FP64 to the split
     precision, and with each other to FP32 summation order."""
     n = (24, 20, 36)
     h = (1 / 36,) * 3
@@ -84,11 +85,16 @@ def test_x_stage_partial_sums(ctx, prec):
         p64, h64 = _apply(ctx, f, m, "fp64")
         ps, hs = _apply(ctx, f, m, prec)                 # one chunk of M nodes
         N = n[0] * n[1] * n[2]
-        ctx.set_workspace_limit(4 * N * 4 + 12 * N * 4)  # one node per chunk: single jobs
-        try:
-            p1, h1 = _apply(ctx, f, m, prec)
-        finally:
-            ctx.set_workspace_limit(16 << 30)
-        for p, hh in ((ps, hs), (p1, h1)):
+        runs = [(ps, hs)]
+        # one node per chunk (single jobs), and chunks of 3 nodes (partial
+        # sums accumulated over several chunks)
+        for kc in (1, 3):
+            ctx.set_workspace_limit(4 * N * 4 + 12 * N * 4 * kc)
+            try:
+                runs.append(_apply(ctx, f, m, prec))
+            finally:
+                ctx.set_workspace_limit(16 << 30)
+        for p, hh in runs:
             assert _rel(p, p64) < tol and _rel(hh, h64) < tol, (M, _rel(p, p64), _rel(hh, h64))
-        assert _rel(ps, p1) < 1e-6 and _rel(hs, h1) < 1e-6
+        for p, hh in runs[1:]:
+            assert _rel(ps, p) < 1e-6 and _rel(hs, hh) < 1e-6
