@@ -229,21 +229,21 @@ void build_chunk(const demag_factors *f, int k0, int kc, double phi_scale,
   s3b.geom = gx;
   s3b.axis = 0;
   s3b.nout = 1;
-  // terms [t0, t1) of the 2 kc terms of an x-stage sum: job s of xsplit
-  auto part = [kc, xsplit](int s, int &t0, int &t1) {
-    const int per = (2 * kc + xsplit - 1) / xsplit;
-    t0 = std::min(2 * kc, s * per);
-    t1 = std::min(2 * kc, t0 + per);
+  // terms [t0, t1) of the 2 kc terms of an x-stage sum: job s of ns, every
+  // one non-empty (ns <= 2 kc), so each partial is written
+  const int ns = std::min(xsplit, 2 * kc);
+  auto part = [kc, ns](int s, int &t0, int &t1) {
+    t0 = s * 2 * kc / ns;
+    t1 = (s + 1) * 2 * kc / ns;
   };
   for (int kl = 0; kl < kc; ++kl) {
     const int k = k0 + kl;
     s3a.terms.push_back(term(B_Y2, y2(kl, 0), gen(F_E, k), gen(F_Q, k)));
     s3a.terms.push_back(term(B_Y2, y2(kl, 2), gen(F_X, k), gen(F_P, k)));
   }
-  for (int sp = 0; sp < xsplit; ++sp) {
+  for (int sp = 0; sp < ns; ++sp) {
     int t0, t1;
     part(sp, t0, t1);
-    if (t1 <= t0) continue;
     MPJob j{};
     j.term0 = t0;
     j.nterms = t1 - t0;
@@ -272,10 +272,9 @@ void build_chunk(const demag_factors *f, int k0, int kc, double phi_scale,
       s3b.terms.push_back(term(B_Y2, y2(kl, su), gen(F_E, k), 0));
       s3b.terms.push_back(term(B_Y2, y2(kl, sv), gen(F_X, k), 0));
     }
-    for (int sp = 0; sp < xsplit; ++sp) {
+    for (int sp = 0; sp < ns; ++sp) {
       int t0, t1;
       part(sp, t0, t1);
-      if (t1 <= t0) continue;
       MPJob j{};
       j.term0 = base + t0;
       j.nterms = t1 - t0;
@@ -718,7 +717,10 @@ demag_status demag_apply_full(demag_ctx *ctx, const demag_factors *fc, demag_pre
       if (st != DEMAG_OK) return st;
     }
     if (plan->xsplit > 1) {
-      st = launch_reduce_partials(ctx, prec, reinterpret_cast<const float *>(y1), plan->xsplit, N,
+      // one x-stage job per partial sum of this chunk (fewer than xsplit
+      // when the chunk has fewer than 2 xsplit terms)
+      const int ns = int(stages[3].jobs.size());
+      st = launch_reduce_partials(ctx, prec, reinterpret_cast<const float *>(y1), ns, N,
                                   static_cast<float *>(bufs[3]), static_cast<float *>(bufs[4]), f->L, c > 0);
       if (st != DEMAG_OK) return st;
     }
