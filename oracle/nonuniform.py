@@ -129,3 +129,25 @@ def exact_direct(m, edges):
             N = exact.demag_tensor_box(tuple(lo), tuple(hi), p, q)
             hf[p] -= np.einsum("zyxcba,cba->zyx", N, m[q])
     return phi, hf
+
+
+def kron_apply_at_cells(m, edges, tau, alpha, cells):
+    """The Kronecker-form result of ``kron_apply`` at sampled target cells
+    (iz, iy, ix): per node, the rows of the dense factors contracted with m
+    one axis at a time (x, then y, then z).  Returns (phi[c], h[c][3])."""
+    F = [dense_factors(edges[d], tau, alpha) for d in range(3)]
+    res_phi = np.zeros(len(cells))
+    res_h = np.zeros((len(cells), 3))
+    for c, (iz, iy, ix) in enumerate(cells):
+        for k in range(len(tau)):
+            rows = [F[0][:, k, ix, :], F[1][:, k, iy, :], F[2][:, k, iz, :]]   # [type][source j]
+            for q in range(3):
+                mx = m[q] @ rows[0].T                       # [z][y][type_x]
+                for out, types in [("phi", sinc.phi_types(q))] + [(p, sinc.field_types(p, q)) for p in range(3)]:
+                    tx, ty, tz = types
+                    val = rows[2][tz] @ (rows[1][ty] @ mx[:, :, tx].T)
+                    if out == "phi":
+                        res_phi[c] += val
+                    else:
+                        res_h[c, out] += val
+    return res_phi, res_h

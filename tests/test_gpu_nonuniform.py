@@ -83,3 +83,30 @@ def test_dense_factors_are_rejected_elsewhere(ctx):
         ctx.prepare_structured(f)
     with pytest.raises(api.DemagError):
         ctx.assemble_grid([np.array([0.0, 1.0, 1.0]), edges[1], edges[2]], M=4)   # edges must increase
+
+
+def test_benchmark_grid_sampled():
+    """The benchmarked configuration: 128^3 cells graded by 1.01, 0.99 and
+    1.005 per cell on [-1/2, 1/2]^3, M = 40, the vortex field; 16 sampled
+    targets (corners and interior) against the oracle's row-by-row sums."""
+    ctx = api.Context(0)
+    n = 128
+    edges = []
+    for r in (1.01, 0.99, 1.005):
+        w = r ** np.arange(n)
+        e = np.concatenate([[0.0], np.cumsum(w)])
+        edges.append(e / e[-1] - 0.5)
+    f = ctx.assemble_grid(edges, M=40, c0=2.15)
+    m = inputs.vortex_field(n, seed=0)
+    phi, hf = ctx.apply_full(f, _dev(m), prec="fp64")
+    torch.cuda.synchronize()
+    p, hh = phi.cpu().numpy(), hf.cpu().numpy()
+    rng = np.random.default_rng(3)
+    cells = [(0, 0, 0), (n - 1, n - 1, n - 1), (0, n - 1, 0), (n - 1, 0, n - 1)]
+    cells += [tuple(int(v) for v in rng.integers(0, n, 3)) for _ in range(12)]
+    _t, tau, alpha = f.nodes()
+    rp, rh = nu.kron_apply_at_cells(m, edges, tau, alpha, cells)   # longest extent 1: scaled = physical
+    gp = np.array([p[c] for c in cells])
+    gh = np.array([hh[:, c[0], c[1], c[2]] for c in cells])
+    assert apply.rel_l2(gp, rp) < 1e-12, apply.rel_l2(gp, rp)
+    assert apply.rel_l2(gh, rh) < 1e-12, apply.rel_l2(gh, rh)

@@ -131,3 +131,41 @@ def test_invalid_arguments(ctx):
         ctx.recompress_cp(n, cols, good, lam, 1e-6, rmax=4)
     with pytest.raises(api.DemagError):
         ctx.recompress_cp(n, cols, good, lam, 1e-6, rmax=65)
+
+
+@pytest.mark.parametrize("eps", [1e-3, 1e-6])
+def test_n4096_potential_sampled(ctx, eps):
+    """The benchmarked case: the potential of a CP apply at n = 4096 (1200
+    terms of smooth rank-10 columns, M = 40), rmax 64.  The tensor has 2^36
+    entries, so the checks hold at any size: orthonormal factor rows, and the
+    relative error over 20000 sampled entries (X from the terms, the Tucker
+    form from core and factors, both in FP64 on the host) agrees with the
+    reported error to within the sampling spread, and the reported error is
+    within eps."""
+    n = 4096
+    f = ctx.assemble((n, n, n), (1.0 / n,) * 3, M=40, c0=2.15)
+    x = np.linspace(0.0, 1.0, n)
+    rng = np.random.default_rng(9)
+    smooth = [np.stack([np.stack([np.cos(np.pi * (l + 1) * rng.uniform(0.5, 1.5) * x + rng.uniform(0, 3))
+                                  for l in range(10)]) for _q in range(3)]).astype(np.float32) for _d in range(3)]
+    out_cols, table = ctx.apply_cp(f, [torch.from_numpy(c).cuda() for c in smooth])
+    tab = np.ascontiguousarray(table[0])
+    T = tab.shape[0]
+    res = ctx.recompress_cp((n, n, n), out_cols, torch.from_numpy(tab).cuda(),
+                            torch.ones(T, dtype=torch.float64, device="cuda"), eps, rmax=64, max_sweeps=10)
+    U = [u.cpu().numpy() for u in res["U"]]
+    for p in range(3):
+        assert np.abs(U[p] @ U[p].T - np.eye(U[p].shape[0])).max() < 1e-10
+    core = res["core"].cpu().numpy()
+    S = 20000
+    idx = np.random.default_rng(4).integers(0, n, (3, S))
+    cols = [o.cpu().numpy().reshape(-1, n) for o in out_cols]
+    A = [cols[p][tab[:, p]][:, idx[p]].astype(np.float64) for p in range(3)]   # [T][S]
+    xs = np.einsum("ts,ts,ts->s", A[0], A[1], A[2])
+    ts = np.einsum("abc,as,bs,cs->s", core, U[0][:, idx[0]], U[1][:, idx[1]], U[2][:, idx[2]], optimize=True)
+    sampled = np.linalg.norm(xs - ts) / np.linalg.norm(xs)
+    print(f"eps {eps:g}: ranks {res['ranks']} reported {res['rel_err']:.3e} sampled {sampled:.3e}")
+    assert res["rel_err"] <= eps
+    # sampling accuracy: the error is spread over the entries of a smooth
+    # tensor, so 20000 samples estimate it within a small factor
+    assert 0.2 * res["rel_err"] <= sampled <= 5.0 * res["rel_err"] + 1e-13

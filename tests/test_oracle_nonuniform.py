@@ -67,3 +67,16 @@ def test_kron_apply_approximates_exact_collocation_on_a_graded_grid():
     p1, h1 = nu.kron_apply(m, edges, tau, alpha)
     p0, h0 = nu.exact_direct(m, edges)
     assert apply.rel_l2(p1, p0) < 1e-7 and apply.rel_l2(h1, h0) < 1e-7, (apply.rel_l2(p1, p0), apply.rel_l2(h1, h0))
+
+
+def test_sampled_cells_equal_the_full_apply():
+    edges = [_graded(7, 1.2), _graded(5, 0.9, 0.7), _graded(6, 1.1, 0.9)]
+    n = tuple(len(e) - 1 for e in edges)
+    m = inputs.random_unit_field(n, seed=9)
+    _t, tau, alpha = sinc.sinc_nodes(8)
+    phi, hf = nu.kron_apply(m, edges, tau, alpha)
+    cells = [(0, 0, 0), (5, 4, 6), (2, 1, 3), (4, 0, 6)]
+    sp, sh = nu.kron_apply_at_cells(m, edges, tau, alpha, cells)
+    for c, (iz, iy, ix) in enumerate(cells):
+        assert abs(sp[c] - phi[iz, iy, ix]) <= 1e-13 * np.abs(phi).max()
+        assert np.abs(sh[c] - hf[:, iz, iy, ix]).max() <= 1e-13 * np.abs(hf).max()
