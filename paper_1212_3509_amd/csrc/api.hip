@@ -213,13 +213,18 @@ void build_chunk(const demag_factors *f, int k0, int kc, double phi_scale,
   s2b.geom = gy;
   s2b.axis = 1;
   s2b.nout = 1;
+  // the two-term jobs of all nodes first, then the one-term jobs: the
+  // workgroups are dispatched in job order, so the launch ends on short work
   for (int kl = 0; kl < kc; ++kl) {
     const int k = k0 + kl;
     add_job(s2a, {term(B_Y1, y1(kl, 0), gen(F_E, k), gen(F_Q, k)), term(B_Y1, y1(kl, 4), gen(F_X, k), gen(F_P, k))},
             B_Y2, y2(kl, 0), 1.0, B_Y2, y2(kl, 1), 1.0);
-    add_job(s2a, {term(B_Y1, y1(kl, 2), gen(F_E, k), gen(F_Q, k))}, B_Y2, y2(kl, 2), 1.0, B_Y2, y2(kl, 3), 1.0);
     add_job(s2b, {term(B_Y1, y1(kl, 1), gen(F_E, k), 0), term(B_Y1, y1(kl, 5), gen(F_X, k), 0)}, B_Y2, y2(kl, 4),
             1.0, 0, 0, 0.0);
+  }
+  for (int kl = 0; kl < kc; ++kl) {
+    const int k = k0 + kl;
+    add_job(s2a, {term(B_Y1, y1(kl, 2), gen(F_E, k), gen(F_Q, k))}, B_Y2, y2(kl, 2), 1.0, B_Y2, y2(kl, 3), 1.0);
     add_job(s2b, {term(B_Y1, y1(kl, 3), gen(F_E, k), 0)}, B_Y2, y2(kl, 5), 1.0, 0, 0, 0.0);
   }
   StagePlan s3a, s3b;
