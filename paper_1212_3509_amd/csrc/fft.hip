@@ -156,18 +156,18 @@ __global__ __launch_bounds__(kThreads) void k_fft_fwd(const ColAxes P, cplx *__r
 #pragma unroll
   for (int q = 0; q < kE; ++q) {
     const int m = threadIdx.x + q * kThreads;
-    if (m < N) wk[pd(m)] = v[q];
+    if (m < N) wk[slot<true>(m)] = v[q];
   }
   __syncthreads();
-  fft_lines<false, kThreads, kPoints>(wk, N, padded_points(N), 1, tlo, thi);
+  fft_lines<false, kThreads, kPoints, true>(wk, N, padded_points(N), 1, tlo, thi);
   double sw, cw;
   sincospi(-1.0 / double(N), &sw, &cw);
   const cplx w1{cw, sw};         // W_L^1
   // X[f] = E + W_L^f O with E = (Z[f] + conj Z[N-f])/2, O = (Z[f] - conj Z[N-f])/(2i)
   cplx *Uc = U + size_t(col) * (N + 1);
   for (int f = threadIdx.x; f <= N; f += kThreads) {
-    const cplx zf = wk[pd(f & (N - 1))];
-    const cplx zcc = cconj(wk[pd((N - f) & (N - 1))]);
+    const cplx zf = wk[slot<true>(f & (N - 1))];
+    const cplx zcc = cconj(wk[slot<true>((N - f) & (N - 1))]);
     const cplx D{0.5 * (zf.x - zcc.x), 0.5 * (zf.y - zcc.y)};
     Uc[f] = cadd(cplx{0.5 * (zf.x + zcc.x), 0.5 * (zf.y + zcc.y)}, cmul(wl(f, N, tlo, thi, w1), cplx{D.y, -D.x}));
   }
@@ -254,14 +254,14 @@ __global__ __launch_bounds__(kThreads) void k_fft_jobs(const ColAxes P, const cp
           const cplx E{0.5 * (yf.x + ycc.x), 0.5 * (yf.y + ycc.y)};
           const cplx Dm{0.5 * (yf.x - ycc.x), 0.5 * (yf.y - ycc.y)};
           const cplx O = cmul(Dm, cconj(wl(f, N, tlo, thi, w1)));
-          wk[pd(f & (N - 1))] = cplx{E.x - O.y, E.y + O.x};
+          wk[slot<true>(f & (N - 1))] = cplx{E.x - O.y, E.y + O.x};
         }
         if (fc != f && fc < N) {
           const cplx yfc = cconj(yf);
           const cplx E{0.5 * (yc.x + yfc.x), 0.5 * (yc.y + yfc.y)};
           const cplx Dm{0.5 * (yc.x - yfc.x), 0.5 * (yc.y - yfc.y)};
           const cplx O = cmul(Dm, cconj(wl(fc, N, tlo, thi, w1)));
-          wk[pd(fc)] = cplx{E.x - O.y, E.y + O.x};
+          wk[slot<true>(fc)] = cplx{E.x - O.y, E.y + O.x};
         }
       }
     }
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_jobs(const ColAxes P, const cp
     // inverse transform; the last pass writes the n outputs (x[2m], x[2m+1]
     // = Re, Im z[m] / N) straight from registers
     float *y = out + ((size_t(q) * 2 + s) * M + k) * size_t(R) * n + size_t(l) * n;
-    fft_lines_to<true, kThreads, kPoints>(wk, N, padded_points(N), 1, tlo, thi,
+    fft_lines_to<true, kThreads, kPoints, OutSink, true>(wk, N, padded_points(N), 1, tlo, thi,
                                           OutSink{y, n, inv_n});
     __syncthreads();
   }

@@ -27,6 +27,14 @@ template <bool INV> __device__ inline cplx mul_mi(cplx a) { return INV ? cplx{-a
 // strided passes put nl lines across lanes (fx fastest, then the point), and
 // are conflict-free for a line stride LS = 8 / min(nl, 8) modulo 8.
 __device__ inline int pd(int i) { return i + (i >> 4); }
+// Single-line transforms (XS) use an unpadded layout instead: point i at
+// slot i ^ ((i >> 4) & 15).  16-byte reads are served 16 lanes per cycle
+// (within each half-wave, the 4-lane blocks (lane >> 2) & 7 of even and of
+// odd bit parity together) and are conflict-free for slots distinct modulo
+// 16: the pad of pd puts two lanes of such a group on one bank when lanes
+// read consecutive points, the swizzle does not, and the Stockham stride-R
+// stores stay distinct modulo 8.
+template <bool XS> __device__ inline int slot(int i) { return XS ? (i ^ ((i >> 4) & 15)) : pd(i); }
 __host__ __device__ constexpr int line_stride(int N, int nl) {
   const int base = N + (N - 1) / 16;                  // pd(N - 1) + 1
   const int t = nl >= 8 ? 1 : 8 / nl;                 // wanted residue modulo 8
@@ -124,7 +132,7 @@ __device__ inline void make_twiddles(cplx *lo, cplx *hi, int N) {
 // last pass of a transform, a functor sink(line, index, value).
 struct ToLds {};
 
-template <bool INV, int R, int KT, int KP, int N, int Ns, typename Sink = ToLds>
+template <bool INV, int R, int KT, int KP, int N, int Ns, typename Sink = ToLds, bool XS = false>
 __device__ inline void pass(cplx *buf, int LS, int nlines, const cplx *tlo, const cplx *thi,
                             const Sink &sink = Sink{}) {
   constexpr int per = N / R;             // butterflies per line
@@ -139,7 +147,7 @@ __device__ inline void pass(cplx *buf, int LS, int nlines, const cplx *tlo, cons
       const int j = g & (per - 1), line = g >> lper;
       const cplx *lb = buf + line * LS;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = lb[pd(j + r * per)];
+      for (int r = 0; r < R; ++r) v[q][r] = lb[slot<XS>(j + r * per)];
       if constexpr (Ns > 1) {
         const int k = j & (Ns - 1);
         cplx w = twid(k * (N / (Ns * R)), tlo, thi);
@@ -181,7 +189,7 @@ __device__ inline void pass(cplx *buf, int LS, int nlines, const cplx *tlo, cons
         const int o = (j / Ns) * Ns * R + k;
         cplx *lb = buf + line * LS;
 #pragma unroll
-        for (int r = 0; r < R; ++r) lb[pd(o + r * Ns)] = v[q][r];
+        for (int r = 0; r < R; ++r) lb[slot<XS>(o + r * Ns)] = v[q][r];
       }
     }
     __syncthreads();
@@ -205,32 +213,32 @@ __device__ inline void pass(cplx *buf, int LS, int nlines, const cplx *tlo, cons
 // LDS: a fixed pass plan per length (radix 16 first), each pass inlined with
 // its sizes known at compile time, so that the register allocation and the
 // index arithmetic are per pass.
-template <bool INV, int KT, int KP, int N, int Ns, typename Sink, int R0, int... Rs>
+template <bool INV, int KT, int KP, int N, int Ns, typename Sink, bool XS, int R0, int... Rs>
 __device__ inline void run_passes(cplx *buf, int LS, int nlines, const cplx *tlo, const cplx *thi, const Sink &sink) {
   if constexpr (sizeof...(Rs) > 0) {
-    pass<INV, R0, KT, KP, N, Ns>(buf, LS, nlines, tlo, thi);
-    run_passes<INV, KT, KP, N, Ns * R0, Sink, Rs...>(buf, LS, nlines, tlo, thi, sink);
+    pass<INV, R0, KT, KP, N, Ns, ToLds, XS>(buf, LS, nlines, tlo, thi);
+    run_passes<INV, KT, KP, N, Ns * R0, Sink, XS, Rs...>(buf, LS, nlines, tlo, thi, sink);
   } else {
-    pass<INV, R0, KT, KP, N, Ns, Sink>(buf, LS, nlines, tlo, thi, sink);
+    pass<INV, R0, KT, KP, N, Ns, Sink, XS>(buf, LS, nlines, tlo, thi, sink);
   }
 }
 // Transforms whose last pass hands its results to sink (ToLds: in place).
-template <bool INV, int KT, int KP, typename Sink>
+template <bool INV, int KT, int KP, typename Sink, bool XS = false>
 __device__ __noinline__ void fft_lines_to(cplx *buf, int N, int LS, int nlines, const cplx *tlo, const cplx *thi,
                                           Sink sink) {
   switch (N) {
-    case 2: run_passes<INV, KT, KP, 2, 1, Sink, 2>(buf, LS, nlines, tlo, thi, sink); break;
-    case 4: run_passes<INV, KT, KP, 4, 1, Sink, 4>(buf, LS, nlines, tlo, thi, sink); break;
-    case 8: run_passes<INV, KT, KP, 8, 1, Sink, 8>(buf, LS, nlines, tlo, thi, sink); break;
-    case 16: run_passes<INV, KT, KP, 16, 1, Sink, 16>(buf, LS, nlines, tlo, thi, sink); break;
-    case 32: run_passes<INV, KT, KP, 32, 1, Sink, 16, 2>(buf, LS, nlines, tlo, thi, sink); break;
-    case 64: run_passes<INV, KT, KP, 64, 1, Sink, 16, 4>(buf, LS, nlines, tlo, thi, sink); break;
-    case 128: run_passes<INV, KT, KP, 128, 1, Sink, 16, 8>(buf, LS, nlines, tlo, thi, sink); break;
-    case 256: run_passes<INV, KT, KP, 256, 1, Sink, 16, 16>(buf, LS, nlines, tlo, thi, sink); break;
-    case 512: run_passes<INV, KT, KP, 512, 1, Sink, 16, 16, 2>(buf, LS, nlines, tlo, thi, sink); break;
-    case 1024: run_passes<INV, KT, KP, 1024, 1, Sink, 16, 16, 4>(buf, LS, nlines, tlo, thi, sink); break;
-    case 2048: run_passes<INV, KT, KP, 2048, 1, Sink, 16, 16, 8>(buf, LS, nlines, tlo, thi, sink); break;
-    case 4096: run_passes<INV, KT, KP, 4096, 1, Sink, 16, 16, 16>(buf, LS, nlines, tlo, thi, sink); break;
+    case 2: run_passes<INV, KT, KP, 2, 1, Sink, XS, 2>(buf, LS, nlines, tlo, thi, sink); break;
+    case 4: run_passes<INV, KT, KP, 4, 1, Sink, XS, 4>(buf, LS, nlines, tlo, thi, sink); break;
+    case 8: run_passes<INV, KT, KP, 8, 1, Sink, XS, 8>(buf, LS, nlines, tlo, thi, sink); break;
+    case 16: run_passes<INV, KT, KP, 16, 1, Sink, XS, 16>(buf, LS, nlines, tlo, thi, sink); break;
+    case 32: run_passes<INV, KT, KP, 32, 1, Sink, XS, 16, 2>(buf, LS, nlines, tlo, thi, sink); break;
+    case 64: run_passes<INV, KT, KP, 64, 1, Sink, XS, 16, 4>(buf, LS, nlines, tlo, thi, sink); break;
+    case 128: run_passes<INV, KT, KP, 128, 1, Sink, XS, 16, 8>(buf, LS, nlines, tlo, thi, sink); break;
+    case 256: run_passes<INV, KT, KP, 256, 1, Sink, XS, 16, 16>(buf, LS, nlines, tlo, thi, sink); break;
+    case 512: run_passes<INV, KT, KP, 512, 1, Sink, XS, 16, 16, 2>(buf, LS, nlines, tlo, thi, sink); break;
+    case 1024: run_passes<INV, KT, KP, 1024, 1, Sink, XS, 16, 16, 4>(buf, LS, nlines, tlo, thi, sink); break;
+    case 2048: run_passes<INV, KT, KP, 2048, 1, Sink, XS, 16, 16, 8>(buf, LS, nlines, tlo, thi, sink); break;
+    case 4096: run_passes<INV, KT, KP, 4096, 1, Sink, XS, 16, 16, 16>(buf, LS, nlines, tlo, thi, sink); break;
     default:   // N = 1: identity
       if constexpr (!std::is_same_v<Sink, ToLds>) {
         for (int line = threadIdx.x; line < nlines; line += KT) sink(line, 0, buf[line * LS]);
@@ -238,9 +246,9 @@ __device__ __noinline__ void fft_lines_to(cplx *buf, int N, int LS, int nlines, 
       break;
   }
 }
-template <bool INV, int KT, int KP>
+template <bool INV, int KT, int KP, bool XS = false>
 __device__ inline void fft_lines(cplx *buf, int N, int LS, int nlines, const cplx *tlo, const cplx *thi) {
-  fft_lines_to<INV, KT, KP>(buf, N, LS, nlines, tlo, thi, ToLds{});
+  fft_lines_to<INV, KT, KP, ToLds, XS>(buf, N, LS, nlines, tlo, thi, ToLds{});
 }
 
 // W_L^f for the real-transform (un)packing, L = 2N: W_N^(f/2), times W_L^1 for odd f.
