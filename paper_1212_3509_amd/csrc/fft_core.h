@@ -20,8 +20,9 @@ __device__ inline cplx cconj(cplx a) { return {a.x, -a.y}; }
 template <bool INV> __device__ inline cplx mul_mi(cplx a) { return INV ? cplx{-a.y, a.x} : cplx{a.y, -a.x}; }
 
 // LDS slot of point i of line b: b * LS + pd(i), with one pad slot after
-// every 16 points.  16-byte LDS accesses are served eight lanes at a time,
-// conflict-free when those lanes hit distinct slots modulo 8.  Butterflies
+// every 16 points.  16-byte LDS writes are served eight lanes at a time,
+// conflict-free when those lanes hit distinct slots modulo 8 (reads: see
+// slot below).  Butterflies
 // run along a line across lanes (consecutive points: distinct, thanks to the
 // pad for the Stockham stride-R stores); the transposed accesses of the
 // strided passes put nl lines across lanes (fx fastest, then the point), and
