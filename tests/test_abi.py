@@ -29,3 +29,15 @@ def test_library_exports_every_declared_symbol():
 
 def test_binding_covers_declarations():
     assert _declared() <= set(api.exported_symbols())
+
+
+def test_bench_refuses_several_gpus():
+    """bench.py measures one GPU; asking for more exits with status 2 and a
+    message, before anything touches a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    res = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert res.returncode == 2
+    assert "single GPU" in res.stderr
