@@ -10,9 +10,11 @@
 // CB blocks of 16 columns and 4 row blocks); per chunk of KC K values the A
 // tiles of the NOUT outputs and the input tile go through LDS, the next
 // chunk's tiles loaded into registers while the current one is multiplied.
-// LDS row strides: A rows of KC + 2 doubles (the 16 rows x 2 K values that
-// one read of a half-wave touches fall in distinct banks), input rows of
-// NC + 16 doubles (consecutive K rows offset by 16 banks, same reason).
+// LDS row strides: A rows of KC + 1 doubles.  8-byte LDS reads are served
+// 16 lanes at a time, and the 16 lanes of one K value read 16 rows: an odd
+// stride puts them in distinct banks (SQ_LDS_BANK_CONFLICT reads 0; an even
+// stride of KC + 2 cost about 4 conflict cycles per read).  Input rows of
+// NC + 16 doubles.
 #include "internal.h"
 
 namespace demag {
@@ -34,7 +36,7 @@ __global__ __launch_bounds__(64 * NW, MINW) void k_dense_left(const MPJob *__res
   constexpr int kAr = 64 * KC / NT;           // A tile values per thread and output
   constexpr int kBrows = NT / NC;             // K rows one pass of the threads stages
   static_assert(kBrows >= 1 && KC % kBrows == 0 && (64 * KC) % NT == 0, "tile shape");
-  __shared__ double As[NOUT][64][KC + 2];
+  __shared__ double As[NOUT][64][KC + 1];
   __shared__ double Bs[KC][NC + 16];
   const MPJob job = jobs[blockIdx.y];
   if (job.nterms <= 0) return;
