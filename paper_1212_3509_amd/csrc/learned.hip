@@ -404,7 +404,9 @@ __device__ void fit_pass(FitLds &L, int b, int S, int R, double h, const int *__
                          const double *__restrict__ Kref, bool jac) {
   const int tid = threadIdx.x;
   const int sl = tid >> 5, k = tid & 31;
-  const int p = tid >> 2, q0 = (tid & 3) * 16;
+  // J^T J: thread (p, qj) sums row p against columns qj + 4 cc, so the four
+  // lanes of one p read four consecutive doubles (distinct LDS banks)
+  const int p = tid >> 2, qj = tid & 3;
   const double cW = 1.0 / (2.0 * pow(kPi, 1.5));
   double acc[16];
 #pragma unroll
@@ -460,9 +462,11 @@ __device__ void fit_pass(FitLds &L, int b, int S, int R, double h, const int *__
       for (int i = 0; i < kFitSB * kNcomp; ++i) {
         const int il = i / kNcomp, c = i % kNcomp;
         const double jp = p < kRmax ? L.jt[il][c][p] : L.ja[il][c][p - kRmax];
-        const double *row = (q0 < kRmax) ? &L.jt[il][c][q0] : &L.ja[il][c][q0 - kRmax];
+        const double *rt = &L.jt[il][c][qj], *ra = &L.ja[il][c][qj];
 #pragma unroll
-        for (int cc = 0; cc < 16; ++cc) acc[cc] += jp * row[cc];
+        for (int cc = 0; cc < 8; ++cc) acc[cc] += jp * rt[4 * cc];
+#pragma unroll
+        for (int cc = 0; cc < 8; ++cc) acc[8 + cc] += jp * ra[4 * cc];
         if ((tid & 3) == 0) gacc += jp * L.res[i];
       }
     }
@@ -470,7 +474,7 @@ __device__ void fit_pass(FitLds &L, int b, int S, int R, double h, const int *__
   }
   if (jac) {
 #pragma unroll
-    for (int cc = 0; cc < 16; ++cc) L.A[p][q0 + cc] = acc[cc];
+    for (int cc = 0; cc < 16; ++cc) L.A[p][qj + 4 * cc] = acc[cc];
     if ((tid & 3) == 0) L.g[p] = gacc;
   }
   if (tid == 0) L.err2 = e2;
