@@ -318,12 +318,15 @@ demag_status get_plan(demag_ctx *ctx, demag_factors *f, demag_prec prec, FullPla
     return DEMAG_E_NOMEM;
   }
   while (kc > 1 && fixed + per_node * kc > ctx->ws_limit) kc = (kc + 1) / 2;
-  // bfloat16 splits: the x stage's sums over nodes run as kXSplit jobs of
-  // partial sums (more workgroups for a stage that otherwise has one or two
-  // jobs), when the chunk's Y1 region holds the 4 kXSplit partial outputs
+  // FP32 and bfloat16 splits: the x stage's sums over nodes run as kXSplit
+  // jobs of partial sums, reduced in FP64 by one elementwise kernel, when the
+  // chunk's Y1 region holds the 4 kXSplit partial outputs.  This gives the
+  // stage more workgroups (it otherwise has one or two jobs) and cuts each
+  // FP32 accumulation chain over the chunk's 2 kc terms of n products to a
+  // quarter, which keeps the FP32 potential within 1e-6 of FP64 at 128^3.
   constexpr int kXSplit = 4;
   const bool bf = (prec == DEMAG_BF16X2 || prec == DEMAG_BF16X3);
-  const int xsplit = (bf && 6 * kc >= 4 * kXSplit) ? kXSplit : 1;
+  const int xsplit = (prec != DEMAG_FP64 && 6 * kc >= 4 * kXSplit) ? kXSplit : 1;
   const int key_prec = (prec == DEMAG_FP64) ? 0 : bf ? 2 : 1;
   auto key = std::make_pair(key_prec, kc);
   auto it = f->plans.find(key);

@@ -446,29 +446,30 @@ namespace {
 // Four consecutive elements per thread of the 4 N outputs (phi, h_x, h_y,
 // h_z), each the sum of nsplit partials.
 __global__ void k_reduce_partials(const float *__restrict__ partials, int nsplit, int64_t N, float *__restrict__ phi,
-                                  float *__restrict__ h, float phi_scale, int accumulate) {
+                                  float *__restrict__ h, double phi_scale, int accumulate) {
   const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) * 4;
   const int o = int(blockIdx.y);                       // 0: phi, 1..3: h_x, h_y, h_z
   if (i >= N) return;
   float *out = (o == 0) ? phi : h + int64_t(o - 1) * N;
-  const float scale = (o == 0) ? phi_scale : 1.0f;
+  const double scale = (o == 0) ? phi_scale : 1.0;
   const int cnt = int(N - i < 4 ? N - i : 4);
-  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  // the partial sums are added in FP64 and rounded once
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int s = 0; s < nsplit; ++s) {
     const float *src = partials + (int64_t(4) * s + o) * N + i;
     if (cnt == 4 && ((reinterpret_cast<uintptr_t>(src) & 15u) == 0)) {
       const float4 v = *reinterpret_cast<const float4 *>(src);
-      acc[0] += v.x;
-      acc[1] += v.y;
-      acc[2] += v.z;
-      acc[3] += v.w;
+      acc[0] += double(v.x);
+      acc[1] += double(v.y);
+      acc[2] += double(v.z);
+      acc[3] += double(v.w);
     } else {
-      for (int e = 0; e < cnt; ++e) acc[e] += src[e];
+      for (int e = 0; e < cnt; ++e) acc[e] += double(src[e]);
     }
   }
   for (int e = 0; e < cnt; ++e) {
-    const float v = scale * acc[e];
-    out[i + e] = accumulate ? out[i + e] + v : v;
+    const double v = scale * acc[e];
+    out[i + e] = float(accumulate ? double(out[i + e]) + v : v);
   }
 }
 
@@ -482,12 +483,11 @@ demag_status launch_reduce_partials(demag_ctx *ctx, demag_prec prec, const float
   if (st != DEMAG_OK) return st;
   const int64_t threads = (N + 3) / 4;
   dim3 grid(unsigned((threads + 255) / 256), 4);
-  k_reduce_partials<<<grid, 256, 0, ctx->stream>>>(partials, nsplit, N, phi, h, float(phi_scale),
-                                                   accumulate ? 1 : 0);
+  k_reduce_partials<<<grid, 256, 0, ctx->stream>>>(partials, nsplit, N, phi, h, phi_scale, accumulate ? 1 : 0);
   DEMAG_TRY_HIP(hipGetLastError());
   if (ev) {
     const double bytes = 4.0 * N * 4.0 * (nsplit + (accumulate ? 2 : 1));
-    st = prof_end(ctx, ev, std::string(prec == DEMAG_BF16X3 ? "bf16x3" : "bf16x2") + "/x/reduce", 0.0, bytes);
+    st = prof_end(ctx, ev, std::string(prec == DEMAG_BF16X3 ? "bf16x3" : prec == DEMAG_BF16X2 ? "bf16x2" : "fp32") + "/x/reduce", 0.0, bytes);
   }
   return st;
 }
