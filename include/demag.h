@@ -42,7 +42,10 @@ typedef enum {
   DEMAG_E_INVAL = 1,        /* argument out of its documented range */
   DEMAG_E_NOMEM = 2,        /* device or host allocation failed */
   DEMAG_E_HIP = 3,          /* HIP runtime error */
-  DEMAG_E_UNSUPPORTED = 4   /* valid request this build does not support */
+  DEMAG_E_UNSUPPORTED = 4,  /* valid request this build does not support */
+  DEMAG_E_ACCURACY = 5      /* no quadrature rule met the requested tolerance
+                               (outputs hold the best rule found; see
+                               demag_quad_predict) */
 } demag_status;
 
 /* Arithmetic of the mode products.  Factor assembly is always FP64.
@@ -94,8 +97,16 @@ typedef struct demag_factors demag_factors;  /* opaque: assembled 1D factors */
 demag_status demag_create(int device, void *hip_stream, demag_ctx **out);
 /* Release the context and its workspace (waits for the stream first). */
 demag_status demag_destroy(demag_ctx *ctx);
-/* Change the stream later calls enqueue on. */
+/* Change the stream later calls enqueue on.  Work enqueued afterwards waits
+ * for the work already enqueued on the previous stream (an event recorded
+ * there), since both share the context's workspace. */
 demag_status demag_set_stream(demag_ctx *ctx, void *hip_stream);
+/* Input check (default off).  When on, demag_apply_full(_ws), demag_apply_fft,
+ * demag_batch_apply and the structured applies first scan their input
+ * magnetization / columns on the device and return DEMAG_E_INVAL, enqueueing
+ * nothing else, if any value is NaN or infinite.  The scan synchronizes the
+ * stream, so calls no longer return before the GPU work completes. */
+demag_status demag_set_input_check(demag_ctx *ctx, int32_t enable);
 /* Upper bound in bytes of the internal workspace of demag_apply_full (the
  * node loop is split into chunks that fit).  Default 16 GiB. */
 demag_status demag_set_workspace_limit(demag_ctx *ctx, size_t bytes);
@@ -133,7 +144,14 @@ demag_status demag_assemble_factors(demag_ctx *ctx, const demag_grid *grid,
  * demag_factors_download returns [4][M][n][n]. */
 demag_status demag_assemble_factors_grid(demag_ctx *ctx, const int32_t n[3], const double *const edges[3],
                                          const demag_quad *quad, demag_factors **out);
+/* Waits for the last work enqueued (on any context) that reads f, then frees it. */
 demag_status demag_factors_free(demag_factors *f);
+/* Length scale L of the factor set: the longest grid extent, by which the
+ * grid was scaled to unit size.  The full-format and FFT applies multiply the
+ * potential by L themselves; the structured results are in the scaled domain,
+ * so the potential of a structured result is L times its sum of terms (the
+ * field is scale-free and needs no factor). */
+demag_status demag_factors_length_scale(const demag_factors *f, double *L);
 /* Number of nodes M of an assembled rule. */
 demag_status demag_factors_count(const demag_factors *f, int32_t *M);
 /* Host copies (length M) of t_k, tau_k and alpha_k in the scaled domain; any
@@ -169,6 +187,19 @@ demag_status demag_apply_fft(demag_ctx *ctx, demag_factors *f, const double *m, 
  * factor rows are sized for it), else DEMAG_E_INVAL. */
 demag_status demag_apply_full(demag_ctx *ctx, const demag_factors *f, demag_prec prec,
                               const void *m, void *phi, void *h);
+/* Workspace of demag_apply_full(_ws) in bytes: *one_chunk runs the whole
+ * node loop per stage launch ((12 M + 4) N elements of the precision's
+ * element type: the per-node intermediates of the z and y stages plus four
+ * scratch outputs), *minimum one node at a time ((12 + 4) N elements).
+ * Either pointer may be NULL.  Host-only; enqueues nothing. */
+demag_status demag_apply_full_workspace_size(const demag_factors *f, demag_prec prec, size_t *one_chunk,
+                                             size_t *minimum);
+/* demag_apply_full on a caller-owned device workspace of workspace_bytes
+ * (16-byte aligned, at least the *minimum above, else DEMAG_E_NOMEM): the node
+ * loop runs in the largest chunks that fit.  The workspace must not be used
+ * by other work until this call's kernels complete (stream order). */
+demag_status demag_apply_full_ws(demag_ctx *ctx, const demag_factors *f, demag_prec prec, const void *m,
+                                 void *phi, void *h, void *workspace, size_t workspace_bytes);
 
 /* ---------------------------------------------------------------- batches
  * Many states on uneven grids (same quadrature rule), FP64 or FP32.  All
@@ -208,8 +239,10 @@ demag_status demag_batch_tune(demag_ctx *ctx, demag_batch *b, const char *path, 
  * Applying the Kronecker operator to a structured tensor needs only the
  * Toeplitz products of its factor columns (Eqs. (kron_eval_cp),
  * (kron_eval_tuck)), computed here through zero-padded FFTs of length
- * L = 2^p >= 2 n_d - 1 (Sec. 4, Eq. (fft_pot)), in FP32 with FP64 kernel
- * spectra.  Axis lengths up to 4096.
+ * L = 2^p >= 2 n_d - 1 (Sec. 4, Eq. (fft_pot)): columns are read and written
+ * in FP32, the transforms and the kernel spectra are FP64.  Axis lengths up
+ * to 4096.  Results are in the scaled domain: multiply the potential by the
+ * length scale (demag_factors_length_scale).
  *
  * Column sets per axis d, all device FP32, one column contiguous:
  *   in[d]:  [3 components q][R_d][n_d]
@@ -229,7 +262,8 @@ demag_status demag_apply_columns(demag_ctx *ctx, demag_factors *f, const int32_t
  * [4 outputs (phi, h_x, h_y, h_z)][3 M r terms][3 axes]: term (q, k, l),
  * index (q M + k) r + l, of output o uses column ((q 2 + s) M + k) r + l of
  * out[d] with s = 1 exactly when o is the field along d.  Output o is
- * sum over its terms of lambda^q_l out[x][.] o out[y][.] o out[z][.]. */
+ * sum over its terms of lambda^q_l out[x][.] o out[y][.] o out[z][.], times
+ * the length scale L for the potential (o = 0). */
 demag_status demag_apply_cp(demag_ctx *ctx, demag_factors *f, int32_t r, const float *const U[3],
                             float *const out[3], int32_t *table);
 /* Tucker input, ranks r[3]: U[d] = [3 q][r_d][n_d].  Result out[d] with

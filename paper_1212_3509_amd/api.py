@@ -17,7 +17,7 @@ _lib = None
 
 DEMAG_FP64, DEMAG_FP32, DEMAG_BF16X2, DEMAG_BF16X3 = 0, 1, 2, 3
 PRECISIONS = {"fp64": DEMAG_FP64, "fp32": DEMAG_FP32, "bf16x2": DEMAG_BF16X2, "bf16x3": DEMAG_BF16X3}
-STATUS = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_UNSUPPORTED"}
+STATUS = {0: "OK", 1: "E_INVAL", 2: "E_NOMEM", 3: "E_HIP", 4: "E_UNSUPPORTED", 5: "E_ACCURACY"}
 
 
 class DemagError(RuntimeError):
@@ -42,14 +42,18 @@ _SIGS = {
     "demag_destroy": (C.c_int, [_P]),
     "demag_set_stream": (C.c_int, [_P, _P]),
     "demag_set_workspace_limit": (C.c_int, [_P, C.c_size_t]),
+    "demag_set_input_check": (C.c_int, [_P, C.c_int32]),
     "demag_set_tiles": (C.c_int, [_P, C.c_int32, C.c_int32]),
     "demag_assemble_factors": (C.c_int, [_P, C.POINTER(Grid), C.POINTER(Quad), C.POINTER(_P)]),
     "demag_factors_free": (C.c_int, [_P]),
     "demag_assemble_factors_grid": (C.c_int, [_P, _P, _P, C.POINTER(Quad), C.POINTER(_P)]),
     "demag_factors_count": (C.c_int, [_P, C.POINTER(C.c_int32)]),
+    "demag_factors_length_scale": (C.c_int, [_P, C.POINTER(C.c_double)]),
     "demag_factors_nodes": (C.c_int, [_P, _P, _P, _P]),
     "demag_factors_download": (C.c_int, [_P, _P, C.c_int32, _P]),
     "demag_apply_full": (C.c_int, [_P, _P, C.c_int, _P, _P, _P]),
+    "demag_apply_full_workspace_size": (C.c_int, [_P, C.c_int, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "demag_apply_full_ws": (C.c_int, [_P, _P, C.c_int, _P, _P, _P, _P, C.c_size_t]),
     "demag_apply_fft": (C.c_int, [_P, _P, _P, _P, _P]),
     "demag_batch_create": (C.c_int, [_P, C.c_int32, _P, C.POINTER(Quad), C.c_int, C.POINTER(_P)]),
     "demag_batch_free": (C.c_int, [_P]),
@@ -131,6 +135,20 @@ class Factors:
         m = C.c_int32()
         _check(library().demag_factors_count(self.handle, C.byref(m)), "demag_factors_count")
         return m.value
+
+    @property
+    def length_scale(self) -> float:
+        """L: structured potentials are L times their sum of terms."""
+        L = C.c_double()
+        _check(library().demag_factors_length_scale(self.handle, C.byref(L)), "demag_factors_length_scale")
+        return L.value
+
+    def workspace_size(self, prec: str = "fp64"):
+        """(one_chunk, minimum) workspace bytes of apply_full(_ws)."""
+        a, b = C.c_size_t(), C.c_size_t()
+        _check(library().demag_apply_full_workspace_size(self.handle, PRECISIONS[prec], C.byref(a), C.byref(b)),
+               "demag_apply_full_workspace_size")
+        return a.value, b.value
 
     def nodes(self):
         M = self.M
@@ -216,6 +234,10 @@ class Context:
     def set_workspace_limit(self, nbytes: int):
         _check(library().demag_set_workspace_limit(self.handle, nbytes), "demag_set_workspace_limit")
 
+    def set_input_check(self, on: bool = True):
+        """Reject NaN / infinite inputs (one device scan and a stream sync per call)."""
+        _check(library().demag_set_input_check(self.handle, 1 if on else 0), "demag_set_input_check")
+
     def set_tiles(self, rows: int = 0, cols: int = 0):
         """Tile shape of the full-format products (0 = automatic)."""
         _check(library().demag_set_tiles(self.handle, rows, cols), "demag_set_tiles")
@@ -267,6 +289,24 @@ class Context:
         self.use_current_stream()
         _check(library().demag_apply_full(self.handle, f.handle, PRECISIONS[prec], _ptr(m), _ptr(phi), _ptr(h)),
                "demag_apply_full")
+        return phi, h
+
+    def apply_full_ws(self, f: Factors, m, workspace, phi=None, h=None, prec: str = "fp64"):
+        """apply_full on a caller-owned workspace (a contiguous CUDA tensor; its
+        byte size bounds the node chunks)."""
+        import torch
+        nx, ny, nz = f.n
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        if m.dtype != dt or not m.is_cuda or not m.is_contiguous() or tuple(m.shape) != (3, nz, ny, nx):
+            raise ValueError(f"m must be a contiguous {dt} CUDA tensor of shape {(3, nz, ny, nx)}")
+        if phi is None:
+            phi = torch.empty((nz, ny, nx), dtype=dt, device=m.device)
+        if h is None:
+            h = torch.empty((3, nz, ny, nx), dtype=dt, device=m.device)
+        nbytes = workspace.numel() * workspace.element_size()
+        self.use_current_stream()
+        _check(library().demag_apply_full_ws(self.handle, f.handle, PRECISIONS[prec], _ptr(m), _ptr(phi), _ptr(h),
+                                             _ptr(workspace), nbytes), "demag_apply_full_ws")
         return phi, h
 
     def apply_fft(self, f: Factors, m, phi=None, h=None):

@@ -306,18 +306,23 @@ void build_chunk_plan(const demag_factors *f, int k0, int kc, double phi_scale, 
 
 namespace {
 
-demag_status get_plan(demag_ctx *ctx, demag_factors *f, demag_prec prec, FullPlan **out) {
+// Workspace of demag_apply_full for a chunk of kc nodes: 12 intermediate
+// tensors per node plus 4 scratch outputs.
+size_t full_ws_bytes(const demag_factors *f, demag_prec prec, int kc) {
   const size_t esize = (prec == DEMAG_FP64) ? 8 : 4;
-  const int64_t N = int64_t(f->n[0]) * f->n[1] * f->n[2];
-  // 12 intermediate tensors per node plus 4 scratch outputs.
-  const size_t per_node = size_t(12) * N * esize;
-  const size_t fixed = size_t(4) * N * esize;
+  const size_t N = size_t(f->n[0]) * f->n[1] * f->n[2];
+  return (size_t(12) * kc + 4) * N * esize;
+}
+
+// Plan whose node chunks fit `limit` bytes of workspace.
+demag_status get_plan(demag_ctx *ctx, demag_factors *f, demag_prec prec, size_t limit, FullPlan **out) {
+  (void)ctx;
   int kc = f->M;
-  if (ctx->ws_limit < fixed + per_node) {
-    set_error("workspace limit too small for one node");
+  if (limit < full_ws_bytes(f, prec, 1)) {
+    set_error("workspace too small for one node (" + std::to_string(full_ws_bytes(f, prec, 1)) + " bytes needed)");
     return DEMAG_E_NOMEM;
   }
-  while (kc > 1 && fixed + per_node * kc > ctx->ws_limit) kc = (kc + 1) / 2;
+  while (kc > 1 && full_ws_bytes(f, prec, kc) > limit) kc = (kc + 1) / 2;
   // FP32 and bfloat16 splits: the x stage's sums over nodes run as kXSplit
   // jobs of partial sums, reduced in FP64 by one elementwise kernel, when the
   // chunk's Y1 region holds the 4 kXSplit partial outputs.  This gives the
@@ -338,7 +343,7 @@ demag_status get_plan(demag_ctx *ctx, demag_factors *f, demag_prec prec, FullPla
   plan->kc = kc;
   plan->xsplit = xsplit;
   plan->nchunks = (f->M + kc - 1) / kc;
-  plan->ws_elems = size_t(12) * kc * N + size_t(4) * N;
+  plan->ws_elems = full_ws_bytes(f, prec, kc) / ((prec == DEMAG_FP64) ? 8 : 4);
   plan->chunks.resize(plan->nchunks);
   for (int c = 0; c < plan->nchunks; ++c) {
     const int k0 = c * kc;
@@ -379,6 +384,48 @@ demag_status ensure_workspace(demag_ctx *ctx, size_t bytes) {
 
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 
+demag_status note_use(demag_ctx *ctx, const demag_factors *fc) {
+  auto *f = const_cast<demag_factors *>(fc);
+  if (!f->used) DEMAG_TRY_HIP(hipEventCreateWithFlags(&f->used, hipEventDisableTiming));
+  DEMAG_TRY_HIP(hipEventRecord(f->used, ctx->stream));
+  return DEMAG_OK;
+}
+
+namespace {
+__global__ void k_clear_flag(int *flag) { *flag = 0; }
+
+template <class T>
+__global__ void k_check_finite(const T *__restrict__ x, size_t count, int *__restrict__ flag) {
+  int bad = 0;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += size_t(gridDim.x) * blockDim.x)
+    if (!isfinite(x[i])) bad = 1;
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+}  // namespace
+
+demag_status check_finite(demag_ctx *ctx, const void *x, size_t count, bool dbl, const char *what, int *dflag) {
+  if (!ctx->check_inputs || count == 0) return DEMAG_OK;
+  if (!dflag) {
+    if (!ctx->d_flag) DEMAG_TRY_HIP(hipMalloc(&ctx->d_flag, sizeof(int)));
+    dflag = ctx->d_flag;
+  }
+  k_clear_flag<<<1, 1, 0, ctx->stream>>>(dflag);
+  const unsigned blocks = unsigned(std::min<size_t>((count + 255) / 256, 4096));
+  if (dbl)
+    k_check_finite<double><<<blocks, 256, 0, ctx->stream>>>(static_cast<const double *>(x), count, dflag);
+  else
+    k_check_finite<float><<<blocks, 256, 0, ctx->stream>>>(static_cast<const float *>(x), count, dflag);
+  DEMAG_TRY_HIP(hipGetLastError());
+  int flag = 0;
+  DEMAG_TRY_HIP(hipMemcpyAsync(&flag, dflag, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  DEMAG_TRY_HIP(hipStreamSynchronize(ctx->stream));
+  if (flag) {
+    set_error(std::string(what) + ": input holds NaN or infinite values");
+    return DEMAG_E_INVAL;
+  }
+  return DEMAG_OK;
+}
+
 }  // namespace demag
 
 using namespace demag;
@@ -409,6 +456,8 @@ demag_status demag_destroy(demag_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->ws) (void)hipFree(ctx->ws);
+  if (ctx->d_flag) (void)hipFree(ctx->d_flag);
+  if (ctx->order_ev) (void)hipEventDestroy(ctx->order_ev);
   for (auto &r : ctx->prof_pending) {
     (void)hipEventDestroy(r.start);
     (void)hipEventDestroy(r.stop);
@@ -422,7 +471,8 @@ demag_status demag_prepare_structured(demag_ctx *ctx, demag_factors *f) {
   DEMAG_REQUIRE(ctx && f, "demag_prepare_structured: NULL argument");
   DEMAG_REQUIRE(!f->dense, "demag_prepare_structured: needs a uniform grid (Toeplitz factors)");
   DEMAG_TRY_HIP(hipSetDevice(ctx->device));
-  return prepare_spectra(ctx, f);
+  demag_status st = prepare_spectra(ctx, f);
+  return st == DEMAG_OK ? note_use(ctx, f) : st;
 }
 
 demag_status demag_apply_columns(demag_ctx *ctx, demag_factors *f, const int32_t R[3], const float *const in[3],
@@ -436,8 +486,10 @@ demag_status demag_apply_columns(demag_ctx *ctx, demag_factors *f, const int32_t
   }
   DEMAG_TRY_HIP(hipSetDevice(ctx->device));
   demag_status st = prepare_spectra(ctx, f);
-  if (st != DEMAG_OK) return st;
-  return launch_columns(ctx, f, R, in, out);
+  for (int d = 0; d < 3 && st == DEMAG_OK; ++d)
+    st = check_finite(ctx, in[d], size_t(3) * R[d] * f->n[d], false, "demag_apply_columns");
+  if (st == DEMAG_OK) st = launch_columns(ctx, f, R, in, out, nullptr, 0);
+  return st == DEMAG_OK ? note_use(ctx, f) : st;
 }
 
 namespace {
@@ -537,7 +589,21 @@ demag_status demag_profile_read(demag_ctx *ctx, int32_t max, char *labels, doubl
 
 demag_status demag_set_stream(demag_ctx *ctx, void *hip_stream) {
   DEMAG_REQUIRE(ctx, "demag_set_stream: ctx is NULL");
-  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  hipStream_t next = static_cast<hipStream_t>(hip_stream);
+  if (next == ctx->stream) return DEMAG_OK;
+  // later work on the new stream must not overtake work still queued on the
+  // old one (it shares the context's workspace)
+  DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  if (!ctx->order_ev) DEMAG_TRY_HIP(hipEventCreateWithFlags(&ctx->order_ev, hipEventDisableTiming));
+  DEMAG_TRY_HIP(hipEventRecord(ctx->order_ev, ctx->stream));
+  DEMAG_TRY_HIP(hipStreamWaitEvent(next, ctx->order_ev, 0));
+  ctx->stream = next;
+  return DEMAG_OK;
+}
+
+demag_status demag_set_input_check(demag_ctx *ctx, int32_t enable) {
+  DEMAG_REQUIRE(ctx, "demag_set_input_check: ctx is NULL");
+  ctx->check_inputs = enable != 0;
   return DEMAG_OK;
 }
 
@@ -597,6 +663,7 @@ demag_status demag_assemble_factors(demag_ctx *ctx, const demag_grid *grid, cons
   }
   st = launch_assemble(ctx, f.get());
   if (st == DEMAG_OK) st = launch_build_windows(ctx, f.get());
+  if (st == DEMAG_OK) st = note_use(ctx, f.get());
   if (st != DEMAG_OK) {
     demag_factors_free(f.release());
     return st;
@@ -621,7 +688,9 @@ demag_status demag_assemble_factors_grid(demag_ctx *ctx, const int32_t n[3], con
   auto f = std::make_unique<demag_factors>();
   f->L = L;
   f->dense = true;
-  std::vector<double> scaled[3];
+  // the scaled edges live in the handle: the assembly copies them to the
+  // device asynchronously
+  std::vector<double> *scaled = f->edges;
   double hmin = 1e300;
   for (int d = 0; d < 3; ++d) {
     f->n[d] = n[d];
@@ -644,6 +713,7 @@ demag_status demag_assemble_factors_grid(demag_ctx *ctx, const int32_t n[3], con
     }
   }
   st = launch_assemble_dense(ctx, f.get(), scaled);
+  if (st == DEMAG_OK) st = note_use(ctx, f.get());
   if (st != DEMAG_OK) {
     demag_factors_free(f.release());
     return st;
@@ -654,7 +724,11 @@ demag_status demag_assemble_factors_grid(demag_ctx *ctx, const int32_t n[3], con
 
 demag_status demag_factors_free(demag_factors *f) {
   if (!f) return DEMAG_OK;
-  (void)hipDeviceSynchronize();
+  // the last enqueued work that reads the factors must be done
+  if (f->used) {
+    (void)hipEventSynchronize(f->used);
+    (void)hipEventDestroy(f->used);
+  }
   for (int d = 0; d < 3; ++d) {
     if (f->f64[d]) (void)hipFree(f->f64[d]);
     if (f->f32[d]) (void)hipFree(f->f32[d]);
@@ -671,6 +745,12 @@ demag_status demag_factors_free(demag_factors *f) {
 demag_status demag_factors_count(const demag_factors *f, int32_t *M) {
   DEMAG_REQUIRE(f && M, "demag_factors_count: NULL argument");
   *M = f->M;
+  return DEMAG_OK;
+}
+
+demag_status demag_factors_length_scale(const demag_factors *f, double *L) {
+  DEMAG_REQUIRE(f && L, "demag_factors_length_scale: NULL argument");
+  *L = f->L;
   return DEMAG_OK;
 }
 
@@ -692,26 +772,37 @@ demag_status demag_factors_download(demag_ctx *ctx, const demag_factors *f, int3
   return DEMAG_OK;
 }
 
-demag_status demag_apply_full(demag_ctx *ctx, const demag_factors *fc, demag_prec prec, const void *m, void *phi,
-                              void *h) {
-  DEMAG_REQUIRE(ctx && fc && m, "demag_apply_full: NULL argument");
-  DEMAG_REQUIRE(phi || h, "demag_apply_full: phi and h are both NULL");
+}  // extern "C"
+
+namespace {
+// demag_apply_full on the context workspace (ws == NULL, grown to the plan's
+// need under the context's limit) or on a caller workspace of ws_bytes.
+demag_status apply_full_impl(demag_ctx *ctx, const demag_factors *fc, demag_prec prec, const void *m, void *phi,
+                             void *h, void *ws_user, size_t ws_user_bytes, const char *where) {
+  DEMAG_REQUIRE(ctx && fc && m, std::string(where) + ": NULL argument");
+  DEMAG_REQUIRE(phi || h, std::string(where) + ": phi and h are both NULL");
   DEMAG_REQUIRE(prec == DEMAG_FP64 || prec == DEMAG_FP32 || prec == DEMAG_BF16X2 || prec == DEMAG_BF16X3,
-                "demag_apply_full: unknown precision");
-  DEMAG_REQUIRE(aligned16(m) && aligned16(phi) && aligned16(h), "demag_apply_full: buffers must be 16-byte aligned");
-  DEMAG_REQUIRE(!fc->dense || prec == DEMAG_FP64, "demag_apply_full: non-uniform grids are applied in FP64");
+                std::string(where) + ": unknown precision");
+  DEMAG_REQUIRE(aligned16(m) && aligned16(phi) && aligned16(h) && aligned16(ws_user),
+                std::string(where) + ": buffers must be 16-byte aligned");
+  DEMAG_REQUIRE(!fc->dense || prec == DEMAG_FP64, std::string(where) + ": non-uniform grids are applied in FP64");
   for (int d = 0; d < 3; ++d)
-    DEMAG_REQUIRE(fc->n[d] <= 1024, "demag_apply_full: full format supports n <= 1024 per axis");
+    DEMAG_REQUIRE(fc->n[d] <= 1024, std::string(where) + ": full format supports n <= 1024 per axis");
   auto *f = const_cast<demag_factors *>(fc);
   DEMAG_TRY_HIP(hipSetDevice(ctx->device));
-  FullPlan *plan = nullptr;
-  demag_status st = get_plan(ctx, f, prec, &plan);
-  if (st != DEMAG_OK) return st;
-  const size_t esize = (prec == DEMAG_FP64) ? 8 : 4;
-  st = ensure_workspace(ctx, plan->ws_elems * esize);
-  if (st != DEMAG_OK) return st;
   const int64_t N = int64_t(f->n[0]) * f->n[1] * f->n[2];
-  char *ws = static_cast<char *>(ctx->ws);
+  const size_t esize = (prec == DEMAG_FP64) ? 8 : 4;
+  demag_status st = check_finite(ctx, m, size_t(3) * N, prec == DEMAG_FP64, where);
+  if (st != DEMAG_OK) return st;
+  FullPlan *plan = nullptr;
+  st = get_plan(ctx, f, prec, ws_user ? ws_user_bytes : ctx->ws_limit, &plan);
+  if (st != DEMAG_OK) return st;
+  char *ws = static_cast<char *>(ws_user);
+  if (!ws) {
+    st = ensure_workspace(ctx, plan->ws_elems * esize);
+    if (st != DEMAG_OK) return st;
+    ws = static_cast<char *>(ctx->ws);
+  }
   char *y1 = ws;
   char *y2 = y1 + size_t(6) * plan->kc * N * esize;
   char *scratch = y2 + size_t(6) * plan->kc * N * esize;
@@ -733,7 +824,31 @@ demag_status demag_apply_full(demag_ctx *ctx, const demag_factors *fc, demag_pre
       if (st != DEMAG_OK) return st;
     }
   }
+  return note_use(ctx, f);
+}
+}  // namespace
+
+extern "C" {
+
+demag_status demag_apply_full(demag_ctx *ctx, const demag_factors *f, demag_prec prec, const void *m, void *phi,
+                              void *h) {
+  return apply_full_impl(ctx, f, prec, m, phi, h, nullptr, 0, "demag_apply_full");
+}
+
+demag_status demag_apply_full_workspace_size(const demag_factors *f, demag_prec prec, size_t *one_chunk,
+                                             size_t *minimum) {
+  DEMAG_REQUIRE(f, "demag_apply_full_workspace_size: f is NULL");
+  DEMAG_REQUIRE(prec == DEMAG_FP64 || prec == DEMAG_FP32 || prec == DEMAG_BF16X2 || prec == DEMAG_BF16X3,
+                "demag_apply_full_workspace_size: unknown precision");
+  if (one_chunk) *one_chunk = full_ws_bytes(f, prec, f->M);
+  if (minimum) *minimum = full_ws_bytes(f, prec, 1);
   return DEMAG_OK;
+}
+
+demag_status demag_apply_full_ws(demag_ctx *ctx, const demag_factors *f, demag_prec prec, const void *m, void *phi,
+                                 void *h, void *workspace, size_t workspace_bytes) {
+  DEMAG_REQUIRE(workspace, "demag_apply_full_ws: workspace is NULL");
+  return apply_full_impl(ctx, f, prec, m, phi, h, workspace, workspace_bytes, "demag_apply_full_ws");
 }
 
 demag_status demag_apply_fft(demag_ctx *ctx, demag_factors *f, const double *m, double *phi, double *h) {
@@ -744,9 +859,13 @@ demag_status demag_apply_fft(demag_ctx *ctx, demag_factors *f, const double *m, 
   DEMAG_TRY_HIP(hipSetDevice(ctx->device));
   demag_status st = prepare_fft3d(ctx, f);
   if (st != DEMAG_OK) return st;
+  const size_t N = size_t(f->n[0]) * f->n[1] * f->n[2];
+  st = check_finite(ctx, m, 3 * N, true, "demag_apply_fft");
+  if (st != DEMAG_OK) return st;
   st = ensure_workspace(ctx, fft3d_workspace_bytes(f));
   if (st != DEMAG_OK) return st;
-  return launch_fft3d(ctx, f, m, phi, h, ctx->ws);
+  st = launch_fft3d(ctx, f, m, phi, h, ctx->ws);
+  return st == DEMAG_OK ? note_use(ctx, f) : st;
 }
 
 }  // extern "C"

@@ -337,6 +337,11 @@ demag_status demag_batch_info(const demag_batch *b, int32_t *node_chunk, int32_t
 demag_status demag_batch_apply(demag_ctx *ctx, demag_batch *b, const void *m, void *phi, void *h, int32_t use_graph) {
   DEMAG_REQUIRE(ctx && b && m && phi && h, "demag_batch_apply: NULL argument");
   DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  {
+    const demag_status cs = check_finite(ctx, m, size_t(3) * size_t(b->off.back()), b->prec == DEMAG_FP64,
+                                         "demag_batch_apply");
+    if (cs != DEMAG_OK) return cs;
+  }
   hipEvent_t ev = nullptr;
   if (!use_graph) {
     demag_status st = prof_begin(ctx, &ev);

@@ -306,8 +306,14 @@ demag_status prepare_spectra(demag_ctx *ctx, demag_factors *f) {
   return DEMAG_OK;
 }
 
+size_t columns_workspace_bytes(const demag_factors *f, const int32_t R[3]) {
+  size_t pts = 0;
+  for (int d = 0; d < 3; ++d) pts += size_t(3) * R[d] * (fft_length(f->n[d]) / 2 + 1);
+  return sizeof(double2) * pts;
+}
+
 demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, const int32_t R[3], const float *const in[3],
-                            float *const out[3]) {
+                            float *const out[3], void *ws, size_t ws_bytes) {
   ColAxes P{};
   P.M = f->M;
   const int njobs = 2 * f->M;
@@ -347,10 +353,20 @@ demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, const int32_
     // compulsory traffic: input columns, spectra, output columns
     bytes += 4.0 * (double(ncols) * A.n + jobs * A.n) + 8.0 * double(F_NTYPES) * f->M * (A.L / 2 + 1);
   }
-  // column spectra of all three axes in the workspace
-  demag_status st = ensure_workspace(ctx, sizeof(double2) * u_points);
-  if (st != DEMAG_OK) return st;
-  cplx *U = static_cast<cplx *>(ctx->ws);
+  // column spectra of all three axes in the workspace (the context's, or
+  // the caller's when ws is given)
+  demag_status st = DEMAG_OK;
+  if (ws) {
+    if (ws_bytes < sizeof(double2) * u_points) {
+      set_error("structured apply: workspace too small");
+      return DEMAG_E_INVAL;
+    }
+  } else {
+    st = ensure_workspace(ctx, sizeof(double2) * u_points);
+    if (st != DEMAG_OK) return st;
+    ws = ctx->ws;
+  }
+  cplx *U = static_cast<cplx *>(ws);
   const int lds_points = padded_points(maxN);
   const size_t lds = sizeof(double2) * (size_t(lds_points) + 128);
   DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_fwd),

@@ -127,6 +127,9 @@ struct ProfTotals {
 struct demag_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipEvent_t order_ev = nullptr;   // orders a new stream after the previous one
+  bool check_inputs = false;       // reject non-finite inputs before launching
+  int *d_flag = nullptr;           // device flag of the finiteness check
   void *ws = nullptr;
   size_t ws_bytes = 0;
   size_t ws_limit = size_t(16) << 30;
@@ -154,6 +157,8 @@ struct demag_factors {
   void *twiddle[3] = {nullptr, nullptr, nullptr};  // double2 [L/2]
   double *k3 = nullptr;    // 3D kernel spectra, octant [Lz/2+1][Ly/2+1][pitch][10] (FFT apply)
   bool dense = false;      // non-uniform grid: f64[d] holds dense factors [4][M][n][n] (FP64 only)
+  std::vector<double> edges[3];   // non-uniform grid: scaled cell edges (source of an async copy)
+  hipEvent_t used = nullptr;      // recorded after the last enqueued work that reads the factors
   std::map<std::pair<int, int>, std::unique_ptr<demag::FullPlan>> plans;  // (prec class, kc)
 };
 
@@ -190,10 +195,21 @@ demag_status launch_split(demag_ctx *ctx, const float *x, uint16_t *parts, size_
 int fft_length(int n);
 demag_status prepare_spectra(demag_ctx *ctx, demag_factors *f);
 demag_status ensure_workspace(demag_ctx *ctx, size_t bytes);
+// Record on the context's stream that work reading f has been enqueued
+// (demag_factors_free waits for it).
+demag_status note_use(demag_ctx *ctx, const demag_factors *f);
+// With the context's input check on: DEMAG_E_INVAL if any of the count
+// values at x (device, FP64 if dbl else FP32) is NaN or infinite (synchronizes
+// the stream); a no-op otherwise.
+demag_status check_finite(demag_ctx *ctx, const void *x, size_t count, bool dbl, const char *what,
+                          int *flag = nullptr);
 demag_status prepare_fft3d(demag_ctx *ctx, demag_factors *f);
 size_t fft3d_workspace_bytes(const demag_factors *f);
 demag_status launch_fft3d(demag_ctx *ctx, const demag_factors *f, const double *m, double *phi, double *h,
                           void *ws);
+// Structured apply of column sets; the column spectra go to ws (ws_bytes,
+// at least columns_workspace_bytes) or, with ws NULL, to the context workspace.
+size_t columns_workspace_bytes(const demag_factors *f, const int32_t R[3]);
 demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, const int32_t R[3], const float *const in[3],
-                            float *const out[3]);
+                            float *const out[3], void *ws, size_t ws_bytes);
 } // namespace demag
