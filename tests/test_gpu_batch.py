@@ -64,6 +64,10 @@ def _unpack(phi, h, off, grids):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_batch_equals_single_state(ctx, prec):
+    """FP64: bitwise equal to the single-state apply.  FP32: the single-state
+    apply sums the x stage's node terms as four partial sums added in FP64,
+    the persistent batch kernel in one FP32 chain per output, so the two
+    agree to FP32 summation order (1e-6 relative L2)."""
     dtype = torch.float64 if prec == "fp64" else torch.float32
     grids = _grids()
     fields = [inputs.random_unit_field(n, seed=20 + s) for s, (n, _h) in enumerate(grids)]
@@ -74,8 +78,12 @@ def test_batch_equals_single_state(ctx, prec):
         f = ctx.assemble(n, hcell, M=12)
         p1, h1 = ctx.apply_full(f, torch.from_numpy(fields[s]).to(device="cuda", dtype=dtype), prec=prec)
         torch.cuda.synchronize()
-        assert np.array_equal(got[s][0], p1.double().cpu().numpy()), s
-        assert np.array_equal(got[s][1], h1.double().cpu().numpy()), s
+        p1, h1 = p1.double().cpu().numpy(), h1.double().cpu().numpy()
+        if prec == "fp64":
+            assert np.array_equal(got[s][0], p1), s
+            assert np.array_equal(got[s][1], h1), s
+        else:
+            assert apply.rel_l2(got[s][0], p1) < 1e-6 and apply.rel_l2(got[s][1], h1) < 1e-6, s
 
 
 def test_batch_fp64_matches_oracle(ctx):
@@ -144,5 +152,7 @@ def test_uneven_batch_recipe_subset(ctx):
         f = ctx.assemble(n, hcell, M=40)
         p1, h1 = ctx.apply_full(f, torch.from_numpy(states[s].m).to(device="cuda", dtype=torch.float32), prec="fp32")
         torch.cuda.synchronize()
-        assert np.array_equal(got[s][0], p1.double().cpu().numpy()), s
-        assert np.array_equal(got[s][1], h1.double().cpu().numpy()), s
+        p1, h1 = p1.double().cpu().numpy(), h1.double().cpu().numpy()
+        ep, eh = apply.rel_l2(got[s][0], p1), apply.rel_l2(got[s][1], h1)
+        print(f"recipe state {s} {n}: batch vs single-state fp32: phi {ep:.2e} h {eh:.2e}")
+        assert ep < 1e-6 and eh < 1e-6, s
