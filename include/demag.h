@@ -255,6 +255,21 @@ demag_status demag_batch_tune(demag_ctx *ctx, demag_batch *b, const char *path, 
 demag_status demag_prepare_structured(demag_ctx *ctx, demag_factors *f);
 demag_status demag_apply_columns(demag_ctx *ctx, demag_factors *f, const int32_t R[3],
                                  const float *const in[3], float *const out[3]);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as demag_apply_columns, bit for bit, with the column spectra in a
+ * static 64 MiB device array per GPU instead of the context workspace; no
+ * hipMalloc, hipFree or other allocating call.  Limits: the column spectra,
+ * 16 (L_d/2 + 1) bytes per input column (3 R_d columns on axis d), must fit
+ * in 64 MiB - 256 bytes (e.g. 1020 columns at n = 4096), else DEMAG_E_INVAL
+ * with the sizes in the message; the factors' kernel spectra must already
+ * exist (demag_prepare_structured, which allocates them), else DEMAG_E_INVAL.
+ * All calls on one GPU share its array, which keeps the last call's
+ * contents: calls that overlap in time on one GPU (other streams, other
+ * threads, other contexts) race.  With profiling enabled the library may
+ * create timing events. */
+demag_status demag_apply_columns_noalloc(demag_ctx *ctx, const demag_factors *f, const int32_t R[3],
+                                         const float *const in[3], float *const out[3]);
 
 /* CP input, rank r per component (weights pass through unchanged):
  * U[d] = [3 q][r][n_d] holds column l of U^{(q,d)}.  Result: out[d] as above

@@ -77,6 +77,7 @@ _SIGS = {
                                      C.c_int32, _P, _P, _P, _P, _P, _P]),
     "demag_prepare_structured": (C.c_int, [_P, _P]),
     "demag_apply_columns": (C.c_int, [_P, _P, _P, _P, _P]),
+    "demag_apply_columns_noalloc": (C.c_int, [_P, _P, _P, _P, _P]),
     "demag_apply_cp": (C.c_int, [_P, _P, C.c_int32, _P, _P, _P]),
     "demag_apply_tucker": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "demag_apply_tt": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P]),

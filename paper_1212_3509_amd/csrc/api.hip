@@ -447,6 +447,9 @@ demag_status demag_create(int device, void *hip_stream, demag_ctx **out) {
   }
   ctx->device = device;
   ctx->stream = static_cast<hipStream_t>(hip_stream);
+  // the allocation-free entry point's static scratch: its device address,
+  // looked up once per device with the device current
+  (void)scratch_init(device);
   *out = ctx;
   return DEMAG_OK;
 }

@@ -212,4 +212,7 @@ demag_status launch_fft3d(demag_ctx *ctx, const demag_factors *f, const double *
 size_t columns_workspace_bytes(const demag_factors *f, const int32_t R[3]);
 demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, const int32_t R[3], const float *const in[3],
                             float *const out[3], void *ws, size_t ws_bytes);
+// Device address of the static scratch array on `device` (set up by
+// demag_create); NULL if its set-up failed.
+demag_status scratch_init(int device);
 } // namespace demag
