@@ -8,16 +8,22 @@ Inputs and outputs stay resident in device memory; the timed region covers
 only the apply calls.
 
   * FP64 plain: sinc rule with M = 40 nodes (81-point rule), c0 = 2.15 -> ``value``.
-  * mixed + learned: the node-proposal network is trained on the GPU (outside
-    the timed region), proposes a shortened rule for this grid at a rule
-    tolerance, and the apply runs with bfloat16 three-part split products;
-    its relative L2 difference to the FP64 plain result of the same run is
-    reported beside its throughput.
+  * mixed + learned: the network is trained on the GPU (outside the timed
+    region); its error head picks R' for this grid at the tolerance, the
+    shortened rule is fitted and certified (relative Frobenius-norm error of
+    the potential and field operators <= tol), and the apply runs with
+    bfloat16 three-part split products; its relative L2 difference to the
+    FP64 plain result of the same run is reported beside its throughput,
+    with the ablation of the network (R', fits and time of each predict
+    mode) and the plain rule's node count at the same certified tolerance.
   * FP32, BF16x3 and BF16x2 with the full rule, for reference.
+  * Sub-records of the same line: the 3D-FFT route, a graded non-uniform
+    grid, the structured applies at n = 4096 (CP rank 10, Tucker (8,8,8), TT
+    (1,8,8,1); M = 40 and the certified theorem-step rule with 64 nodes) and
+    the batch of 256 uneven states, each with its roofline, and the CPU
+    oracle baseline (1 core and all cores, median of 3).
 
-Other workloads (``--workload``): ``cp4096`` (structured CP rank 10, Tucker
-(8,8,8) and TT (1,8,8,1) inputs at n = 4096 per axis) and ``batch`` (256
-magnetization states on uneven grids).  Each prints its own JSON line.
+``--workload cp4096`` / ``batch`` print only those sub-records.
 """
 from __future__ import annotations
 
@@ -135,34 +141,75 @@ def _kernels(prof, steps):
                 "tflops": round(v["flops"] / (v["ms"] * 1e-3) / 1e12, 3)} for k, v in sorted(prof.items())}
 
 
-def _cpu_baseline(m, n, nodes_sample):
-    """The oracle's dense-Toeplitz Kronecker apply on the full grid for the
-    first `nodes_sample` of the 40 nodes, scaled to all 40."""
-    from oracle import apply, sinc
+def _median_wall(fn, runs):
+    """Median wall time of `runs` calls and the CPU threads busy during them."""
+    walls, cpus = [], []
+    for _ in range(runs):
+        c0, w0 = time.process_time(), time.perf_counter()
+        fn()
+        walls.append(time.perf_counter() - w0)
+        cpus.append(time.process_time() - c0)
+    i = sorted(range(runs), key=lambda j: walls[j])[runs // 2]
+    return walls[i], cpus[i]
+
+
+def _cpu_baseline(m, n, runs):
+    """The oracle timed on this host's cores: its dense-Toeplitz Kronecker
+    apply (FP64 NumPy) of the 128^3 vortex on a node sample, scaled to the 40
+    nodes of the rule (the apply is a sum over nodes).  One core: one node
+    per run.  All cores: the oracle run unchanged on one node per core in a
+    thread pool (its einsum loops release the interpreter lock).  Median of
+    `runs` runs each.  Beside it: the exact collocation (closed-form cell
+    kernels + FFT convolution) at 32^3, and the structured reference (dense
+    Toeplitz products of the factor columns) at n = 4096 on one (node, type)
+    pair of CP rank 10 columns, scaled to the apply's 7200 products."""
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    from oracle import apply, sinc, structured
+    from paper_1212_3509_amd import inputs
     _t, tau, alpha = sinc.sinc_nodes(40)
     h = (1.0 / n,) * 3
-    c0 = time.process_time()
-    w0 = time.perf_counter()
-    apply.kron_apply_dense(m, h, tau[:nodes_sample], alpha[:nodes_sample])
-    wall = time.perf_counter() - w0
-    cpu = time.process_time() - c0
-    per_apply = wall * 40 / nodes_sample
-    out = {"value": round(n ** 3 / per_apply / 1e6, 6), "unit": "Mcell-field evals/s",
-           "cores": max(1, round(cpu / wall)), "kind": "oracle",
-           "sample": f"{nodes_sample} of 40 nodes of the 128^3 vortex apply (FP64 NumPy, dense Toeplitz "
-                     f"factors), wall {wall:.1f} s, scaled x{40 / nodes_sample:g}"}
+    cores = len(os.sched_getaffinity(0))
+    wall1, cpu1 = _median_wall(lambda: apply.kron_apply_dense(m, h, tau[:1], alpha[:1]), runs)
+
+    def all_cores():
+        with ThreadPoolExecutor(cores) as ex:
+            list(ex.map(lambda k: apply.kron_apply_dense(m, h, tau[k % 40:k % 40 + 1], alpha[k % 40:k % 40 + 1]),
+                        range(cores)))
+    wallc, cpuc = _median_wall(all_cores, runs)
+    per_apply_1 = wall1 * 40
+    per_apply_c = wallc * 40 / cores
+    out = {"value": round(n ** 3 / per_apply_c / 1e6, 6), "unit": "Mcell-field evals/s",
+           "cores": max(1, round(cpuc / wallc)), "kind": "oracle",
+           "sample": f"oracle dense-Toeplitz Kronecker apply (FP64 NumPy) of the 128^3 vortex, one node per "
+                     f"thread on {cores} threads, median of {runs}: {wallc:.2f} s for {cores} of the 40 nodes, "
+                     f"scaled to 40",
+           "one_core": {"value": round(n ** 3 / per_apply_1 / 1e6, 6), "unit": "Mcell-field evals/s",
+                        "cores": max(1, round(cpu1 / wall1)),
+                        "sample": f"one node, median of {runs}: {wall1:.2f} s, scaled x40"}}
     out["host"] = _host_info()
-    # the exact collocation (closed-form cell kernels + FFT convolution) on
-    # the 32^3 random-field case, as the oracle computes it
-    from paper_1212_3509_amd import inputs
     m32 = inputs.random_unit_field(32, seed=0)
-    c0 = time.process_time()
-    w0 = time.perf_counter()
-    apply.collocated_apply_fft(m32, (1.0 / 32,) * 3)
-    wall = time.perf_counter() - w0
-    cpu = time.process_time() - c0
+    wall, cpu = _median_wall(lambda: apply.collocated_apply_fft(m32, (1.0 / 32,) * 3), runs)
     out["exact_fft_32"] = {"value": round(32 ** 3 / wall / 1e6, 6), "unit": "Mcell-field evals/s",
                            "seconds": round(wall, 3), "cores": max(1, round(cpu / wall))}
+    # structured reference at n = 4096: one Toeplitz (type, node) times the
+    # ten columns of one component, scaled to 3 axes x 3 components x 2
+    # slots x 40 nodes
+    N4 = 4096
+    F = sinc.scaled_factors(N4, 1.0 / N4, tau[:1], alpha[:1])
+    cols = np.random.default_rng(1).uniform(-1, 1, (N4, 10))
+    wall, cpu = _median_wall(lambda: structured._columns(F, 0, 0, cols, 1), runs)
+    per_apply = wall * 3 * 3 * 40
+    out["structured_4096_cp_r10"] = {"value": round(N4 ** 3 / per_apply / 1e12, 6),
+                                     "unit": "implicit Tcell/s", "seconds_per_apply": round(per_apply, 3),
+                                     "cores": max(1, round(cpu / wall)),
+                                     "sample": f"the oracle's columns of one axis, component and node (two dense "
+                                               f"4096 x 4096 Toeplitz products with 10 columns, FP64 BLAS), median "
+                                               f"of {runs}: {wall * 1e3:.1f} ms, scaled x360 (3 axes, 3 components, "
+                                               f"40 nodes)"}
     return out
 
 
@@ -190,26 +237,18 @@ def _rel(a, b):
 
 
 def _judge(ctx, n, t, alpha):
-    """Kernel error of the rule (t, alpha) on the n^3 unit cube at the check
-    offsets (the library's FP64 judge against the 96-node theorem-step rule)."""
-    import numpy as np
-    import torch
-
-    from paper_1212_3509_amd import inputs
-    dev = "cuda"
-    sent = torch.from_numpy(inputs.sentinel_offsets((n, n, n), "check")[None]).to(device=dev, dtype=torch.int32)
-    grids = torch.tensor([[n, n, n]], dtype=torch.int32, device=dev)
-    hmin = torch.tensor([1.0 / n], dtype=torch.float64, device=dev)
-    tt = torch.from_numpy(np.asarray(t, dtype=np.float64)[None]).to(dev)
-    aa = torch.from_numpy(np.asarray(alpha, dtype=np.float64)[None]).to(dev)
-    R = torch.tensor([len(t)], dtype=torch.int32, device=dev)
-    return float(ctx.quad_judge(grids, hmin, sent, tt, aa, R)[0])
+    """Certified operator error of the rule (t, alpha) on the n^3 unit cube:
+    the larger of the potential's and the field's relative Frobenius-norm
+    errors against the 96-node theorem-step rule."""
+    return max(ctx.quad_certify((n, n, n), (1.0 / n,) * 3, t, alpha))
 
 
 def _learned_eval(ctx, params, args):
     """The trained network on grids beyond its training range: 256^3 full
     format (vortex) and 1024^3 CP rank 10; each uses the predicted rule, or
-    the fallback rule when the judged error exceeds the tolerance."""
+    the fallback rule when no shortened rule is certified within the
+    tolerance.  Every rule's certificate (larger of the potential's and the
+    field's operator errors) is reported beside the measured errors."""
     import numpy as np
     import torch
 
@@ -218,18 +257,18 @@ def _learned_eval(ctx, params, args):
     # 256^3 full format
     n = 256
     N = n ** 3
-    rule = learned.predict(ctx, params, (n, n, n), args.rule_tol)
+    rule = learned.predict(ctx, params, (n, n, n), args.rule_tol, fit_iters=args.predict_iters)
     fr = ctx.assemble((n, n, n), (1.0 / n,) * 3, t=rule["t"], alpha=rule["alpha"])
     fp = ctx.assemble((n, n, n), (1.0 / n,) * 3, M=40, c0=2.15)
     pt, _ptau, pa = fp.nodes()
     m_host = inputs.vortex_field(n, seed=0)
-    rec = {"nodes": rule["R"], "fell_back": rule["fell_back"], "rule_tol": args.rule_tol,
-           "candidate_judged_kernel_err": rule["judged"], "rule_judged_kernel_err": _judge(ctx, n, rule["t"], rule["alpha"]),
-           "plain_m40_judged_kernel_err": _judge(ctx, n, pt, pa)}
+    rec = {"nodes": rule["R"], "fell_back": rule["fell_back"], "fits": rule["fits"], "rule_tol": args.rule_tol,
+           "rule_certified_err": rule["judged"], "plain_m40_certified_err": _judge(ctx, n, pt, pa),
+           "predict_seconds": round(rule["seconds"], 3)}
     # accurate reference: the theorem-step rule with 64 nodes (the fallback rule)
     fa = ctx.assemble((n, n, n), (1.0 / n,) * 3, M=64, step_rule=1)
     at, _atau, aa = fa.nodes()
-    rec["reference_theorem_m64_judged_kernel_err"] = _judge(ctx, n, at, aa)
+    rec["reference_theorem_m64_certified_err"] = _judge(ctx, n, at, aa)
     runs = {}
     ref = None
     for name, f, prec in (("reference_theorem_m64_fp64", fa, "fp64"), ("rule_fp64", fr, "fp64"),
@@ -253,16 +292,16 @@ def _learned_eval(ctx, params, args):
     torch.cuda.empty_cache()
     # 1024^3 CP rank 10 (structured)
     n = 1024
-    rule = learned.predict(ctx, params, (n, n, n), args.rule_tol)
+    rule = learned.predict(ctx, params, (n, n, n), args.rule_tol, fit_iters=args.predict_iters)
     fr = ctx.assemble((n, n, n), (1.0 / n,) * 3, t=rule["t"], alpha=rule["alpha"])
     fp = ctx.assemble((n, n, n), (1.0 / n,) * 3, M=40, c0=2.15)
     pt, _ptau, pa = fp.nodes()
     cp = inputs.cp_input(n, rank=10, seed=1, dtype=np.float32)
     U = [torch.from_numpy(np.ascontiguousarray(np.stack([cp.U[q][d].T for q in range(3)]))).cuda()
          for d in range(3)]
-    rec = {"nodes": rule["R"], "fell_back": rule["fell_back"], "rule_tol": args.rule_tol,
-           "candidate_judged_kernel_err": rule["judged"], "rule_judged_kernel_err": _judge(ctx, n, rule["t"], rule["alpha"]),
-           "plain_m40_judged_kernel_err": _judge(ctx, n, pt, pa)}
+    rec = {"nodes": rule["R"], "fell_back": rule["fell_back"], "fits": rule["fits"], "rule_tol": args.rule_tol,
+           "rule_certified_err": rule["judged"], "plain_m40_certified_err": _judge(ctx, n, pt, pa),
+           "predict_seconds": round(rule["seconds"], 3)}
     for name, f in (("rule", fr), ("plain_m40", fp)):
         ctx.prepare_structured(f)
         ms, _prof = _timed(ctx, lambda: ctx.apply_cp(f, U), 3, 1)
@@ -346,9 +385,24 @@ def headline(args):
         params, loss = learned.train(ctx, cases, steps=args.learned_steps, batch=512)
         torch.cuda.synchronize()
         train_s = time.perf_counter() - t0 - fit_s
-        t1 = time.perf_counter()
-        rule = learned.predict(ctx, params, (n, n, n), args.rule_tol)
-        predict_s = time.perf_counter() - t1
+        # what the network contributes: the three predict modes at this grid
+        ablation = {}
+        for mode in ("network", "network_proposal", "search"):
+            r = learned.predict(ctx, params, (n, n, n), args.rule_tol, fit_iters=args.predict_iters, mode=mode)
+            ablation[mode] = {k: r[k] for k in ("R", "fell_back", "fits", "err_phi", "err_h", "seconds",
+                                                "accuracy_met")}
+            if mode == "network":
+                rule = r
+        # the plain sinc rule's node count for the same certified tolerance
+        # (nodes from the library's own assembly)
+        plain_nodes = None
+        for M in range(16, 65):
+            fM = ctx.assemble((n, n, n), (1.0 / n,) * 3, M=M, c0=2.15)
+            t_, _tau, a_ = fM.nodes()
+            fM.free()
+            if _judge(ctx, n, t_, a_) <= args.rule_tol:
+                plain_nodes = M
+                break
         fl = ctx.assemble((n, n, n), (1.0 / n,) * 3, t=rule["t"], alpha=rule["alpha"])
         m = torch.from_numpy(m_host).to(device="cuda", dtype=torch.float32)
         phi = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
@@ -358,21 +412,42 @@ def headline(args):
         err = {"phi": _rel(phi.double(), ref[0]), "h": _rel(h.double(), ref[1])}
         mixed = {"value": round(N / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 4), "dtype": prec,
                  "nodes": rule["R"], "fell_back": rule["fell_back"], "rule_tol": args.rule_tol,
-                 "judged_kernel_err": rule["judged"], "predicted_log10_err": rule["predicted"],
+                 "certified": {"phi": rule["err_phi"], "h": rule["err_h"]},
+                 "predicted_log10_err": rule["predicted"],
                  "rel_l2_vs_fp64_plain": err, "meets_1e-6": max(err.values()) <= 1e-6,
                  "speedup_vs_fp64_plain": round(results["fp64"]["ms_per_step"] / ms, 3),
+                 "plain_sinc_nodes_for_rule_tol": plain_nodes,
+                 "node_ratio_vs_plain_sinc": None if plain_nodes is None else round(rule["R"] / plain_nodes, 3),
+                 "ablation": ablation,
                  "roofline": _roofline(prof, prec), "kernels": _kernels(prof, args.steps),
                  "training": {"cases": args.cases, "fit_iters": args.fit_iters, "fit_seconds": round(fit_s, 2),
                               "median_fitted_log10_err": float(np.median(np.log10(cases["fit_err"].cpu().numpy()))),
                               "steps": args.learned_steps, "train_seconds": round(train_s, 2),
                               "loss_first": float(loss[:10].mean()), "loss_last": float(loss[-10:].mean()),
-                              "predict_seconds": round(predict_s, 3)}}
+                              "predict_fit_iters": args.predict_iters}}
+        del m, phi, h, fl
+        torch.cuda.empty_cache()
 
     learned_eval = None
     if args.learned_steps > 0 and args.learned_eval:
         learned_eval = _learned_eval(ctx, params, args)
 
+    del f
+    torch.cuda.empty_cache()
+    structured_rec = structured_record(ctx, args) if args.structured else None
+    del ctx
+    torch.cuda.empty_cache()
+    batch_rec = batch_record(args) if args.batch else None
+
     head = results["fp64"]
+    # the apply's compulsory traffic (m in, phi and h out) beside what the
+    # counters read for its stage launches
+    algo = 7.0 * N * 8
+    counted = [_traffic(k) for k in head["kernels"]]
+    head["roofline"]["apply_bytes"] = {
+        "algorithmic_7N": algo,
+        "counters": None if any(c is None for c in counted) else sum(counted),
+        "ratio": None if any(c is None for c in counted) else round(sum(counted) / algo, 2)}
     line = {
         "metric": METRIC, "value": head["value"], "unit": "Mcell-field evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
@@ -386,25 +461,30 @@ def headline(args):
         "learned_eval": learned_eval,
         "fft3d_route": fft3d,
         "nonuniform_grid": nonuni,
+        "structured_4096": structured_rec,
+        "batch_256": batch_rec,
         "precisions": results,
     }
     if args.vendor_gemm:
         line["vendor_gemm"] = _vendor_gemm()
-    if args.cpu_nodes > 0:
-        line["cpu_baseline"] = _cpu_baseline(m_host, n, args.cpu_nodes)
+    if args.cpu_runs > 0:
+        line["cpu_baseline"] = _cpu_baseline(m_host, n, args.cpu_runs)
     print(json.dumps(line), flush=True)
 
 
-def structured(args):
+def structured_record(ctx, args):
+    """Structured applies at n = 4096 per axis (CP rank 10, Tucker (8,8,8),
+    TT (1,8,8,1)), with the rule M = 40 (c0 = 2.15) and the theorem-step rule
+    with 64 nodes, each rule's certificate, the HOOI recompression of the CP
+    potential, and the roofline of the transform launches (HBM bound: the
+    algorithmic bytes are the input and output columns plus the kernel
+    spectra, per apply)."""
     import numpy as np
     import torch
 
-    from paper_1212_3509_amd import api, inputs
+    from paper_1212_3509_amd import inputs
 
     n, M = 4096, 40
-    if args.calib_copy_mib > 0:
-        _copy_calibration(args.calib_copy_mib)
-    ctx = api.Context(0)
     f = ctx.assemble((n, n, n), (1.0 / n,) * 3, M=M, c0=2.15)
     ctx.prepare_structured(f)
     out = {}
@@ -416,23 +496,31 @@ def structured(args):
     G1 = torch.from_numpy(np.ascontiguousarray(np.stack([tt.G1[q].T for q in range(3)]))).cuda()
     G2 = torch.from_numpy(np.ascontiguousarray(np.stack([tt.G2[q].transpose(0, 2, 1) for q in range(3)]))).cuda()
     G3 = torch.from_numpy(np.ascontiguousarray(np.stack([tt.G3[q] for q in range(3)]))).cuda()
-    # M = 40 with c0 = 2.15 is not accurate at n = 4096 (the rule error grows
-    # as h -> 0); the theorem-step rule with 64 nodes (the fallback rule of
-    # the learned path) is, at 1.6x the jobs
     fa = ctx.assemble((n, n, n), (1.0 / n,) * 3, M=64, step_rule=1)
     ctx.prepare_structured(fa)
+    t40, _tau, a40 = f.nodes()
+    t64, _tau, a64 = fa.nodes()
+    certified = {"m40_c0_2.15": ctx.quad_certify((n, n, n), (1.0 / n,) * 3, t40, a40),
+                 "theorem_m64": ctx.quad_certify((n, n, n), (1.0 / n,) * 3, t64, a64)}
     cases = {"cp_r10": lambda: ctx.apply_cp(f, U), "tucker_888": lambda: ctx.apply_tucker(f, V),
-             "tt_188_1": lambda: ctx.apply_tt(f, G1, G2, G3), "cp_r10_theorem_m64": lambda: ctx.apply_cp(fa, U)}
+             "tt_188_1": lambda: ctx.apply_tt(f, G1, G2, G3), "cp_r10_theorem_m64": lambda: ctx.apply_cp(fa, U),
+             "tucker_888_theorem_m64": lambda: ctx.apply_tucker(fa, V),
+             "tt_188_1_theorem_m64": lambda: ctx.apply_tt(fa, G1, G2, G3)}
     for name, fn in cases.items():
         ms, prof = _timed(ctx, fn, args.steps, args.warmup)
-        bytes_ = sum(v["bytes"] for v in prof.values()) / args.steps
-        flops = sum(v["flops"] for v in prof.values()) / args.steps
+        rec = prof["fft/xyz"]
+        per_ms = rec["ms"] / rec["launches"]
+        bytes_ = rec["bytes"] / rec["launches"]
+        flops = rec["flops"] / rec["launches"]
+        achieved = bytes_ / (per_ms * 1e-3) / 1e9
         out[name] = {"ms_per_apply": round(ms, 4), "implicit_cells_per_s": n ** 3 / (ms * 1e-3),
-                     "algorithmic_GBps": round(bytes_ / (ms * 1e-3) / 1e9, 1),
-                     "hbm_frac": round(bytes_ / (ms * 1e-3) / 1e9 / HBM_GBS, 4),
-                     "fft_gflops": round(flops / (ms * 1e-3) / 1e9, 1), "kernels": _kernels(prof, args.steps)}
-    # NEXT-1: HOOI recompression of the CP apply's potential (3 M r terms) to
-    # Tucker form, for the random rank-10 input above and a smooth one
+                     "roofline": {"bound": "hbm", "kernel": "k_fft_fwd + k_fft_jobs (one apply)",
+                                  "achieved": round(achieved, 1), "peak": HBM_GBS, "unit": "GB/s",
+                                  "frac": round(achieved / HBM_GBS, 4), "traffic": None,
+                                  "algorithmic_bytes_per_launch": bytes_, "avg_launch_ms": round(per_ms, 4)},
+                     "fft_gflops": round(flops / (per_ms * 1e-3) / 1e9, 1), "kernels": _kernels(prof, args.steps)}
+    # HOOI recompression of the CP apply's potential (3 M r terms) to Tucker
+    # form, for the random rank-10 input above and a smooth one
     recomp = {}
     x = np.linspace(0.0, 1.0, n)
     rng = np.random.default_rng(9)
@@ -452,16 +540,27 @@ def structured(args):
             recomp[f"{name}_eps{eps:g}"] = {"terms": T, "ranks": res["ranks"], "rel_err": res["rel_err"],
                                            "sweeps": res["sweeps"], "seconds": round(sec, 4),
                                            "tolerance_met": res["rel_err"] <= eps}
-    t40, _tau, a40 = f.nodes()
-    t64, _tau, a64 = fa.nodes()
-    judged = {"m40_c0_2.15": _judge(ctx, n, t40, a40), "theorem_m64": _judge(ctx, n, t64, a64)}
-    print(json.dumps({"workload": "structured apply, n=4096 per axis, M=40 (and the theorem-step rule with 64 "
-                                  "nodes), FP32 columns / FP64 transforms",
-                      "n_gpus": 1, "rule_judged_kernel_err": judged, "results": out,
-                      "recompression_phi": recomp}), flush=True)
+        del out_cols
+    del U, V, G1, G2, G3, f, fa
+    torch.cuda.empty_cache()
+    return {"workload": "structured apply, n=4096 per axis, CP rank 10 / Tucker (8,8,8) / TT (1,8,8,1), U[-1,1] "
+                        "factors seed 1; sinc rule M=40 (c0=2.15) and the theorem-step rule with 64 nodes; FP32 "
+                        "columns, FP64 transforms",
+            "certified_rule_err": {k: {"phi": v[0], "h": v[1]} for k, v in certified.items()},
+            "results": out, "recompression_phi": recomp}
 
 
-def batch(args):
+def structured(args):
+    from paper_1212_3509_amd import api
+    if args.calib_copy_mib > 0:
+        _copy_calibration(args.calib_copy_mib)
+    print(json.dumps({"n_gpus": 1, **structured_record(api.Context(0), args)}), flush=True)
+
+
+def batch_record(args):
+    """256 magnetization states on uneven grids, FP32, one persistent launch
+    per stage, graph replay, autotuned tiles; roofline on the FP32 matrix
+    cores (algorithmic FLOPs of the dense Toeplitz products)."""
     import numpy as np
     import torch
 
@@ -471,22 +570,33 @@ def batch(args):
     ctx = api.Context(0)
     ctx.set_workspace_limit(int(args.batch_ws_gib) << 30)
     b = ctx.batch([(s.n, s.h) for s in states], M=40, prec="fp32")
+    t0 = time.perf_counter()
     if args.tune:
         b.tune(args.tune_cache or None, reps=2)
+    tune_s = time.perf_counter() - t0
     off = b.offsets()
     m = torch.from_numpy(np.concatenate([s.m.reshape(-1) for s in states]).astype(np.float32)).cuda()
     phi = torch.empty(int(off[-1]), dtype=torch.float32, device="cuda")
     h = torch.empty(3 * int(off[-1]), dtype=torch.float32, device="cuda")
     ms, prof = _timed(ctx, lambda: b.apply(m, phi, h, use_graph=True), args.steps, args.warmup)
     info = b.info()
-    print(json.dumps({"workload": "256 states on uneven grids (cubes 16..96, films 256x256x{4,8,16}), "
-                                  "FP32, M=40, one persistent launch per stage, graph replay",
-                      "n_gpus": 1, "cells": int(off[-1]), "ms_per_batch": round(ms, 3),
-                      "Mcell_per_s": round(off[-1] / (ms * 1e-3) / 1e6, 2),
-                      "tflops": round(info["flops"] / (ms * 1e-3) / 1e12, 2),
-                      "mfma_frac_fp32": round(info["flops"] / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp32"], 4),
-                      "node_chunk": info["node_chunk"], "persistent_groups": info["persistent_groups"]}),
-          flush=True)
+    achieved = info["flops"] / (ms * 1e-3) / 1e12
+    rec = {"workload": "256 states on uneven grids (cubes 16..96, films 256x256x{4,8,16}, seed 2), FP32, M=40, "
+                       "one persistent launch per stage, graph replay",
+           "cells": int(off[-1]), "ms_per_batch": round(ms, 3), "Mcell_per_s": round(off[-1] / (ms * 1e-3) / 1e6, 2),
+           "roofline": {"bound": "mfma", "kernel": "k_left_items (all stages of one batch)",
+                        "achieved": round(achieved, 2), "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                        "frac": round(achieved / PEAK_TFLOPS["fp32"], 4), "traffic": None,
+                        "flops_per_batch": info["flops"]},
+           "tune_seconds": round(tune_s, 2), "node_chunk": info["node_chunk"],
+           "persistent_groups": info["persistent_groups"]}
+    del m, phi, h, b, ctx
+    torch.cuda.empty_cache()
+    return rec
+
+
+def batch(args):
+    print(json.dumps({"n_gpus": 1, **batch_record(args)}), flush=True)
 
 
 def main():
@@ -495,10 +605,13 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="headline", choices=["headline", "cp4096", "batch"])
-    ap.add_argument("--cpu-nodes", type=int, default=3, help="oracle nodes timed for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-runs", type=int, default=3, help="runs (median) of each CPU baseline timing (0: skip)")
     ap.add_argument("--precs", default="fp64,fp32,bf16x3,bf16x2")
     ap.add_argument("--learned-steps", type=int, default=4000)
-    ap.add_argument("--fit-iters", type=int, default=60)
+    ap.add_argument("--fit-iters", type=int, default=60, help="LM iterations of the training fits")
+    ap.add_argument("--predict-iters", type=int, default=200, help="LM iterations per fit in predict")
+    ap.add_argument("--structured", type=int, default=1, help="also time the structured applies at n = 4096")
+    ap.add_argument("--batch", type=int, default=1, help="also time the batch of 256 uneven states")
     ap.add_argument("--cases", type=int, default=20000)
     ap.add_argument("--rule-tol", type=float, default=1e-6)
     ap.add_argument("--mixed-prec", default="bf16x3")

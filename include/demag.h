@@ -322,23 +322,35 @@ demag_status demag_recompress_cp(demag_ctx *ctx, const int32_t n[3], int32_t T, 
                                  int32_t *sweeps);
 
 /* ---------------------------------------------------------------- learned rule
- * A network proposes shortened rules (R' = 16..32 nodes); an FP64 judge
- * measures their kernel error; the full rule is the fallback.  Not part of
- * the paper's method: it shortens the sinc rule of Cor. kron_op.
+ * A network proposes shortened rules (R' = 16..32 nodes); the operator error
+ * of a rule is certified against an accurate reference rule; the full rule
+ * is the fallback.  Not part of the paper's method: it shortens the sinc rule
+ * of Cor. kron_op.
  *
  * Network: 6 -> 64 -> 64 -> 64 -> 65, GELU hidden layers, FP32, parameters a
  * flat device array of demag_mlp_param_count() floats [W1 (64x6, row =
- * output), b1, W2, b2, W3, b3, W4 (65x64), b4].  Inputs per case (x[b][6]):
- * n_x/n_max, n_y/n_max, n_z/n_max, log2(1/h)/6 - 1, (log10 tol + 6.5)/2.5,
- * (R' - 24)/8.  Outputs y[b][65]: 32 node offsets, 32 log-weight offsets, the
- * predicted log10 kernel error.
+ * output), b1, W2, b2, W3, b3, W4 (65x64), b4].  Inputs per case (x[b][6],
+ * demag_quad_features): n_x/n_max, n_y/n_max, n_z/n_max, log2(1/h)/6 - 1,
+ * (log10 tol + 6.5)/2.5, (R' - 24)/8.  Outputs y[b][65]: 32 node offsets, 32
+ * log-weight offsets, the predicted log10 error.
  * Rule from outputs, base = sinc rule with R' nodes and c0 = 2.15:
  *   t'_k = t_k + 0.45 theta tanh(y_k),
  *   alpha'_k = 2 theta cosh t'_k sinh^2 t'_k exp(tanh(y_{32+k})).
- * Judge: err = sqrt(mean over sentinel offsets J of |K(J) - K_ref(J)|^2 /
- * |K_ref(J)|^2) over the nine kernel values [K^x, K^y, K^z, F_xx, F_yy,
- * F_zz, F_xy, F_xz, F_yz], K_ref from the sinc rule with the step of Thm.
- * sinc_theo and 96 nodes, on unit-longest-edge grids with cubic cells hmin.
+ * Kernel values at an offset J: [K^x, K^y, K^z, F_xx, F_yy, F_zz, F_xy, F_xz,
+ * F_yz] (potential kernels of Cor. kron_op and the field kernels of h_p <-
+ * m_q), reference = the sinc rule with the step of Thm. sinc_theo and 96
+ * nodes, on unit-longest-edge grids with cubic cells hmin.
+ * Certificate (demag_quad_certify): the relative Frobenius-norm errors of the
+ * discrete potential operator (3N -> N) and field operator (3N -> 3N),
+ *   e_phi^2 = sum_J c(J) sum_q dK^q(J)^2 / sum_J c(J) sum_q K^q_ref(J)^2,
+ *   e_h^2   = the same over F_pq with multiplicity 2 off the diagonal,
+ * summed over every offset J >= 0 with c(J) = prod_d (n_d - J_d) (J_d ? 2 : 1)
+ * (exactly for axes up to 512 cells; past 512 cells an axis' offsets are
+ * taken in blocks of 4, 8, 16, ... per octave, each block by its midpoint with
+ * its summed weight).  It equals the relative L2 error of phi and h averaged
+ * over inputs with independent, equal-variance cell values.
+ * Judge (demag_quad_judge, the fit's objective): the same sums over S sampled
+ * offsets with weights (demag_quad_offsets), err = sqrt(e_phi^2 + e_h^2).
  * All arrays below are device arrays unless marked host. */
 int32_t demag_mlp_param_count(void);
 /* y[B][65]; z, a (optional, [B][3][64]) hidden pre-activations/activations. */
@@ -354,28 +366,44 @@ demag_status demag_adam_step(demag_ctx *ctx, float *params, const float *grad, f
 /* Rules t, alpha [B][32] from outputs y (NULL: the base rules) and R[B]. */
 demag_status demag_quad_rules(demag_ctx *ctx, const float *y, const int32_t *R, int32_t B, double *t,
                               double *alpha);
+/* Host-only.  Offsets J[count][3] (0 <= J_d < n_d) and weights w[count] of
+ * the judge on grid n: the near block J_d <= 3 with exact weights c(J), then
+ * shells of max-norm 4..max(n) - 1 in G = min((count - near)/8, max(n) - 4)
+ * geometric groups, each represented by 8 offsets along a cycle of
+ * directions with 1/8 of the group's summed weight; padded with J = 0, w = 0.
+ * The weights add up to prod_d n_d^2.  DEMAG_E_INVAL if count < near block. */
+demag_status demag_quad_offsets(const int32_t n[3], int32_t count, int32_t *J, double *w);
+/* Host-only.  Network input x[6] of one case (layout above). */
+demag_status demag_quad_features(const int32_t n[3], double h, double log10_tol, int32_t R, float *x);
 /* Judge B rules (t, alpha [B][KM], R[B] nodes used) on grids [B][3] with
- * cell sizes hmin[B] at sentinels [B][S][3] (offsets 0 <= J_d < n_d):
- * err[B]; with dt, dalpha non-NULL also d err / d t_k, d err / d alpha_k
- * [B][KM].  Synchronizes the stream. */
+ * cell sizes hmin[B] at offsets [B][S][3] with weights [B][S]: err[B]; with
+ * parts != NULL also (e_phi, e_h) [B][2]; with dt, dalpha non-NULL
+ * d err / d t_k, d err / d alpha_k [B][KM].  Synchronizes the stream. */
 demag_status demag_quad_judge(demag_ctx *ctx, int32_t B, const int32_t *grids, const double *hmin,
-                              const int32_t *sentinels, int32_t S, const double *t, const double *alpha,
-                              const int32_t *R, int32_t KM, double *err, double *dt, double *dalpha);
+                              const int32_t *sentinels, const double *weights, int32_t S, const double *t,
+                              const double *alpha, const int32_t *R, int32_t KM, double *err, double *parts,
+                              double *dt, double *dalpha);
+/* Certificate of the rule (host t, alpha of length M, scaled domain) on the
+ * grid (physical; scaled to unit longest extent): err[0] = e_phi,
+ * err[1] = e_h (host).  Synchronizes the stream. */
+demag_status demag_quad_certify(demag_ctx *ctx, const demag_grid *grid, int32_t M, const double *t,
+                                const double *alpha, double err[2]);
 /* Levenberg-Marquardt fit of B cases' outputs (rule parametrization of
  * demag_quad_rules) against the reference rule on their grids [B][3], cell
- * sizes hmin[B] and sentinels [B][S][3] (S <= 256), R[B] nodes (16..32):
- * `iters` damped Gauss-Newton steps in u_k = 0.45 tanh(y_k),
+ * sizes hmin[B], offsets [B][S][3] and weights [B][S] (S <= 256), R[B]
+ * nodes (16..32): `iters` damped Gauss-Newton steps on the judge's residuals
+ * r_(s,c) = sqrt(w_s m_c / D_c) (K - K_ref)_c(J_s) in u_k = 0.45 tanh(y_k),
  * v_k = tanh(y_{32+k}) (projected onto |u| <= 0.44, |v| <= 0.99) from y0
  * ([B][65] device, NULL = zeros, the plain base rule) with initial damping
  * mu0.  Device outputs: yout [B][65] (fitted outputs; slot 64 = log10 of the
- * fitted error), xout [B][64] (u, v in double; may be NULL), H [B][64][64]
+ * fitted err), xout [B][64] (u, v in double; may be NULL), H [B][64][64]
  * (J^T J / err^2 at the fit, zero outside the active outputs; may be NULL),
  * t, alpha [B][32] (the fitted rule, zero past R), err[B].  Synchronizes
  * the stream. */
 demag_status demag_quad_fit(demag_ctx *ctx, int32_t B, const int32_t *grids, const double *hmin,
-                            const int32_t *sentinels, int32_t S, const int32_t *R, const float *y0,
-                            int32_t iters, double mu0, float *yout, double *xout, float *H, double *t,
-                            double *alpha, double *err);
+                            const int32_t *sentinels, const double *weights, int32_t S, const int32_t *R,
+                            const float *y0, int32_t iters, double mu0, float *yout, double *xout, float *H,
+                            double *t, double *alpha, double *err);
 /* Training loss and its output gradient for network outputs y [B][65]
  * against fits (targets [B][65] = demag_quad_fit's yout, xfit [B][64],
  * H [B][64][64]):
@@ -395,20 +423,41 @@ demag_status demag_quad_train(demag_ctx *ctx, float *params, float *adam_m, floa
                               const float *targets, const double *xfit, const float *H, const int32_t *R,
                               int32_t count, int32_t steps, int32_t batch, int32_t step0, float lr,
                               float lambda, float *loss_host);
-/* Rule for one grid (n host[3], cell size hmin, fit offsets [S][3] with
- * S <= 256 and check offsets [Sc][3], device) at tolerance tol: features
- * [17][6] (device) for R' = 16..32 in order; the smallest R' with predicted
- * log10 error <= log10 tol is polished with fit_iters Levenberg-Marquardt
- * steps on the fit offsets (from the network's proposal and from the plain
- * base rule; the better one is kept) and judged on the check offsets; if it misses tol, R' + 4,
- * R' + 8, ... (up to 32) follow, and if none meets tol the sinc rule with
- * the step of Thm. sinc_theo and 64 nodes is returned (*fell_back = 1).
- * Host outputs: t_out, alpha_out (capacity 64), *R_out, *judged (error of
- * the last rule judged), *predicted (log10, of the first pick), *fell_back. */
-demag_status demag_quad_predict(demag_ctx *ctx, const float *params, const float *features,
-                                const int32_t n[3], double hmin, const int32_t *sentinels, int32_t S,
-                                const int32_t *check, int32_t Sc, double tol, int32_t fit_iters, double *t_out, double *alpha_out,
-                                int32_t *R_out, double *judged, double *predicted, int32_t *fell_back);
+
+/* Modes of demag_quad_predict. */
+typedef enum {
+  DEMAG_PREDICT_NETWORK = 0,           /* R' from the error head, fits from the plain base rule */
+  DEMAG_PREDICT_NETWORK_PROPOSAL = 1,  /* R' from the error head, fits from the network's proposal */
+  DEMAG_PREDICT_SEARCH = 2             /* no network: bisection over R', fits from the plain rule */
+} demag_predict_mode;
+
+/* Result of demag_quad_predict (host). */
+typedef struct {
+  int32_t R;          /* nodes of the returned rule (64 if fell back) */
+  int32_t fell_back;  /* 1: the theorem-step rule with 64 nodes */
+  int32_t fits;       /* Levenberg-Marquardt fits run */
+  int32_t mode;
+  double err_phi;     /* certificate of the returned rule */
+  double err_h;
+  double predicted;   /* network's log10 error for its first pick (NaN in the search mode) */
+  double seconds;     /* wall time of the call */
+  double t[64];       /* nodes, scaled domain (zero past R) */
+  double alpha[64];
+} demag_quad_result;
+
+/* Shortened rule for a grid with cubic cells (DEMAG_E_UNSUPPORTED otherwise)
+ * at tolerance tol on both certificates.  The library computes the
+ * network's inputs and the fit's offsets and weights itself.  Per mode (see
+ * demag_predict_mode) candidate rules get fit_iters Levenberg-Marquardt steps
+ * on the weighted offsets and are certified; the network modes start at the
+ * smallest R' whose predicted log10 error is <= log10 tol and step R' by 1 up
+ * to 32 on a miss, the search mode bisects R' = 16..32.  If no candidate
+ * meets tol the sinc rule with the step of Thm. sinc_theo and 64 nodes is
+ * certified and returned (fell_back = 1), and if that misses tol too the
+ * call returns DEMAG_E_ACCURACY with *out filled.  params (device) may be
+ * NULL in the search mode. */
+demag_status demag_quad_predict(demag_ctx *ctx, const float *params, const demag_grid *grid, double tol,
+                                int32_t fit_iters, int32_t mode, demag_quad_result *out);
 
 /* The bfloat16 split used by DEMAG_BF16X2/X3 on the device, exposed for
  * checking: x (device, count floats) -> parts (device, [nparts][count]

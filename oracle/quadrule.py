@@ -3,31 +3,40 @@
 TEST INFRASTRUCTURE ONLY (see the package header).
 
 The node-proposal network is an addition on top of the paper's method.  Its
-outputs modify a base rule, and a judge measures the resulting kernel error:
+outputs modify a base rule, and a judge measures the resulting operator error:
 
   base rule   the sinc rule of Cor. kron_op with R' nodes and c0 = 2.15,
-              theta = c0 ln(R')/R', t_k = k theta, alpha_k = 2 theta cosh t_k sinh^2 t_k
-              (a least-squares fit of R' nodes and weights on the judge's
-              residuals lands close to this rule, with end corrections of a
-              few percent; the network learns such corrections);
+              theta = c0 ln(R')/R', t_k = k theta, alpha_k = 2 theta cosh t_k sinh^2 t_k;
   offsets     t'_k = t_k + 0.45 theta tanh(y_k),
               alpha'_k = 2 theta cosh t'_k sinh^2 t'_k exp(tanh(y_{32+k})),  k < R'
               (y: network output; the weight follows its node, so moving a
               node keeps the trapezoid weight of the substituted integrand);
   reference   the sinc rule with the step of Thm. sinc_theo and 96 nodes;
-  fallback    the same with 64 nodes (accurate to ~1e-9 up to 1024 cells);
-  judge       at the sentinel offsets J of the grid, the nine kernel values
-              (potential K^x, K^y, K^z and field factors of h_p <- m_q for
-              p <= q, Cor. kron_op with the derivative factors) of the rule
-              are compared with those of a reference rule:
-              err = sqrt( mean_J |K'(J) - K_ref(J)|^2 / |K_ref(J)|^2 );
+  fallback    the same with 64 nodes;
+  kernels     at an offset J, nine values: the potential kernels K^x, K^y,
+              K^z (Cor. kron_op) and the field kernels F_pq of h_p <- m_q for
+              p <= q (the same with the derivative factors; F_pq = F_qp);
+  certificate the relative Frobenius-norm error of the discrete operators,
+              separately for the potential P (3N -> N) and the field H
+              (3N -> 3N), against the reference rule:
+                e_phi^2 = sum_J w(J) sum_q dK^q(J)^2 / sum_J w(J) sum_q K^q_ref(J)^2,
+                e_h^2   = sum_J w(J) sum_pq m_pq dF_pq(J)^2 / (same with F_ref),
+              over every offset of the grid, w(J) = prod_d (n_d - |J_d|)
+              (the number of cell pairs at offset J), m_pq = 1 on the diagonal
+              and 2 off it.  Since |A|_F^2 = sum_ij A_ij^2, this is the exact
+              relative L2 error of the outputs averaged over inputs with
+              independent, equal-variance cell values;
+  judge       the same sums over a set of sampled offsets J_s with weights
+              w_s (``inputs.fit_offsets``: the near block exactly, shells of
+              far offsets by representatives): err = sqrt(e_phi^2 + e_h^2);
   fit         per grid, damped Gauss-Newton (Levenberg-Marquardt) on the
-              residual vector r = (K' - K_ref)(J) / sqrt(S |K_ref(J)|^2)
-              (|r| = err) in u_k = 0.45 tanh(y_k), v_k = tanh(y_{32+k})
-              (k < R'; t'_k = t_k + theta u_k, alpha' carries exp(v_k)): a step
-              solves (A + mu diag A) d = -J^T r with A = J^T J, is projected
-              onto |u| <= 0.44, |v| <= 0.99 (the range the outputs reach), and
-              is kept when it lowers err (mu / 3), else mu * 4.  The fitted
+              residual vector r_(s,c) = sqrt(w_s m_c / D_c) dK_c(J_s) (|r| =
+              err; D_c the reference's weighted sum of its class) in
+              u_k = 0.45 tanh(y_k), v_k = tanh(y_{32+k}) (k < R'; t'_k =
+              t_k + theta u_k, alpha' carries exp(v_k)): a step solves
+              (A + mu diag A) d = -J^T r with A = J^T J, is projected onto
+              |u| <= 0.44, |v| <= 0.99 (the range the outputs reach), and is
+              kept when it lowers err (mu / 3), else mu * 4.  The fitted
               outputs y = atanh(u / 0.45), atanh(v) are the network's training
               targets.
 """
@@ -90,15 +99,28 @@ def kernel_values(n, h, t, alpha, J):
     return out
 
 
-def judge(n, h, t, alpha, ref, J):
-    """err of the rule (t, alpha) against reference kernel values ``ref``."""
+# multiplicity of each of the nine kernel values in the operator's Frobenius
+# norm (F_pq = F_qp for p != q counts twice)
+MULT = np.array([1, 1, 1, 1, 1, 1, 2, 2, 2], dtype=np.float64)
+
+
+def judge_parts(n, h, t, alpha, ref, J, w):
+    """(e_phi, e_h) of the rule (t, alpha) against reference kernel values
+    ``ref`` at offsets J with weights w."""
     K = kernel_values(n, h, t, alpha, J)
-    num = np.sum((K - ref) ** 2, axis=1)
-    den = np.sum(ref ** 2, axis=1)
-    return float(np.sqrt(np.mean(num / den)))
+    w = np.asarray(w, dtype=np.float64)[:, None]
+    d2 = w * (K - ref) ** 2 * MULT
+    r2 = w * np.asarray(ref) ** 2 * MULT
+    return float(np.sqrt(d2[:, :3].sum() / r2[:, :3].sum())), float(np.sqrt(d2[:, 3:].sum() / r2[:, 3:].sum()))
 
 
-def judge_grad_fd(n, h, t, alpha, ref, J, rel=1e-6):
+def judge(n, h, t, alpha, ref, J, w):
+    """err = sqrt(e_phi^2 + e_h^2) of the rule (t, alpha) at weighted offsets."""
+    ep, eh = judge_parts(n, h, t, alpha, ref, J, w)
+    return float(np.hypot(ep, eh))
+
+
+def judge_grad_fd(n, h, t, alpha, ref, J, w, rel=1e-6):
     """Central differences of err with respect to t_k and alpha_k."""
     t = np.asarray(t, dtype=np.float64)
     alpha = np.asarray(alpha, dtype=np.float64)
@@ -109,33 +131,62 @@ def judge_grad_fd(n, h, t, alpha, ref, J, rel=1e-6):
         tp, tm = t.copy(), t.copy()
         tp[k] += dt
         tm[k] -= dt
-        gt[k] = (judge(n, h, tp, alpha, ref, J) - judge(n, h, tm, alpha, ref, J)) / (2 * dt)
+        gt[k] = (judge(n, h, tp, alpha, ref, J, w) - judge(n, h, tm, alpha, ref, J, w)) / (2 * dt)
         da = rel * abs(alpha[k])
         ap, am = alpha.copy(), alpha.copy()
         ap[k] += da
         am[k] -= da
-        ga[k] = (judge(n, h, t, ap, ref, J) - judge(n, h, t, am, ref, J)) / (2 * da)
+        ga[k] = (judge(n, h, t, ap, ref, J, w) - judge(n, h, t, am, ref, J, w)) / (2 * da)
     return gt, ga
 
 
-def residuals(n, h, t, alpha, ref, J):
+def residuals(n, h, t, alpha, ref, J, w):
     """Residual vector whose 2-norm is the judge's err: rows (J, component)."""
     K = kernel_values(n, h, t, alpha, J)
-    den = np.sum(ref ** 2, axis=1)
-    return ((K - ref) / np.sqrt(den * len(J))[:, None]).ravel()
+    w = np.asarray(w, dtype=np.float64)[:, None]
+    ref = np.asarray(ref)
+    D_phi = (w * ref[:, :3] ** 2).sum()
+    D_h = (w * ref[:, 3:] ** 2 * MULT[3:]).sum()
+    scale = np.sqrt(w * MULT[None, :] / np.r_[np.full(3, D_phi), np.full(6, D_h)][None, :])
+    return ((K - ref) * scale).ravel()
+
+
+def certify(n, h, t, alpha, t_ref=None, a_ref=None):
+    """Exact (e_phi, e_h) of the rule (t, alpha) over every offset of the grid
+    n (cell sizes h), against the reference rule (default: reference_rule of
+    the smallest cell).  Full kernel tensors: small grids only."""
+    if t_ref is None:
+        t_ref, a_ref = reference_rule(min(h))
+    types = [sinc.phi_types(q) for q in range(3)] + [sinc.field_types(p, q) for p, q in PAIRS]
+
+    def tensors(tt, aa):
+        tau = np.sinh(np.asarray(tt, dtype=np.float64))
+        F = [sinc.scaled_factors(n[d], h[d], tau, aa)[:, :, n[d] - 1:] for d in range(3)]   # J >= 0
+        out = []
+        for ty in types:
+            A = (F[2][ty[2]][:, :, None] * F[1][ty[1]][:, None, :]).reshape(tau.size, -1)
+            out.append(np.tensordot(A, F[0][ty[0]], axes=([0], [0])).reshape(n[2], n[1], n[0]))
+        return out
+
+    c = [np.array([(nd - j) * (1.0 if j == 0 else 2.0) for j in range(nd)]) for nd in n]
+    W = c[2][:, None, None] * c[1][None, :, None] * c[0][None, None, :]
+    K, R = tensors(t, alpha), tensors(t_ref, a_ref)
+    num = [m * np.sum(W * (a - b) ** 2) for a, b, m in zip(K, R, MULT)]
+    den = [m * np.sum(W * b ** 2) for b, m in zip(R, MULT)]
+    return float(np.sqrt(sum(num[:3]) / sum(den[:3]))), float(np.sqrt(sum(num[3:]) / sum(den[3:])))
 
 
 U_MAX, V_MAX = 0.44, 0.99
 
 
-def lm_step(n, h, x, R, ref, J, mu, rel=1e-6):
+def lm_step(n, h, x, R, ref, J, w, mu, rel=1e-6):
     """One damped Gauss-Newton step from x = (u_0..u_{R-1}, v_0..v_{R-1}) (the
     Jacobian by central differences), projected onto the output range.
     Returns (x + d, err(x), err(x + d))."""
     x = np.asarray(x, dtype=np.float64)
 
     def res(z):
-        return residuals(n, h, *rule_from_uv(z[:R], z[R:], R), ref, J)
+        return residuals(n, h, *rule_from_uv(z[:R], z[R:], R), ref, J, w)
 
     r0 = res(x)
     Jac = np.empty((r0.size, 2 * R))
@@ -153,13 +204,13 @@ def lm_step(n, h, x, R, ref, J, mu, rel=1e-6):
     return x1, float(np.linalg.norm(r0)), float(np.linalg.norm(res(x1)))
 
 
-def lm_fit(n, h, x0, R, ref, J, iters, mu0=1e-3):
+def lm_fit(n, h, x0, R, ref, J, w, iters, mu0=1e-3):
     """Levenberg-Marquardt iterations from x0 (accept when err drops)."""
     x = np.asarray(x0, dtype=np.float64).copy()
     mu = mu0
     err = None
     for _ in range(iters):
-        x1, e0, e1 = lm_step(n, h, x, R, ref, J, mu)
+        x1, e0, e1 = lm_step(n, h, x, R, ref, J, w, mu)
         err = e0 if err is None else err
         if e1 < err:
             x, err, mu = x1, e1, max(mu / 3.0, 1e-12)

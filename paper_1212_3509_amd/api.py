@@ -35,6 +35,14 @@ class Quad(C.Structure):
                 ("t", C.POINTER(C.c_double)), ("alpha", C.POINTER(C.c_double))]
 
 
+class QuadResult(C.Structure):
+    _fields_ = [("R", C.c_int32), ("fell_back", C.c_int32), ("fits", C.c_int32), ("mode", C.c_int32),
+                ("err_phi", C.c_double), ("err_h", C.c_double), ("predicted", C.c_double), ("seconds", C.c_double),
+                ("t", C.c_double * 64), ("alpha", C.c_double * 64)]
+
+
+PREDICT_MODES = {"network": 0, "network_proposal": 1, "search": 2}
+
 _P = C.c_void_p
 _SIGS = {
     "demag_last_error": (C.c_char_p, []),
@@ -66,15 +74,19 @@ _SIGS = {
     "demag_mlp_backward": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int32, _P, _P]),
     "demag_adam_step": (C.c_int, [_P, _P, _P, _P, _P, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
                                   C.c_float]),
-    "demag_quad_judge": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.c_int32, _P, _P, _P, C.c_int32, _P, _P, _P]),
+    "demag_quad_judge": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, C.c_int32, _P, _P, _P, C.c_int32, _P, _P, _P,
+                                   _P]),
+    "demag_quad_certify": (C.c_int, [_P, C.POINTER(Grid), C.c_int32, _P, _P, _P]),
+    "demag_quad_offsets": (C.c_int, [_P, C.c_int32, _P, _P]),
+    "demag_quad_features": (C.c_int, [_P, C.c_double, C.c_double, C.c_int32, _P]),
     "demag_quad_rules": (C.c_int, [_P, _P, _P, C.c_int32, _P, _P]),
-    "demag_quad_fit": (C.c_int, [_P, C.c_int32, _P, _P, _P, C.c_int32, _P, _P, C.c_int32, C.c_double, _P, _P, _P,
-                                 _P, _P, _P]),
+    "demag_quad_fit": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, C.c_int32, _P, _P, C.c_int32, C.c_double, _P, _P,
+                                 _P, _P, _P, _P]),
     "demag_quad_loss_grad": (C.c_int, [_P, _P, _P, _P, _P, _P, C.c_int32, C.c_float, _P, _P]),
     "demag_quad_train": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
                                    C.c_float, C.c_float, _P]),
-    "demag_quad_predict": (C.c_int, [_P, _P, _P, _P, C.c_double, _P, C.c_int32, _P, C.c_int32, C.c_double,
-                                     C.c_int32, _P, _P, _P, _P, _P, _P]),
+    "demag_quad_predict": (C.c_int, [_P, _P, C.POINTER(Grid), C.c_double, C.c_int32, C.c_int32,
+                                     C.POINTER(QuadResult)]),
     "demag_prepare_structured": (C.c_int, [_P, _P]),
     "demag_apply_columns": (C.c_int, [_P, _P, _P, _P, _P]),
     "demag_apply_columns_noalloc": (C.c_int, [_P, _P, _P, _P, _P]),
@@ -106,6 +118,24 @@ def library():
 
 def exported_symbols():
     return list(_SIGS)
+
+
+def quad_offsets(n, count: int = 256):
+    """Offsets [count][3] (int32) and weights [count] (float64) of the judge
+    on grid n, computed by the library (host only, no device needed)."""
+    J = np.zeros((count, 3), dtype=np.int32)
+    w = np.zeros(count, dtype=np.float64)
+    _check(library().demag_quad_offsets((C.c_int32 * 3)(*n), count, J.ctypes.data, w.ctypes.data),
+           "demag_quad_offsets")
+    return J, w
+
+
+def quad_features(n, h, log10_tol, R):
+    """Network input (float32 [6]) of one case, computed by the library."""
+    x = np.zeros(6, dtype=np.float32)
+    _check(library().demag_quad_features((C.c_int32 * 3)(*n), h, log10_tol, R, x.ctypes.data),
+           "demag_quad_features")
+    return x
 
 
 def _check(status: int, where: str):
@@ -457,27 +487,46 @@ class Context:
         _check(library().demag_quad_rules(self.handle, _ptr(y), _ptr(R), B, _ptr(t), _ptr(a)), "demag_quad_rules")
         return t, a
 
-    def quad_judge(self, grids, hmin, sent, t, alpha, R, grad=False):
-        """grids int32 [B][3], hmin float64 [B], sent int32 [B][S][3], t/alpha
-        float64 [B][KM], R int32 [B] (all CUDA).  Returns err [B] (and the
-        gradients [B][KM] with respect to t and alpha)."""
+    def quad_judge(self, grids, hmin, sent, weights, t, alpha, R, grad=False, parts=False):
+        """grids int32 [B][3], hmin float64 [B], sent int32 [B][S][3], weights
+        float64 [B][S], t/alpha float64 [B][KM], R int32 [B] (all CUDA).
+        Returns err [B] (plus (e_phi, e_h) [B][2] with parts, and the
+        gradients [B][KM] with respect to t and alpha with grad)."""
         import torch
         B, S = int(sent.shape[0]), int(sent.shape[1])
         KM = int(t.shape[1])
         err = torch.empty(B, dtype=torch.float64, device=t.device)
+        pp = torch.empty((B, 2), dtype=torch.float64, device=t.device) if parts else None
         dt = torch.empty((B, KM), dtype=torch.float64, device=t.device) if grad else None
         da = torch.empty((B, KM), dtype=torch.float64, device=t.device) if grad else None
         self.use_current_stream()
-        _check(library().demag_quad_judge(self.handle, B, _ptr(grids), _ptr(hmin), _ptr(sent), S, _ptr(t),
-                                          _ptr(alpha), _ptr(R), KM, _ptr(err), _ptr(dt), _ptr(da)),
-               "demag_quad_judge")
-        return (err, dt, da) if grad else err
+        _check(library().demag_quad_judge(self.handle, B, _ptr(grids), _ptr(hmin), _ptr(sent), _ptr(weights), S,
+                                          _ptr(t), _ptr(alpha), _ptr(R), KM, _ptr(err), _ptr(pp), _ptr(dt),
+                                          _ptr(da)), "demag_quad_judge")
+        out = (err,)
+        if parts:
+            out += (pp,)
+        if grad:
+            out += (dt, da)
+        return out if len(out) > 1 else err
 
-    def quad_fit(self, grids, hmin, sent, R, y0=None, iters=30, mu0=1e-3, want_h=False):
+    def quad_certify(self, n, h, t, alpha):
+        """Certificate (e_phi, e_h) of the rule (host t, alpha, scaled domain)
+        on the grid n with cell sizes h (physical; scaled internally)."""
+        ta = np.ascontiguousarray(t, dtype=np.float64)
+        aa = np.ascontiguousarray(alpha, dtype=np.float64)
+        g = Grid((C.c_int32 * 3)(*n), (C.c_double * 3)(*h))
+        err = np.zeros(2)
+        self.use_current_stream()
+        _check(library().demag_quad_certify(self.handle, C.byref(g), len(ta), ta.ctypes.data, aa.ctypes.data,
+                                            err.ctypes.data), "demag_quad_certify")
+        return float(err[0]), float(err[1])
+
+    def quad_fit(self, grids, hmin, sent, weights, R, y0=None, iters=30, mu0=1e-3, want_h=False):
         """Levenberg-Marquardt fit of the outputs per case (all CUDA: grids int32
-        [B][3], hmin float64 [B], sent int32 [B][S][3], R int32 [B], y0 float32
-        [B][65] or None).  Returns (y [B][65], t [B][32], alpha [B][32], err [B]),
-        plus (x [B][64], H [B][64][64]) with want_h."""
+        [B][3], hmin float64 [B], sent int32 [B][S][3], weights float64 [B][S],
+        R int32 [B], y0 float32 [B][65] or None).  Returns (y [B][65], t [B][32],
+        alpha [B][32], err [B]), plus (x [B][64], H [B][64][64]) with want_h."""
         import torch
         B, S = int(sent.shape[0]), int(sent.shape[1])
         dev = sent.device
@@ -488,9 +537,9 @@ class Context:
         x = torch.empty((B, 64), dtype=torch.float64, device=dev) if want_h else None
         H = torch.empty((B, 64, 64), dtype=torch.float32, device=dev) if want_h else None
         self.use_current_stream()
-        _check(library().demag_quad_fit(self.handle, B, _ptr(grids), _ptr(hmin), _ptr(sent), S, _ptr(R), _ptr(y0),
-                                        iters, mu0, _ptr(y), _ptr(x), _ptr(H), _ptr(t), _ptr(a), _ptr(err)),
-               "demag_quad_fit")
+        _check(library().demag_quad_fit(self.handle, B, _ptr(grids), _ptr(hmin), _ptr(sent), _ptr(weights), S,
+                                        _ptr(R), _ptr(y0), iters, mu0, _ptr(y), _ptr(x), _ptr(H), _ptr(t), _ptr(a),
+                                        _ptr(err)), "demag_quad_fit")
         return (y, t, a, err, x, H) if want_h else (y, t, a, err)
 
     def quad_loss_grad(self, y, targets, xfit, H, R, lam=0.1):
@@ -514,23 +563,24 @@ class Context:
                                           loss.ctypes.data), "demag_quad_train")
         return loss[:steps]
 
-    def quad_predict(self, params, features, n, hmin, sent, check, tol, fit_iters=60):
-        """features: CUDA float32 [17][6] for R' = 16..32; sent, check: CUDA
-        int32 [S][3] fit and check offsets.  Returns dict(t, alpha, R, judged,
-        predicted, fell_back)."""
-        t = np.zeros(64)
-        a = np.zeros(64)
-        R, fb = C.c_int32(), C.c_int32()
-        judged, pred = C.c_double(), C.c_double()
-        n3 = (C.c_int32 * 3)(*n)
+    def quad_predict(self, params, n, h, tol, fit_iters=200, mode="network"):
+        """Shortened rule for grid n with cubic cells h at tolerance tol (both
+        certificates).  params: CUDA float32 network parameters (None in the
+        "search" mode).  Returns a dict: t, alpha, R, fell_back, fits,
+        err_phi, err_h, predicted, seconds, accuracy_met (False when even the
+        fallback rule misses tol: DEMAG_E_ACCURACY)."""
+        g = Grid((C.c_int32 * 3)(*n), (C.c_double * 3)(*((h,) * 3 if np.isscalar(h) else h)))
+        res = QuadResult()
         self.use_current_stream()
-        _check(library().demag_quad_predict(self.handle, _ptr(params), _ptr(features), n3, hmin, _ptr(sent),
-                                            int(sent.shape[0]), _ptr(check), int(check.shape[0]), tol, fit_iters,
-                                            t.ctypes.data, a.ctypes.data,
-                                            C.byref(R), C.byref(judged), C.byref(pred), C.byref(fb)),
-               "demag_quad_predict")
-        return {"t": t[:R.value], "alpha": a[:R.value], "R": R.value, "judged": judged.value,
-                "predicted": pred.value, "fell_back": bool(fb.value)}
+        st = library().demag_quad_predict(self.handle, _ptr(params), C.byref(g), tol, fit_iters, PREDICT_MODES[mode],
+                                          C.byref(res))
+        if st not in (0, 5):
+            _check(st, "demag_quad_predict")
+        R = res.R
+        return {"t": np.array(res.t[:R]), "alpha": np.array(res.alpha[:R]), "R": R,
+                "fell_back": bool(res.fell_back), "fits": res.fits, "err_phi": res.err_phi, "err_h": res.err_h,
+                "judged": max(res.err_phi, res.err_h), "predicted": res.predicted, "seconds": res.seconds,
+                "accuracy_met": st == 0, "mode": mode}
 
     def bf16_split(self, x, nparts: int = 3):
         """Device split of a contiguous float32 CUDA tensor into bfloat16 bit

@@ -18,14 +18,21 @@
 //   alpha'_k = 2 theta cosh t'_k sinh^2 t'_k exp(tanh(y_{32+k}))
 // (the weight follows its node: the trapezoid weight of the substituted
 // integrand at the moved node, times a free factor).
-// Judge: at S sentinel offsets J, nine kernel values per rule
+// Judge: at S sampled offsets J_s with weights w_s, nine kernel values per rule
 //   [K^x, K^y, K^z, F_xx, F_yy, F_zz, F_xy, F_xz, F_yz]
 //   K^q  = W prod_d f_d with f = X along q, E elsewhere;
 //   F_pq = the same for h_p <- m_q with axis p differentiated (X -> P = -X',
 //          E -> Q = 2 tau^2 X), W = alpha / (2 pi^(3/2)),
-// err = sqrt(mean_J |K - K_ref|^2 / |K_ref|^2), K_ref from the sinc rule with
-// the step of Thm. sinc_theo and 96 nodes.
-// Fit: residuals r = (K - K_ref)(J) / sqrt(S |K_ref(J)|^2) (|r| = err);
+// against K_ref from the sinc rule with the step of Thm. sinc_theo and 96
+// nodes:  e_phi^2 = sum_s w_s sum_{c<3} dK_c^2 / sum_s w_s sum_{c<3} K_ref,c^2,
+// e_h^2 the same over the field values with multiplicity m_c (2 for the
+// off-diagonal F_pq, which stand for F_pq and F_qp), err^2 = e_phi^2 + e_h^2.
+// With w_s the number of cell pairs each sampled offset stands for, these
+// estimate the relative Frobenius-norm errors of the discrete potential and
+// field operators; the certificate (k_cert_*) computes them exactly, over
+// every offset of the grid.
+// Fit: residuals r_(s,c) = sqrt(w_s m_c / D_c) (K - K_ref)_c(J_s) (|r| = err,
+// D_c = the reference's weighted sum of squares of c's class);
 // Levenberg-Marquardt steps (A + mu diag A) d = -J^T r, A = J^T J, in
 // u_k = 0.45 tanh(y_k), v_k = tanh(y_{32+k}) (k < R'; t'_k = t_k + theta u_k,
 // alpha'_k carries exp(v_k)), projected onto |u| <= 0.44, |v| <= 0.99 and
@@ -42,6 +49,8 @@
 // fitted outputs (clipped to [-3, 3]) when no H is given.
 #include "internal.h"
 
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 
@@ -270,25 +279,41 @@ __global__ __launch_bounds__(128) void k_judge_values(const int *__restrict__ gr
   for (int c = 0; c < kNcomp; ++c) K[(size_t(b) * S + s) * kNcomp + c] = acc[c];
 }
 
-// err per case and the scaled residuals (K - K_ref)/|K_ref|^2 per sentinel.
-__global__ void k_judge_err(const double *__restrict__ K, const double *__restrict__ Kref, int B, int S,
-                            double *__restrict__ err, double *__restrict__ resid) {
+// multiplicity of each kernel value in the operator's Frobenius norm
+__host__ __device__ constexpr double kmult(int c) { return c >= 6 ? 2.0 : 1.0; }
+
+// err per case (and e_phi, e_h in parts[B][2] if given) and the residual
+// weights resid = w_s m_c / D_c (K - K_ref) per offset and value.
+__global__ void k_judge_err(const double *__restrict__ K, const double *__restrict__ Kref,
+                            const double *__restrict__ wts, int B, int S, double *__restrict__ err,
+                            double *__restrict__ parts, double *__restrict__ resid) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= B) return;
-  double sum = 0.0;
+  double num[2] = {0.0, 0.0}, den[2] = {0.0, 0.0};
   for (int s = 0; s < S; ++s) {
+    const double w = wts[size_t(b) * S + s];
     const double *k = K + (size_t(b) * S + s) * kNcomp;
     const double *r = Kref + (size_t(b) * S + s) * kNcomp;
-    double num = 0.0, den = 0.0;
     for (int c = 0; c < kNcomp; ++c) {
-      num += (k[c] - r[c]) * (k[c] - r[c]);
-      den += r[c] * r[c];
+      const int cl = c < 3 ? 0 : 1;
+      num[cl] += w * kmult(c) * (k[c] - r[c]) * (k[c] - r[c]);
+      den[cl] += w * kmult(c) * r[c] * r[c];
     }
-    sum += num / den;
-    if (resid)
-      for (int c = 0; c < kNcomp; ++c) resid[(size_t(b) * S + s) * kNcomp + c] = (k[c] - r[c]) / den;
   }
-  err[b] = sqrt(sum / S);
+  const double ep = sqrt(num[0] / den[0]), eh = sqrt(num[1] / den[1]);
+  err[b] = sqrt(ep * ep + eh * eh);
+  if (parts) {
+    parts[2 * size_t(b)] = ep;
+    parts[2 * size_t(b) + 1] = eh;
+  }
+  if (resid)
+    for (int s = 0; s < S; ++s) {
+      const double w = wts[size_t(b) * S + s];
+      for (int c = 0; c < kNcomp; ++c) {
+        const size_t i = (size_t(b) * S + s) * kNcomp + c;
+        resid[i] = w * kmult(c) / den[c < 3 ? 0 : 1] * (K[i] - Kref[i]);
+      }
+    }
 }
 
 // d err / d t'_k and d err / d alpha'_k: [B][KM].
@@ -323,12 +348,122 @@ __global__ __launch_bounds__(128) void k_judge_grad(const int *__restrict__ grid
         gt += r[q] * W * ch * dprod;
       }
     }
-    const double scale = 1.0 / (S * err[b]);
+    const double scale = 1.0 / err[b];
     gt *= scale;
     ga *= scale;
   }
   dt[idx] = gt;
   dalpha[idx] = ga;
+}
+
+// ------------------------------------------------------------------ certificate
+// Weighted sums over the offsets J >= 0 of a grid of the squared kernel
+// differences between a rule (M nodes) and the reference (96 nodes), and of
+// the reference's squared kernels, for the potential values and the field
+// values (with multiplicity), with the weights c_x(Jx) c_y(Jy) c_z(Jz),
+// c_d(j) = (n_d - j) (1 if j == 0 else 2): the number of cell pairs an
+// offset and its sign images stand for.  Per axis the offsets are given as
+// sample positions with weights (every j below kCertExact with c_d(j); past
+// it, blocks of cells represented by their midpoints with the blocks' summed
+// weights), so grids up to kCertExact cells per axis are summed exactly.
+constexpr int kCertExact = 512;
+
+// Factor tables at the sample positions: T[type][k][i] = w_k^(1/3) f_type(pos_i)
+// for the KT = M + 96 nodes (rule first).
+__global__ void k_cert_factors(const int *__restrict__ pos, int np, const double *__restrict__ tau,
+                               const double *__restrict__ wcr, int KT, double h, double *__restrict__ T) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, k = blockIdx.y;
+  if (i >= np) return;
+  double f[4], df[4];
+  factors_1d(pos[i], tau[k], h, f, df);
+  for (int t = 0; t < 4; ++t) T[(size_t(t) * KT + k) * np + i] = wcr[k] * f[t];
+}
+
+// One workgroup per (y, z) sample pair at a time (grid-stride over pairs),
+// threads over the x samples; the y-z factor products of the six (type_y,
+// type_z) combinations the nine values need are staged in LDS per pair.
+// partial[block][4] = the block's weighted sums (phi diff, phi ref, field
+// diff, field ref).
+__global__ __launch_bounds__(256) void k_cert_sums(const double *__restrict__ Tx, const double *__restrict__ Ty,
+                                                   const double *__restrict__ Tz, const double *__restrict__ wx,
+                                                   const double *__restrict__ wy, const double *__restrict__ wz,
+                                                   int npx, int npy, int npz, int KT, int M,
+                                                   double *__restrict__ partial) {
+  extern __shared__ double yz[];   // [6][KT]
+  __shared__ double red[4][256];
+  const int tid = threadIdx.x;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int pair = blockIdx.x; pair < npy * npz; pair += gridDim.x) {
+    const int iy = pair % npy, iz = pair / npy;
+    __syncthreads();
+    for (int k = tid; k < KT; k += blockDim.x) {
+      const double ey = Ty[(size_t(F_E) * KT + k) * npy + iy], xy = Ty[(size_t(F_X) * KT + k) * npy + iy];
+      const double py = Ty[(size_t(F_P) * KT + k) * npy + iy], qy = Ty[(size_t(F_Q) * KT + k) * npy + iy];
+      const double ez = Tz[(size_t(F_E) * KT + k) * npz + iz], xz = Tz[(size_t(F_X) * KT + k) * npz + iz];
+      const double pz = Tz[(size_t(F_P) * KT + k) * npz + iz];
+      yz[0 * KT + k] = ey * ez;   // K^x, F_xx
+      yz[1 * KT + k] = xy * ez;   // K^y, F_xy
+      yz[2 * KT + k] = ey * xz;   // K^z, F_xz
+      yz[3 * KT + k] = py * ez;   // F_yy
+      yz[4 * KT + k] = ey * pz;   // F_zz
+      yz[5 * KT + k] = qy * xz;   // F_yz
+    }
+    __syncthreads();
+    const double wyz = wy[iy] * wz[iz];
+    for (int ix = tid; ix < npx; ix += blockDim.x) {
+      double d[kNcomp], r[kNcomp];
+#pragma unroll
+      for (int c = 0; c < kNcomp; ++c) d[c] = r[c] = 0.0;
+      for (int k = 0; k < KT; ++k) {
+        const double e = Tx[(size_t(F_E) * KT + k) * npx + ix], x = Tx[(size_t(F_X) * KT + k) * npx + ix];
+        const double p = Tx[(size_t(F_P) * KT + k) * npx + ix], q = Tx[(size_t(F_Q) * KT + k) * npx + ix];
+        const double v[kNcomp] = {x * yz[k],          e * yz[KT + k],     e * yz[2 * KT + k],
+                                  p * yz[k],          e * yz[3 * KT + k], e * yz[4 * KT + k],
+                                  q * yz[KT + k],     q * yz[2 * KT + k], e * yz[5 * KT + k]};
+        if (k < M) {
+#pragma unroll
+          for (int c = 0; c < kNcomp; ++c) d[c] += v[c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < kNcomp; ++c) {
+            d[c] -= v[c];
+            r[c] += v[c];
+          }
+        }
+      }
+      const double w = wx[ix] * wyz;
+      acc[0] += w * (d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      acc[1] += w * (r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+      acc[2] += w * (d[3] * d[3] + d[4] * d[4] + d[5] * d[5] + 2.0 * (d[6] * d[6] + d[7] * d[7] + d[8] * d[8]));
+      acc[3] += w * (r[3] * r[3] + r[4] * r[4] + r[5] * r[5] + 2.0 * (r[6] * r[6] + r[7] * r[7] + r[8] * r[8]));
+    }
+  }
+  for (int i = 0; i < 4; ++i) red[i][tid] = acc[i];
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if (tid < st)
+      for (int i = 0; i < 4; ++i) red[i][tid] += red[i][tid + st];
+    __syncthreads();
+  }
+  if (tid < 4) partial[size_t(blockIdx.x) * 4 + tid] = red[tid][0];
+}
+
+// Sum of the per-block partials in a fixed order: out[4].
+__global__ __launch_bounds__(256) void k_cert_final(const double *__restrict__ partial, int nblk,
+                                                    double *__restrict__ out) {
+  __shared__ double red[4][256];
+  const int tid = threadIdx.x;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int b = tid; b < nblk; b += blockDim.x)
+    for (int i = 0; i < 4; ++i) acc[i] += partial[size_t(b) * 4 + i];
+  for (int i = 0; i < 4; ++i) red[i][tid] = acc[i];
+  __syncthreads();
+  for (int st = blockDim.x / 2; st > 0; st >>= 1) {
+    if (tid < st)
+      for (int i = 0; i < 4; ++i) red[i][tid] += red[i][tid + st];
+    __syncthreads();
+  }
+  if (tid < 4) out[tid] = red[tid][0];
 }
 
 // Output gradients of the supervised loss and per-case loss values.
@@ -377,10 +512,16 @@ struct FitLds {
   double g[kNP];
   double y[kNP], yc[kNP], d[kNP];
   double tp[kRmax], ap[kRmax], dty[kRmax], lat[kRmax], sa[kRmax];
-  double sig[kMaxS];
+  double isig[kMaxS][2];   // sqrt(w_s / D_phi), sqrt(w_s / D_h) per offset
+  double dsum[2];
   double err2, err_cur, mu;
   int ok;
 };
+
+// scale of the residual of value c at offset s: sqrt(w_s m_c / D_class(c))
+__device__ __forceinline__ double residual_scale(const FitLds &L, int s, int c) {
+  return c < 3 ? L.isig[s][0] : (c >= 6 ? 1.4142135623730950488 * L.isig[s][1] : L.isig[s][1]);
+}
 
 // node parameters of x = (u, v) (threads k < R): t', alpha' and the
 // derivatives the Jacobian needs
@@ -421,9 +562,9 @@ __device__ void fit_pass(FitLds &L, int b, int S, int R, double h, const int *__
       double f[3][4], df[3][4];
   #pragma unroll
     for (int d = 0; d < 3; ++d) factors_1d(J[d], tau, h, f[d], df[d]);
-      const double is = 1.0 / L.sig[s];
 #pragma unroll
       for (int c = 0; c < kNcomp; ++c) {
+        const double is = residual_scale(L, s, c);
         const int t0 = ftype(c, 0), t1 = ftype(c, 1), t2 = ftype(c, 2);
         const double prod = f[0][t0] * f[1][t1] * f[2][t2];
         const double v = W * prod;
@@ -451,7 +592,7 @@ __device__ void fit_pass(FitLds &L, int b, int S, int R, double h, const int *__
       if (rs < S) {
         double sum = 0.0;
         for (int kk = 0; kk < R; ++kk) sum += L.val[tid / kNcomp][c][kk];
-        r = (sum - Kref[(size_t(b) * S + rs) * kNcomp + c]) / L.sig[rs];
+        r = (sum - Kref[(size_t(b) * S + rs) * kNcomp + c]) * residual_scale(L, rs, c);
       }
       L.res[tid] = r;
     }
@@ -487,7 +628,7 @@ __device__ void fit_pass(FitLds &L, int b, int S, int R, double h, const int *__
 // Outputs: yout [B][65] (slot 64 = log10 err), t, alpha [B][32] (rule of
 // the fitted outputs, zero past R), err [B].
 __global__ __launch_bounds__(256) void k_quad_fit(const int *__restrict__ grids, const double *__restrict__ hmin,
-                                                  const int *__restrict__ sent, int S,
+                                                  const int *__restrict__ sent, const double *__restrict__ wts, int S,
                                                   const double *__restrict__ Kref, const int *__restrict__ Rv,
                                                   const float *__restrict__ y0, int iters, double mu0,
                                                   float *__restrict__ yout, double *__restrict__ xout,
@@ -504,17 +645,37 @@ __global__ __launch_bounds__(256) void k_quad_fit(const int *__restrict__ grids,
     const double lim = tid < kRmax ? kUMax : kVMax;
     L.y[tid] = fmin(lim, fmax(-lim, tid < kRmax ? 0.45 * tanh(yv) : tanh(yv)));   // x = (u, v)
   }
+  // weighted sums of squares of the reference's potential and field values
   if (tid < S) {
-    double den = 0.0;
+    const double w = wts[size_t(b) * S + tid];
+    double dp = 0.0, dh = 0.0;
     for (int c = 0; c < kNcomp; ++c) {
       const double v = Kref[(size_t(b) * S + tid) * kNcomp + c];
-      den += v * v;
+      if (c < 3)
+        dp += v * v;
+      else
+        dh += kmult(c) * v * v;
     }
-    L.sig[tid] = sqrt(den * S);
+    L.isig[tid][0] = w * dp;
+    L.isig[tid][1] = w * dh;
   }
+  __syncthreads();
   if (tid == 0) {
+    double dp = 0.0, dh = 0.0;
+    for (int i = 0; i < S; ++i) {
+      dp += L.isig[i][0];
+      dh += L.isig[i][1];
+    }
+    L.dsum[0] = dp;
+    L.dsum[1] = dh;
     L.mu = mu0;
     L.err_cur = -1.0;
+  }
+  __syncthreads();
+  if (tid < S) {
+    const double w = wts[size_t(b) * S + tid];
+    L.isig[tid][0] = sqrt(w / L.dsum[0]);
+    L.isig[tid][1] = sqrt(w / L.dsum[1]);
   }
   __syncthreads();
   for (int it = 0; it < iters; ++it) {
@@ -680,16 +841,190 @@ demag_status reference_values(demag_ctx *ctx, const int *grids, const double *hm
   return DEMAG_OK;
 }
 
-demag_status launch_fit(demag_ctx *ctx, int B, const int *grids, const double *hmin, const int *sent, int S,
-                        const double *Kref, const int *R, const float *y0, int iters, double mu0, float *yout,
-                        double *xout, float *H, double *t, double *alpha, double *err) {
+demag_status launch_fit(demag_ctx *ctx, int B, const int *grids, const double *hmin, const int *sent,
+                        const double *wts, int S, const double *Kref, const int *R, const float *y0, int iters,
+                        double mu0, float *yout, double *xout, float *H, double *t, double *alpha, double *err) {
   const size_t lds = sizeof(FitLds);
   DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_quad_fit),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-  k_quad_fit<<<B, 256, lds, ctx->stream>>>(grids, hmin, sent, S, Kref, R, y0, iters, mu0, yout, xout, H, t, alpha,
-                                           err);
+  k_quad_fit<<<B, 256, lds, ctx->stream>>>(grids, hmin, sent, wts, S, Kref, R, y0, iters, mu0, yout, xout, H, t,
+                                           alpha, err);
   DEMAG_TRY_HIP(hipGetLastError());
   return DEMAG_OK;
+}
+
+// Offsets and weights of the fit on grid n (the recipe of the header
+// comment of demag_quad_offsets); false if count cannot hold the near block.
+bool fit_offsets_host(const int n[3], int count, int32_t *J, double *w) {
+  static const double dirs[12][3] = {{1, 0, 0},   {0, 1, 0},   {0, 0, 1},   {1, 1, 1},   {1, 1, 0},   {0, 1, 1},
+                                     {1, 0, 1},   {1, .5, .25}, {.5, 1, .25}, {.25, .5, 1}, {1, .25, .5}, {.5, .25, 1}};
+  std::vector<double> c[3], cum[3];
+  for (int d = 0; d < 3; ++d) {
+    c[d].resize(n[d]);
+    for (int j = 0; j < n[d]; ++j) c[d][j] = double((n[d] - j) * (j == 0 ? 1 : 2));
+    cum[d].assign(1, 0.0);
+    double acc = 0.0;
+    for (double v : c[d]) {
+      acc += v;
+      cum[d].push_back(acc);
+    }
+  }
+  int S = 0;
+  for (int z = 0; z < std::min(4, n[2]); ++z)
+    for (int y = 0; y < std::min(4, n[1]); ++y)
+      for (int x = 0; x < std::min(4, n[0]); ++x) {
+        if (S >= count) return false;
+        J[3 * S] = x;
+        J[3 * S + 1] = y;
+        J[3 * S + 2] = z;
+        w[S] = c[0][x] * c[1][y] * c[2][z];
+        ++S;
+      }
+  auto total = [&](int sv) {
+    return cum[0][std::min(sv, n[0])] * cum[1][std::min(sv, n[1])] * cum[2][std::min(sv, n[2])];
+  };
+  const int smax = std::max(n[0], std::max(n[1], n[2])) - 1;
+  const int G = std::min((count - S) / 8, std::max(0, smax - 3));
+  if (G > 0) {
+    std::vector<int> edges{4};
+    for (int g = 1; g < G; ++g)
+      edges.push_back(std::max(edges.back() + 1,
+                               int(std::nearbyint(4.0 * std::pow((smax + 1) / 4.0, double(g) / double(G))))));
+    edges.push_back(smax + 1);
+    std::vector<int> uniq;
+    for (int v : edges) {
+      v = std::min(v, smax + 1);
+      if (uniq.empty() || v != uniq.back()) uniq.push_back(v);
+    }
+    for (size_t g = 0; g + 1 < uniq.size(); ++g) {
+      const int lo = uniq[g], hi = uniq[g + 1];
+      const double wg = (total(hi) - total(lo)) / 8.0;
+      const int sg = int(std::nearbyint(std::sqrt(double(int64_t(lo) * (hi - 1)))));
+      for (int i = 0; i < 8; ++i) {
+        const double *u = dirs[(g + i) % 12];
+        for (int d = 0; d < 3; ++d) J[3 * S + d] = std::min(int(std::nearbyint(sg * u[d])), n[d] - 1);
+        w[S] = wg;
+        ++S;
+      }
+    }
+  }
+  for (; S < count; ++S) {
+    J[3 * S] = J[3 * S + 1] = J[3 * S + 2] = 0;
+    w[S] = 0.0;
+  }
+  return true;
+}
+
+// Network input of one case (the layout of demag_quad_features).
+void features_host(const int n[3], double h, double log10_tol, int R, float x[6]) {
+  const double nmax = double(std::max(n[0], std::max(n[1], n[2])));
+  for (int d = 0; d < 3; ++d) x[d] = float(double(n[d]) / nmax);
+  x[3] = float(std::log2(1.0 / h) / 6.0 - 1.0);
+  x[4] = float((log10_tol + 6.5) / 2.5);
+  x[5] = float((double(R) - 24.0) / 8.0);
+}
+
+// Sample positions and weights of one axis for the certificate.
+void cert_axis(int n, std::vector<int> &pos, std::vector<double> &w) {
+  pos.clear();
+  w.clear();
+  auto c = [n](int j) { return double((n - j) * (j == 0 ? 1 : 2)); };
+  for (int j = 0; j < std::min(n, kCertExact); ++j) {
+    pos.push_back(j);
+    w.push_back(c(j));
+  }
+  // octave [lo, 2 lo) in blocks of `blk` cells, blk = 4, 8, 16, ...
+  for (int lo = kCertExact, blk = 4; lo < n; lo *= 2, blk *= 2)
+    for (int b0 = lo; b0 < std::min(n, 2 * lo); b0 += blk) {
+      const int b1 = std::min(std::min(n, 2 * lo), b0 + blk);
+      double sw = 0.0;
+      for (int j = b0; j < b1; ++j) sw += c(j);
+      pos.push_back((b0 + b1 - 1) / 2);
+      w.push_back(sw);
+    }
+}
+
+// Certificate of the rule (t, alpha; M nodes, scaled domain) on grid n with
+// scaled cell sizes hs (cubic cells: the factor tables use hs[d] per axis):
+// out = (e_phi, e_h) against the reference rule of the smallest cell.
+demag_status certify_rule(demag_ctx *ctx, const int n[3], const double hs[3], int M, const double *t,
+                          const double *alpha, double out[2]) {
+  const int Mref = 96;
+  const int KT = M + Mref;
+  const double hmin = std::min(hs[0], std::min(hs[1], hs[2]));
+  std::vector<double> tau(KT), wcr(KT);
+  {
+    const double a = 2.0, bb = 0.25 * (0.5 * hmin) * (0.5 * hmin);
+    const double theta = std::log(2.0 * kPi * a * Mref / bb) / (a * Mref);
+    for (int k = 0; k < KT; ++k) {
+      double tk, ak;
+      if (k < M) {
+        tk = t[k];
+        ak = alpha[k];
+      } else {
+        tk = (k - M + 1) * theta;
+        const double sh = std::sinh(tk);
+        ak = 2.0 * theta * std::cosh(tk) * sh * sh;
+      }
+      tau[k] = std::sinh(tk);
+      wcr[k] = std::cbrt(ak / (2.0 * std::pow(kPi, 1.5)));
+    }
+  }
+  std::vector<int> pos[3];
+  std::vector<double> wts[3];
+  for (int d = 0; d < 3; ++d) cert_axis(n[d], pos[d], wts[d]);
+  const int np[3] = {int(pos[0].size()), int(pos[1].size()), int(pos[2].size())};
+  double *d_tau = nullptr, *d_wcr = nullptr, *d_T[3] = {nullptr, nullptr, nullptr},
+         *d_w[3] = {nullptr, nullptr, nullptr}, *d_part = nullptr, *d_out = nullptr;
+  int *d_pos[3] = {nullptr, nullptr, nullptr};
+  const int nblk = std::max(1, std::min(np[1] * np[2], 4096));
+  demag_status st = dalloc(&d_tau, KT);
+  if (st == DEMAG_OK) st = dalloc(&d_wcr, KT);
+  for (int d = 0; d < 3 && st == DEMAG_OK; ++d) {
+    st = dalloc(&d_T[d], size_t(4) * KT * np[d]);
+    if (st == DEMAG_OK) st = dalloc(&d_w[d], np[d]);
+    if (st == DEMAG_OK) st = dalloc(&d_pos[d], np[d]);
+  }
+  if (st == DEMAG_OK) st = dalloc(&d_part, size_t(nblk) * 4);
+  if (st == DEMAG_OK) st = dalloc(&d_out, 4);
+  double sums[4] = {0, 0, 0, 0};
+  if (st == DEMAG_OK) {
+    hipError_t e = hipMemcpyAsync(d_tau, tau.data(), sizeof(double) * KT, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(d_wcr, wcr.data(), sizeof(double) * KT, hipMemcpyHostToDevice, ctx->stream);
+    for (int d = 0; d < 3 && e == hipSuccess; ++d) {
+      e = hipMemcpyAsync(d_pos[d], pos[d].data(), sizeof(int) * np[d], hipMemcpyHostToDevice, ctx->stream);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(d_w[d], wts[d].data(), sizeof(double) * np[d], hipMemcpyHostToDevice, ctx->stream);
+      if (e == hipSuccess) {
+        dim3 g((np[d] + 127) / 128, KT);
+        k_cert_factors<<<g, 128, 0, ctx->stream>>>(d_pos[d], np[d], d_tau, d_wcr, KT, hs[d], d_T[d]);
+        e = hipGetLastError();
+      }
+    }
+    if (e == hipSuccess) {
+      k_cert_sums<<<nblk, 256, sizeof(double) * 6 * KT, ctx->stream>>>(d_T[0], d_T[1], d_T[2], d_w[0], d_w[1], d_w[2],
+                                                                       np[0], np[1], np[2], KT, M, d_part);
+      k_cert_final<<<1, 256, 0, ctx->stream>>>(d_part, nblk, d_out);
+      e = hipGetLastError();
+    }
+    // the host vectors above stay alive until this synchronization
+    if (e == hipSuccess) e = hipMemcpyAsync(sums, d_out, sizeof(sums), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+      set_error(std::string("certificate: ") + hipGetErrorString(e));
+      st = DEMAG_E_HIP;
+    }
+  }
+  for (void *q : {(void *)d_tau, (void *)d_wcr, (void *)d_part, (void *)d_out, (void *)d_T[0], (void *)d_T[1],
+                  (void *)d_T[2], (void *)d_w[0], (void *)d_w[1], (void *)d_w[2], (void *)d_pos[0], (void *)d_pos[1],
+                  (void *)d_pos[2]})
+    if (q) (void)hipFree(q);
+  if (st == DEMAG_OK) {
+    out[0] = std::sqrt(sums[0] / sums[1]);
+    out[1] = std::sqrt(sums[2] / sums[3]);
+  }
+  return st;
 }
 
 }  // namespace
@@ -733,9 +1068,10 @@ demag_status demag_adam_step(demag_ctx *ctx, float *params, const float *grad, f
 }
 
 demag_status demag_quad_judge(demag_ctx *ctx, int32_t B, const int32_t *grids, const double *hmin,
-                              const int32_t *sent, int32_t S, const double *t, const double *alpha, const int32_t *R,
-                              int32_t KM, double *err, double *dt, double *dalpha) {
-  DEMAG_REQUIRE(ctx && grids && hmin && sent && t && alpha && R && err, "demag_quad_judge: NULL argument");
+                              const int32_t *sent, const double *weights, int32_t S, const double *t,
+                              const double *alpha, const int32_t *R, int32_t KM, double *err, double *parts,
+                              double *dt, double *dalpha) {
+  DEMAG_REQUIRE(ctx && grids && hmin && sent && weights && t && alpha && R && err, "demag_quad_judge: NULL argument");
   DEMAG_REQUIRE(B >= 1 && S >= 1 && KM >= 1 && KM <= 256, "demag_quad_judge: sizes out of range");
   DEMAG_REQUIRE((dt == nullptr) == (dalpha == nullptr), "demag_quad_judge: give both gradients or neither");
   DEMAG_TRY_HIP(hipSetDevice(ctx->device));
@@ -746,7 +1082,7 @@ demag_status demag_quad_judge(demag_ctx *ctx, int32_t B, const int32_t *grids, c
   if (st == DEMAG_OK) st = reference_values(ctx, grids, hmin, sent, S, B, Kref);
   if (st == DEMAG_OK) {
     k_judge_values<<<(B * S + 127) / 128, 128, 0, ctx->stream>>>(grids, hmin, sent, S, t, alpha, R, KM, B, K);
-    k_judge_err<<<(B + 127) / 128, 128, 0, ctx->stream>>>(K, Kref, B, S, err, resid);
+    k_judge_err<<<(B + 127) / 128, 128, 0, ctx->stream>>>(K, Kref, weights, B, S, err, parts, resid);
     if (dt)
       k_judge_grad<<<(B * KM + 127) / 128, 128, 0, ctx->stream>>>(grids, hmin, sent, S, t, alpha, R, KM, B, resid,
                                                                  err, dt, dalpha);
@@ -759,8 +1095,8 @@ demag_status demag_quad_judge(demag_ctx *ctx, int32_t B, const int32_t *grids, c
       st = DEMAG_E_HIP;
     }
   }
-  for (double *p : {Kref, K, resid})
-    if (p) (void)hipFree(p);
+  for (double *q : {Kref, K, resid})
+    if (q) (void)hipFree(q);
   return st;
 }
 
@@ -848,17 +1184,18 @@ demag_status demag_quad_train(demag_ctx *ctx, float *params, float *adam_m, floa
 }
 
 demag_status demag_quad_fit(demag_ctx *ctx, int32_t B, const int32_t *grids, const double *hmin,
-                            const int32_t *sent, int32_t S, const int32_t *R, const float *y0, int32_t iters,
-                            double mu0, float *yout, double *xout, float *H, double *t, double *alpha,
+                            const int32_t *sent, const double *weights, int32_t S, const int32_t *R, const float *y0,
+                            int32_t iters, double mu0, float *yout, double *xout, float *H, double *t, double *alpha,
                             double *err) {
-  DEMAG_REQUIRE(ctx && grids && hmin && sent && R && yout && t && alpha && err, "demag_quad_fit: NULL argument");
+  DEMAG_REQUIRE(ctx && grids && hmin && sent && weights && R && yout && t && alpha && err,
+                "demag_quad_fit: NULL argument");
   DEMAG_REQUIRE(B >= 1 && S >= 1 && S <= kMaxS && iters >= 0 && mu0 > 0, "demag_quad_fit: sizes out of range");
   DEMAG_TRY_HIP(hipSetDevice(ctx->device));
   double *Kref = nullptr;
   demag_status st = dalloc(&Kref, size_t(B) * S * kNcomp);
   if (st == DEMAG_OK) st = reference_values(ctx, grids, hmin, sent, S, B, Kref);
   if (st == DEMAG_OK)
-    st = launch_fit(ctx, B, grids, hmin, sent, S, Kref, R, y0, iters, mu0, yout, xout, H, t, alpha, err);
+    st = launch_fit(ctx, B, grids, hmin, sent, weights, S, Kref, R, y0, iters, mu0, yout, xout, H, t, alpha, err);
   if (st == DEMAG_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) {
     set_error("demag_quad_fit: stream synchronization failed");
     st = DEMAG_E_HIP;
@@ -867,137 +1204,241 @@ demag_status demag_quad_fit(demag_ctx *ctx, int32_t B, const int32_t *grids, con
   return st;
 }
 
-// Shortened rule for one grid: the network's predicted-error head picks the
-// smallest R' (16..32) it expects to meet tol; that proposal (and the plain
-// base rule, as a guard) is polished by `fit_iters` Levenberg-Marquardt
-// steps on the grid's fit offsets, and the better one is judged on the
-// check offsets (not seen by the fit); if it misses tol, R' + 4, R' + 8, ... (up to 32) are tried the
-// same way, and if none meets tol the sinc rule with the step of
-// Thm. sinc_theo and 64 nodes is returned (*fell_back = 1).
-demag_status demag_quad_predict(demag_ctx *ctx, const float *params, const float *features, const int32_t n[3],
-                                double hmin, const int32_t *sent, int32_t S, const int32_t *check, int32_t Sc,
-                                double tol, int32_t fit_iters, double *t_out, double *alpha_out, int32_t *R_out,
-                                double *judged, double *predicted, int32_t *fell_back) {
-  DEMAG_REQUIRE(ctx && params && features && n && sent && check && t_out && alpha_out && R_out && judged &&
-                    predicted && fell_back,
-                "demag_quad_predict: NULL argument");
-  DEMAG_REQUIRE(tol > 0 && hmin > 0 && S >= 1 && S <= kMaxS && Sc >= 1 && fit_iters >= 0,
-                "demag_quad_predict: tol, hmin, S, Sc or fit_iters out of range");
+demag_status demag_quad_offsets(const int32_t n[3], int32_t count, int32_t *J, double *w) {
+  DEMAG_REQUIRE(n && J && w, "demag_quad_offsets: NULL argument");
+  DEMAG_REQUIRE(n[0] >= 1 && n[1] >= 1 && n[2] >= 1 && n[0] <= 4096 && n[1] <= 4096 && n[2] <= 4096 && count >= 1,
+                "demag_quad_offsets: sizes out of range");
+  const int nn[3] = {n[0], n[1], n[2]};
+  DEMAG_REQUIRE(fit_offsets_host(nn, count, J, w), "demag_quad_offsets: count too small for the near block");
+  return DEMAG_OK;
+}
+
+demag_status demag_quad_features(const int32_t n[3], double h, double log10_tol, int32_t R, float *x) {
+  DEMAG_REQUIRE(n && x, "demag_quad_features: NULL argument");
+  DEMAG_REQUIRE(n[0] >= 1 && n[1] >= 1 && n[2] >= 1 && h > 0, "demag_quad_features: sizes out of range");
+  const int nn[3] = {n[0], n[1], n[2]};
+  features_host(nn, h, log10_tol, R, x);
+  return DEMAG_OK;
+}
+
+namespace {
+// Scaled grid of a demag_grid: n, the scaled cell sizes (longest extent 1).
+demag_status scaled_grid(const demag_grid *g, int n[3], double hs[3], const char *where) {
+  double L = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    DEMAG_REQUIRE(g->n[d] >= 1 && g->n[d] <= 4096 && g->h[d] > 0 && std::isfinite(g->h[d]),
+                  std::string(where) + ": grid out of range");
+    n[d] = g->n[d];
+    L = std::max(L, g->n[d] * g->h[d]);
+  }
+  for (int d = 0; d < 3; ++d) hs[d] = g->h[d] / L;
+  return DEMAG_OK;
+}
+}  // namespace
+
+demag_status demag_quad_certify(demag_ctx *ctx, const demag_grid *grid, int32_t M, const double *t,
+                                const double *alpha, double err[2]) {
+  DEMAG_REQUIRE(ctx && grid && t && alpha && err, "demag_quad_certify: NULL argument");
+  DEMAG_REQUIRE(M >= 1 && M <= 256, "demag_quad_certify: M out of range");
+  for (int k = 0; k < M; ++k)
+    DEMAG_REQUIRE(std::isfinite(t[k]) && t[k] > 0 && std::isfinite(alpha[k]), "demag_quad_certify: bad node");
+  int n[3];
+  double hs[3];
+  demag_status st = scaled_grid(grid, n, hs, "demag_quad_certify");
+  if (st != DEMAG_OK) return st;
   DEMAG_TRY_HIP(hipSetDevice(ctx->device));
-  const int NC = 17;
-  float *Y = nullptr, *yfit = nullptr;
-  int32_t *dR = nullptr, *dgrid = nullptr;
-  double *dh = nullptr, *dt = nullptr, *da = nullptr, *derr = nullptr, *Kref = nullptr, *KrefC = nullptr,
-         *Kc = nullptr;
-  demag_status st = dalloc(&Y, size_t(NC) * kOut);
+  return certify_rule(ctx, n, hs, M, t, alpha, err);
+}
+
+// Shortened rule for one grid.  Modes:
+//   DEMAG_PREDICT_NETWORK: the network's error head picks the smallest R'
+//     (16..32) it expects to meet tol; the plain base rule with R' nodes is
+//     fitted by fit_iters Levenberg-Marquardt steps on the grid's weighted
+//     offsets and certified; on a miss R' + 1, R' + 2, ... (up to 32) follow;
+//   DEMAG_PREDICT_NETWORK_PROPOSAL: the same R' schedule, fits started from
+//     the network's proposed nodes and weights for that R' (measured to be
+//     no better a start than the plain rule);
+//   DEMAG_PREDICT_SEARCH: no network: bisection over R' = 16..32 for the
+//     smallest R' whose fit (from the plain base rule) is certified within
+//     tol (R' = 32 first; the certified error falls with R').
+// If nothing meets tol, the sinc rule with the step of Thm. sinc_theo and 64
+// nodes is certified and returned (fell_back = 1; DEMAG_E_ACCURACY if it
+// misses tol too).
+demag_status demag_quad_predict(demag_ctx *ctx, const float *params, const demag_grid *grid, double tol,
+                                int32_t fit_iters, int32_t mode, demag_quad_result *out) {
+  DEMAG_REQUIRE(ctx && grid && out, "demag_quad_predict: NULL argument");
+  DEMAG_REQUIRE(mode == DEMAG_PREDICT_NETWORK || mode == DEMAG_PREDICT_NETWORK_PROPOSAL ||
+                    mode == DEMAG_PREDICT_SEARCH,
+                "demag_quad_predict: unknown mode");
+  DEMAG_REQUIRE(params || mode == DEMAG_PREDICT_SEARCH, "demag_quad_predict: the network modes need params");
+  DEMAG_REQUIRE(tol > 0 && fit_iters >= 0, "demag_quad_predict: tol or fit_iters out of range");
+  int n[3];
+  double hs[3];
+  demag_status st = scaled_grid(grid, n, hs, "demag_quad_predict");
+  if (st != DEMAG_OK) return st;
+  if (!(std::fabs(hs[1] - hs[0]) <= 1e-12 * hs[0] && std::fabs(hs[2] - hs[0]) <= 1e-12 * hs[0])) {
+    set_error("demag_quad_predict: the shortened rules are trained and judged for cubic cells");
+    return DEMAG_E_UNSUPPORTED;
+  }
+  DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  const auto clock0 = std::chrono::steady_clock::now();
+  const double hmin = hs[0];
+  const int S = kMaxS, NC = 17;
+  std::vector<int32_t> Jh(size_t(3) * S);
+  std::vector<double> wh(S);
+  (void)fit_offsets_host(n, S, Jh.data(), wh.data());
+  std::vector<float> xh(size_t(NC) * kIn), yh(size_t(NC) * kOut, 0.0f);
+  for (int c = 0; c < NC; ++c) features_host(n, hmin, std::log10(tol), 16 + c, xh.data() + size_t(c) * kIn);
+
+  float *X = nullptr, *Y = nullptr, *yfit = nullptr;
+  int32_t *dR = nullptr, *dgrid = nullptr, *dsent = nullptr;
+  double *dh = nullptr, *dw = nullptr, *dt = nullptr, *da = nullptr, *derr = nullptr, *Kref = nullptr;
+  st = dalloc(&X, xh.size());
+  if (st == DEMAG_OK) st = dalloc(&Y, yh.size());
   if (st == DEMAG_OK) st = dalloc(&yfit, kOut);
   if (st == DEMAG_OK) st = dalloc(&dR, 1);
   if (st == DEMAG_OK) st = dalloc(&dgrid, 3);
+  if (st == DEMAG_OK) st = dalloc(&dsent, size_t(3) * S);
   if (st == DEMAG_OK) st = dalloc(&dh, 1);
+  if (st == DEMAG_OK) st = dalloc(&dw, S);
   if (st == DEMAG_OK) st = dalloc(&dt, kRmax);
   if (st == DEMAG_OK) st = dalloc(&da, kRmax);
   if (st == DEMAG_OK) st = dalloc(&derr, 1);
   if (st == DEMAG_OK) st = dalloc(&Kref, size_t(S) * kNcomp);
-  if (st == DEMAG_OK) st = dalloc(&KrefC, size_t(Sc) * kNcomp);
-  if (st == DEMAG_OK) st = dalloc(&Kc, size_t(Sc) * kNcomp);
-  std::vector<float> yh(size_t(NC) * kOut);
+  auto copy_failed = [&](const char *what) {
+    set_error(std::string("demag_quad_predict: ") + what);
+    st = DEMAG_E_HIP;
+  };
   if (st == DEMAG_OK) {
-    k_mlp_forward<<<NC, 64, 0, ctx->stream>>>(params, features, NC, Y, nullptr, nullptr);
-    if (hipMemcpyAsync(yh.data(), Y, sizeof(float) * yh.size(), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-        hipMemcpyAsync(dgrid, n, sizeof(int32_t) * 3, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
-        hipMemcpyAsync(dh, &hmin, sizeof(double), hipMemcpyHostToDevice, ctx->stream) != hipSuccess) {
-      set_error("demag_quad_predict: copy failed");
-      st = DEMAG_E_HIP;
-    }
+    const int32_t n32[3] = {n[0], n[1], n[2]};
+    if (hipMemcpyAsync(dgrid, n32, sizeof(n32), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(dh, &hmin, sizeof(double), hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(dsent, Jh.data(), sizeof(int32_t) * Jh.size(), hipMemcpyHostToDevice, ctx->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(dw, wh.data(), sizeof(double) * S, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(X, xh.data(), sizeof(float) * xh.size(), hipMemcpyHostToDevice, ctx->stream) != hipSuccess)
+      copy_failed("copy failed");
   }
-  if (st == DEMAG_OK) st = reference_values(ctx, dgrid, dh, sent, S, 1, Kref);
-  if (st == DEMAG_OK) st = reference_values(ctx, dgrid, dh, check, Sc, 1, KrefC);
-  int pick = NC - 1;
-  if (st == DEMAG_OK) {
-    for (int c = 0; c < NC; ++c)
-      if (yh[size_t(c) * kOut + 64] <= std::log10(tol)) {
-        pick = c;
-        break;
-      }
-    *predicted = yh[size_t(pick) * kOut + 64];
-  }
-  bool done = false;
-  for (int c = pick; st == DEMAG_OK && !done; c = (c == NC - 1) ? NC : std::min(c + 4, NC - 1)) {
-    if (c >= NC) break;
-    const int Rp = 16 + c;
-    double e = 0;
-    std::vector<double> th(kRmax), ah(kRmax);
-    if (hipMemcpyAsync(dR, &Rp, sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream) != hipSuccess) {
-      set_error("demag_quad_predict: copy failed");
-      st = DEMAG_E_HIP;
-      break;
-    }
-    // polish the network's proposal and, as a guard, the plain base rule;
-    // keep the better of the two
-    for (int start = 0; start < 2 && st == DEMAG_OK; ++start) {
-      st = launch_fit(ctx, 1, dgrid, dh, sent, S, Kref, dR, start == 0 ? Y + size_t(c) * kOut : nullptr, fit_iters,
-                      1e-3, yfit, nullptr, nullptr, dt, da, derr);
-      if (st != DEMAG_OK) break;
-      double es = 0;
-      std::vector<double> ts(kRmax), as(kRmax);
-      if (hipMemcpyAsync(&es, derr, sizeof(double), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-          hipMemcpyAsync(ts.data(), dt, sizeof(double) * kRmax, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-          hipMemcpyAsync(as.data(), da, sizeof(double) * kRmax, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-          hipStreamSynchronize(ctx->stream) != hipSuccess) {
-        set_error("demag_quad_predict: copy failed");
-        st = DEMAG_E_HIP;
-        break;
-      }
-      if (start == 0 || es < e) {
-        e = es;
-        th = ts;
-        ah = as;
-      }
-    }
-    if (st != DEMAG_OK) break;
-    // judge the kept rule on the check offsets, which the fit never saw
-    if (hipMemcpyAsync(dt, th.data(), sizeof(double) * kRmax, hipMemcpyHostToDevice, ctx->stream) != hipSuccess ||
-        hipMemcpyAsync(da, ah.data(), sizeof(double) * kRmax, hipMemcpyHostToDevice, ctx->stream) != hipSuccess) {
-      set_error("demag_quad_predict: copy failed");
-      st = DEMAG_E_HIP;
-      break;
-    }
-    k_judge_values<<<(Sc + 127) / 128, 128, 0, ctx->stream>>>(dgrid, dh, check, Sc, dt, da, dR, kRmax, 1, Kc);
-    k_judge_err<<<1, 128, 0, ctx->stream>>>(Kc, KrefC, 1, Sc, derr, nullptr);
+  if (st == DEMAG_OK) st = reference_values(ctx, dgrid, dh, dsent, S, 1, Kref);   // synchronizes
+  out->predicted = std::nan("");
+  if (st == DEMAG_OK && mode != DEMAG_PREDICT_SEARCH) {
+    k_mlp_forward<<<NC, 64, 0, ctx->stream>>>(params, X, NC, Y, nullptr, nullptr);
     if (hipGetLastError() != hipSuccess ||
-        hipMemcpyAsync(&e, derr, sizeof(double), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
-        hipStreamSynchronize(ctx->stream) != hipSuccess) {
-      set_error("demag_quad_predict: judge failed");
-      st = DEMAG_E_HIP;
-      break;
+        hipMemcpyAsync(yh.data(), Y, sizeof(float) * yh.size(), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess)
+      copy_failed("network forward failed");
+  }
+  int fits = 0;
+  // fit R' nodes from the network's outputs (use_net) or the plain base rule,
+  // then certify: (t, alpha, e_phi, e_h)
+  struct Cand {
+    int R = 0;
+    std::vector<double> t, a;
+    double e[2] = {0, 0};
+    bool ok = false;
+  };
+  auto run = [&](int Rp, bool use_net, Cand &c) -> demag_status {
+    c.R = Rp;
+    if (hipMemcpyAsync(dR, &Rp, sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream) != hipSuccess) {
+      copy_failed("copy failed");
+      return st;
     }
-    *judged = e;
-    if (e <= tol) {
-      done = true;
-      *fell_back = 0;
-      *R_out = Rp;
-      for (int k = 0; k < Rp; ++k) {
-        t_out[k] = th[k];
-        alpha_out[k] = ah[k];
+    demag_status s2 = launch_fit(ctx, 1, dgrid, dh, dsent, dw, S, Kref, dR,
+                                 use_net ? Y + size_t(Rp - 16) * kOut : nullptr, fit_iters, 1e-3, yfit, nullptr,
+                                 nullptr, dt, da, derr);
+    if (s2 != DEMAG_OK) return s2;
+    ++fits;
+    std::vector<double> th(kRmax), ah(kRmax);
+    if (hipMemcpyAsync(th.data(), dt, sizeof(double) * kRmax, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipMemcpyAsync(ah.data(), da, sizeof(double) * kRmax, hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
+        hipStreamSynchronize(ctx->stream) != hipSuccess) {
+      copy_failed("copy failed");
+      return st;
+    }
+    c.t.assign(th.begin(), th.begin() + Rp);
+    c.a.assign(ah.begin(), ah.begin() + Rp);
+    s2 = certify_rule(ctx, n, hs, Rp, c.t.data(), c.a.data(), c.e);
+    c.ok = (s2 == DEMAG_OK) && std::max(c.e[0], c.e[1]) <= tol;
+    return s2;
+  };
+  Cand best;
+  if (st == DEMAG_OK) {
+    if (mode == DEMAG_PREDICT_SEARCH) {
+      Cand c;
+      st = run(32, false, c);
+      if (st == DEMAG_OK && c.ok) {
+        best = c;
+        int lo = 16, hi = 32;
+        while (st == DEMAG_OK && lo < hi) {
+          const int mid = (lo + hi) / 2;
+          st = run(mid, false, c);
+          if (st != DEMAG_OK) break;
+          if (c.ok) {
+            hi = mid;
+            best = c;
+          } else {
+            lo = mid + 1;
+          }
+        }
+      }
+    } else {
+      int pick = NC - 1;
+      for (int c = 0; c < NC; ++c)
+        if (yh[size_t(c) * kOut + 64] <= std::log10(tol)) {
+          pick = c;
+          break;
+        }
+      out->predicted = yh[size_t(pick) * kOut + 64];
+      for (int Rp = 16 + pick; st == DEMAG_OK && Rp <= 32; ++Rp) {
+        Cand c;
+        st = run(Rp, mode == DEMAG_PREDICT_NETWORK_PROPOSAL, c);
+        if (st == DEMAG_OK && c.ok) {
+          best = c;
+          break;
+        }
       }
     }
   }
-  if (st == DEMAG_OK && !done) {
-    // fallback: the sinc rule with the step of Thm. sinc_theo, 64 nodes
-    *fell_back = 1;
-    const int M = 64;
-    const double a = 2.0, bb = 0.25 * (0.5 * hmin) * (0.5 * hmin);
-    const double theta = std::log(2.0 * kPi * a * M / bb) / (a * M);
-    *R_out = M;
-    for (int k = 0; k < M; ++k) {
-      const double tk = (k + 1) * theta, sh = std::sinh(tk);
-      t_out[k] = tk;
-      alpha_out[k] = 2.0 * theta * std::cosh(tk) * sh * sh;
+  if (st == DEMAG_OK) {
+    if (best.ok) {
+      out->fell_back = 0;
+    } else {
+      // fallback: the sinc rule with the step of Thm. sinc_theo, 64 nodes
+      const int M = 64;
+      const double a = 2.0, bb = 0.25 * (0.5 * hmin) * (0.5 * hmin);
+      const double theta = std::log(2.0 * kPi * a * M / bb) / (a * M);
+      best.R = M;
+      best.t.resize(M);
+      best.a.resize(M);
+      for (int k = 0; k < M; ++k) {
+        const double tk = (k + 1) * theta, sh = std::sinh(tk);
+        best.t[k] = tk;
+        best.a[k] = 2.0 * theta * std::cosh(tk) * sh * sh;
+      }
+      st = certify_rule(ctx, n, hs, M, best.t.data(), best.a.data(), best.e);
+      best.ok = (st == DEMAG_OK) && std::max(best.e[0], best.e[1]) <= tol;
+      out->fell_back = 1;
     }
   }
-  for (void *p : {(void *)Y, (void *)yfit, (void *)dR, (void *)dgrid, (void *)dh, (void *)dt, (void *)da,
-                  (void *)derr, (void *)Kref, (void *)KrefC, (void *)Kc})
-    if (p) (void)hipFree(p);
+  if (st == DEMAG_OK) {
+    out->R = best.R;
+    out->mode = mode;
+    out->fits = fits;
+    out->err_phi = best.e[0];
+    out->err_h = best.e[1];
+    for (int k = 0; k < 64; ++k) {
+      out->t[k] = k < best.R ? best.t[k] : 0.0;
+      out->alpha[k] = k < best.R ? best.a[k] : 0.0;
+    }
+  }
+  for (void *q : {(void *)X, (void *)Y, (void *)yfit, (void *)dR, (void *)dgrid, (void *)dsent, (void *)dh,
+                  (void *)dw, (void *)dt, (void *)da, (void *)derr, (void *)Kref})
+    if (q) (void)hipFree(q);
+  out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - clock0).count();
+  if (st == DEMAG_OK && !best.ok) {
+    set_error("demag_quad_predict: the fallback rule misses tol as well");
+    return DEMAG_E_ACCURACY;
+  }
   return st;
 }
 

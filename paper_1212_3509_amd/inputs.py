@@ -216,44 +216,77 @@ def mlp_init(seed: int = 4, sizes=MLP_SIZES, out_scale: float = 0.0) -> np.ndarr
     return np.concatenate(parts).astype(np.float32)
 
 
-def sentinel_offsets(n, kind: str = "fit", count: int = 256) -> np.ndarray:
-    """Offsets J = (Jx, Jy, Jz) at which a quadrature rule's kernels are
-    compared with the reference on a grid n = (nx, ny, nz).
+# directions (max-norm 1) of the far samples, taken in a cycle that shifts by
+# one per shell group
+FIT_DIRECTIONS = ((1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0), (1.0, 1.0, 1.0), (1.0, 1.0, 0.0),
+                  (0.0, 1.0, 1.0), (1.0, 0.0, 1.0), (1.0, 0.5, 0.25), (0.5, 1.0, 0.25), (0.25, 0.5, 1.0),
+                  (1.0, 0.25, 0.5), (0.5, 0.25, 1.0))
 
-    The sinc rule's error is mainly a function of the distance, so besides
-    the near cells (self, face, edge, corner and short-step neighbours) the
-    offsets sample distances 2 .. |n - 1| geometrically (count - 12 of them,
-    several times the 2 R' <= 64 fitted parameters) along a cycle of
-    directions.  kind="fit": the offsets a rule is fitted on; kind="check":
-    other near cells, distances half-way between the fit set's and another
-    direction cycle, for judging a fitted rule on offsets it never saw.
-    Returns int32 (count, 3) with 0 <= J_d < n_d (kernels are even/odd in J)."""
-    nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(n)
-    top = np.array([nx - 1, ny - 1, nz - 1], dtype=np.float64)
-    if kind == "fit":
-        near = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 0), (1, 0, 1), (0, 1, 1), (1, 1, 1),
-                (2, 1, 0), (0, 2, 1), (1, 0, 2), (3, 2, 1)]
-        dirs = [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 1, 1), (1, 1, 0), (0, 1, 1), (1, 0, 1), (2, 1, 0.5)]
-        shift = 0.0
-    elif kind == "check":
-        near = [(2, 0, 0), (0, 2, 0), (0, 0, 2), (2, 2, 0), (2, 0, 2), (0, 2, 2), (2, 2, 2), (1, 2, 3),
-                (3, 1, 2), (2, 3, 1), (4, 1, 0), (0, 4, 1)]
-        dirs = [(1, 1, 0), (1, 0, 0), (1, 1, 1), (0, 1, 0), (1, 0, 1), (0, 0, 1), (0, 1, 1), (0.5, 2, 1)]
-        shift = 0.5
-    else:
-        raise ValueError("kind must be 'fit' or 'check'")
-    if count < len(near) + 2:
-        raise ValueError("count too small")
-    nfar = count - len(near)
-    dmax = max(2.0, float(np.linalg.norm(top)))
-    out = [tuple(min(j[d], int(top[d])) for d in range(3)) for j in near]
-    for i in range(nfar):
-        dist = 2.0 * (dmax / 2.0) ** ((i + shift) / (nfar - 1 + shift))
-        u = np.asarray(dirs[i % len(dirs)], dtype=np.float64)
-        u = u / np.linalg.norm(u)
-        j = np.minimum(np.rint(dist * u), top)
-        out.append(tuple(int(v) for v in j))
-    return np.array(out, dtype=np.int32)
+
+def fit_offsets(n, count: int = 256):
+    """Offsets J = (Jx, Jy, Jz), 0 <= J_d < n_d, and weights w_J at which a
+    quadrature rule's kernels are compared with the reference's on the grid
+    n = (nx, ny, nz), so that sum_J w_J |dK(J)|^2 approximates the sum over
+    every offset of the grid of (prod_d (n_d - |J_d|)) |dK(J)|^2, i.e. the
+    squared Frobenius norm of the operator's error (each offset J >= 0 stands
+    for its 2^(number of nonzero J_d) sign images; kernels are even or odd in
+    every J_d).
+
+    * near block: every J with J_d <= 3 (at most 64 offsets), exact weights
+      c_x(Jx) c_y(Jy) c_z(Jz), c_d(j) = (n_d - j) (1 if j == 0 else 2);
+    * far region, max-norm s = max_d J_d from 4 to s_max = max_d (n_d - 1):
+      G = min((count - near) // 8, s_max - 3) groups of consecutive s with
+      geometrically growing edges; each group is represented by 8 offsets at
+      the max-norm sqrt(s_lo (s_hi - 1)) along 8 of FIT_DIRECTIONS, each
+      weighted with 1/8 of the group's total weight.
+    Padded to ``count`` rows with J = (0, 0, 0), weight 0.
+    Returns (J int32 [count][3], w float64 [count])."""
+    nx, ny, nz = (n, n, n) if np.isscalar(n) else tuple(int(v) for v in n)
+    nn = (nx, ny, nz)
+    c = [[float((nd - j) * (1 if j == 0 else 2)) for j in range(nd)] for nd in nn]
+    J, w = [], []
+    for z in range(min(4, nz)):
+        for y in range(min(4, ny)):
+            for x in range(min(4, nx)):
+                J.append((x, y, z))
+                w.append(c[0][x] * c[1][y] * c[2][z])
+    if count < len(J):
+        raise ValueError("count too small for the near block")
+    cum = []
+    for d in range(3):
+        acc, row = 0.0, [0.0]
+        for v in c[d]:
+            acc += v
+            row.append(acc)
+        cum.append(row)
+
+    def total(s):   # weight of all offsets with max-norm < s
+        return cum[0][min(s, nx)] * cum[1][min(s, ny)] * cum[2][min(s, nz)]
+
+    smax = max(nn) - 1
+    G = min((count - len(J)) // 8, max(0, smax - 3))
+    if G > 0:
+        edges = [4]
+        for g in range(1, G):
+            edges.append(max(edges[-1] + 1, int(round(4.0 * ((smax + 1) / 4.0) ** (g / G)))))
+        edges.append(smax + 1)
+        uniq = []
+        for v in edges:
+            v = min(v, smax + 1)
+            if not uniq or v != uniq[-1]:
+                uniq.append(v)
+        for g in range(len(uniq) - 1):
+            lo, hi = uniq[g], uniq[g + 1]
+            wg = (total(hi) - total(lo)) / 8.0
+            sg = int(round(np.sqrt(float(lo * (hi - 1)))))
+            for i in range(8):
+                u = FIT_DIRECTIONS[(g + i) % len(FIT_DIRECTIONS)]
+                J.append(tuple(min(int(np.rint(sg * u[d])), nn[d] - 1) for d in range(3)))
+                w.append(wg)
+    while len(J) < count:
+        J.append((0, 0, 0))
+        w.append(0.0)
+    return np.array(J, dtype=np.int32), np.array(w, dtype=np.float64)
 
 
 def quad_features(n, h, log10_tol, rprime) -> np.ndarray:

@@ -1,20 +1,23 @@
-"""GPU checks of the shortened-rule network, its judge and the per-grid fit
-against the oracle.
+"""GPU checks of the shortened-rule network, its judge, its certificate and
+the per-grid fit against the oracle, and of what the learned path gains.
 
 Network (FP32 on the GPU, FP64 in the oracle): outputs to 1e-5 relative,
 parameter gradients to 1e-4 relative L2.  Judge (FP64 on both sides, own
 factor code on each): errors to 1e-6 relative, gradients against central
-differences of the oracle judge to 1e-4.  Fit: one damped Gauss-Newton step
-(analytic Jacobian on the GPU, central differences in the oracle) to 1e-4 of
-the step; fitted errors must equal the oracle's judge of the returned rule.
-The trained network's error head must predict the fitted error of held-out
-cases, and the learned path must meet a tolerance with fewer nodes than the
-plain sinc rule needs."""
+differences of the oracle judge to 1e-4.  Certificate: the exact operator
+Frobenius-norm errors of the oracle to 1e-9 (small grids); on the 128^3 and
+256^3 vortex and random fields it bounds the measured relative L2 error of
+every rule (vortex: measured <= certified; random inputs: the certificate is
+the expected error, measured <= 1.1 x certified).  Fit: one damped
+Gauss-Newton step (analytic Jacobian on the GPU, central differences in the
+oracle) to 1e-4 of the step; fitted errors equal the oracle's judge of the
+returned rule.  Gain: at 128^3 and 1e-6 the learned rule needs at most 0.8x
+the nodes the plain sinc rule needs for the same certified tolerance."""
 import numpy as np
 import pytest
 import torch
 
-from oracle import mlp, quadrule
+from oracle import mlp, quadrule, sinc
 from paper_1212_3509_amd import api, inputs, learned
 
 pytestmark = pytest.mark.gpu
@@ -71,11 +74,14 @@ def test_rules_and_judge_match_oracle(ctx):
     Yd = torch.from_numpy(Y).cuda()
     Rd = torch.from_numpy(R).cuda()
     t, a = ctx.quad_rules(Yd, Rd)
-    sent = np.stack([inputs.sentinel_offsets(tuple(g)) for g in grids])
-    err, dt, da = ctx.quad_judge(torch.from_numpy(grids).cuda(), torch.from_numpy(h).cuda(),
-                                 torch.from_numpy(sent).cuda(), t, a, Rd, grad=True)
+    ow = [inputs.fit_offsets(tuple(int(v) for v in g)) for g in grids]
+    sent = np.stack([o[0] for o in ow])
+    wts = np.stack([o[1] for o in ow])
+    err, parts, dt, da = ctx.quad_judge(torch.from_numpy(grids).cuda(), torch.from_numpy(h).cuda(),
+                                        torch.from_numpy(sent).cuda(), torch.from_numpy(wts).cuda(), t, a, Rd,
+                                        grad=True, parts=True)
     torch.cuda.synchronize()
-    t, a, err, dt, da = (x.cpu().numpy() for x in (t, a, err, dt, da))
+    t, a, err, parts, dt, da = (x.cpu().numpy() for x in (t, a, err, parts, dt, da))
     for b in range(B):
         n = tuple(int(v) for v in grids[b])
         hh = (h[b],) * 3
@@ -84,11 +90,30 @@ def test_rules_and_judge_match_oracle(ctx):
         assert np.all(t[b, R[b]:] == 0)
         t_ref, a_ref = quadrule.reference_rule(h[b])
         ref = quadrule.kernel_values(n, hh, t_ref, a_ref, sent[b])
-        e_or = quadrule.judge(n, hh, tr, ar, ref, sent[b])
+        e_or = quadrule.judge(n, hh, tr, ar, ref, sent[b], wts[b])
         assert abs(err[b] - e_or) <= 1e-6 * e_or
-        gt, ga = quadrule.judge_grad_fd(n, hh, tr, ar, ref, sent[b])
+        ep, eh = quadrule.judge_parts(n, hh, tr, ar, ref, sent[b], wts[b])
+        assert abs(parts[b, 0] - ep) <= 1e-6 * ep and abs(parts[b, 1] - eh) <= 1e-6 * eh
+        gt, ga = quadrule.judge_grad_fd(n, hh, tr, ar, ref, sent[b], wts[b])
         assert np.linalg.norm(dt[b, :R[b]] - gt) <= 1e-4 * np.linalg.norm(gt)
         assert np.linalg.norm(da[b, :R[b]] - ga) <= 1e-4 * np.linalg.norm(ga)
+
+
+@pytest.mark.parametrize("n,h", [((24, 20, 16), (1 / 24,) * 3), ((40, 33, 17), (0.025, 0.03, 0.05)),
+                                 ((4, 3, 5), (0.2,) * 3)])
+def test_certificate_matches_oracle(ctx, n, h):
+    """The GPU certificate (weighted sums over every offset) against the
+    oracle's exact operator Frobenius-norm errors, plain and theorem-step rules."""
+    L = max(n[d] * h[d] for d in range(3))
+    hs = tuple(x / L for x in h)
+    for t, a in (quadrule.base_rule(12)[:2], quadrule.base_rule(20)[:2],
+                 sinc.sinc_nodes(24, step_rule=1, h_min=min(hs))[0::2]):
+        got = ctx.quad_certify(n, h, t, a)
+        ref = quadrule.certify(n, hs, t, a)
+        # both sides form each kernel difference from ~100 FP64 terms of size
+        # |K|: an absolute floor of ~1e-15 on the relative error
+        assert abs(got[0] - ref[0]) <= 1e-9 * ref[0] + 1e-13, (got, ref)
+        assert abs(got[1] - ref[1]) <= 1e-9 * ref[1] + 1e-13, (got, ref)
 
 
 def test_fit_step_matches_oracle(ctx):
@@ -97,9 +122,11 @@ def test_fit_step_matches_oracle(ctx):
     h = 1.0 / grids.max(axis=1)
     rng = np.random.default_rng(4)
     y0 = (0.2 * rng.standard_normal((2, 65))).astype(np.float32)
-    sent = np.stack([inputs.sentinel_offsets(tuple(g)) for g in grids])
+    ow = [inputs.fit_offsets(tuple(int(v) for v in g)) for g in grids]
+    sent = np.stack([o[0] for o in ow])
+    wts = np.stack([o[1] for o in ow])
     dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()  # noqa: E731
-    y1, t1, a1, e1 = ctx.quad_fit(dev(grids), dev(h), dev(sent), dev(R), dev(y0), iters=1, mu0=1e-2)
+    y1, t1, a1, e1 = ctx.quad_fit(dev(grids), dev(h), dev(sent), dev(wts), dev(R), dev(y0), iters=1, mu0=1e-2)
     torch.cuda.synchronize()
     y1, t1, a1, e1 = (x.cpu().numpy() for x in (y1, t1, a1, e1))
     for b in range(2):
@@ -110,40 +137,44 @@ def test_fit_step_matches_oracle(ctx):
         ref = quadrule.kernel_values(n, hh, tr, ar, sent[b])
         yb = y0[b].astype(np.float64)
         x0 = np.r_[np.clip(0.45 * np.tanh(yb[:Rb]), -0.44, 0.44), np.clip(np.tanh(yb[32:32 + Rb]), -0.99, 0.99)]
-        xo, e_before, e_after = quadrule.lm_step(n, hh, x0, Rb, ref, sent[b], 1e-2)
+        xo, e_before, e_after = quadrule.lm_step(n, hh, x0, Rb, ref, sent[b], wts[b], 1e-2)
         expect = xo if e_after < e_before else x0
         yg = y1[b].astype(np.float64)
         xg = np.r_[0.45 * np.tanh(yg[:Rb]), np.tanh(yg[32:32 + Rb])]
         assert np.linalg.norm(xg - expect) <= 1e-4 * np.linalg.norm(xo - x0) + 1e-6, b
         # the reported error is the oracle's judge of the returned rule
-        e_or = quadrule.judge(n, hh, t1[b, :Rb], a1[b, :Rb], ref, sent[b])
+        e_or = quadrule.judge(n, hh, t1[b, :Rb], a1[b, :Rb], ref, sent[b], wts[b])
         assert abs(e1[b] - e_or) <= 1e-8 * e_or
         assert np.all(t1[b, Rb:] == 0)
 
 
 def test_fit_lowers_the_error_of_held_out_cases(ctx):
     cases = learned.prepare_cases(64, seed=21, shuffle_seed=22)
-    y, t, a, err = ctx.quad_fit(cases["grids"], cases["hmin"], cases["sent"], cases["R"], None, iters=30)
+    y, t, a, err = ctx.quad_fit(cases["grids"], cases["hmin"], cases["sent"], cases["w"], cases["R"], None, iters=30)
     t0, a0 = ctx.quad_rules(None, cases["R"])
-    e0 = ctx.quad_judge(cases["grids"], cases["hmin"], cases["sent"], t0, a0, cases["R"])
-    e1 = ctx.quad_judge(cases["grids"], cases["hmin"], cases["sent"], t, a, cases["R"])
+    e0 = ctx.quad_judge(cases["grids"], cases["hmin"], cases["sent"], cases["w"], t0, a0, cases["R"])
+    e1 = ctx.quad_judge(cases["grids"], cases["hmin"], cases["sent"], cases["w"], t, a, cases["R"])
     torch.cuda.synchronize()
     err, e0, e1 = (x.cpu().numpy() for x in (err, e0, e1))
     assert np.allclose(err, e1, rtol=1e-9, atol=0)
     assert np.all(err <= e0)
     ratio = err / e0
-    print(f"fit: geometric mean error ratio fitted/base {np.exp(np.mean(np.log(ratio))):.3e}")
-    assert np.exp(np.mean(np.log(ratio))) < 0.8
+    gm = float(np.exp(np.mean(np.log(ratio))))
+    print(f"fit: geometric mean error ratio fitted/base {gm:.3e}, median {np.median(ratio):.3e}")
+    # the fit gains most where the base rule is short of nodes for the grid
+    # (the large errors); a quarter of the cases must gain at least 2x
+    assert np.quantile(ratio, 0.25) < 0.5
     # one case checked end to end by the oracle
     b = 0
     n = tuple(int(v) for v in cases["n"][b])
     hh = (float(cases["h"][b]),) * 3
     tr, ar = quadrule.reference_rule(hh[0])
     sent = cases["sent"][b].cpu().numpy()
+    w = cases["w"][b].cpu().numpy()
     ref = quadrule.kernel_values(n, hh, tr, ar, sent)
     R = int(cases["Rhost"][b])
     tt, aa = t[b, :R].cpu().numpy(), a[b, :R].cpu().numpy()
-    assert abs(quadrule.judge(n, hh, tt, aa, ref, sent) - err[b]) <= 1e-8 * err[b]
+    assert abs(quadrule.judge(n, hh, tt, aa, ref, sent, w) - err[b]) <= 1e-8 * err[b]
     to, ao = quadrule.rule_from_outputs(y[b].cpu().numpy().astype(np.float64), R, hh[0])
     assert np.allclose(to, tt, rtol=1e-6) and np.allclose(ao, aa, rtol=1e-5)
 
@@ -189,7 +220,7 @@ def test_training_learns_the_achievable_error(ctx, trained):
     assert loss[-20:].mean() < 0.2 * loss[:5].mean()
     test = learned.prepare_cases(256, seed=11, shuffle_seed=12)
     y, _z, _a = ctx.mlp_forward(params, test["x"])
-    _y, _t, _a2, efit = ctx.quad_fit(test["grids"], test["hmin"], test["sent"], test["R"], None, 60)
+    _y, _t, _a2, efit = ctx.quad_fit(test["grids"], test["hmin"], test["sent"], test["w"], test["R"], None, 60)
     torch.cuda.synchronize()
     head = y[:, 64].cpu().numpy()
     target = np.log10(efit.cpu().numpy())
@@ -199,25 +230,108 @@ def test_training_learns_the_achievable_error(ctx, trained):
     assert corr > 0.9 and mae < 0.3
 
 
-def test_learned_rule_beats_sinc_at_equal_nodes(ctx, trained):
-    """At 128^3 and tol 1e-6 the learned path picks R' <= 32 nodes (the plain
-    rule uses 40), meets tol on the check offsets the fit never saw, and is
-    no worse there than the plain sinc rule with the same R'."""
+def _apply(ctx, n, m, t=None, a=None, **rule):
+    f = ctx.assemble((n, n, n), (1.0 / n,) * 3, t=t, alpha=a, **rule)
+    phi, h = ctx.apply_full(f, torch.from_numpy(m).cuda(), prec="fp64")
+    torch.cuda.synchronize()
+    f.free()
+    return phi, h
+
+
+def _rel(a, b):
+    return float((a - b).norm() / b.norm())
+
+
+@pytest.mark.parametrize("n", [128, 256])
+def test_certificate_bounds_the_field_error(ctx, trained, n):
+    """Each rule's certified operator errors against the measured relative L2
+    errors of its FP64 apply against the reference rule's (the certificate's
+    reference, 96 nodes), on the vortex and on a random unit field: the
+    vortex errors stay below the certificate and the random-field errors,
+    whose expectation the certificate is, within 10 % above it.  The plain
+    M = 40 rule is rejected at 256^3 (its near-cell error), accepted at 128^3."""
+    params, _loss = trained
+    h = 1.0 / n
+    fields = {"vortex": inputs.vortex_field(n, seed=0), "random": inputs.random_unit_field(n, seed=1)}
+    tr, ar = quadrule.reference_rule(h)
+    refs = {k: _apply(ctx, n, m, t=tr, a=ar) for k, m in fields.items()}
+    rules = {"c0 M=40": quadrule.base_rule(40)[:2], "c0 M=28": quadrule.base_rule(28)[:2],
+             "theorem M=64": sinc.sinc_nodes(64, step_rule=1, h_min=h)[0::2]}
+    r = learned.predict(ctx, params, (n, n, n), 1e-6)
+    rules["learned"] = (r["t"], r["alpha"])
+    certs = {}
+    for name, (t, a) in rules.items():
+        cp, ch = ctx.quad_certify((n, n, n), (h,) * 3, t, a)
+        certs[name] = (cp, ch)
+        for fk, m in fields.items():
+            phi, hf = _apply(ctx, n, m, t=np.asarray(t), a=np.asarray(a))
+            ep, eh = _rel(phi, refs[fk][0]), _rel(hf, refs[fk][1])
+            print(f"{n}^3 {name:12s} certified phi {cp:.2e} h {ch:.2e} | {fk} measured phi {ep:.2e} h {eh:.2e}")
+            slack = 1.0 if fk == "vortex" else 1.1
+            assert ep <= slack * cp and eh <= slack * ch, (name, fk)
+    plain = max(certs["c0 M=40"])
+    assert (plain > 1e-6) if n == 256 else (plain < 1e-6)
+
+
+@pytest.fixture(scope="module")
+def gain(ctx, trained):
     params, _loss = trained
     n = (128, 128, 128)
-    r = learned.predict(ctx, params, n, 1e-6)
-    print("predict 128^3 at 1e-6:", {k: v for k, v in r.items() if k not in ("t", "alpha")})
-    assert not r["fell_back"] and r["judged"] <= 1e-6 and r["R"] <= 32
-    h = 1.0 / 128
-    check = inputs.sentinel_offsets(n, "check")
-    tr, ar = quadrule.reference_rule(h)
-    ref = quadrule.kernel_values(n, (h,) * 3, tr, ar, check)
-    e_learned = quadrule.judge(n, (h,) * 3, r["t"], r["alpha"], ref, check)
-    assert abs(e_learned - r["judged"]) <= 1e-8 * r["judged"]
-    t0, a0, _ = quadrule.base_rule(r["R"])
-    e_plain = quadrule.judge(n, (h,) * 3, t0, a0, ref, check)
-    print(f"check offsets: learned {e_learned:.3e}, plain sinc with R'={r['R']} {e_plain:.3e}")
-    assert e_learned <= e_plain
+    out = {mode: learned.predict(ctx, params, n, 1e-6, mode=mode)
+           for mode in ("network", "network_proposal", "search")}
+    # plain sinc rules (c0 = 2.15): the fewest nodes certified within 1e-6
+    plain = None
+    for M in range(24, 41):
+        t, a, _ = quadrule.base_rule(M)
+        if max(ctx.quad_certify(n, (1 / 128,) * 3, t, a)) <= 1e-6:
+            plain = M
+            break
+    return out, plain
+
+
+def test_learned_rule_needs_fewer_nodes_than_plain_sinc(ctx, gain):
+    """At 128^3 and a certified 1e-6 the learned rule needs at most 0.8x the
+    nodes of the plain sinc rule (reading: the node count sets the apply's
+    work linearly, so 0.8x is a 1.25x shorter apply)."""
+    out, plain = gain
+    r = out["network"]
+    print("plain sinc nodes for 1e-6 at 128^3:", plain)
+    for mode, rr in out.items():
+        print(mode, {k: v for k, v in rr.items() if k not in ("t", "alpha")})
+    assert plain is not None
+    assert not r["fell_back"] and r["accuracy_met"] and r["judged"] <= 1e-6
+    assert r["R"] <= 0.8 * plain
+
+
+def test_network_versus_search_without_network(ctx, gain):
+    """Ablation.  Without the network, bisection over R' finds the smallest
+    fitted rule; the network's error head lands within 2 nodes of it with
+    fewer fits.  Both certified within tol."""
+    out, _plain = gain
+    net, search = out["network"], out["search"]
+    assert search["accuracy_met"] and not search["fell_back"]
+    assert net["R"] <= search["R"] + 2
+    assert net["fits"] < search["fits"]
+
+
+def test_network_proposal_is_no_better_start(ctx, trained):
+    """Ablation of the proposed nodes and weights, on held-out cases: fits
+    started from the network's outputs end above fits started from the plain
+    rule (geometric mean of the error ratio > 1 at every iteration count
+    measured): the proposals are no warm start, so the default mode fits
+    from the plain rule and the network contributes its error head."""
+    params, _loss = trained
+    test = learned.prepare_cases(256, seed=11, shuffle_seed=12)
+    y, _z, _a = ctx.mlp_forward(params, test["x"])
+    for it in (0, 20, 60):
+        _y, _t, _a2, e_net = ctx.quad_fit(test["grids"], test["hmin"], test["sent"], test["w"], test["R"], y, it)
+        _y, _t, _a2, e_pl = ctx.quad_fit(test["grids"], test["hmin"], test["sent"], test["w"], test["R"], None, it)
+        torch.cuda.synchronize()
+        r = (e_net / e_pl).cpu().numpy()
+        gm = float(np.exp(np.mean(np.log(r))))
+        print(f"{it} LM iterations: error from the proposal / from the plain rule, geometric mean {gm:.2f}, "
+              f"better in {np.mean(r < 1):.0%} of the cases")
+        assert gm > 1.0
 
 
 def test_predict_and_fallback(ctx, trained):
@@ -225,5 +339,18 @@ def test_predict_and_fallback(ctx, trained):
     r = learned.predict(ctx, params, (48, 64, 40), 1e-6)
     print("predict 48x64x40 at 1e-6:", {k: v for k, v in r.items() if k not in ("t", "alpha")})
     assert not r["fell_back"] and 16 <= r["R"] <= 32 and r["judged"] <= 1e-6
-    r2 = learned.predict(ctx, params, (48, 64, 40), 1e-13)   # unattainable with R' <= 32
-    assert r2["fell_back"] and r2["R"] == 64 and r2["judged"] > 1e-13
+    # unattainable with R' <= 32: the 64-node theorem-step rule, which meets it
+    r2 = learned.predict(ctx, params, (48, 64, 40), 1e-13)
+    assert r2["fell_back"] and r2["R"] == 64 and r2["judged"] <= 1e-13 and r2["accuracy_met"]
+    # the returned fallback rule's certificate is its own
+    h = 1.0 / 64
+    t, a = sinc.sinc_nodes(64, step_rule=1, h_min=h)[0::2]
+    assert np.allclose(r2["t"], t, rtol=1e-15) and np.allclose(r2["alpha"], a, rtol=1e-14)
+    cp, ch = ctx.quad_certify((48, 64, 40), (h,) * 3, t, a)
+    assert abs(r2["err_phi"] - cp) <= 1e-9 * cp + 1e-13 and abs(r2["err_h"] - ch) <= 1e-9 * ch + 1e-13
+    # below the certificate's FP64 floor nothing qualifies: DEMAG_E_ACCURACY,
+    # with the fallback rule returned
+    r3 = learned.predict(ctx, params, (48, 64, 40), 1e-17)
+    assert r3["fell_back"] and r3["R"] == 64 and not r3["accuracy_met"] and r3["judged"] > 1e-17
+    with pytest.raises(api.DemagError):
+        ctx.quad_predict(params, (32, 32, 16), (0.1, 0.1, 0.2), 1e-6)   # non-cubic cells
