@@ -141,6 +141,59 @@ def test_cp_4096_rank10_sampled(ctx):
     print(f"cp 4096: worst sampled column rel err {worst:.2e}")
 
 
+def _check_sampled(got_all, cols_of, R, n, F, M, rng, label, count=30):
+    """count sampled (q, s, k, column) jobs per axis against direct FP64
+    convolutions of the oracle's generators with the input columns."""
+    worst = 0.0
+    for d in range(3):
+        for _ in range(count):
+            q, s, k, l = int(rng.integers(3)), int(rng.integers(2)), int(rng.integers(M)), int(rng.integers(R[d]))
+            t = structured.type_of(q, d, s)
+            u = cols_of(q, d, l).astype(np.float64)
+            ref = np.convolve(F[t, k], u)[n - 1:2 * n - 1]
+            got = got_all[d][q, s, k, l].astype(np.float64)
+            nrm = np.linalg.norm(ref)
+            err = np.linalg.norm(got - ref)
+            assert err <= 1e-6 * nrm + 1e-12 * np.abs(F[t, k]).sum() * np.linalg.norm(u), (label, d, q, s, k, l)
+            if nrm > 0:
+                worst = max(worst, err / nrm)
+    print(f"{label} 4096: worst sampled column rel err {worst:.2e}")
+
+
+def test_tucker_tt_4096_sampled(ctx):
+    """n = 4096 per axis, M = 40: Tucker (8,8,8) and TT (1,8,8,1) inputs (seed 1),
+    30 sampled jobs of each axis against direct FP64 convolutions; block
+    tables exactly."""
+    n, M = 4096, 40
+    f = ctx.assemble((n, n, n), (1 / n,) * 3, M=M)
+    _t, tau, alpha = sinc.sinc_nodes(M)
+    F = sinc.scaled_factors(n, 1 / n, tau, alpha)
+    rng = np.random.default_rng(5)
+    tk = inputs.tucker_input(n, ranks=(8, 8, 8), seed=1, dtype=np.float32)
+    V = [_dev(np.stack([tk.U[q][d].T for q in range(3)])) for d in range(3)]
+    out, table = ctx.apply_tucker(f, V)
+    torch.cuda.synchronize()
+    assert np.array_equal(table, structured.block_table(M, (8, 8, 8)))
+    _check_sampled([o.cpu().numpy() for o in out], lambda q, d, l: tk.U[q][d][:, l], (8, 8, 8), n, F, M, rng,
+                   "tucker (8,8,8)")
+    del out
+    tt = inputs.tt_input(n, ranks=(8, 8), seed=1, dtype=np.float32)
+    G1 = _dev(np.stack([tt.G1[q].T for q in range(3)]))
+    G2 = _dev(np.stack([tt.G2[q].transpose(0, 2, 1) for q in range(3)]))
+    G3 = _dev(np.stack([tt.G3[q] for q in range(3)]))
+    out, table = ctx.apply_tt(f, G1, G2, G3)
+    torch.cuda.synchronize()
+    assert np.array_equal(table, structured.block_table(M, (8, 64, 8)))
+
+    def tt_cols(q, d, l):
+        if d == 0:
+            return tt.G1[q][:, l]                    # column l of G1
+        if d == 1:
+            return tt.G2[q][l // 8, :, l % 8]        # fibre (a, b) = (l // r2, l % r2)
+        return tt.G3[q][l, :]                        # row l of G3
+    _check_sampled([o.cpu().numpy() for o in out], tt_cols, (8, 64, 8), n, F, M, rng, "tt (1,8,8,1)")
+
+
 def test_columns_rejects_bad_arguments(ctx):
     f = ctx.assemble((8, 8, 8), (0.125,) * 3, M=4)
     lib = api.library()
