@@ -502,18 +502,20 @@ def structured_record(ctx, args):
     t64, _tau, a64 = fa.nodes()
     certified = {"m40_c0_2.15": ctx.quad_certify((n, n, n), (1.0 / n,) * 3, t40, a40),
                  "theorem_m64": ctx.quad_certify((n, n, n), (1.0 / n,) * 3, t64, a64)}
-    cases = {"cp_r10": lambda: ctx.apply_cp(f, U), "tucker_888": lambda: ctx.apply_tucker(f, V),
-             "tt_188_1": lambda: ctx.apply_tt(f, G1, G2, G3), "cp_r10_theorem_m64": lambda: ctx.apply_cp(fa, U),
-             "tucker_888_theorem_m64": lambda: ctx.apply_tucker(fa, V),
-             "tt_188_1_theorem_m64": lambda: ctx.apply_tt(fa, G1, G2, G3)}
-    for name, fn in cases.items():
+    cases = {}
+    for prec in ("fp64", "fp32"):
+        for rname, ff in (("", f), ("_theorem_m64", fa)):
+            cases[f"cp_r10{rname}_{prec}"] = (prec, lambda ff=ff, prec=prec: ctx.apply_cp(ff, U, prec=prec))
+            cases[f"tucker_888{rname}_{prec}"] = (prec, lambda ff=ff, prec=prec: ctx.apply_tucker(ff, V, prec=prec))
+            cases[f"tt_188_1{rname}_{prec}"] = (prec, lambda ff=ff, prec=prec: ctx.apply_tt(ff, G1, G2, G3, prec=prec))
+    for name, (prec, fn) in cases.items():
         ms, prof = _timed(ctx, fn, args.steps, args.warmup)
-        rec = prof["fft/xyz"]
+        rec = prof["fft/xyz" if prec == "fp64" else "fft32/xyz"]
         per_ms = rec["ms"] / rec["launches"]
         bytes_ = rec["bytes"] / rec["launches"]
         flops = rec["flops"] / rec["launches"]
         achieved = bytes_ / (per_ms * 1e-3) / 1e9
-        out[name] = {"ms_per_apply": round(ms, 4), "implicit_cells_per_s": n ** 3 / (ms * 1e-3),
+        out[name] = {"ms_per_apply": round(ms, 4), "implicit_cells_per_s": n ** 3 / (ms * 1e-3), "transforms": prec,
                      "roofline": {"bound": "hbm", "kernel": "k_fft_fwd + k_fft_jobs (one apply)",
                                   "achieved": round(achieved, 1), "peak": HBM_GBS, "unit": "GB/s",
                                   "frac": round(achieved / HBM_GBS, 4), "traffic": None,
@@ -545,7 +547,7 @@ def structured_record(ctx, args):
     torch.cuda.empty_cache()
     return {"workload": "structured apply, n=4096 per axis, CP rank 10 / Tucker (8,8,8) / TT (1,8,8,1), U[-1,1] "
                         "factors seed 1; sinc rule M=40 (c0=2.15) and the theorem-step rule with 64 nodes; FP32 "
-                        "columns, FP64 transforms",
+                        "columns; FP64 transforms, and FP32 transforms (FP64 forward transforms of the inputs)",
             "certified_rule_err": {k: {"phi": v[0], "h": v[1]} for k, v in certified.items()},
             "results": out, "recompression_phi": recomp}
 

@@ -239,10 +239,14 @@ demag_status demag_batch_tune(demag_ctx *ctx, demag_batch *b, const char *path, 
  * Applying the Kronecker operator to a structured tensor needs only the
  * Toeplitz products of its factor columns (Eqs. (kron_eval_cp),
  * (kron_eval_tuck)), computed here through zero-padded FFTs of length
- * L = 2^p >= 2 n_d - 1 (Sec. 4, Eq. (fft_pot)): columns are read and written
- * in FP32, the transforms and the kernel spectra are FP64.  Axis lengths up
- * to 4096.  Results are in the scaled domain: multiply the potential by the
- * length scale (demag_factors_length_scale).
+ * L = 2^p >= 2 n_d - 1 (Sec. 4, Eq. (fft_pot)).  Columns are read and written
+ * in FP32; `prec` sets the transforms: DEMAG_FP64 runs every transform and
+ * product in FP64; DEMAG_FP32 runs the forward transforms of the input
+ * columns in FP64 and the kernel spectra, products and inverse transforms (one
+ * per output column) in FP32.  DEMAG_BF16X2/X3 give DEMAG_E_UNSUPPORTED (the
+ * butterflies are no matrix-core contractions).  Axis lengths up to 4096.
+ * Results are in the scaled domain: multiply the potential by the length
+ * scale (demag_factors_length_scale).
  *
  * Column sets per axis d, all device FP32, one column contiguous:
  *   in[d]:  [3 components q][R_d][n_d]
@@ -253,11 +257,11 @@ demag_status demag_batch_tune(demag_ctx *ctx, demag_batch *b, const char *path, 
  * differentiated for the field component along d.  The caller owns all
  * buffers; out must not overlap in. */
 demag_status demag_prepare_structured(demag_ctx *ctx, demag_factors *f);
-demag_status demag_apply_columns(demag_ctx *ctx, demag_factors *f, const int32_t R[3],
+demag_status demag_apply_columns(demag_ctx *ctx, demag_factors *f, demag_prec prec, const int32_t R[3],
                                  const float *const in[3], float *const out[3]);
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
- * result as demag_apply_columns, bit for bit, with the column spectra in a
+ * result as demag_apply_columns with DEMAG_FP64, bit for bit, with the column spectra in a
  * static 64 MiB device array per GPU instead of the context workspace; no
  * hipMalloc, hipFree or other allocating call.  Limits: the column spectra,
  * 16 (L_d/2 + 1) bytes per input column (3 R_d columns on axis d), must fit
@@ -279,18 +283,18 @@ demag_status demag_apply_columns_noalloc(demag_ctx *ctx, const demag_factors *f,
  * out[d] with s = 1 exactly when o is the field along d.  Output o is
  * sum over its terms of lambda^q_l out[x][.] o out[y][.] o out[z][.], times
  * the length scale L for the potential (o = 0). */
-demag_status demag_apply_cp(demag_ctx *ctx, demag_factors *f, int32_t r, const float *const U[3],
+demag_status demag_apply_cp(demag_ctx *ctx, demag_factors *f, demag_prec prec, int32_t r, const float *const U[3],
                             float *const out[3], int32_t *table);
 /* Tucker input, ranks r[3]: U[d] = [3 q][r_d][n_d].  Result out[d] with
  * R_d = r_d and the host block table [4][3 M blocks][3 axes]: block (q, k),
  * index q M + k, of output o is [[C^q; out[x] cols c_x..c_x+r_x-1, ...]]
  * with first columns c_d = ((q 2 + s) M + k) r_d. */
-demag_status demag_apply_tucker(demag_ctx *ctx, demag_factors *f, const int32_t r[3],
+demag_status demag_apply_tucker(demag_ctx *ctx, demag_factors *f, demag_prec prec, const int32_t r[3],
                                 const float *const U[3], float *const out[3], int32_t *table);
 /* TT input with ranks (1, r1, r2, 1): G1 = [3 q][r1][n_x] (columns of G1),
  * G2 = [3 q][r1][r2][n_y] (fibres G2[a, :, b]), G3 = [3 q][r2][n_z] (rows of
  * G3).  As Tucker with R = (r1, r1 r2, r2); block table as for Tucker. */
-demag_status demag_apply_tt(demag_ctx *ctx, demag_factors *f, int32_t r1, int32_t r2,
+demag_status demag_apply_tt(demag_ctx *ctx, demag_factors *f, demag_prec prec, int32_t r1, int32_t r2,
                             const float *G1, const float *G2, const float *G3,
                             float *const out[3], int32_t *table);
 

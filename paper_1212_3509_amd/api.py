@@ -88,11 +88,11 @@ _SIGS = {
     "demag_quad_predict": (C.c_int, [_P, _P, C.POINTER(Grid), C.c_double, C.c_int32, C.c_int32,
                                      C.POINTER(QuadResult)]),
     "demag_prepare_structured": (C.c_int, [_P, _P]),
-    "demag_apply_columns": (C.c_int, [_P, _P, _P, _P, _P]),
+    "demag_apply_columns": (C.c_int, [_P, _P, C.c_int, _P, _P, _P]),
     "demag_apply_columns_noalloc": (C.c_int, [_P, _P, _P, _P, _P]),
-    "demag_apply_cp": (C.c_int, [_P, _P, C.c_int32, _P, _P, _P]),
-    "demag_apply_tucker": (C.c_int, [_P, _P, _P, _P, _P, _P]),
-    "demag_apply_tt": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P, _P, _P, _P, _P]),
+    "demag_apply_cp": (C.c_int, [_P, _P, C.c_int, C.c_int32, _P, _P, _P]),
+    "demag_apply_tucker": (C.c_int, [_P, _P, C.c_int, _P, _P, _P, _P]),
+    "demag_apply_tt": (C.c_int, [_P, _P, C.c_int, C.c_int32, C.c_int32, _P, _P, _P, _P, _P]),
     "demag_recompress_cp": (C.c_int, [_P, _P, C.c_int32, _P, _P, _P, _P, C.c_double, C.c_int32, C.c_int32, _P,
                                       _P, _P, _P, _P, _P, _P]),
     "demag_bf16_split": (C.c_int, [_P, _P, _P, C.c_size_t, C.c_int32]),
@@ -380,44 +380,44 @@ class Context:
         self.use_current_stream()
         _check(library().demag_prepare_structured(self.handle, f.handle), "demag_prepare_structured")
 
-    def apply_columns(self, f: Factors, cols_in):
+    def apply_columns(self, f: Factors, cols_in, prec: str = "fp64"):
         """cols_in[d]: float32 CUDA tensor [3][R_d][n_d].  Returns out[d]
-        [3][2][M][R_d][n_d]."""
+        [3][2][M][R_d][n_d].  prec: "fp64" or "fp32" transforms."""
         R = [int(c.shape[1]) for c in cols_in]
         out = self._cols_out(f, R, cols_in[0].device)
         self.use_current_stream()
         Ra = (C.c_int32 * 3)(*R)
-        _check(library().demag_apply_columns(self.handle, f.handle, Ra, self._ptr3(cols_in), self._ptr3(out)),
-               "demag_apply_columns")
+        _check(library().demag_apply_columns(self.handle, f.handle, PRECISIONS[prec], Ra, self._ptr3(cols_in),
+                                             self._ptr3(out)), "demag_apply_columns")
         return out
 
-    def apply_cp(self, f: Factors, U):
+    def apply_cp(self, f: Factors, U, prec: str = "fp64"):
         """U[d]: float32 CUDA tensor [3][r][n_d].  Returns (out[3], table)."""
         r = int(U[0].shape[1])
         out = self._cols_out(f, [r, r, r], U[0].device)
         table = np.empty((4, 3 * f.M * r, 3), dtype=np.int32)
         self.use_current_stream()
-        _check(library().demag_apply_cp(self.handle, f.handle, r, self._ptr3(U), self._ptr3(out),
+        _check(library().demag_apply_cp(self.handle, f.handle, PRECISIONS[prec], r, self._ptr3(U), self._ptr3(out),
                                         table.ctypes.data), "demag_apply_cp")
         return out, table
 
-    def apply_tucker(self, f: Factors, U):
+    def apply_tucker(self, f: Factors, U, prec: str = "fp64"):
         r = [int(u.shape[1]) for u in U]
         out = self._cols_out(f, r, U[0].device)
         table = np.empty((4, 3 * f.M, 3), dtype=np.int32)
         self.use_current_stream()
-        _check(library().demag_apply_tucker(self.handle, f.handle, (C.c_int32 * 3)(*r), self._ptr3(U),
-                                            self._ptr3(out), table.ctypes.data), "demag_apply_tucker")
+        _check(library().demag_apply_tucker(self.handle, f.handle, PRECISIONS[prec], (C.c_int32 * 3)(*r),
+                                            self._ptr3(U), self._ptr3(out), table.ctypes.data), "demag_apply_tucker")
         return out, table
 
-    def apply_tt(self, f: Factors, G1, G2, G3):
+    def apply_tt(self, f: Factors, G1, G2, G3, prec: str = "fp64"):
         """G1 [3][r1][n_x], G2 [3][r1][r2][n_y], G3 [3][r2][n_z] (float32 CUDA)."""
         r1, r2 = int(G1.shape[1]), int(G3.shape[1])
         out = self._cols_out(f, [r1, r1 * r2, r2], G1.device)
         table = np.empty((4, 3 * f.M, 3), dtype=np.int32)
         self.use_current_stream()
-        _check(library().demag_apply_tt(self.handle, f.handle, r1, r2, _ptr(G1), _ptr(G2), _ptr(G3),
-                                        self._ptr3(out), table.ctypes.data), "demag_apply_tt")
+        _check(library().demag_apply_tt(self.handle, f.handle, PRECISIONS[prec], r1, r2, _ptr(G1), _ptr(G2),
+                                        _ptr(G3), self._ptr3(out), table.ctypes.data), "demag_apply_tt")
         return out, table
 
     def recompress_cp(self, n, cols, table, lam, eps, rmax=32, max_sweeps=10, seed=7):

@@ -478,9 +478,15 @@ demag_status demag_prepare_structured(demag_ctx *ctx, demag_factors *f) {
   return st == DEMAG_OK ? note_use(ctx, f) : st;
 }
 
-demag_status demag_apply_columns(demag_ctx *ctx, demag_factors *f, const int32_t R[3], const float *const in[3],
-                                 float *const out[3]) {
+demag_status demag_apply_columns(demag_ctx *ctx, demag_factors *f, demag_prec prec, const int32_t R[3],
+                                 const float *const in[3], float *const out[3]) {
   DEMAG_REQUIRE(ctx && f && R && in && out, "demag_apply_columns: NULL argument");
+  if (prec == DEMAG_BF16X2 || prec == DEMAG_BF16X3) {
+    set_error("demag_apply_columns: the transforms' butterflies are no matrix-core contractions; no bfloat16 "
+              "split (use DEMAG_FP32 or DEMAG_FP64)");
+    return DEMAG_E_UNSUPPORTED;
+  }
+  DEMAG_REQUIRE(prec == DEMAG_FP64 || prec == DEMAG_FP32, "demag_apply_columns: unknown precision");
   DEMAG_REQUIRE(!f->dense, "demag_apply_columns: needs a uniform grid (Toeplitz factors)");
   for (int d = 0; d < 3; ++d) {
     DEMAG_REQUIRE(R[d] >= 0 && R[d] <= 65536, "demag_apply_columns: R out of range");
@@ -491,7 +497,7 @@ demag_status demag_apply_columns(demag_ctx *ctx, demag_factors *f, const int32_t
   demag_status st = prepare_spectra(ctx, f);
   for (int d = 0; d < 3 && st == DEMAG_OK; ++d)
     st = check_finite(ctx, in[d], size_t(3) * R[d] * f->n[d], false, "demag_apply_columns");
-  if (st == DEMAG_OK) st = launch_columns(ctx, f, R, in, out, nullptr, 0);
+  if (st == DEMAG_OK) st = launch_columns(ctx, f, prec, R, in, out, nullptr, 0);
   return st == DEMAG_OK ? note_use(ctx, f) : st;
 }
 
@@ -501,12 +507,12 @@ inline int32_t col_index(int q, int s, int k, int l, int M, int R) { return ((q 
 inline int slot_of(int o, int d) { return (o == d + 1) ? 1 : 0; }
 }  // namespace
 
-demag_status demag_apply_cp(demag_ctx *ctx, demag_factors *f, int32_t r, const float *const U[3], float *const out[3],
-                            int32_t *table) {
+demag_status demag_apply_cp(demag_ctx *ctx, demag_factors *f, demag_prec prec, int32_t r, const float *const U[3],
+                            float *const out[3], int32_t *table) {
   DEMAG_REQUIRE(ctx && f && U && out, "demag_apply_cp: NULL argument");
   DEMAG_REQUIRE(r >= 1, "demag_apply_cp: rank must be >= 1");
   const int32_t R[3] = {r, r, r};
-  demag_status st = demag_apply_columns(ctx, f, R, U, out);
+  demag_status st = demag_apply_columns(ctx, f, prec, R, U, out);
   if (st != DEMAG_OK || !table) return st;
   const int M = f->M;
   for (int o = 0; o < 4; ++o)
@@ -530,22 +536,22 @@ void block_table(int M, const int32_t R[3], int32_t *table) {
 }
 }  // namespace
 
-demag_status demag_apply_tucker(demag_ctx *ctx, demag_factors *f, const int32_t r[3], const float *const U[3],
-                                float *const out[3], int32_t *table) {
+demag_status demag_apply_tucker(demag_ctx *ctx, demag_factors *f, demag_prec prec, const int32_t r[3],
+                                const float *const U[3], float *const out[3], int32_t *table) {
   DEMAG_REQUIRE(ctx && f && r && U && out, "demag_apply_tucker: NULL argument");
   DEMAG_REQUIRE(r[0] >= 1 && r[1] >= 1 && r[2] >= 1, "demag_apply_tucker: ranks must be >= 1");
-  demag_status st = demag_apply_columns(ctx, f, r, U, out);
+  demag_status st = demag_apply_columns(ctx, f, prec, r, U, out);
   if (st == DEMAG_OK && table) block_table(f->M, r, table);
   return st;
 }
 
-demag_status demag_apply_tt(demag_ctx *ctx, demag_factors *f, int32_t r1, int32_t r2, const float *G1,
-                            const float *G2, const float *G3, float *const out[3], int32_t *table) {
+demag_status demag_apply_tt(demag_ctx *ctx, demag_factors *f, demag_prec prec, int32_t r1, int32_t r2,
+                            const float *G1, const float *G2, const float *G3, float *const out[3], int32_t *table) {
   DEMAG_REQUIRE(ctx && f && G1 && G2 && G3 && out, "demag_apply_tt: NULL argument");
   DEMAG_REQUIRE(r1 >= 1 && r2 >= 1, "demag_apply_tt: ranks must be >= 1");
   const int32_t R[3] = {r1, r1 * r2, r2};
   const float *const in[3] = {G1, G2, G3};
-  demag_status st = demag_apply_columns(ctx, f, R, in, out);
+  demag_status st = demag_apply_columns(ctx, f, prec, R, in, out);
   if (st == DEMAG_OK && table) block_table(f->M, R, table);
   return st;
 }
@@ -738,6 +744,7 @@ demag_status demag_factors_free(demag_factors *f) {
     if (f->bf[d]) (void)hipFree(f->bf[d]);
     if (f->bfw[d]) (void)hipFree(f->bfw[d]);
     if (f->spec[d]) (void)hipFree(f->spec[d]);
+    if (f->spec32[d]) (void)hipFree(f->spec32[d]);
     if (f->twiddle[d]) (void)hipFree(f->twiddle[d]);
   }
   if (f->k3) (void)hipFree(f->k3);

@@ -30,6 +30,23 @@
 // job it reads the column's frequency pairs (f, N - f) and the kernel
 // spectrum (from L2: every job group of a column reads the same 64 KB),
 // multiplies, transforms back and writes the n outputs.
+//
+// FP32 transforms (DEMAG_FP32): the forward transforms stay FP64, the kernel
+// spectra and the per-job inverse transforms are FP32.  An FP32 rounding of
+// a spectrum element is relative to that element and survives the product
+// unchanged, and an FP32 inverse transform's roundoff is relative to the
+// norm of its own output (Parseval), so the columns keep the 1e-6 bar; an
+// FP32 forward transform would not (its roundoff, relative to the input
+// column's norm, is shaped by the kernel spectrum).  The packing of the
+// half-length complex inverse transform is linear in the two spectrum
+// values a job multiplies: with G the kernel spectrum,
+//   Z[f] = G[f] A[f] + G[N-f] B[f]   (even kernels, G real),
+//   Z[f] = i (g[f] A[f] - g[N-f] B[f])   (odd kernels, G = i g),
+//   A[f] = U[f] (1 + i conj W_L^f) / 2,  B[f] = conj U[N-f] (1 - i conj W_L^f) / 2,
+// so k_fft_fwd32 stores A and B (FP32) per column, and k_fft_jobs32 keeps
+// each thread's 16 pairs in registers across the workgroup's jobs, forms its
+// 16 points of Z per job and runs the first radix-16 pass on them in
+// registers (no LDS round for the packing).
 #include "fft_core.h"
 #include "internal.h"
 
@@ -99,6 +116,11 @@ __global__ void k_twiddles(double2 *__restrict__ tw, int N) {
   tw[e] = make_double2(c, s);
 }
 
+__global__ void k_to_f32(const double *__restrict__ src, float *__restrict__ dst, size_t count) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = float(src[i]);
+}
+
 // ---------------------------------------------------------------- jobs
 // frequency pairs (f, N - f), f = 0..N/2, per thread at N = 4096: 2049 pairs
 constexpr int kMaxPairs = (kPoints / 2 + 1 + kThreads - 1) / kThreads;
@@ -109,6 +131,8 @@ struct ColAxis {
   const float *in;
   float *out;
   const double *spec;
+  const float *spec32;       // FP32 copies of the kernel spectra (FP32 transforms)
+  const cplx32 *tw32;        // FP32 twiddles W_N^e, e < N (FP32 transforms)
   const double2 *tw;
   size_t u_off;              // first spectrum of this axis in U (points)
   int n, L, R;
@@ -133,8 +157,11 @@ __device__ inline int axis_of(const ColAxes &P, int idx, bool wg) {
   return d;
 }
 
-// Forward real transform of every column: U[col][f], f = 0..N (N + 1 values).
-__global__ __launch_bounds__(kThreads) void k_fft_fwd(const ColAxes P, cplx *__restrict__ Uall, int lds_points) {
+// Forward real transform of every column (FP64).  AB == false: the unpacked
+// spectrum U[col][f], f = 0..N (N + 1 values, FP64).  AB == true: the FP32
+// packing factors A[col][f], B[col][f], f < N (2 N values per column, A first).
+template <bool AB>
+__global__ __launch_bounds__(kThreads) void k_fft_fwd(const ColAxes P, void *__restrict__ Uout, int lds_points) {
   extern __shared__ cplx wk[];   // N points (padded), then the twiddle tables
   const int d = axis_of(P, blockIdx.x, false);
   const ColAxis &A = P.a[d];
@@ -142,7 +169,6 @@ __global__ __launch_bounds__(kThreads) void k_fft_fwd(const ColAxes P, cplx *__r
   cplx *tlo = wk + lds_points, *thi = tlo + 64;
   const int col = blockIdx.x - A.col0;
   load_twiddles(tlo, thi, N, A.tw);
-  cplx *U = Uall + A.u_off;
   const float *u = A.in + size_t(col) * n;
   // all loads of a thread in flight before the LDS stores
   constexpr int kE = kPoints / kThreads;
@@ -164,12 +190,27 @@ __global__ __launch_bounds__(kThreads) void k_fft_fwd(const ColAxes P, cplx *__r
   sincospi(-1.0 / double(N), &sw, &cw);
   const cplx w1{cw, sw};         // W_L^1
   // X[f] = E + W_L^f O with E = (Z[f] + conj Z[N-f])/2, O = (Z[f] - conj Z[N-f])/(2i)
-  cplx *Uc = U + size_t(col) * (N + 1);
-  for (int f = threadIdx.x; f <= N; f += kThreads) {
+  auto spectrum = [&](int f) {
     const cplx zf = wk[slot<true>(f & (N - 1))];
     const cplx zcc = cconj(wk[slot<true>((N - f) & (N - 1))]);
     const cplx D{0.5 * (zf.x - zcc.x), 0.5 * (zf.y - zcc.y)};
-    Uc[f] = cadd(cplx{0.5 * (zf.x + zcc.x), 0.5 * (zf.y + zcc.y)}, cmul(wl(f, N, tlo, thi, w1), cplx{D.y, -D.x}));
+    return cadd(cplx{0.5 * (zf.x + zcc.x), 0.5 * (zf.y + zcc.y)}, cmul(wl(f, N, tlo, thi, w1), cplx{D.y, -D.x}));
+  };
+  if constexpr (!AB) {
+    cplx *Uc = static_cast<cplx *>(Uout) + A.u_off + size_t(col) * (N + 1);
+    for (int f = threadIdx.x; f <= N; f += kThreads) Uc[f] = spectrum(f);
+  } else {
+    cplx32 *Ac = static_cast<cplx32 *>(Uout) + A.u_off + size_t(col) * (2 * N);
+    cplx32 *Bc = Ac + N;
+    for (int f = threadIdx.x; f < N; f += kThreads) {
+      const cplx uf = spectrum(f), uc = cconj(spectrum(N - f));
+      const cplx wc = cconj(wl(f, N, tlo, thi, w1));
+      const cplx iw{-wc.y, wc.x};                       // i conj W_L^f
+      const cplx a = cmul(uf, cplx{1.0 + iw.x, iw.y});
+      const cplx b = cmul(uc, cplx{1.0 - iw.x, -iw.y});
+      Ac[f] = cplx32{float(0.5 * a.x), float(0.5 * a.y)};
+      Bc[f] = cplx32{float(0.5 * b.x), float(0.5 * b.y)};
+    }
   }
 }
 
@@ -275,6 +316,135 @@ __global__ __launch_bounds__(kThreads) void k_fft_jobs(const ColAxes P, const cp
   }
 }
 
+// Output of the FP32 inverse transform (as OutSink).
+struct OutSink32 {
+  float *y;
+  int n;
+  float inv_n;
+  __device__ void operator()(int, int m, cplx32 z) const {
+    const int a = 2 * m;
+    if (a + 1 < n) {
+      *reinterpret_cast<float2 *>(y + a) = make_float2(z.x * inv_n, z.y * inv_n);
+    } else if (a < n) {
+      y[a] = z.x * inv_n;
+    }
+  }
+};
+
+// Passes of the inverse transform after the first (radix 16, done by the
+// caller in registers), with the last pass writing the outputs.
+template <int N>
+__device__ inline void inverse_rest(cplx32 *wk, const cplx32 *tlo, const cplx32 *thi, const OutSink32 &sink) {
+  if constexpr (N == 4096) run_passes<true, kThreads, kPoints, 4096, 16, OutSink32, true, 16, 16>(wk, 0, 1, tlo, thi, sink);
+  if constexpr (N == 2048) run_passes<true, kThreads, kPoints, 2048, 16, OutSink32, true, 16, 8>(wk, 0, 1, tlo, thi, sink);
+  if constexpr (N == 1024) run_passes<true, kThreads, kPoints, 1024, 16, OutSink32, true, 16, 4>(wk, 0, 1, tlo, thi, sink);
+  if constexpr (N == 512) run_passes<true, kThreads, kPoints, 512, 16, OutSink32, true, 16, 2>(wk, 0, 1, tlo, thi, sink);
+  if constexpr (N == 256) run_passes<true, kThreads, kPoints, 256, 16, OutSink32, true, 16>(wk, 0, 1, tlo, thi, sink);
+}
+
+// FP32 jobs of one column on a line of N >= 256 points: thread g < N / 16
+// owns the points f = g + (N / 16) r, r < 16, of the first pass.
+template <int N>
+__device__ inline void jobs32_line(const ColAxis &A, int axis, int M, int q, int l, int j0, int j1,
+                                   const cplx32 *__restrict__ AB, cplx32 *wk, const cplx32 *tlo, const cplx32 *thi) {
+  constexpr int per = N / 16;
+  const int g = threadIdx.x;
+  const bool act = g < per;
+  const int n = A.n, R = A.R;
+  cplx32 a[16], b[16];
+  if (act) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      a[r] = AB[g + per * r];
+      b[r] = AB[N + g + per * r];
+    }
+  }
+  const float inv_n = 1.0f / float(N);
+  for (int j = j0; j < j1; ++j) {
+    const int s = j / M, k = j % M;
+    const int type = (axis == q) ? (s ? F_P : F_X) : (s ? F_Q : F_E);
+    const bool odd = (type == F_X || type == F_Q);
+    const float *gs = A.spec32 + size_t(type * M + k) * (N + 1);
+    if (act) {
+      float gf[16], gc[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        gf[r] = gs[g + per * r];
+        gc[r] = gs[N - g - per * r];
+      }
+      cplx32 v[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        if (odd) {
+          // i (g_f A - g_c B)
+          const float re = gf[r] * a[r].x - gc[r] * b[r].x, im = gf[r] * a[r].y - gc[r] * b[r].y;
+          v[r] = cplx32{-im, re};
+        } else {
+          v[r] = cplx32{gf[r] * a[r].x + gc[r] * b[r].x, gf[r] * a[r].y + gc[r] * b[r].y};
+        }
+      }
+      dftR<true, 16>(v);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) wk[slot<true>(16 * g + r)] = v[r];
+    }
+    __syncthreads();
+    float *y = A.out + ((size_t(q) * 2 + s) * M + k) * size_t(R) * n + size_t(l) * n;
+    inverse_rest<N>(wk, tlo, thi, OutSink32{y, n, inv_n});
+    __syncthreads();
+  }
+}
+
+// FP32 jobs: workgroup = (axis, input column q * R + l, job group), as
+// k_fft_jobs, on the column's FP32 packing factors A, B.
+__global__ __launch_bounds__(kThreads) void k_fft_jobs32(const ColAxes P, const cplx32 *__restrict__ ABall) {
+  __shared__ cplx32 wk[kPoints];
+  __shared__ cplx32 tlo[kPoints];   // W_N^e, e < N (FP32 twiddles: the whole table)
+  const cplx32 *thi = nullptr;
+  const int w = int(xcd_work_index(blockIdx.x, gridDim.x));
+  const int axis = axis_of(P, w, true);
+  const ColAxis &A = P.a[axis];
+  const int N = A.L / 2, R = A.R, M = P.M;
+  const int local = w - A.wg0;
+  const int col = local / A.groups, grp = local - col * A.groups;   // col = q * R + l
+  const int q = col / R, l = col % R;
+  for (int e = threadIdx.x; e < N; e += kThreads) tlo[e] = A.tw32[e];
+  __syncthreads();
+  const cplx32 *AB = ABall + A.u_off + size_t(col) * (2 * N);
+  const int njobs = 2 * M;
+  const int j0 = grp * A.per;
+  const int j1 = min(njobs, j0 + A.per);
+  switch (N) {
+    case 4096: jobs32_line<4096>(A, axis, M, q, l, j0, j1, AB, wk, tlo, thi); return;
+    case 2048: jobs32_line<2048>(A, axis, M, q, l, j0, j1, AB, wk, tlo, thi); return;
+    case 1024: jobs32_line<1024>(A, axis, M, q, l, j0, j1, AB, wk, tlo, thi); return;
+    case 512: jobs32_line<512>(A, axis, M, q, l, j0, j1, AB, wk, tlo, thi); return;
+    case 256: jobs32_line<256>(A, axis, M, q, l, j0, j1, AB, wk, tlo, thi); return;
+    default: break;
+  }
+  // short lines (N < 256): the packed points through LDS, then all passes
+  const float inv_n = 1.0f / float(N);
+  for (int j = j0; j < j1; ++j) {
+    const int s = j / M, k = j % M;
+    const int type = (axis == q) ? (s ? F_P : F_X) : (s ? F_Q : F_E);
+    const bool odd = (type == F_X || type == F_Q);
+    const float *gs = A.spec32 + size_t(type * M + k) * (N + 1);
+    for (int f = threadIdx.x; f < N; f += kThreads) {
+      const cplx32 a = AB[f], b = AB[N + f];
+      const float gf = gs[f], gc = gs[N - f];
+      if (odd) {
+        const float re = gf * a.x - gc * b.x, im = gf * a.y - gc * b.y;
+        wk[slot<true>(f)] = cplx32{-im, re};
+      } else {
+        wk[slot<true>(f)] = cplx32{gf * a.x + gc * b.x, gf * a.y + gc * b.y};
+      }
+    }
+    __syncthreads();
+    float *y = A.out + ((size_t(q) * 2 + s) * M + k) * size_t(R) * A.n + size_t(l) * A.n;
+    fft_lines_to<true, kThreads, kPoints, OutSink32, true, float>(wk, N, 0, 1, tlo, thi, OutSink32{y, A.n, inv_n});
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 int fft_length(int n) {
@@ -301,6 +471,13 @@ demag_status prepare_spectra(demag_ctx *ctx, demag_factors *f) {
     dim3 grid((N + 1 + 255) / 256, F_NTYPES * f->M);
     k_spectra<<<grid, 256, lds, ctx->stream>>>(f->f64[d], f->spec[d], n, L, f->M);
     DEMAG_TRY_HIP(hipGetLastError());
+    // FP32 spectra, then the FP32 twiddles W_N^e (2 N floats, 8-byte aligned: nspec is even or padded)
+    const size_t nspec_pad = nspec + (nspec & 1);
+    DEMAG_TRY_HIP(hipMalloc(&f->spec32[d], (nspec_pad + 2 * size_t(N)) * sizeof(float)));
+    k_to_f32<<<unsigned((nspec + 255) / 256), 256, 0, ctx->stream>>>(f->spec[d], f->spec32[d], nspec);
+    k_to_f32<<<unsigned((2 * size_t(N) + 255) / 256), 256, 0, ctx->stream>>>(
+        reinterpret_cast<const double *>(f->twiddle[d]), f->spec32[d] + nspec_pad, 2 * size_t(N));
+    DEMAG_TRY_HIP(hipGetLastError());
   }
   f->spec_ready = true;
   return DEMAG_OK;
@@ -312,8 +489,9 @@ size_t columns_workspace_bytes(const demag_factors *f, const int32_t R[3]) {
   return sizeof(double2) * pts;
 }
 
-demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, const int32_t R[3], const float *const in[3],
-                            float *const out[3], void *ws, size_t ws_bytes) {
+demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, demag_prec prec, const int32_t R[3],
+                            const float *const in[3], float *const out[3], void *ws, size_t ws_bytes) {
+  const bool f32 = (prec == DEMAG_FP32);
   ColAxes P{};
   P.M = f->M;
   const int njobs = 2 * f->M;
@@ -334,6 +512,12 @@ demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, const int32_
     A.in = in[d];
     A.out = out[d];
     A.spec = f->spec[d];
+    A.spec32 = f->spec32[d];
+    {
+      // the FP32 twiddles follow the FP32 spectra (see prepare_spectra)
+      const size_t nspec = size_t(F_NTYPES) * f->M * (fft_length(f->n[d]) / 2 + 1);
+      A.tw32 = reinterpret_cast<const cplx32 *>(f->spec32[d] + nspec + (nspec & 1));
+    }
     A.tw = reinterpret_cast<const double2 *>(f->twiddle[d]);
     A.n = f->n[d];
     A.L = fft_length(f->n[d]);
@@ -345,40 +529,53 @@ demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, const int32_
     A.u_off = u_points;
     col0 += ncols;
     wg0 += ncols * groups;
-    u_points += size_t(ncols) * (A.L / 2 + 1);
+    // FP64: U[0..N] per column (16-byte points); FP32: A, B (2 N 8-byte points)
+    u_points += size_t(ncols) * (f32 ? A.L : A.L / 2 + 1);
     if (ncols > 0) maxN = std::max(maxN, A.L / 2);
     // real FFT of length L ~ 2.5 L log2 L flops, forward once per column
     const double jobs = double(ncols) * njobs, lg = std::log2(double(A.L));
     flops += (jobs + ncols) * 2.5 * A.L * lg;
     // compulsory traffic: input columns, spectra, output columns
-    bytes += 4.0 * (double(ncols) * A.n + jobs * A.n) + 8.0 * double(F_NTYPES) * f->M * (A.L / 2 + 1);
+    bytes += 4.0 * (double(ncols) * A.n + jobs * A.n) + (f32 ? 4.0 : 8.0) * double(F_NTYPES) * f->M * (A.L / 2 + 1);
   }
   // column spectra of all three axes in the workspace (the context's, or
   // the caller's when ws is given)
   demag_status st = DEMAG_OK;
+  const size_t need = (f32 ? sizeof(cplx32) : sizeof(double2)) * u_points;
   if (ws) {
-    if (ws_bytes < sizeof(double2) * u_points) {
+    if (ws_bytes < need) {
       set_error("structured apply: workspace too small");
       return DEMAG_E_INVAL;
     }
   } else {
-    st = ensure_workspace(ctx, sizeof(double2) * u_points);
+    st = ensure_workspace(ctx, need);
     if (st != DEMAG_OK) return st;
     ws = ctx->ws;
   }
-  cplx *U = static_cast<cplx *>(ws);
   const int lds_points = padded_points(maxN);
   const size_t lds = sizeof(double2) * (size_t(lds_points) + 128);
-  DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_fwd),
+  hipEvent_t ev = nullptr;
+  if (f32) {
+    DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_fwd<true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    st = prof_begin(ctx, &ev);
+    if (st != DEMAG_OK) return st;
+    k_fft_fwd<true><<<ncols_all, kThreads, lds, ctx->stream>>>(P, ws, lds_points);
+    DEMAG_TRY_HIP(hipGetLastError());
+    k_fft_jobs32<<<wg0, kThreads, 0, ctx->stream>>>(P, static_cast<const cplx32 *>(ws));
+    DEMAG_TRY_HIP(hipGetLastError());
+    if (ev) st = prof_end(ctx, ev, "fft32/xyz", flops, bytes);
+    return st;
+  }
+  DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_fwd<false>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_jobs),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-  hipEvent_t ev = nullptr;
   st = prof_begin(ctx, &ev);
   if (st != DEMAG_OK) return st;
-  k_fft_fwd<<<ncols_all, kThreads, lds, ctx->stream>>>(P, U, lds_points);
+  k_fft_fwd<false><<<ncols_all, kThreads, lds, ctx->stream>>>(P, ws, lds_points);
   DEMAG_TRY_HIP(hipGetLastError());
-  k_fft_jobs<<<wg0, kThreads, lds, ctx->stream>>>(P, U, lds_points);
+  k_fft_jobs<<<wg0, kThreads, lds, ctx->stream>>>(P, static_cast<const cplx *>(ws), lds_points);
   DEMAG_TRY_HIP(hipGetLastError());
   if (ev) st = prof_end(ctx, ev, "fft/xyz", flops, bytes);
   return st;

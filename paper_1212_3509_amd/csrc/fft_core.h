@@ -1,6 +1,8 @@
-// FP64 complex FFTs in LDS shared by the structured apply and the 3D FFT
-// route: radix 16/8/4/2 Stockham passes over one or several lines, with
-// sizes known at compile time per line length.
+// Complex FFTs in LDS shared by the structured apply and the 3D FFT route:
+// radix 16/8/4/2 Stockham passes over one or several lines, with sizes known
+// at compile time per line length.  Templated on the real type: FP64
+// (cplx) throughout the 3D route and the structured forward transforms, FP32
+// (cplx32) for the structured inverse transforms of the FP32 apply.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -10,14 +12,21 @@
 namespace demag {
 namespace fftc {
 
-struct alignas(16) cplx {
-  double x, y;
+template <class T>
+struct alignas(2 * sizeof(T)) cx {
+  T x, y;
 };
-__device__ inline cplx cadd(cplx a, cplx b) { return {a.x + b.x, a.y + b.y}; }
-__device__ inline cplx csub(cplx a, cplx b) { return {a.x - b.x, a.y - b.y}; }
-__device__ inline cplx cmul(cplx a, cplx b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
-__device__ inline cplx cconj(cplx a) { return {a.x, -a.y}; }
-template <bool INV> __device__ inline cplx mul_mi(cplx a) { return INV ? cplx{-a.y, a.x} : cplx{a.y, -a.x}; }
+using cplx = cx<double>;
+using cplx32 = cx<float>;
+template <class T> __device__ inline cx<T> cadd(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <class T> __device__ inline cx<T> csub(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <class T> __device__ inline cx<T> cmul(cx<T> a, cx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <class T> __device__ inline cx<T> cconj(cx<T> a) { return {a.x, -a.y}; }
+template <bool INV, class T> __device__ inline cx<T> mul_mi(cx<T> a) {
+  return INV ? cx<T>{-a.y, a.x} : cx<T>{a.y, -a.x};
+}
 
 // LDS slot of point i of line b: b * LS + pd(i), with one pad slot after
 // every 16 points.  16-byte LDS writes are served eight lanes at a time,
@@ -53,14 +62,14 @@ __host__ __device__ inline int lines_per_wg(int N, int KP, int g = 1) {
   return nl;
 }
 
-template <bool INV> __device__ inline void dft2(cplx *v) {
-  const cplx t = v[0];
+template <bool INV, class T> __device__ inline void dft2(cx<T> *v) {
+  const cx<T> t = v[0];
   v[0] = cadd(t, v[1]);
   v[1] = csub(t, v[1]);
 }
-template <bool INV> __device__ inline void dft4(cplx *v) {
-  const cplx s0 = cadd(v[0], v[2]), d0 = csub(v[0], v[2]);
-  const cplx s1 = cadd(v[1], v[3]), d1 = mul_mi<INV>(csub(v[1], v[3]));
+template <bool INV, class T> __device__ inline void dft4(cx<T> *v) {
+  const cx<T> s0 = cadd(v[0], v[2]), d0 = csub(v[0], v[2]);
+  const cx<T> s1 = cadd(v[1], v[3]), d1 = mul_mi<INV>(csub(v[1], v[3]));
   v[0] = cadd(s0, s1);
   v[2] = csub(s0, s1);
   v[1] = cadd(d0, d1);
@@ -77,11 +86,11 @@ __device__ constexpr double cos16(int e) {
 __device__ constexpr double sin16(int e) { return cos16(e + 12); }   // sin x = cos(x - pi/2)
 
 // radix 8 = 4 x 2 and 16 = 4 x 4 (Cooley-Tukey split with constant twiddles)
-template <bool INV, int R1, int R2> __device__ inline void dft_split(cplx *v) {
-  cplx t[R1 * R2];
+template <bool INV, int R1, int R2, class T> __device__ inline void dft_split(cx<T> *v) {
+  cx<T> t[R1 * R2];
 #pragma unroll
   for (int b = 0; b < R2; ++b) {
-    cplx col[R1];
+    cx<T> col[R1];
 #pragma unroll
     for (int a = 0; a < R1; ++a) col[a] = v[R2 * a + b];
     dft4<INV>(col);
@@ -91,13 +100,13 @@ template <bool INV, int R1, int R2> __device__ inline void dft_split(cplx *v) {
         t[b * R1 + k1] = col[k1];
       } else {
         const int e = (b * k1 * (16 / (R1 * R2))) & 15;   // angle 2 pi e / 16
-        t[b * R1 + k1] = cmul(col[k1], cplx{cos16(e), INV ? sin16(e) : -sin16(e)});
+        t[b * R1 + k1] = cmul(col[k1], cx<T>{T(cos16(e)), T(INV ? sin16(e) : -sin16(e))});
       }
     }
   }
 #pragma unroll
   for (int k1 = 0; k1 < R1; ++k1) {
-    cplx row[R2];
+    cx<T> row[R2];
 #pragma unroll
     for (int b = 0; b < R2; ++b) row[b] = t[b * R1 + k1];
     if (R2 == 2) dft2<INV>(row);
@@ -106,23 +115,31 @@ template <bool INV, int R1, int R2> __device__ inline void dft_split(cplx *v) {
     for (int k2 = 0; k2 < R2; ++k2) v[k1 + R1 * k2] = row[k2];
   }
 }
-template <bool INV, int R> __device__ inline void dftR(cplx *v) {
+template <bool INV, int R, class T> __device__ inline void dftR(cx<T> *v) {
   if (R == 2) dft2<INV>(v);
   else if (R == 4) dft4<INV>(v);
   else if (R == 8) dft_split<INV, 4, 2>(v);
   else dft_split<INV, 4, 4>(v);
 }
 
-// W_N^e (forward sign) from two LDS tables: lo[i] = W_N^i, hi[i] = W_N^(64 i).
-__device__ inline cplx twid(int e, const cplx *lo, const cplx *hi) {
-  const cplx a = lo[e & 63];
-  return (e >> 6) ? cmul(a, hi[e >> 6]) : a;
+// W_N^e (forward sign).  FP64: from two LDS tables lo[i] = W_N^i, hi[i] =
+// W_N^(64 i) (one product).  FP32: lo is the whole table W_N^e, e < N, each
+// entry rounded once from FP64 (hi unused), so every twiddle is within half
+// an ulp; products of rounded entries would double that.
+template <class T> __device__ inline cx<T> twid(int e, const cx<T> *lo, const cx<T> *hi) {
+  if constexpr (std::is_same_v<T, float>) {
+    (void)hi;
+    return lo[e];
+  } else {
+    const cx<T> a = lo[e & 63];
+    return (e >> 6) ? cmul(a, hi[e >> 6]) : a;
+  }
 }
-__device__ inline void make_twiddles(cplx *lo, cplx *hi, int N) {
+template <class T> __device__ inline void make_twiddles(cx<T> *lo, cx<T> *hi, int N) {
   for (int t = threadIdx.x; t < 128; t += blockDim.x) {
     double s, c;
     sincospi(-2.0 * double(t < 64 ? t : 64 * (t - 64)) / double(N), &s, &c);
-    (t < 64 ? lo[t] : hi[t - 64]) = cplx{c, s};
+    (t < 64 ? lo[t] : hi[t - 64]) = cx<T>{T(c), T(s)};
   }
 }
 
@@ -133,28 +150,40 @@ __device__ inline void make_twiddles(cplx *lo, cplx *hi, int N) {
 // last pass of a transform, a functor sink(line, index, value).
 struct ToLds {};
 
-template <bool INV, int R, int KT, int KP, int N, int Ns, typename Sink = ToLds, bool XS = false>
-__device__ inline void pass(cplx *buf, int LS, int nlines, const cplx *tlo, const cplx *thi,
+template <bool INV, int R, int KT, int KP, int N, int Ns, typename Sink = ToLds, bool XS = false, class T>
+__device__ inline void pass(cx<T> *buf, int LS, int nlines, const cx<T> *tlo, const cx<T> *thi,
                             const Sink &sink = Sink{}) {
   constexpr int per = N / R;             // butterflies per line
   constexpr int lper = ilog2(per);
   constexpr int kMaxB = (KP / R + KT - 1) / KT;
   const int nb = nlines << lper;
-  cplx v[kMaxB][R];
+  cx<T> v[kMaxB][R];
 #pragma unroll
   for (int q = 0; q < kMaxB; ++q) {
     const int g = threadIdx.x + q * KT;
     if (g < nb) {
       const int j = g & (per - 1), line = g >> lper;
-      const cplx *lb = buf + line * LS;
+      const cx<T> *lb = buf + line * LS;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = lb[slot<XS>(j + r * per)];
-      if constexpr (Ns > 1) {
+      if constexpr (Ns > 1 && std::is_same_v<T, float>) {
+        // FP32: every power w^r straight from the table (one rounded entry
+        // each); a chain of products would compound FP32 roundoff over the
+        // passes
         const int k = j & (Ns - 1);
-        cplx w = twid(k * (N / (Ns * R)), tlo, thi);
+        const int e = k * (N / (Ns * R));
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cx<T> w = twid((e * r) & (N - 1), tlo, thi);
+          if (INV) w = cconj(w);
+          v[q][r] = cmul(v[q][r], w);
+        }
+      } else if constexpr (Ns > 1) {
+        const int k = j & (Ns - 1);
+        cx<T> w = twid(k * (N / (Ns * R)), tlo, thi);
         if (INV) w = cconj(w);
         // powers w^r, r < R, as w^(4a + b) = (w^4)^a w^b: dependency depth 5
-        cplx wp[R];
+        cx<T> wp[R];
         wp[1] = w;
         if constexpr (R > 2) {
           wp[2] = cmul(w, w);
@@ -188,7 +217,7 @@ __device__ inline void pass(cplx *buf, int LS, int nlines, const cplx *tlo, cons
         const int j = g & (per - 1), line = g >> lper;
         const int k = j & (Ns - 1);
         const int o = (j / Ns) * Ns * R + k;
-        cplx *lb = buf + line * LS;
+        cx<T> *lb = buf + line * LS;
 #pragma unroll
         for (int r = 0; r < R; ++r) lb[slot<XS>(o + r * Ns)] = v[q][r];
       }
@@ -214,8 +243,9 @@ __device__ inline void pass(cplx *buf, int LS, int nlines, const cplx *tlo, cons
 // LDS: a fixed pass plan per length (radix 16 first), each pass inlined with
 // its sizes known at compile time, so that the register allocation and the
 // index arithmetic are per pass.
-template <bool INV, int KT, int KP, int N, int Ns, typename Sink, bool XS, int R0, int... Rs>
-__device__ inline void run_passes(cplx *buf, int LS, int nlines, const cplx *tlo, const cplx *thi, const Sink &sink) {
+template <bool INV, int KT, int KP, int N, int Ns, typename Sink, bool XS, int R0, int... Rs, class T>
+__device__ inline void run_passes(cx<T> *buf, int LS, int nlines, const cx<T> *tlo, const cx<T> *thi,
+                                  const Sink &sink) {
   if constexpr (sizeof...(Rs) > 0) {
     pass<INV, R0, KT, KP, N, Ns, ToLds, XS>(buf, LS, nlines, tlo, thi);
     run_passes<INV, KT, KP, N, Ns * R0, Sink, XS, Rs...>(buf, LS, nlines, tlo, thi, sink);
@@ -224,8 +254,8 @@ __device__ inline void run_passes(cplx *buf, int LS, int nlines, const cplx *tlo
   }
 }
 // Transforms whose last pass hands its results to sink (ToLds: in place).
-template <bool INV, int KT, int KP, typename Sink, bool XS = false>
-__device__ __noinline__ void fft_lines_to(cplx *buf, int N, int LS, int nlines, const cplx *tlo, const cplx *thi,
+template <bool INV, int KT, int KP, typename Sink, bool XS = false, class T = double>
+__device__ __noinline__ void fft_lines_to(cx<T> *buf, int N, int LS, int nlines, const cx<T> *tlo, const cx<T> *thi,
                                           Sink sink) {
   switch (N) {
     case 2: run_passes<INV, KT, KP, 2, 1, Sink, XS, 2>(buf, LS, nlines, tlo, thi, sink); break;
@@ -247,14 +277,14 @@ __device__ __noinline__ void fft_lines_to(cplx *buf, int N, int LS, int nlines, 
       break;
   }
 }
-template <bool INV, int KT, int KP, bool XS = false>
-__device__ inline void fft_lines(cplx *buf, int N, int LS, int nlines, const cplx *tlo, const cplx *thi) {
-  fft_lines_to<INV, KT, KP, ToLds, XS>(buf, N, LS, nlines, tlo, thi, ToLds{});
+template <bool INV, int KT, int KP, bool XS = false, class T>
+__device__ inline void fft_lines(cx<T> *buf, int N, int LS, int nlines, const cx<T> *tlo, const cx<T> *thi) {
+  fft_lines_to<INV, KT, KP, ToLds, XS, T>(buf, N, LS, nlines, tlo, thi, ToLds{});
 }
 
 // W_L^f for the real-transform (un)packing, L = 2N: W_N^(f/2), times W_L^1 for odd f.
-__device__ inline cplx wl(int f, int N, const cplx *tlo, const cplx *thi, cplx w1) {
-  cplx w = twid((f >> 1) & (N - 1), tlo, thi);
+template <class T> __device__ inline cx<T> wl(int f, int N, const cx<T> *tlo, const cx<T> *thi, cx<T> w1) {
+  cx<T> w = twid((f >> 1) & (N - 1), tlo, thi);
   if (f & 1) w = cmul(w, w1);
   return w;
 }

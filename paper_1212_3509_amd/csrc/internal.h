@@ -154,6 +154,7 @@ struct demag_factors {
   void *bfw[3] = {nullptr, nullptr, nullptr};      // [4][M][2n+151][3 parts] 16-byte windows (n <= 1024)
   bool spec_ready = false;
   double *spec[3] = {nullptr, nullptr, nullptr};   // [4][M][L/2+1] real or imaginary parts (structured path)
+  float *spec32[3] = {nullptr, nullptr, nullptr};  // FP32 copies (structured path, FP32 transforms)
   void *twiddle[3] = {nullptr, nullptr, nullptr};  // double2 [L/2]
   double *k3 = nullptr;    // 3D kernel spectra, octant [Lz/2+1][Ly/2+1][pitch][10] (FFT apply)
   bool dense = false;      // non-uniform grid: f64[d] holds dense factors [4][M][n][n] (FP64 only)
@@ -210,8 +211,8 @@ demag_status launch_fft3d(demag_ctx *ctx, const demag_factors *f, const double *
 // Structured apply of column sets; the column spectra go to ws (ws_bytes,
 // at least columns_workspace_bytes) or, with ws NULL, to the context workspace.
 size_t columns_workspace_bytes(const demag_factors *f, const int32_t R[3]);
-demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, const int32_t R[3], const float *const in[3],
-                            float *const out[3], void *ws, size_t ws_bytes);
+demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, demag_prec prec, const int32_t R[3],
+                            const float *const in[3], float *const out[3], void *ws, size_t ws_bytes);
 // Device address of the static scratch array on `device` (set up by
 // demag_create); NULL if its set-up failed.
 demag_status scratch_init(int device);

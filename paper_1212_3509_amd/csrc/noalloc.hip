@@ -83,7 +83,7 @@ extern "C" demag_status demag_apply_columns_noalloc(demag_ctx *ctx, const demag_
   if (st != DEMAG_OK) return st;
   // every spectrum point is written by the forward transforms before the
   // jobs read it, so the array needs no clearing between calls
-  st = launch_columns(ctx, fc, R, in, out, base + kFlagBytes, kScratchBytes - kFlagBytes);
+  st = launch_columns(ctx, fc, DEMAG_FP64, R, in, out, base + kFlagBytes, kScratchBytes - kFlagBytes);
   if (st != DEMAG_OK) return st;
   if (fc->used) DEMAG_TRY_HIP(hipEventRecord(fc->used, ctx->stream));   // the event exists since assembly
   return DEMAG_OK;
