@@ -88,6 +88,55 @@ def _traffic(label):
     return None if k is None else k["hbm_bytes_per_launch"]
 
 
+def write_traffic(fetch_csv, write_csv, calib_mib):
+    """Rewrite the counter summary from two rocprofv3 --pmc runs (FETCH_SIZE,
+    then WRITE_SIZE, KiB per dispatch) of the FP64 headline with a plain copy
+    of `calib_mib` MiB first.  The stage labels keep their kernel names from
+    the existing summary; each stage's counters are the median over its
+    dispatches, scaled by what the counters read for the copy."""
+    import csv
+    import statistics
+
+    def per_kernel(path, counter):
+        vals = {}
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+        return vals
+
+    fetch, write = per_kernel(fetch_csv, "FETCH_SIZE"), per_kernel(write_csv, "WRITE_SIZE")
+    nbytes = calib_mib << 20
+    # the copy: of the elementwise kernels that write its byte count (the
+    # fill of its source does too), the one that also reads
+    copy = [k for k, v in write.items() if "elementwise" in k and abs(max(v) * 1024 - nbytes) < 0.01 * nbytes]
+    if not copy:
+        raise SystemExit("write_traffic: calibration copy not found")
+    copy = max(copy, key=lambda k: max(fetch.get(k, [0.0])))
+    fk, wk = max(fetch[copy]), max(write[copy])
+    cal = {"bytes": nbytes, "fetch_kib": fk, "write_kib": wk, "fetch_scale": nbytes / (fk * 1024),
+           "write_scale": nbytes / (wk * 1024)}
+    with open(TRAFFIC_FILE) as fh:
+        rec = json.load(fh)
+    def lookup(vals, kernel):   # full demangled names: "...::k_left<double, 8, 2, 2, true>(args)"
+        hits = [v for name, v in vals.items() if "::" + kernel + "(" in name]
+        if len(hits) != 1:
+            raise SystemExit(f"write_traffic: {len(hits)} dispatches groups match {kernel}")
+        return statistics.median(hits[0])
+
+    for label, k in rec["kernels"].items():
+        f = lookup(fetch, k["kernel"])
+        w = lookup(write, k["kernel"])
+        k.update({"fetch_kib": f, "write_kib": w,
+                  "hbm_bytes_per_launch": 1024 * (f * cal["fetch_scale"] + w * cal["write_scale"])})
+    rec["copy_calibration"] = cal
+    rec["kernel_source_sha256"] = _kernel_source_hash()
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 def _roofline(prof, prec):
     label, rec = max(prof.items(), key=lambda kv: kv[1]["ms"])
     per_launch_ms = rec["ms"] / rec["launches"]
@@ -629,7 +678,13 @@ def main():
                     help="also time torch.matmul at FP64/FP32/BF16 as context for the matrix-core figures")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run a plain copy of this many MiB first (byte-counter calibration)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no GPU work: rewrite the HBM counter summary from two rocprofv3 --pmc CSVs "
+                         "(with --calib-copy-mib of the profiled run)")
     args = ap.parse_args()
+    if args.write_traffic:
+        write_traffic(*args.write_traffic, args.calib_copy_mib)
+        return
     if args.gpus != 1:
         print("bench.py: this library runs on a single GPU; multi-GPU runs (sharding the quadrature nodes, "
               "states or structured jobs over ranks) are not implemented", file=sys.stderr)
