@@ -484,6 +484,7 @@ def headline(args):
     del f
     torch.cuda.empty_cache()
     structured_rec = structured_record(ctx, args) if args.structured else None
+    tucker_rec = tucker_record(ctx, args) if args.tucker else None
     del ctx
     torch.cuda.empty_cache()
     batch_rec = batch_record(args) if args.batch else None
@@ -511,6 +512,7 @@ def headline(args):
         "fft3d_route": fft3d,
         "nonuniform_grid": nonuni,
         "structured_4096": structured_rec,
+        "tucker_route": tucker_rec,
         "batch_256": batch_rec,
         "precisions": results,
     }
@@ -601,11 +603,55 @@ def structured_record(ctx, args):
             "results": out, "recompression_phi": recomp}
 
 
+def tucker_record(ctx, args):
+    """Alg. scpot_fft_tucker (structured DFTs with tolerance-controlled
+    Tucker arithmetic): the paper's uniform-magnetization case on cubes of
+    n = 256, 1024, 4096 cells per axis, and a smooth rank-(2,2,2)
+    magnetization at n = 4096; M = 40 (c0 = 2.15), tol 1e-8.  Wall times of
+    the set-up (kernel compression and DFTs) and of one potential (the loop
+    and the approximate summation; median of 3), with the ranks."""
+    import torch
+
+    from paper_1212_3509_amd import inputs
+
+    def dev(t):
+        core, U = t
+        return (torch.from_numpy(core.copy()).cuda(), [torch.from_numpy(U[p].T.copy()).cuda() for p in range(3)])
+
+    out = {"workload": "Alg. scpot_fft_tucker, uniform magnetization (0.3, -0.5, 0.8) on n^3 cubes and a smooth "
+                       "rank-(2,2,2) magnetization at n = 4096, M = 40 (c0 = 2.15), tol 1e-8, FP64",
+           "cases": []}
+    for n, kind in ((256, "uniform"), (1024, "uniform"), (4096, "uniform"), (4096, "smooth")):
+        nn = (n, n, n)
+        f = ctx.assemble(nn, (1.0 / n,) * 3, M=40)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kt = ctx.ktucker(f, 1e-8)
+        setup = time.perf_counter() - t0
+        mag = [dev(t) for t in inputs.tucker_magnetization(nn, kind, (2, 2, 2))]
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            core, rows = ctx.potential_tucker(kt, mag, 1e-8)
+            times.append(time.perf_counter() - t0)
+        out["cases"].append({"n": n, "input": kind, "kernel_ranks": [list(kt.ranks(q)) for q in range(3)],
+                             "potential_ranks": list(core.shape), "setup_ms": round(setup * 1e3, 2),
+                             "potential_ms": round(sorted(times)[1] * 1e3, 2)})
+        kt.close()
+        f.free()
+    return out
+
+
 def structured(args):
     from paper_1212_3509_amd import api
     if args.calib_copy_mib > 0:
         _copy_calibration(args.calib_copy_mib)
     print(json.dumps({"n_gpus": 1, **structured_record(api.Context(0), args)}), flush=True)
+
+
+def tucker(args):
+    from paper_1212_3509_amd import api
+    print(json.dumps({"n_gpus": 1, **tucker_record(api.Context(0), args)}), flush=True)
 
 
 def batch_record(args):
@@ -655,7 +701,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="headline", choices=["headline", "cp4096", "batch"])
+    ap.add_argument("--workload", default="headline", choices=["headline", "cp4096", "batch", "tucker"])
     ap.add_argument("--cpu-runs", type=int, default=3, help="runs (median) of each CPU baseline timing (0: skip)")
     ap.add_argument("--precs", default="fp64,fp32,bf16x3,bf16x2")
     ap.add_argument("--learned-steps", type=int, default=4000)
@@ -663,6 +709,7 @@ def main():
     ap.add_argument("--predict-iters", type=int, default=200, help="LM iterations per fit in predict")
     ap.add_argument("--structured", type=int, default=1, help="also time the structured applies at n = 4096")
     ap.add_argument("--batch", type=int, default=1, help="also time the batch of 256 uneven states")
+    ap.add_argument("--tucker", type=int, default=1, help="also time the Tucker DFT route (Alg. scpot_fft_tucker)")
     ap.add_argument("--cases", type=int, default=20000)
     ap.add_argument("--rule-tol", type=float, default=1e-6)
     ap.add_argument("--mixed-prec", default="bf16x3")
@@ -689,7 +736,7 @@ def main():
         print("bench.py: this library runs on a single GPU; multi-GPU runs (sharding the quadrature nodes, "
               "states or structured jobs over ranks) are not implemented", file=sys.stderr)
         sys.exit(2)
-    {"headline": headline, "cp4096": structured, "batch": batch}[args.workload](args)
+    {"headline": headline, "cp4096": structured, "batch": batch, "tucker": tucker}[args.workload](args)
 
 
 if __name__ == "__main__":

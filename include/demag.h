@@ -325,6 +325,70 @@ demag_status demag_recompress_cp(demag_ctx *ctx, const int32_t n[3], int32_t T, 
                                  double *const U[3], double *core, int32_t ranks[3], double *rel_err,
                                  int32_t *sweeps);
 
+/* ---------------------------------------------------------------- Tucker route
+ * The scalar potential of a Tucker magnetization by structured DFTs
+ * (Sec. 4.2, Alg. scpot_fft_tucker), the approximate summation of Tucker
+ * tensors and TT rounding (App. C).  FP64 throughout; every pointer in these
+ * calls is device memory except the rank arrays (host).  Layouts: a Tucker
+ * tensor is a core [r0][r1][r2] (index (a r1 + b) r2 + c) and factor rows
+ * rows[p] [r_p][n_p] (row i = the i-th factor column of mode p, contiguous).
+ * Each recompression is HOOI (Alg. HOOI) with the rank rule of
+ * demag_recompress_cp (discarded singular values of norm at most
+ * tol / sqrt(3) of all of them, per mode), on the core of the tensor in
+ * orthonormal bases of its factor rows; a factor-row set whose span exceeds
+ * 128 dimensions in one mode gives DEMAG_E_UNSUPPORTED.  The calls allocate
+ * device memory for their intermediates, synchronize the context's stream
+ * and return ranks above rmax as DEMAG_E_UNSUPPORTED with the needed ranks in
+ * rout and the outputs untouched.  Potentials are in the factors' scaled units
+ * (multiply by demag_factors_length_scale), as for the structured applies. */
+typedef struct demag_ktucker demag_ktucker;
+typedef struct {
+  int32_t r[3];             /* ranks, 1..128 each */
+  const double *core;       /* [r0][r1][r2] */
+  const double *rows[3];    /* [r_p][n_p] */
+} demag_tucker_in;
+
+/* Set-up of Alg. scpot_fft_tucker for the uniform-grid factors f (mode sizes
+ * 1..4096, at most 512 nodes): the three CP kernels of Eq. (conv_pot), one
+ * term per node with the X generator on axis q and E generators elsewhere
+ * (length 2 n_p - 1, offset J at J + n_p - 1), compressed to Tucker with tol
+ * in (0, 1), and the DFTs of their factor rows (length L_p = the smallest
+ * power of two >= 2 n_p - 1, Lemma DFT_tucker).  *out owns device memory
+ * until demag_ktucker_free; f may be freed afterwards. */
+demag_status demag_ktucker_create(demag_ctx *ctx, const demag_factors *f, double tol, demag_ktucker **out);
+/* Ranks of the compressed kernel of component q (0..2). */
+demag_status demag_ktucker_ranks(const demag_ktucker *kt, int32_t q, int32_t r[3]);
+/* Copy of the compressed kernel q: core (r0 r1 r2 values) and factor rows
+ * rows[p] ([r_p][2 n_p - 1]), device buffers of the caller. */
+demag_status demag_ktucker_copy(demag_ctx *ctx, const demag_ktucker *kt, int32_t q, double *core,
+                                double *const rows[3]);
+demag_status demag_ktucker_free(demag_ktucker *kt);
+/* The loop and the closing step of Alg. scpot_fft_tucker for the magnetization
+ * components m[0..2] (mode sizes those of the kernels): per component the DFT
+ * of the factor rows, the Hadamard product with the kernel in Fourier space
+ * (App. B, Eq. (t_had2); kernel rank times magnetization rank at most 512 per
+ * mode), the inverse DFT cut to the convolution window, the product
+ * recompressed with tol; then the approximate summation of the three
+ * products with tol.  Output: ranks rout, core (capacity rmax^3) and rows[p]
+ * (capacity rmax n_p). */
+demag_status demag_potential_tucker(demag_ctx *ctx, const demag_ktucker *kt, const demag_tucker_in m[3], double tol,
+                                    int32_t rmax, int32_t rout[3], double *core, double *const rows[3]);
+/* Approximate summation: sum_t terms[t] (1..512 terms, mode sizes n[p] in
+ * 1..16384, at most 512 factor rows per mode in all) recompressed with tol. */
+demag_status demag_tucker_sum(demag_ctx *ctx, const int32_t n[3], int32_t nterms, const demag_tucker_in *terms,
+                              double tol, int32_t rmax, int32_t rout[3], double *core, double *const rows[3]);
+/* TT rounding (App. C) of the 3D tensor train G1 [r1][n0] (rows: the columns
+ * of the first core), G2 [r1][r2][n1] (fibres G2[a, :, b] contiguous), G3
+ * [r2][n2], ranks 1..128, mode sizes 1..16384: the outer cores are
+ * orthonormalised, then two truncated SVDs from the left each discard
+ * singular values of norm at most tol / sqrt(2) times the tensor norm, so
+ * the result is within tol of the input in relative Frobenius norm.  Outputs
+ * in the same layout: ranks rout[2], G1o (capacity rmax n0), G2o (rmax^2 n1),
+ * G3o (rmax n2). */
+demag_status demag_tt_round(demag_ctx *ctx, const int32_t n[3], int32_t r1, int32_t r2, const double *G1,
+                            const double *G2, const double *G3, double tol, int32_t rmax, int32_t rout[2],
+                            double *G1o, double *G2o, double *G3o);
+
 /* ---------------------------------------------------------------- learned rule
  * A network proposes shortened rules (R' = 16..32 nodes); the operator error
  * of a rule is certified against an accurate reference rule; the full rule

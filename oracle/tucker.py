@@ -26,8 +26,9 @@ What each function states, and the passage it follows:
   potential_tucker  Alg. scpot_fft_tucker, step by step: the CP kernels, their
                     compression to Tucker with tol, their DFTs; per component
                     the DFT of the magnetization, the Hadamard product in
-                    Fourier space, the inverse DFT; then the approximate
-                    summation with tol.
+                    Fourier space, the inverse DFT, the product
+                    recompressed with tol; then the approximate summation with
+                    tol.
   tucker_sum        the approximate summation: the exact sum of Tucker tensors
                     (factors side by side, block-diagonal core) recompressed by
                     hooi with tol.
@@ -38,6 +39,9 @@ What each function states, and the passage it follows:
                     result is within eps of the input in relative norm.
   tt_from_tucker    App. C, Eq. (tt_3d_2) read backwards: the middle factor
                     multiplied into the core gives the TT cores.
+  potential_at_cells  Eq. (kron_eval_tuck) at single target cells: the
+                    uncompressed Kronecker operator's potential of a Tucker
+                    magnetization, for sizes where no dense tensor fits.
 
 Readings:
   * DFT length.  The paper pads to 2 n_p - 1 points; every length
@@ -46,8 +50,11 @@ Readings:
   * Window.  Output i of the Toeplitz product is entry i + n - 1 of the
     convolution of the kernel generator (offset J stored at J + n - 1) with the
     input column.
-  * "Hadamard products ... using e.g. the tolerance tol": the products are
-    formed exactly here; tol enters the kernel compression and the summation.
+  * "Hadamard products ... using e.g. the tolerance tol": each product is
+    formed exactly (Eq. (t_had2)), then recompressed by HOOI with tol (App. B
+    recommends recompressing the product); the summation recompresses again
+    with tol.  The errors of the three steps add up: the potential is within
+    a small multiple of tol of the uncompressed route.
   * Index order of a product's combined rank index: (l, i) -> l * r + i for
     l a rank index of the second operand (the magnetization) and i one of the
     first (the kernel), in the core and in the factor columns alike (the
@@ -200,7 +207,30 @@ def potential_tucker(mag, n, h, tau, alpha, tol):
     of the magnetization components.  Returns the potential as a Tucker
     tensor (core, U) (kernel units: the same scale as oracle.apply)."""
     kernels = kernel_tucker(n, h, tau, alpha, tol)
-    return tucker_sum(hadamard_products(kernels, mag, n), tol)
+    prods = []
+    for E, W in hadamard_products(kernels, mag, n):
+        core, U, _sw = hooi(tucker_dense(E, W), tol)
+        prods.append((core, U))
+    return tucker_sum(prods, tol)
+
+
+def potential_at_cells(mag, n, h, tau, alpha, cells):
+    """The Kronecker operator's potential (Cor. kron_op) of a Tucker
+    magnetization at target cells (i1, i2, i3), without any dense tensor:
+    Eq. (kron_eval_tuck) evaluated row by row, each Toeplitz factor row
+    contracted with the factor matrix of its mode."""
+    F = [sinc.scaled_factors(n[d], h[d], tau, alpha) for d in range(3)]
+    out = np.zeros(len(cells))
+    for c, i in enumerate(cells):
+        for q in range(3):
+            core, U = mag[q]
+            ty = sinc.phi_types(q)
+            P = []
+            for d in range(3):
+                j = np.arange(n[d])
+                P.append(F[d][ty[d]][:, i[d] - j + n[d] - 1] @ U[d])     # [M][r_d]
+            out[c] += np.einsum("abc,ka,kb,kc->", core, P[0], P[1], P[2])
+    return out
 
 
 # ------------------------------------------------------------------- TT (App. C)

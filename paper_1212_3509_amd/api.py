@@ -43,6 +43,10 @@ class QuadResult(C.Structure):
 
 PREDICT_MODES = {"network": 0, "network_proposal": 1, "search": 2}
 
+
+class TuckerIn(C.Structure):
+    _fields_ = [("r", C.c_int32 * 3), ("core", C.c_void_p), ("rows", C.c_void_p * 3)]
+
 _P = C.c_void_p
 _SIGS = {
     "demag_last_error": (C.c_char_p, []),
@@ -95,6 +99,14 @@ _SIGS = {
     "demag_apply_tt": (C.c_int, [_P, _P, C.c_int, C.c_int32, C.c_int32, _P, _P, _P, _P, _P]),
     "demag_recompress_cp": (C.c_int, [_P, _P, C.c_int32, _P, _P, _P, _P, C.c_double, C.c_int32, C.c_int32, _P,
                                       _P, _P, _P, _P, _P, _P]),
+    "demag_ktucker_create": (C.c_int, [_P, _P, C.c_double, C.POINTER(_P)]),
+    "demag_ktucker_ranks": (C.c_int, [_P, C.c_int32, _P]),
+    "demag_ktucker_copy": (C.c_int, [_P, _P, C.c_int32, _P, _P]),
+    "demag_ktucker_free": (C.c_int, [_P]),
+    "demag_potential_tucker": (C.c_int, [_P, _P, _P, C.c_double, C.c_int32, _P, _P, _P]),
+    "demag_tucker_sum": (C.c_int, [_P, _P, C.c_int32, _P, C.c_double, C.c_int32, _P, _P, _P]),
+    "demag_tt_round": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P, _P, _P, C.c_double, C.c_int32, _P, _P, _P,
+                                 _P]),
     "demag_bf16_split": (C.c_int, [_P, _P, _P, C.c_size_t, C.c_int32]),
     "demag_profile_enable": (C.c_int, [_P, C.c_int32]),
     "demag_profile_read": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, C.POINTER(C.c_int32)]),
@@ -582,6 +594,72 @@ class Context:
                 "judged": max(res.err_phi, res.err_h), "predicted": res.predicted, "seconds": res.seconds,
                 "accuracy_met": st == 0, "mode": mode}
 
+    # ------------------------------------------------------------ Tucker route
+
+    def ktucker(self, f: "Factors", tol: float):
+        """Set-up of Alg. scpot_fft_tucker: the factors' three kernels
+        compressed to Tucker with tol, with their factor-row DFTs."""
+        h = C.c_void_p()
+        _check(library().demag_ktucker_create(self.handle, f.handle, tol, C.byref(h)), "demag_ktucker_create")
+        return KTucker(self, h, f.n)
+
+    @staticmethod
+    def _tucker_in(t):
+        core, rows = t
+        for x in (core, *rows):
+            if not (x.is_cuda and x.is_contiguous()) or str(x.dtype) != "torch.float64":
+                raise ValueError("Tucker cores and factor rows must be contiguous float64 CUDA tensors")
+        r = [int(rows[p].shape[0]) for p in range(3)]
+        if tuple(core.shape) != tuple(r):
+            raise ValueError(f"core shape {tuple(core.shape)} does not match the factor rows {r}")
+        return TuckerIn((C.c_int32 * 3)(*r), core.data_ptr(), (C.c_void_p * 3)(*[rows[p].data_ptr() for p in range(3)]))
+
+    def _tucker_out(self, call, n, rmax, where):
+        import torch
+        core = torch.empty(rmax ** 3, dtype=torch.float64, device="cuda")
+        rows = [torch.empty((rmax, n[p]), dtype=torch.float64, device="cuda") for p in range(3)]
+        rout = (C.c_int32 * 3)()
+        self.use_current_stream()
+        _check(call(rout, _ptr(core), self._ptr3(rows)), where)
+        r = [rout[p] for p in range(3)]
+        return core[:r[0] * r[1] * r[2]].reshape(r), [rows[p][:r[p]] for p in range(3)]
+
+    def potential_tucker(self, kt: "KTucker", mag, tol: float, rmax: int = 128):
+        """Alg. scpot_fft_tucker for the three magnetization components
+        mag[q] = (core [r0][r1][r2], [rows_p [r_p][n_p]]) (float64 CUDA).
+        Returns the potential (core, rows) in the factors' scaled units."""
+        ins = (TuckerIn * 3)(*[self._tucker_in(mag[q]) for q in range(3)])
+        return self._tucker_out(lambda ro, co, ro3: library().demag_potential_tucker(
+            self.handle, kt.handle, ins, tol, rmax, ro, co, ro3), kt.n, rmax, "demag_potential_tucker")
+
+    def tucker_sum(self, n, terms, tol: float, rmax: int = 128):
+        """Approximate summation of the Tucker tensors terms[t] = (core, rows)."""
+        ins = (TuckerIn * len(terms))(*[self._tucker_in(t) for t in terms])
+        n3 = (C.c_int32 * 3)(*n)
+        return self._tucker_out(lambda ro, co, ro3: library().demag_tucker_sum(
+            self.handle, n3, len(terms), ins, tol, rmax, ro, co, ro3), n, rmax, "demag_tucker_sum")
+
+    def tt_round(self, G1, G2, G3, tol: float, rmax: int = 128):
+        """TT rounding of G1 [r1][n0], G2 [r1][r2][n1], G3 [r2][n2] (float64
+        CUDA).  Returns the rounded cores in the same layout."""
+        import torch
+        r1, r2 = int(G1.shape[0]), int(G3.shape[0])
+        n = (int(G1.shape[1]), int(G2.shape[2]), int(G3.shape[1]))
+        if tuple(G2.shape) != (r1, r2, n[1]):
+            raise ValueError("G2 must be [r1][r2][n1]")
+        for x in (G1, G2, G3):
+            if not (x.is_cuda and x.is_contiguous()) or x.dtype != torch.float64:
+                raise ValueError("TT cores must be contiguous float64 CUDA tensors")
+        H1 = torch.empty((rmax, n[0]), dtype=torch.float64, device="cuda")
+        H2 = torch.empty(rmax * rmax * n[1], dtype=torch.float64, device="cuda")
+        H3 = torch.empty((rmax, n[2]), dtype=torch.float64, device="cuda")
+        rout = (C.c_int32 * 2)()
+        self.use_current_stream()
+        _check(library().demag_tt_round(self.handle, (C.c_int32 * 3)(*n), r1, r2, _ptr(G1), _ptr(G2), _ptr(G3), tol,
+                                        rmax, rout, _ptr(H1), _ptr(H2), _ptr(H3)), "demag_tt_round")
+        s1, s2 = rout[0], rout[1]
+        return H1[:s1], H2[:s1 * s2 * n[1]].reshape(s1, s2, n[1]), H3[:s2]
+
     def bf16_split(self, x, nparts: int = 3):
         """Device split of a contiguous float32 CUDA tensor into bfloat16 bit
         patterns, returned as an int16 tensor [nparts][numel]."""
@@ -615,6 +693,40 @@ class Context:
     def close(self):
         if self.handle:
             library().demag_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class KTucker:
+    """Compressed kernels of Alg. scpot_fft_tucker (library handle)."""
+
+    def __init__(self, ctx: "Context", handle, n):
+        self.ctx, self.handle, self.n = ctx, handle, tuple(n)
+
+    def ranks(self, q: int):
+        r = (C.c_int32 * 3)()
+        _check(library().demag_ktucker_ranks(self.handle, q, r), "demag_ktucker_ranks")
+        return tuple(r)
+
+    def kernel(self, q: int):
+        """(core, rows) of the compressed kernel q: rows[p] [r_p][2 n_p - 1]."""
+        import torch
+        r = self.ranks(q)
+        core = torch.empty(r, dtype=torch.float64, device="cuda")
+        rows = [torch.empty((r[p], 2 * self.n[p] - 1), dtype=torch.float64, device="cuda") for p in range(3)]
+        self.ctx.use_current_stream()
+        _check(library().demag_ktucker_copy(self.ctx.handle, self.handle, q, _ptr(core), Context._ptr3(rows)),
+               "demag_ktucker_copy")
+        return core, rows
+
+    def close(self):
+        if self.handle:
+            library().demag_ktucker_free(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -239,8 +239,8 @@ __device__ inline void pass(cx<T> *buf, int LS, int nlines, const cx<T> *tlo, co
   }
 }
 
-// Complex FFTs of nlines lines of N points at line stride LS (power of 2, N <= 4096) in
-// LDS: a fixed pass plan per length (radix 16 first), each pass inlined with
+// Complex FFTs of nlines lines of N points at line stride LS (power of 2, N <= 4096,
+// or 8192 in workgroups of KP >= 8192 points) in LDS: a fixed pass plan per length (radix 16 first), each pass inlined with
 // its sizes known at compile time, so that the register allocation and the
 // index arithmetic are per pass.
 template <bool INV, int KT, int KP, int N, int Ns, typename Sink, bool XS, int R0, int... Rs, class T>
@@ -270,6 +270,9 @@ __device__ __noinline__ void fft_lines_to(cx<T> *buf, int N, int LS, int nlines,
     case 1024: run_passes<INV, KT, KP, 1024, 1, Sink, XS, 16, 16, 4>(buf, LS, nlines, tlo, thi, sink); break;
     case 2048: run_passes<INV, KT, KP, 2048, 1, Sink, XS, 16, 16, 8>(buf, LS, nlines, tlo, thi, sink); break;
     case 4096: run_passes<INV, KT, KP, 4096, 1, Sink, XS, 16, 16, 16>(buf, LS, nlines, tlo, thi, sink); break;
+    case 8192:
+      if constexpr (KP >= 8192) run_passes<INV, KT, KP, 8192, 1, Sink, XS, 16, 16, 16, 2>(buf, LS, nlines, tlo, thi, sink);
+      break;
     default:   // N = 1: identity
       if constexpr (!std::is_same_v<Sink, ToLds>) {
         for (int line = threadIdx.x; line < nlines; line += KT) sink(line, 0, buf[line * LS]);

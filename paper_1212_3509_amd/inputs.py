@@ -152,6 +152,45 @@ class BatchState:
     m: np.ndarray = field(repr=False, default=None)
 
 
+def tucker_magnetization(n, kind: str = "uniform", ranks=(2, 3, 2), seed: int = 5):
+    """Three magnetization components in Tucker form, each (core [r0][r1][r2],
+    [U_x [n_x][r0], U_y [n_y][r1], U_z [n_z][r2]]) in float64:
+      uniform  m = (0.3, -0.5, 0.8): rank (1, 1, 1), unit factor columns of ones;
+      smooth   cosines cos(pi (l + 1) x) and sines sin(2 x + l) of the cell
+               midpoints x in [0, 1] (column l), standard-normal cores;
+      random   U[-1, 1] factors and standard-normal cores."""
+    rng = _rng(seed)
+    out = []
+    for q in range(3):
+        if kind == "uniform":
+            core = np.array([[[(0.3, -0.5, 0.8)[q]]]])
+            U = [np.ones((n[p], 1)) for p in range(3)]
+        elif kind == "smooth":
+            core = rng.standard_normal(ranks)
+            U = []
+            for p in range(3):
+                x = (np.arange(n[p]) + 0.5) / n[p]
+                cols = [np.cos(np.pi * (l + 1) * x) if l % 2 == 0 else np.sin(2.0 * x + l) for l in range(ranks[p])]
+                U.append(np.stack(cols, axis=1))
+        else:
+            core = rng.standard_normal(ranks)
+            U = [rng.uniform(-1.0, 1.0, (n[p], ranks[p])) for p in range(3)]
+        out.append((core, U))
+    return out
+
+
+def tt_cores(n, ranks=(6, 5), decay=(0.3, 0.4), seed: int = 6):
+    """A 3D tensor train (G1 [n0][r1], G2 [r1][n1][r2], G3 [r2][n2]) with
+    standard-normal entries, the columns of G1 scaled by decay[0]^a and the
+    rows of G3 by decay[1]^b (decaying unfolding spectra), float64."""
+    rng = _rng(seed)
+    r1, r2 = ranks
+    G1 = rng.standard_normal((n[0], r1)) * decay[0] ** np.arange(r1)[None, :]
+    G2 = rng.standard_normal((r1, n[1], r2))
+    G3 = rng.standard_normal((r2, n[2])) * decay[1] ** np.arange(r2)[:, None]
+    return G1, G2, G3
+
+
 def batch_grids(count: int = 256, seed: int = 2, with_fields: bool = True):
     """Uneven batch: state s with s % 8 == 7 is a 256x256xnz film with
     nz = (4, 8, 16)[(s // 8) % 3]; every other state is a cube with edge drawn
