@@ -23,6 +23,12 @@ Modules
   mlp         float64 multilayer perceptron with hand-written backward and Adam
   smooth      exact potential of a smooth magnetization by singularity
               subtraction (reference for Lemma conv_coll / Fig. fig_err)
+  quadrule    shortened rules, their operator-norm certificate and fit
+  recompress  HOOI recompression of CP tensors (Alg. HOOI)
+  fftconv     the Kronecker operator as one 3D FFT convolution
+  nonuniform  dense 1D factors of non-uniform tensor grids
+  tucker      Alg. scpot_fft_tucker (kernel compression, Fourier-space
+              Tucker Hadamard products, approximate summation), TT rounding
 
 Readings of the paper that the oracle adopts are listed in each module header.
 """

@@ -57,7 +57,8 @@ constexpr int kOPer = 32;             // points per thread
 constexpr int kOLen = kOT * kOPer;    // longest row (chunk) per workgroup
 constexpr int kOMax = 512;            // rows per orthonormalisation
 constexpr int kSvd = 128;             // rows of a small SVD (rank cap per mode)
-constexpr int kST = 256;              // Jacobi workgroup
+constexpr int kST = 1024;             // Jacobi workgroup
+constexpr int kGrp = 16;              // lanes per column pair (kST / kGrp >= kSvd / 2)
 constexpr double kDrop = 1e-14;       // dependent-row threshold (relative)
 constexpr int kMaxN = 4096;           // mode sizes (L <= 8192)
 
@@ -124,16 +125,31 @@ __global__ __launch_bounds__(kOT) void k_orth(RowView Y, int k, int len, int chu
     const double nrm0 = block_sum(sq);
     for (int i = tid; i < kept; i += kOT) acc[i] = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
-      for (int i = 0; i < kept; ++i) {
-        const double *qi = Qc + size_t(i) * chunk;
-        double d = 0.0;
+      // dot products with the basis rows, four at a time so that their
+      // cross-lane reductions overlap
+      for (int i0 = 0; i0 < kept; i0 += 4) {
+        double d[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int e = 0; e < kOPer; ++e) {
-          const int x = tid + kOT * e;
-          if (x < m) d += qi[x] * v[e];
+        for (int u = 0; u < 4; ++u) {
+          if (i0 + u < kept) {
+            const double *qi = Qc + size_t(i0 + u) * chunk;
+#pragma unroll
+            for (int e = 0; e < kOPer; ++e) {
+              const int x = tid + kOT * e;
+              if (x < m) d[u] += qi[x] * v[e];
+            }
+          }
         }
-        d = wave_sum(d);
-        if (lane == 0) part[wave][i] = d;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) d[u] += __shfl_xor(d[u], o);
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (i0 + u < kept) part[wave][i0 + u] = d[u];
+        }
       }
       __syncthreads();
       for (int i = tid; i < kept; i += kOT) {
@@ -179,16 +195,23 @@ __global__ __launch_bounds__(kOT) void k_orth(RowView Y, int k, int len, int chu
 
 // Singular values and left singular vectors of the m x c matrix C (row
 // stride ldc, m, c <= kSvd) by one-sided Jacobi on its columns: pairs of
-// columns (round-robin order, disjoint pairs in parallel, one wave per pair)
-// are rotated until every pair is orthogonal to 1e-15 of the product of their
-// norms; then C J = U diag(sig).  Outputs sig[0..c) descending and
-// U[i ldu + k] = column k of U (zero for a zero singular value).
+// columns (round-robin order) are rotated until every pair is orthogonal to
+// 1e-15 of the product of their norms; then C J = U diag(sig).  One group of
+// kGrp lanes per pair, so all disjoint pairs of a step run at once.  Outputs
+// sig[0..c) descending and U[i ldu + k] = column k of U (zero for a zero
+// singular value).
+__device__ inline double group_sum(double x) {
+#pragma unroll
+  for (int o = kGrp / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kGrp);
+  return x;
+}
 __global__ __launch_bounds__(kST) void k_svd_cols(const double *__restrict__ C, int ldc, int m, int c,
                                                   double *__restrict__ sig, double *__restrict__ U, int ldu) {
   extern __shared__ double col[];   // column k at col + k * LD
-  __shared__ double wmax[kST / 64];
+  __shared__ double gmax[kST / kGrp];
   __shared__ double nrm[kSvd];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  __shared__ int stop;
+  const int tid = threadIdx.x, grp = tid / kGrp, gl = tid % kGrp;
   const int cp = c + (c & 1), LD = m + 1;
   for (int e = tid; e < cp * m; e += kST) {
     const int k = e / m, i = e - k * m;
@@ -198,25 +221,25 @@ __global__ __launch_bounds__(kST) void k_svd_cols(const double *__restrict__ C, 
   for (int sweep = 0; sweep < 60 && cp >= 2; ++sweep) {
     double off = 0.0;
     for (int step = 0; step < cp - 1; ++step) {
-      auto idx = [&](int t) { return t == 0 ? 0 : 1 + (t - 1 + step) % (cp - 1); };
-      for (int pr = wave; pr < cp / 2; pr += kST / 64) {
-        double *x = col + idx(pr) * LD, *y = col + idx(cp - 1 - pr) * LD;
+      if (grp < cp / 2) {
+        auto idx = [&](int t) { return t == 0 ? 0 : 1 + (t - 1 + step) % (cp - 1); };
+        double *x = col + idx(grp) * LD, *y = col + idx(cp - 1 - grp) * LD;
         double a = 0.0, b = 0.0, g = 0.0;
-        for (int i = lane; i < m; i += 64) {
+        for (int i = gl; i < m; i += kGrp) {
           a += x[i] * x[i];
           b += y[i] * y[i];
           g += x[i] * y[i];
         }
-        a = wave_sum(a);
-        b = wave_sum(b);
-        g = wave_sum(g);
+        a = group_sum(a);
+        b = group_sum(b);
+        g = group_sum(g);
         if (fabs(g) > 1e-300 && fabs(g) > 1e-15 * sqrt(a * b)) {
           off = fmax(off, fabs(g) / sqrt(a * b));
           const double zeta = (b - a) / (2.0 * g);
           const double t = fabs(zeta) > 1e150 ? 0.5 / zeta
                                                : (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
           const double cs = 1.0 / sqrt(1.0 + t * t), sn = cs * t;
-          for (int i = lane; i < m; i += 64) {
+          for (int i = gl; i < m; i += kGrp) {
             const double xi = x[i], yi = y[i];
             x[i] = cs * xi - sn * yi;
             y[i] = sn * xi + cs * yi;
@@ -225,19 +248,21 @@ __global__ __launch_bounds__(kST) void k_svd_cols(const double *__restrict__ C, 
       }
       __syncthreads();
     }
-    if (lane == 0) wmax[wave] = off;
+    if (gl == 0) gmax[grp] = off;
     __syncthreads();
-    double mx = 0.0;
-#pragma unroll
-    for (int w = 0; w < kST / 64; ++w) mx = fmax(mx, wmax[w]);
+    if (tid == 0) {
+      double mx = 0.0;
+      for (int w = 0; w < kST / kGrp; ++w) mx = fmax(mx, gmax[w]);
+      stop = !(mx > 1e-15);
+    }
     __syncthreads();
-    if (!(mx > 1e-15)) break;
+    if (stop) break;
   }
-  for (int k = wave; k < c; k += kST / 64) {
+  for (int k = grp; k < c; k += kST / kGrp) {
     double s = 0.0;
-    for (int i = lane; i < m; i += 64) s += col[k * LD + i] * col[k * LD + i];
-    s = wave_sum(s);
-    if (lane == 0) nrm[k] = sqrt(s);
+    for (int i = gl; i < m; i += kGrp) s += col[k * LD + i] * col[k * LD + i];
+    s = group_sum(s);
+    if (gl == 0) nrm[k] = sqrt(s);
   }
   __syncthreads();
   for (int k = tid; k < c; k += kST) {
