@@ -229,15 +229,20 @@ __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__rest
             acc[o][rb] = TRANS ? Mf::step(b, a[u & 1][o][rb], acc[o][rb]) : Mf::step(a[u & 1][o][rb], b, acc[o][rb]);
       }
     } else {
-      // straight-line K-steps (no branch, so the LDS reads of a step are
-      // issued while the previous step's products run); in the last chunk
-      // of a term the steps past n multiply a zero input
+      // K-steps of the chunk; on a ragged axis the last chunk of a term
+      // stops at the first step wholly past n (its inputs are all zero), and
+      // row blocks wholly past n (never stored) are skipped: both conditions
+      // are uniform, and skipping adds nothing but exact zeros
+      const int live_u = WHOLE ? kUnroll : min(kUnroll, (n - j0 + 3) >> 2);
+      const int live_rb = WHOLE ? RB : min(RB, (n - row0 + 15) >> 4);
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
+        if (!WHOLE && u >= live_u) break;
         const int jj = j0 + 4 * u;
         const T b = (WHOLE || jj + kq < n) ? cur[u] : T(0);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
+          if (!WHOLE && rb >= live_rb) break;
           const int idx = ibase + 16 * rb - jj;
 #pragma unroll
           for (int o = 0; o < NOUT; ++o)
