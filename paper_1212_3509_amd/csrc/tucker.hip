@@ -88,6 +88,7 @@ struct RowView {
 // kept, kmax + 1 if an independent row found the basis full.  Thread t owns
 // the points t + kOT e of the chunk: the basis rows it writes are the ones it
 // reads back.
+template <int PER, int GRP>
 __global__ __launch_bounds__(kOT) void k_orth(RowView Y, int k, int len, int chunk, double *__restrict__ Q, int kmax,
                                               double *__restrict__ C, int ldc, int *__restrict__ kout, double drop) {
   __shared__ double part[kOT / 64][kOMax];
@@ -110,10 +111,10 @@ __global__ __launch_bounds__(kOT) void k_orth(RowView Y, int k, int len, int chu
   int kept = 0;
   bool overflow = false;
   for (int j = 0; j < k; ++j) {
-    double v[kOPer];
+    double v[PER];
     double sq = 0.0;
 #pragma unroll
-    for (int e = 0; e < kOPer; ++e) {
+    for (int e = 0; e < PER; ++e) {
       const int x = tid + kOT * e;
       v[e] = 0.0;
       if (x < m) {
@@ -125,16 +126,18 @@ __global__ __launch_bounds__(kOT) void k_orth(RowView Y, int k, int len, int chu
     const double nrm0 = block_sum(sq);
     for (int i = tid; i < kept; i += kOT) acc[i] = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
-      // dot products with the basis rows, four at a time so that their
-      // cross-lane reductions overlap
-      for (int i0 = 0; i0 < kept; i0 += 4) {
-        double d[4] = {0.0, 0.0, 0.0, 0.0};
+      // dot products with the basis rows, GRP at a time so that their loads
+      // and cross-lane reductions overlap
+      for (int i0 = 0; i0 < kept; i0 += GRP) {
+        double d[GRP];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < GRP; ++u) d[u] = 0.0;
+#pragma unroll
+        for (int u = 0; u < GRP; ++u) {
           if (i0 + u < kept) {
             const double *qi = Qc + size_t(i0 + u) * chunk;
 #pragma unroll
-            for (int e = 0; e < kOPer; ++e) {
+            for (int e = 0; e < PER; ++e) {
               const int x = tid + kOT * e;
               if (x < m) d[u] += qi[x] * v[e];
             }
@@ -143,11 +146,11 @@ __global__ __launch_bounds__(kOT) void k_orth(RowView Y, int k, int len, int chu
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u) d[u] += __shfl_xor(d[u], o);
+          for (int u = 0; u < GRP; ++u) d[u] += __shfl_xor(d[u], o);
         }
         if (lane == 0) {
 #pragma unroll
-          for (int u = 0; u < 4; ++u)
+          for (int u = 0; u < GRP; ++u)
             if (i0 + u < kept) part[wave][i0 + u] = d[u];
         }
       }
@@ -160,11 +163,12 @@ __global__ __launch_bounds__(kOT) void k_orth(RowView Y, int k, int len, int chu
         acc[i] += s;
       }
       __syncthreads();
+#pragma unroll 4
       for (int i = 0; i < kept; ++i) {
         const double cf = coef[i];
         const double *qi = Qc + size_t(i) * chunk;
 #pragma unroll
-        for (int e = 0; e < kOPer; ++e) {
+        for (int e = 0; e < PER; ++e) {
           const int x = tid + kOT * e;
           if (x < m) v[e] -= cf * qi[x];
         }
@@ -172,7 +176,7 @@ __global__ __launch_bounds__(kOT) void k_orth(RowView Y, int k, int len, int chu
     }
     sq = 0.0;
 #pragma unroll
-    for (int e = 0; e < kOPer; ++e) sq += v[e] * v[e];
+    for (int e = 0; e < PER; ++e) sq += v[e] * v[e];
     const double nrm = block_sum(sq);
     const bool indep = nrm > 0.0 && nrm > drop * drop * nrm0;
     if (indep && kept == kmax) overflow = true;
@@ -183,7 +187,7 @@ __global__ __launch_bounds__(kOT) void k_orth(RowView Y, int k, int len, int chu
       const double inv = 1.0 / sqrt(nrm);
       double *qk = Qc + size_t(kept) * chunk;
 #pragma unroll
-      for (int e = 0; e < kOPer; ++e) {
+      for (int e = 0; e < PER; ++e) {
         const int x = tid + kOT * e;
         if (x < m) qk[x] = v[e] * inv;
       }
@@ -191,6 +195,32 @@ __global__ __launch_bounds__(kOT) void k_orth(RowView Y, int k, int len, int chu
     }
   }
   if (tid == 0) kout[c] = overflow ? kmax + 1 : kept;
+}
+
+// Basis rows of the two-level Gram-Schmidt: Q[i][c chunk + x] =
+// sum_(a < kout[c]) Q2[i][c kmax1 + a] Qs[c][a][x] for i < *rho (chunk c's
+// basis rows past kout[c] were never written and are not read).
+__global__ __launch_bounds__(256) void k_tsqr_rows(const double *__restrict__ Qs, int kmax1, int chunk, int len,
+                                                   const int *__restrict__ kout, const double *__restrict__ Q2, int ld2,
+                                                   const int *__restrict__ rho, int kmax, double *__restrict__ Q) {
+  const int c = blockIdx.y, xl = blockIdx.x * 256 + threadIdx.x, i0 = blockIdx.z * 8;
+  const int x = c * chunk + xl;
+  const int nr = min(*rho, kmax);
+  if (xl >= chunk || x >= len || i0 >= nr) return;
+  const int ka = min(kout[c], kmax1);
+  double acc[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) acc[u] = 0.0;
+  const double *qs = Qs + size_t(c) * kmax1 * chunk + xl;
+  for (int a = 0; a < ka; ++a) {
+    const double v = qs[size_t(a) * chunk];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (i0 + u < nr) acc[u] += Q2[size_t(i0 + u) * ld2 + size_t(c) * kmax1 + a] * v;
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+    if (i0 + u < nr) Q[size_t(i0 + u) * len + x] = acc[u];
 }
 
 // Singular values and left singular vectors of the m x c matrix C (row
@@ -479,18 +509,65 @@ RowView unfolding(const double *T, const int d[3], int p) {
   return RowView{T, 1, d[2], 1};
 }
 
-// Orthonormal basis of the k rows of Y (length len <= kOLen): basis rows Q
-// [kmax][len], coefficients C [k][kmax], basis size *rho.
-demag_status orth_rows(demag_ctx *ctx, DevMem &mem, RowView Y, int k, int len, int kmax, double **Q, double **C,
-                       int *rho) {
-  DEMAG_REQUIRE(k >= 1 && k <= kOMax && len >= 1 && len <= kOLen && kmax >= 1 && kmax <= kOMax,
-                "tucker: orthonormalisation of " + std::to_string(k) + " rows of length " + std::to_string(len) +
-                    " exceeds its limits");
-  TK_ALLOC(q, double, size_t(kmax) * len);
+// k_orth with the points per thread sized to the chunk: short chunks keep
+// more basis rows' loads in flight.
+void launch_orth(hipStream_t st, int grid, RowView Y, int k, int len, int chunk, double *Q, int kmax, double *C,
+                 int ldc, int *kout) {
+  if (chunk <= kOT * 4)
+    k_orth<4, 16><<<grid, kOT, 0, st>>>(Y, k, len, chunk, Q, kmax, C, ldc, kout, kDrop);
+  else
+    k_orth<kOPer, 4><<<grid, kOT, 0, st>>>(Y, k, len, chunk, Q, kmax, C, ldc, kout, kDrop);
+}
+
+// Orthonormal basis of the k rows of Y (length len <= 16384 chunks): basis
+// rows Q [kmax][len] (only with want_q), coefficients C [k][kmax], basis size
+// *rho.  Short rows: Gram-Schmidt in one workgroup.  Longer rows: every chunk
+// of the points in a workgroup of its own (bases Qs, coefficients C1 of the
+// rows on them, stacked per row), then Gram-Schmidt of the stacked
+// coefficient rows (bases Q2, coefficients C): row j = sum_i C[j][i] q_i with
+// q_i = sum_(c, a) Q2[i][(c, a)] (chunk c's basis row a).  The chunk count
+// balances the two levels (about sqrt(len / k) chunks).
+demag_status orth_rows(demag_ctx *ctx, DevMem &mem, RowView Y, int k, int64_t len, int kmax, bool want_q, double **Q,
+                       double **C, int *rho) {
+  DEMAG_REQUIRE(k >= 1 && k <= kOMax && len >= 1 && kmax >= 1 && kmax <= kOMax,
+                "tucker: orthonormalisation of " + std::to_string(k) + " rows exceeds its limits");
+  int64_t nch = 1;
+  if (len > 2048) nch = std::max<int64_t>(2, std::llround(std::sqrt(double(len) / std::min(k, kSvd))));
+  int64_t chunk = (len + nch - 1) / nch;
+  int kmax1 = int(std::min<int64_t>(k, chunk));
+  while (nch > 1 && nch * kmax1 > kOLen) {
+    nch = kOLen / kmax1;
+    chunk = (len + nch - 1) / nch;
+    kmax1 = int(std::min<int64_t>(k, chunk));
+  }
+  DEMAG_REQUIRE(chunk <= kOLen, "tucker: rows of " + std::to_string(len) + " points are too long");
+  nch = (len + chunk - 1) / chunk;
   TK_ALLOC(c, double, size_t(k) * kmax);
   TK_ALLOC(ko, int, 1);
-  k_orth<<<1, kOT, 0, ctx->stream>>>(Y, k, len, len, q, kmax, c, kmax, ko, kDrop);
-  TK_LAUNCH();
+  double *q = nullptr;
+  if (nch == 1) {
+    TK_ALLOC(q1, double, size_t(kmax) * len);
+    launch_orth(ctx->stream, 1, Y, k, int(len), int(len), q1, kmax, c, kmax, ko);
+    TK_LAUNCH();
+    q = q1;
+  } else {
+    const int ld1 = int(nch) * kmax1;
+    TK_ALLOC(Qs, double, size_t(nch) * kmax1 * chunk);
+    TK_ALLOC(C1, double, size_t(k) * ld1);
+    TK_ALLOC(ko1, int, nch);
+    launch_orth(ctx->stream, int(nch), Y, k, int(len), int(chunk), Qs, kmax1, C1, ld1, ko1);
+    TK_LAUNCH();
+    TK_ALLOC(Q2, double, size_t(kmax) * ld1);
+    launch_orth(ctx->stream, 1, contiguous(C1, ld1, ld1), k, ld1, ld1, Q2, kmax, c, kmax, ko);
+    TK_LAUNCH();
+    if (want_q) {
+      TK_ALLOC(qq, double, size_t(kmax) * len);
+      dim3 g(unsigned((chunk + 255) / 256), unsigned(nch), unsigned((kmax + 7) / 8));
+      k_tsqr_rows<<<g, 256, 0, ctx->stream>>>(Qs, kmax1, int(chunk), int(len), ko1, Q2, ld1, ko, kmax, qq);
+      TK_LAUNCH();
+      q = qq;
+    }
+  }
   int h = 0;
   DEMAG_TRY_HIP(hipMemcpyAsync(&h, ko, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
   DEMAG_TRY_HIP(hipStreamSynchronize(ctx->stream));
@@ -505,30 +582,15 @@ demag_status orth_rows(demag_ctx *ctx, DevMem &mem, RowView Y, int k, int len, i
 }
 
 // Singular values (host, descending) and left singular vectors U [m][kSvd]
-// (device, column k = vector k) of the m rows of Y (length len).  Rows
-// longer than kOLen: Gram-Schmidt per chunk, then over the stacked chunk
-// coefficients.
+// (device, column k = vector k) of the m rows of Y (length len): the rows'
+// coefficients on an orthonormal basis, then one-sided Jacobi.
 demag_status svd_rows(demag_ctx *ctx, DevMem &mem, RowView Y, int m, int64_t len, std::vector<double> &sig,
                       double **U) {
   DEMAG_REQUIRE(m >= 1 && m <= kSvd, "tucker: more than " + std::to_string(kSvd) + " rows in one mode");
-  double *C = nullptr;
+  double *C = nullptr, *Q = nullptr;
   int kc = 0;
-  if (len <= kOLen) {
-    double *Q = nullptr;
-    demag_status st = orth_rows(ctx, mem, Y, m, int(len), m, &Q, &C, &kc);
-    if (st != DEMAG_OK) return st;
-  } else {
-    const int64_t nch = (len + kOLen - 1) / kOLen;
-    DEMAG_REQUIRE(nch * m <= kOLen, "tucker: unfolding rows too long (" + std::to_string(len) + " points)");
-    TK_ALLOC(Qs, double, size_t(nch) * m * kOLen);
-    TK_ALLOC(C1, double, size_t(m) * nch * m);
-    TK_ALLOC(ko, int, nch);
-    k_orth<<<int(nch), kOT, 0, ctx->stream>>>(Y, m, int(len), kOLen, Qs, m, C1, int(nch * m), ko, kDrop);
-    TK_LAUNCH();
-    double *Q = nullptr;
-    demag_status st = orth_rows(ctx, mem, contiguous(C1, nch * m, nch * m), m, int(nch * m), m, &Q, &C, &kc);
-    if (st != DEMAG_OK) return st;
-  }
+  demag_status st = orth_rows(ctx, mem, Y, m, len, m, false, &Q, &C, &kc);
+  if (st != DEMAG_OK) return st;
   TK_ALLOC(sd, double, kSvd);
   TK_ALLOC(u, double, size_t(m) * kSvd);
   sig.assign(kc, 0.0);
@@ -727,8 +789,8 @@ demag_status recompress_sum(demag_ctx *ctx, DevMem &mem, const int n[3], const s
                                    hipMemcpyDeviceToDevice, ctx->stream));
       off += t.r[p];
     }
-    demag_status st = orth_rows(ctx, mem, contiguous(all, n[p], n[p]), tot[p], n[p], std::min(tot[p], kSvd), &Q[p],
-                                &Cf[p], &rho[p]);
+    demag_status st = orth_rows(ctx, mem, contiguous(all, n[p], n[p]), tot[p], n[p], std::min(tot[p], kSvd), true,
+                                &Q[p], &Cf[p], &rho[p]);
     if (st == DEMAG_E_UNSUPPORTED && tot[p] > kSvd) {
       set_error("tucker: the factor rows of one mode span more than " + std::to_string(kSvd) + " dimensions");
       return DEMAG_E_UNSUPPORTED;
@@ -858,8 +920,8 @@ extern "C" demag_status demag_ktucker_create(demag_ctx *ctx, const demag_factors
         const int len = 2 * f->n[p] - 1;
         const int type = p == q ? F_X : F_E;
         const double *D = f->f64[p] + size_t(type) * M * len;
-        demag_status s = orth_rows(ctx, mem, contiguous(D, len, len), M, len, std::min(M, kSvd), &Q[p], &Cf[p],
-                                   &rho[p]);
+        demag_status s = orth_rows(ctx, mem, contiguous(D, len, len), M, len, std::min(M, kSvd), true, &Q[p],
+                                   &Cf[p], &rho[p]);
         if (s != DEMAG_OK) return s;
         rho[p] = std::max(rho[p], 1);
       }
@@ -1025,9 +1087,9 @@ extern "C" demag_status demag_tt_round(demag_ctx *ctx, const int32_t n[3], int32
   // outer cores orthonormalised: G1 rows = C1 Q1, G3 rows = C3 Q3
   double *Q1, *C1, *Q3, *C3;
   int k1, k3;
-  st = orth_rows(ctx, mem, contiguous(G1, n[0], n[0]), r1, n[0], r1, &Q1, &C1, &k1);
+  st = orth_rows(ctx, mem, contiguous(G1, n[0], n[0]), r1, n[0], r1, true, &Q1, &C1, &k1);
   if (st != DEMAG_OK) return st;
-  st = orth_rows(ctx, mem, contiguous(G3, n[2], n[2]), r2, n[2], r2, &Q3, &C3, &k3);
+  st = orth_rows(ctx, mem, contiguous(G3, n[2], n[2]), r2, n[2], r2, true, &Q3, &C3, &k3);
   if (st != DEMAG_OK) return st;
   k1 = std::max(k1, 1);
   k3 = std::max(k3, 1);
