@@ -45,6 +45,14 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x2": 2500.0, "bf16x3": 2500.0}
 HBM_GBS = 8000.0
 
 
+_T0 = time.perf_counter()
+
+
+def _progress(msg):
+    """One line on stderr per finished part of the run (long runs show progress)."""
+    print(f"bench: {msg} ({time.perf_counter() - _T0:.1f} s)", file=sys.stderr, flush=True)
+
+
 def _timed(ctx, fn, steps, warmup):
     import torch
     for _ in range(warmup):
@@ -389,6 +397,7 @@ def headline(args):
         results[prec] = entry
         del m, phi, h
         torch.cuda.empty_cache()
+        _progress(f"{prec} apply timed")
 
     # the same operator by 3D FFT convolution (Sec. 4.2's route for full tensors)
     fft3d = None
@@ -404,6 +413,7 @@ def headline(args):
                  "hbm_frac": round(rec["bytes"] / (rec["ms"] * 1e-3) / 1e9 / HBM_GBS, 4)}
         del m, phi, h
         torch.cuda.empty_cache()
+        _progress("3D-FFT route timed")
 
     # the same operator on a non-uniform grid (graded cells, dense factors)
     nonuni = None
@@ -423,6 +433,7 @@ def headline(args):
                   "roofline": _roofline(prof, "fp64"), "kernels": _kernels(prof, max(2, args.steps // 2))}
         del m, phi, h, fn
         torch.cuda.empty_cache()
+        _progress("non-uniform grid timed")
 
     mixed = None
     if args.learned_steps > 0:
@@ -431,9 +442,11 @@ def headline(args):
         learned.fit_targets(ctx, cases, iters=args.fit_iters)
         torch.cuda.synchronize()
         fit_s = time.perf_counter() - t0
+        _progress("training targets fitted")
         params, loss = learned.train(ctx, cases, steps=args.learned_steps, batch=512)
         torch.cuda.synchronize()
         train_s = time.perf_counter() - t0 - fit_s
+        _progress("network trained")
         # what the network contributes: the three predict modes at this grid
         ablation = {}
         for mode in ("network", "network_proposal", "search"):
@@ -442,6 +455,7 @@ def headline(args):
                                                 "accuracy_met")}
             if mode == "network":
                 rule = r
+            _progress(f"predict ({mode}) done")
         # the plain sinc rule's node count for the same certified tolerance
         # (nodes from the library's own assembly)
         plain_nodes = None
@@ -479,15 +493,20 @@ def headline(args):
 
     learned_eval = None
     if args.learned_steps > 0 and args.learned_eval:
+        _progress("mixed + learned apply timed")
         learned_eval = _learned_eval(ctx, params, args)
 
     del f
     torch.cuda.empty_cache()
+    _progress("learned rule done")
     structured_rec = structured_record(ctx, args) if args.structured else None
+    _progress("structured applies timed")
     tucker_rec = tucker_record(ctx, args) if args.tucker else None
+    _progress("Tucker route timed")
     del ctx
     torch.cuda.empty_cache()
     batch_rec = batch_record(args) if args.batch else None
+    _progress("batch timed")
 
     head = results["fp64"]
     # the apply's compulsory traffic (m in, phi and h out) beside what the
@@ -518,8 +537,10 @@ def headline(args):
     }
     if args.vendor_gemm:
         line["vendor_gemm"] = _vendor_gemm()
+    _progress("vendor GEMM context done")
     if args.cpu_runs > 0:
         line["cpu_baseline"] = _cpu_baseline(m_host, n, args.cpu_runs)
+        _progress("CPU baseline done")
     print(json.dumps(line), flush=True)
 
 

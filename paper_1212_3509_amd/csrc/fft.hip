@@ -116,9 +116,9 @@ __global__ void k_twiddles(double2 *__restrict__ tw, int N) {
   tw[e] = make_double2(c, s);
 }
 
-__global__ void k_to_f32(const double *__restrict__ src, float *__restrict__ dst, size_t count) {
+__global__ void k_to_f32(const double *__restrict__ src, float *__restrict__ dst, size_t count, double scale) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (i < count) dst[i] = float(src[i]);
+  if (i < count) dst[i] = float(src[i] * scale);
 }
 
 // ---------------------------------------------------------------- jobs
@@ -316,20 +316,36 @@ __global__ __launch_bounds__(kThreads) void k_fft_jobs(const ColAxes P, const cp
   }
 }
 
-// Output of the FP32 inverse transform (as OutSink).
+// Output of the FP32 inverse transform (as OutSink; the 1 / N is in the
+// FP32 kernel spectra).
 struct OutSink32 {
   float *y;
   int n;
-  float inv_n;
   __device__ void operator()(int, int m, cplx32 z) const {
     const int a = 2 * m;
     if (a + 1 < n) {
-      *reinterpret_cast<float2 *>(y + a) = make_float2(z.x * inv_n, z.y * inv_n);
+      *reinterpret_cast<float2 *>(y + a) = make_float2(z.x, z.y);
     } else if (a < n) {
-      y[a] = z.x * inv_n;
+      y[a] = z.x;
     }
   }
 };
+
+// Products of the first pass for one thread: g_f A + g_c B (even factor
+// types) or i (g_f A - g_c B) (odd types).
+template <bool ODD>
+__device__ __forceinline__ void spectrum_products(cplx32 *v, const cplx32 *a, const cplx32 *b, const float *gf,
+                                                  const float *gc) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    if constexpr (ODD) {
+      const float re = gf[r] * a[r].x - gc[r] * b[r].x, im = gf[r] * a[r].y - gc[r] * b[r].y;
+      v[r] = cplx32{-im, re};
+    } else {
+      v[r] = cplx32{gf[r] * a[r].x + gc[r] * b[r].x, gf[r] * a[r].y + gc[r] * b[r].y};
+    }
+  }
+}
 
 // Passes of the inverse transform after the first (radix 16, done by the
 // caller in registers), with the last pass writing the outputs.
@@ -359,7 +375,6 @@ __device__ inline void jobs32_line(const ColAxis &A, int axis, int M, int q, int
       b[r] = AB[N + g + per * r];
     }
   }
-  const float inv_n = 1.0f / float(N);
   for (int j = j0; j < j1; ++j) {
     const int s = j / M, k = j % M;
     const int type = (axis == q) ? (s ? F_P : F_X) : (s ? F_Q : F_E);
@@ -373,23 +388,17 @@ __device__ inline void jobs32_line(const ColAxis &A, int axis, int M, int q, int
         gc[r] = gs[N - g - per * r];
       }
       cplx32 v[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        if (odd) {
-          // i (g_f A - g_c B)
-          const float re = gf[r] * a[r].x - gc[r] * b[r].x, im = gf[r] * a[r].y - gc[r] * b[r].y;
-          v[r] = cplx32{-im, re};
-        } else {
-          v[r] = cplx32{gf[r] * a[r].x + gc[r] * b[r].x, gf[r] * a[r].y + gc[r] * b[r].y};
-        }
-      }
+      if (odd)
+        spectrum_products<true>(v, a, b, gf, gc);
+      else
+        spectrum_products<false>(v, a, b, gf, gc);
       dftR<true, 16>(v);
 #pragma unroll
       for (int r = 0; r < 16; ++r) wk[slot<true>(16 * g + r)] = v[r];
     }
     __syncthreads();
     float *y = A.out + ((size_t(q) * 2 + s) * M + k) * size_t(R) * n + size_t(l) * n;
-    inverse_rest<N>(wk, tlo, thi, OutSink32{y, n, inv_n});
+    inverse_rest<N>(wk, tlo, thi, OutSink32{y, n});
     __syncthreads();
   }
 }
@@ -422,7 +431,6 @@ __global__ __launch_bounds__(kThreads) void k_fft_jobs32(const ColAxes P, const 
     default: break;
   }
   // short lines (N < 256): the packed points through LDS, then all passes
-  const float inv_n = 1.0f / float(N);
   for (int j = j0; j < j1; ++j) {
     const int s = j / M, k = j % M;
     const int type = (axis == q) ? (s ? F_P : F_X) : (s ? F_Q : F_E);
@@ -440,7 +448,7 @@ __global__ __launch_bounds__(kThreads) void k_fft_jobs32(const ColAxes P, const 
     }
     __syncthreads();
     float *y = A.out + ((size_t(q) * 2 + s) * M + k) * size_t(R) * A.n + size_t(l) * A.n;
-    fft_lines_to<true, kThreads, kPoints, OutSink32, true, float>(wk, N, 0, 1, tlo, thi, OutSink32{y, A.n, inv_n});
+    fft_lines_to<true, kThreads, kPoints, OutSink32, true, float>(wk, N, 0, 1, tlo, thi, OutSink32{y, A.n});
     __syncthreads();
   }
 }
@@ -474,9 +482,12 @@ demag_status prepare_spectra(demag_ctx *ctx, demag_factors *f) {
     // FP32 spectra, then the FP32 twiddles W_N^e (2 N floats, 8-byte aligned: nspec is even or padded)
     const size_t nspec_pad = nspec + (nspec & 1);
     DEMAG_TRY_HIP(hipMalloc(&f->spec32[d], (nspec_pad + 2 * size_t(N)) * sizeof(float)));
-    k_to_f32<<<unsigned((nspec + 255) / 256), 256, 0, ctx->stream>>>(f->spec[d], f->spec32[d], nspec);
+    // the FP32 spectra carry the inverse transform's 1 / N (a power of two:
+    // exact in the normal range)
+    k_to_f32<<<unsigned((nspec + 255) / 256), 256, 0, ctx->stream>>>(f->spec[d], f->spec32[d], nspec,
+                                                                      1.0 / double(N));
     k_to_f32<<<unsigned((2 * size_t(N) + 255) / 256), 256, 0, ctx->stream>>>(
-        reinterpret_cast<const double *>(f->twiddle[d]), f->spec32[d] + nspec_pad, 2 * size_t(N));
+        reinterpret_cast<const double *>(f->twiddle[d]), f->spec32[d] + nspec_pad, 2 * size_t(N), 1.0);
     DEMAG_TRY_HIP(hipGetLastError());
   }
   f->spec_ready = true;

@@ -207,3 +207,39 @@ def test_invalid_arguments(ctx):
     with pytest.raises(api.DemagError) as e:
         ctx.potential_tucker(kt, mag, 2.0)
     assert e.value.status == 1
+
+
+def test_potential_non_cubic_cells_and_length_scale(ctx):
+    """Unequal cell sizes with a longest edge of 2.5: the route works in the
+    factors' scaled units (longest edge 1), so potential * L equals the
+    oracle's route on the scaled cells times L."""
+    n, M, tol = (12, 9, 7), 16, 1e-8
+    h = (0.25, 0.2, 0.3)                          # edges 3.0, 1.8, 2.1: L = 3
+    f = ctx.assemble(n, h, M=M)
+    L = f.length_scale()
+    assert L == pytest.approx(3.0)
+    mag = inputs.tucker_magnetization(n, "random", (2, 1, 2), seed=17)
+    kt = ctx.ktucker(f, tol)
+    core, rows = _host(*ctx.potential_tucker(kt, [_dev(mag[q]) for q in range(3)], tol))
+    hs = tuple(x / L for x in h)
+    _t, tau, alpha = sinc.sinc_nodes(M)
+    c_o, U_o = tk.potential_tucker(mag, n, hs, tau, alpha, tol)
+    assert core.shape == c_o.shape
+    assert _rel(L * tk.tucker_dense(core, rows), L * tk.tucker_dense(c_o, U_o)) < 1e-9
+
+
+def test_tucker_sum_single_cell_modes_and_one_term(ctx):
+    rng = np.random.default_rng(18)
+    n = (1, 17, 1)
+    t = (rng.standard_normal((1, 3, 1)), [rng.standard_normal((n[p], r)) for p, r in enumerate((1, 3, 1))])
+    core, rows = _host(*ctx.tucker_sum(n, [_dev(t)], 1e-10))
+    X = tk.tucker_dense(*t)
+    assert core.shape[0] == 1 and core.shape[2] == 1
+    assert _rel(tk.tucker_dense(core, rows), X) < 1e-13
+
+
+def test_tt_round_rank_one(ctx):
+    G1, G2, G3 = inputs.tt_cores((9, 8, 7), (1, 1), seed=19)
+    H = ctx.tt_round(*_tt_dev(G1, G2, G3), 1e-10)
+    assert (H[0].shape[0], H[2].shape[0]) == (1, 1)
+    assert _rel(_tt_dense_dev(*H), tk.tt_dense(G1, G2, G3)) < 1e-13
