@@ -216,7 +216,7 @@ def test_potential_non_cubic_cells_and_length_scale(ctx):
     n, M, tol = (12, 9, 7), 16, 1e-8
     h = (0.25, 0.2, 0.3)                          # edges 3.0, 1.8, 2.1: L = 3
     f = ctx.assemble(n, h, M=M)
-    L = f.length_scale()
+    L = f.length_scale
     assert L == pytest.approx(3.0)
     mag = inputs.tucker_magnetization(n, "random", (2, 1, 2), seed=17)
     kt = ctx.ktucker(f, tol)
