@@ -331,22 +331,6 @@ struct OutSink32 {
   }
 };
 
-// Products of the first pass for one thread: g_f A + g_c B (even factor
-// types) or i (g_f A - g_c B) (odd types).
-template <bool ODD>
-__device__ __forceinline__ void spectrum_products(cplx32 *v, const cplx32 *a, const cplx32 *b, const float *gf,
-                                                  const float *gc) {
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    if constexpr (ODD) {
-      const float re = gf[r] * a[r].x - gc[r] * b[r].x, im = gf[r] * a[r].y - gc[r] * b[r].y;
-      v[r] = cplx32{-im, re};
-    } else {
-      v[r] = cplx32{gf[r] * a[r].x + gc[r] * b[r].x, gf[r] * a[r].y + gc[r] * b[r].y};
-    }
-  }
-}
-
 // Passes of the inverse transform after the first (radix 16, done by the
 // caller in registers), with the last pass writing the outputs.
 template <int N>
@@ -388,10 +372,16 @@ __device__ inline void jobs32_line(const ColAxis &A, int axis, int M, int q, int
         gc[r] = gs[N - g - per * r];
       }
       cplx32 v[16];
-      if (odd)
-        spectrum_products<true>(v, a, b, gf, gc);
-      else
-        spectrum_products<false>(v, a, b, gf, gc);
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        if (odd) {
+          // i (g_f A - g_c B)
+          const float re = gf[r] * a[r].x - gc[r] * b[r].x, im = gf[r] * a[r].y - gc[r] * b[r].y;
+          v[r] = cplx32{-im, re};
+        } else {
+          v[r] = cplx32{gf[r] * a[r].x + gc[r] * b[r].x, gf[r] * a[r].y + gc[r] * b[r].y};
+        }
+      }
       dftR<true, 16>(v);
 #pragma unroll
       for (int r = 0; r < 16; ++r) wk[slot<true>(16 * g + r)] = v[r];
