@@ -391,6 +391,12 @@ __global__ __launch_bounds__(256) void k_zero(double *__restrict__ x, int64_t co
   for (int64_t i = blockIdx.x * int64_t(256) + threadIdx.x; i < count; i += int64_t(gridDim.x) * 256) x[i] = 0.0;
 }
 
+// x = (1, 0, 0, ...): the basis of a set of rows that are all zero.
+__global__ __launch_bounds__(256) void k_unit(double *__restrict__ x, int64_t count) {
+  for (int64_t i = blockIdx.x * int64_t(256) + threadIdx.x; i < count; i += int64_t(gridDim.x) * 256)
+    x[i] = i == 0 ? 1.0 : 0.0;
+}
+
 // DFT (L points, zero-padded) of the nrows real rows (length len, stride ld):
 // rows 2w and 2w + 1 go through one complex transform z = a + i b, then
 // A_f = (z_f + conj z_{-f}) / 2, B_f = (z_f - conj z_{-f}) / (2i).  spec
@@ -575,6 +581,14 @@ demag_status orth_rows(demag_ctx *ctx, DevMem &mem, RowView Y, int k, int64_t le
     set_error("tucker: more than " + std::to_string(kmax) + " independent rows");
     return DEMAG_E_UNSUPPORTED;
   }
+  if (h == 0) {
+    // every row is zero (a zero tensor): one unit basis row, zero coefficients
+    if (q != nullptr) {
+      k_unit<<<grid_for(len), 256, 0, ctx->stream>>>(q, len);
+      TK_LAUNCH();
+    }
+    h = 1;
+  }
   *Q = q;
   *C = c;
   *rho = h;
@@ -593,6 +607,10 @@ demag_status svd_rows(demag_ctx *ctx, DevMem &mem, RowView Y, int m, int64_t len
   if (st != DEMAG_OK) return st;
   TK_ALLOC(sd, double, kSvd);
   TK_ALLOC(u, double, size_t(m) * kSvd);
+  // a zero matrix (unit basis row, zero coefficients): no singular values,
+  // and the first unit vector as its only left singular vector
+  k_unit<<<grid_for(int64_t(m) * kSvd), 256, 0, ctx->stream>>>(u, int64_t(m) * kSvd);
+  TK_LAUNCH();
   sig.assign(kc, 0.0);
   if (kc > 0) {
     const size_t lds = size_t(kc + (kc & 1)) * (m + 1) * sizeof(double);

@@ -243,3 +243,30 @@ def test_tt_round_rank_one(ctx):
     H = ctx.tt_round(*_tt_dev(G1, G2, G3), 1e-10)
     assert (H[0].shape[0], H[2].shape[0]) == (1, 1)
     assert _rel(_tt_dense_dev(*H), tk.tt_dense(G1, G2, G3)) < 1e-13
+
+
+def test_potential_with_zero_components(ctx):
+    """Uniform magnetization along z: the x and y components are zero
+    tensors (zero cores), whose products and bases must stay finite."""
+    n, M, tol = (14, 12, 10), 16, 1e-8
+    h = _h(n)
+    mag = [(np.array([[[v]]]), [np.ones((n[p], 1)) for p in range(3)]) for v in (0.0, 0.0, 0.7)]
+    kt = ctx.ktucker(ctx.assemble(n, h, M=M), tol)
+    core, rows = _host(*ctx.potential_tucker(kt, [_dev(mag[q]) for q in range(3)], tol))
+    G = tk.tucker_dense(core, rows)
+    assert np.all(np.isfinite(G))
+    _t, tau, alpha = sinc.sinc_nodes(M)
+    c_o, U_o = tk.potential_tucker(mag, n, h, tau, alpha, tol)
+    assert core.shape == c_o.shape
+    assert _rel(G, tk.tucker_dense(c_o, U_o)) < 1e-9
+
+
+def test_tucker_sum_with_zero_term(ctx):
+    rng = np.random.default_rng(20)
+    n = (10, 9, 8)
+    a = (rng.standard_normal((2, 2, 2)), [rng.standard_normal((n[p], 2)) for p in range(3)])
+    z = (np.zeros((1, 2, 1)), [np.zeros((n[p], r)) for p, r in enumerate((1, 2, 1))])
+    core, rows = _host(*ctx.tucker_sum(n, [_dev(z), _dev(a)], 1e-10))
+    G = tk.tucker_dense(core, rows)
+    assert np.all(np.isfinite(G)) and core.shape == (2, 2, 2)
+    assert _rel(G, tk.tucker_dense(*a)) < 1e-13
