@@ -185,11 +185,12 @@ demag_status launch_build_windows(demag_ctx *ctx, demag_factors *f);
 // non-uniform grids: dense factors from the scaled cell edges (host, n_d + 1 per axis)
 demag_status launch_assemble_dense(demag_ctx *ctx, demag_factors *f, const std::vector<double> edges[3]);
 demag_status launch_dense_stage(hipStream_t s, const StagePlan &sp, const double *mats, const Bufs &bufs, int beta);
-// Outputs from the x stage's partial sums (FP32): phi = phi_scale sum_s
-// partials[4 s], h_p = sum_s partials[4 s + 1 + p] (element blocks of N),
-// added to the outputs when accumulate is set.
-demag_status launch_reduce_partials(demag_ctx *ctx, demag_prec prec, const float *partials, int nsplit, int64_t N,
-                                    float *phi, float *h, double phi_scale, bool accumulate);
+// Outputs from the x stage's partial sums (FP64 for DEMAG_FP64, else FP32):
+// phi = phi_scale sum_s partials[4 s], h_p = sum_s partials[4 s + 1 + p]
+// (element blocks of N), added in FP64, added to the outputs when
+// accumulate is set.
+demag_status launch_reduce_partials(demag_ctx *ctx, demag_prec prec, const void *partials, int nsplit, int64_t N,
+                                    void *phi, void *h, double phi_scale, bool accumulate);
 demag_status launch_left_stage_bf16(demag_ctx *ctx, const demag_factors *f, demag_prec prec,
                                     const StagePlan &sp, void *const bufs[6], int beta);
 demag_status launch_split(demag_ctx *ctx, const float *x, uint16_t *parts, size_t count, int nparts);

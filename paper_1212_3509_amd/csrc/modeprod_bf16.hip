@@ -445,19 +445,20 @@ namespace {
 
 // Four consecutive elements per thread of the 4 N outputs (phi, h_x, h_y,
 // h_z), each the sum of nsplit partials.
-__global__ void k_reduce_partials(const float *__restrict__ partials, int nsplit, int64_t N, float *__restrict__ phi,
-                                  float *__restrict__ h, double phi_scale, int accumulate) {
+template <class T>
+__global__ void k_reduce_partials(const T *__restrict__ partials, int nsplit, int64_t N, T *__restrict__ phi,
+                                  T *__restrict__ h, double phi_scale, int accumulate) {
   const int64_t i = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) * 4;
   const int o = int(blockIdx.y);                       // 0: phi, 1..3: h_x, h_y, h_z
   if (i >= N) return;
-  float *out = (o == 0) ? phi : h + int64_t(o - 1) * N;
+  T *out = (o == 0) ? phi : h + int64_t(o - 1) * N;
   const double scale = (o == 0) ? phi_scale : 1.0;
   const int cnt = int(N - i < 4 ? N - i : 4);
   // the partial sums are added in FP64 and rounded once
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int s = 0; s < nsplit; ++s) {
-    const float *src = partials + (int64_t(4) * s + o) * N + i;
-    if (cnt == 4 && ((reinterpret_cast<uintptr_t>(src) & 15u) == 0)) {
+    const T *src = partials + (int64_t(4) * s + o) * N + i;
+    if (std::is_same_v<T, float> && cnt == 4 && ((reinterpret_cast<uintptr_t>(src) & 15u) == 0)) {
       const float4 v = *reinterpret_cast<const float4 *>(src);
       acc[0] += double(v.x);
       acc[1] += double(v.y);
@@ -469,25 +470,35 @@ __global__ void k_reduce_partials(const float *__restrict__ partials, int nsplit
   }
   for (int e = 0; e < cnt; ++e) {
     const double v = scale * acc[e];
-    out[i + e] = float(accumulate ? double(out[i + e]) + v : v);
+    out[i + e] = T(accumulate ? double(out[i + e]) + v : v);
   }
 }
 
 }  // namespace
 
-demag_status launch_reduce_partials(demag_ctx *ctx, demag_prec prec, const float *partials, int nsplit, int64_t N,
-                                    float *phi, float *h, double phi_scale, bool accumulate) {
+demag_status launch_reduce_partials(demag_ctx *ctx, demag_prec prec, const void *partials, int nsplit, int64_t N,
+                                    void *phi, void *h, double phi_scale, bool accumulate) {
   if (N == 0) return DEMAG_OK;
   hipEvent_t ev = nullptr;
   demag_status st = prof_begin(ctx, &ev);
   if (st != DEMAG_OK) return st;
   const int64_t threads = (N + 3) / 4;
   dim3 grid(unsigned((threads + 255) / 256), 4);
-  k_reduce_partials<<<grid, 256, 0, ctx->stream>>>(partials, nsplit, N, phi, h, phi_scale, accumulate ? 1 : 0);
+  const bool f64 = prec == DEMAG_FP64;
+  if (f64)
+    k_reduce_partials<double><<<grid, 256, 0, ctx->stream>>>(static_cast<const double *>(partials), nsplit, N,
+                                                             static_cast<double *>(phi), static_cast<double *>(h),
+                                                             phi_scale, accumulate ? 1 : 0);
+  else
+    k_reduce_partials<float><<<grid, 256, 0, ctx->stream>>>(static_cast<const float *>(partials), nsplit, N,
+                                                            static_cast<float *>(phi), static_cast<float *>(h),
+                                                            phi_scale, accumulate ? 1 : 0);
   DEMAG_TRY_HIP(hipGetLastError());
   if (ev) {
-    const double bytes = 4.0 * N * 4.0 * (nsplit + (accumulate ? 2 : 1));
-    st = prof_end(ctx, ev, std::string(prec == DEMAG_BF16X3 ? "bf16x3" : prec == DEMAG_BF16X2 ? "bf16x2" : "fp32") + "/x/reduce", 0.0, bytes);
+    const double es = f64 ? 8.0 : 4.0;
+    const double bytes = es * N * 4.0 * (nsplit + (accumulate ? 2 : 1));
+    const char *name = f64 ? "fp64" : prec == DEMAG_BF16X3 ? "bf16x3" : prec == DEMAG_BF16X2 ? "bf16x2" : "fp32";
+    st = prof_end(ctx, ev, std::string(name) + "/x/reduce", 0.0, bytes);
   }
   return st;
 }
