@@ -41,6 +41,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -738,7 +739,9 @@ size_t fft_lds() {
 }
 
 demag_status set_fft_attrs(int device) {
+  static std::mutex mu;
   static uint64_t done = 0;   // one bit per device
+  std::lock_guard<std::mutex> lock(mu);
   if (device < 64 && ((done >> device) & 1u)) return DEMAG_OK;
   DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_row_spectra<256, 4096>),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(fft_lds<256, 4096>())));
