@@ -24,8 +24,11 @@
  *     completes (the caller synchronizes).  Host outputs documented as such are
  *     complete on return.
  *   - Every call returns a status; arguments are validated before anything is
- *     launched, and on error nothing has been enqueued.  demag_last_error()
- *     gives a message for the calling thread's last failure.
+ *     launched, and on error nothing has been enqueued (except the Tucker-route
+ *     calls, whose ranks are decided as they run: a failure there, e.g. a rank
+ *     above rmax, comes after their GPU work has finished, with the outputs
+ *     untouched).  demag_last_error() gives a message for the calling thread's
+ *     last failure.
  */
 #ifndef DEMAG_H
 #define DEMAG_H
@@ -388,6 +391,24 @@ demag_status demag_tucker_sum(demag_ctx *ctx, const int32_t n[3], int32_t nterms
 demag_status demag_tt_round(demag_ctx *ctx, const int32_t n[3], int32_t r1, int32_t r2, const double *G1,
                             const double *G2, const double *G3, double tol, int32_t rmax, int32_t rout[2],
                             double *G1o, double *G2o, double *G3o);
+/* Conversions between the formats (App. C), same layouts.  CP -> TT: the
+ * rank-R CP tensor sum_a lam[a] U0[a] o U1[a] o U2[a] (lam [R], U[p]
+ * [R][n_p]) as a TT with ranks (R, R) and the diagonal middle core
+ * G2[a][b][j] = (a == b) lam[a] U1[a][j]; outputs G1 [R][n0], G2 [R][R][n1],
+ * G3 [R][n2] (round it with demag_tt_round).  Enqueued only. */
+demag_status demag_cp_to_tt(demag_ctx *ctx, const int32_t n[3], int32_t R, const double *lam,
+                            const double *const U[3], double *G1, double *G2, double *G3);
+/* Tucker -> TT (Eq. (tt_3d_2) read backwards): G1 = rows[0] [r0][n0],
+ * G2[a][c][j] = sum_b core[a][b][c] rows[1][b][j] ([r0][r2][n1]), G3 =
+ * rows[2] [r2][n2].  Enqueued only. */
+demag_status demag_tucker_to_tt(demag_ctx *ctx, const int32_t n[3], const demag_tucker_in *t, double *G1,
+                                double *G2, double *G3);
+/* TT -> Tucker: the Tucker2 form of Eq. (tt_3d_2) with the middle mode in an
+ * orthonormal basis of the r1 r2 fibres G2[a, b, :] (r1 r2 <= 512, spanning
+ * at most 128 dimensions), recompressed by HOOI with tol as above. */
+demag_status demag_tt_to_tucker(demag_ctx *ctx, const int32_t n[3], int32_t r1, int32_t r2, const double *G1,
+                                const double *G2, const double *G3, double tol, int32_t rmax, int32_t rout[3],
+                                double *core, double *const rows[3]);
 
 /* ---------------------------------------------------------------- learned rule
  * A network proposes shortened rules (R' = 16..32 nodes); the operator error

@@ -39,6 +39,10 @@ What each function states, and the passage it follows:
                     result is within eps of the input in relative norm.
   tt_from_tucker    App. C, Eq. (tt_3d_2) read backwards: the middle factor
                     multiplied into the core gives the TT cores.
+  tt_from_cp        App. C (CP2TT): a rank-R CP tensor is a TT with ranks (R, R)
+                    and a diagonal middle core.
+  tucker_from_tt    App. C: the Tucker2 form of Eq. (tt_3d_2) recompressed to
+                    Tucker (HOOI with tol).
   potential_at_cells  Eq. (kron_eval_tuck) at single target cells: the
                     uncompressed Kronecker operator's potential of a Tucker
                     magnetization, for sizes where no dense tensor fits.
@@ -272,3 +276,20 @@ def tt_round(G1, G2, G3, eps):
 def tt_from_tucker(core, U):
     """Tucker -> TT: G1 = U1, G2 = core x_2 U2, G3 = U3^T."""
     return U[0].copy(), mode_product(core, U[1], 1), U[2].T.copy()
+
+
+def tt_from_cp(lam, U):
+    """CP -> TT (the conversion the paper cites with TT rounding): ranks
+    (R, R), G1 = U1, G2[a, :, b] = delta_ab lam_a U2[:, a], G3 = U3^T."""
+    R = len(lam)
+    G2 = np.zeros((R, U[1].shape[0], R))
+    for a in range(R):
+        G2[a, :, a] = lam[a] * U[1][:, a]
+    return U[0].copy(), G2, U[2].T.copy()
+
+
+def tucker_from_tt(G1, G2, G3, tol):
+    """TT -> Tucker (Eq. (tt_3d_2) read as a Tucker2 tensor [[G2; G1, id,
+    G3^T]], then recompressed): HOOI of the dense tensor with tol."""
+    core, U, _sw = hooi(tt_dense(G1, G2, G3), tol)
+    return core, U

@@ -107,6 +107,9 @@ _SIGS = {
     "demag_tucker_sum": (C.c_int, [_P, _P, C.c_int32, _P, C.c_double, C.c_int32, _P, _P, _P]),
     "demag_tt_round": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P, _P, _P, C.c_double, C.c_int32, _P, _P, _P,
                                  _P]),
+    "demag_cp_to_tt": (C.c_int, [_P, _P, C.c_int32, _P, _P, _P, _P, _P]),
+    "demag_tucker_to_tt": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "demag_tt_to_tucker": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P, _P, _P, C.c_double, C.c_int32, _P, _P, _P]),
     "demag_bf16_split": (C.c_int, [_P, _P, _P, C.c_size_t, C.c_int32]),
     "demag_profile_enable": (C.c_int, [_P, C.c_int32]),
     "demag_profile_read": (C.c_int, [_P, C.c_int32, _P, _P, _P, _P, _P, C.POINTER(C.c_int32)]),
@@ -659,6 +662,50 @@ class Context:
                                         rmax, rout, _ptr(H1), _ptr(H2), _ptr(H3)), "demag_tt_round")
         s1, s2 = rout[0], rout[1]
         return H1[:s1], H2[:s1 * s2 * n[1]].reshape(s1, s2, n[1]), H3[:s2]
+
+    def cp_to_tt(self, lam, U):
+        """CP (lam [R], U[p] [R][n_p], float64 CUDA) -> TT cores G1 [R][n0],
+        G2 [R][R][n1], G3 [R][n2] (the library's TT layout)."""
+        import torch
+        R = int(lam.shape[0])
+        n = [int(U[p].shape[1]) for p in range(3)]
+        for x in (lam, *U):
+            if not (x.is_cuda and x.is_contiguous()) or x.dtype != torch.float64:
+                raise ValueError("CP weights and factor rows must be contiguous float64 CUDA tensors")
+        G1 = torch.empty((R, n[0]), dtype=torch.float64, device="cuda")
+        G2 = torch.empty((R, R, n[1]), dtype=torch.float64, device="cuda")
+        G3 = torch.empty((R, n[2]), dtype=torch.float64, device="cuda")
+        self.use_current_stream()
+        _check(library().demag_cp_to_tt(self.handle, (C.c_int32 * 3)(*n), R, _ptr(lam), self._ptr3(U), _ptr(G1),
+                                        _ptr(G2), _ptr(G3)), "demag_cp_to_tt")
+        return G1, G2, G3
+
+    def tucker_to_tt(self, core, rows):
+        """Tucker (core, rows) -> TT cores in the library's TT layout."""
+        import torch
+        t = self._tucker_in((core, rows))
+        n = [int(rows[p].shape[1]) for p in range(3)]
+        r = [int(rows[p].shape[0]) for p in range(3)]
+        G1 = torch.empty((r[0], n[0]), dtype=torch.float64, device="cuda")
+        G2 = torch.empty((r[0], r[2], n[1]), dtype=torch.float64, device="cuda")
+        G3 = torch.empty((r[2], n[2]), dtype=torch.float64, device="cuda")
+        self.use_current_stream()
+        _check(library().demag_tucker_to_tt(self.handle, (C.c_int32 * 3)(*n), C.byref(t), _ptr(G1), _ptr(G2),
+                                            _ptr(G3)), "demag_tucker_to_tt")
+        return G1, G2, G3
+
+    def tt_to_tucker(self, G1, G2, G3, tol: float, rmax: int = 128):
+        """TT cores (library layout) -> Tucker (core, rows), recompressed with tol."""
+        import torch
+        r1, r2 = int(G1.shape[0]), int(G3.shape[0])
+        n = (int(G1.shape[1]), int(G2.shape[2]), int(G3.shape[1]))
+        for x in (G1, G2, G3):
+            if not (x.is_cuda and x.is_contiguous()) or x.dtype != torch.float64:
+                raise ValueError("TT cores must be contiguous float64 CUDA tensors")
+        n3 = (C.c_int32 * 3)(*n)
+        return self._tucker_out(lambda ro, co, ro3: library().demag_tt_to_tucker(
+            self.handle, n3, r1, r2, _ptr(G1), _ptr(G2), _ptr(G3), tol, rmax, ro, co, ro3), n, rmax,
+            "demag_tt_to_tucker")
 
     def bf16_split(self, x, nparts: int = 3):
         """Device split of a contiguous float32 CUDA tensor into bfloat16 bit

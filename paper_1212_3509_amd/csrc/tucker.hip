@@ -456,6 +456,39 @@ __global__ __launch_bounds__(KT) void k_conv_rows(const cplx *__restrict__ SK, i
   }
 }
 
+// CP -> TT (ranks (R, R)): G2[a][b][j] = (a == b) lam_a U2[a][j].
+__global__ __launch_bounds__(256) void k_cp_tt_mid(const double *__restrict__ lam, const double *__restrict__ U2, int R,
+                                                   int n, double *__restrict__ G2) {
+  const int64_t total = int64_t(R) * R * n;
+  for (int64_t o = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; o < total; o += int64_t(gridDim.x) * blockDim.x) {
+    const int j = int(o % n), b = int((o / n) % R), a = int(o / (int64_t(n) * R));
+    G2[o] = a == b ? lam[a] * U2[int64_t(a) * n + j] : 0.0;
+  }
+}
+
+// Tucker -> TT middle core: G2[a][c][j] = sum_b core[a][b][c] U2[b][j].
+__global__ __launch_bounds__(256) void k_tucker_tt_mid(const double *__restrict__ core, int r0, int r1, int r2,
+                                                       const double *__restrict__ U2, int n, double *__restrict__ G2) {
+  const int64_t total = int64_t(r0) * r2 * n;
+  for (int64_t o = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; o < total; o += int64_t(gridDim.x) * blockDim.x) {
+    const int j = int(o % n), c = int((o / n) % r2), a = int(o / (int64_t(n) * r2));
+    double s = 0.0;
+    for (int b = 0; b < r1; ++b) s += core[(int64_t(a) * r1 + b) * r2 + c] * U2[int64_t(b) * n + j];
+    G2[o] = s;
+  }
+}
+
+// TT -> Tucker core in the fibres' basis: core[a][i][b] = C[(a r2 + b) ldc + i]
+// (C: coefficients of fibre G2[a, b, :] on basis row i), i < rho.
+__global__ __launch_bounds__(256) void k_tt_core(const double *__restrict__ C, int ldc, int r1, int r2, int rho,
+                                                 double *__restrict__ core) {
+  const int64_t total = int64_t(r1) * rho * r2;
+  for (int64_t o = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; o < total; o += int64_t(gridDim.x) * blockDim.x) {
+    const int b = int(o % r2), i = int((o / r2) % rho), a = int(o / (int64_t(r2) * rho));
+    core[o] = C[(int64_t(a) * r2 + b) * ldc + i];
+  }
+}
+
 // ------------------------------------------------------------------ host side
 
 int dft_length(int n) {
@@ -1170,4 +1203,78 @@ extern "C" demag_status demag_tt_round(demag_ctx *ctx, const int32_t n[3], int32
   DEMAG_TRY_HIP(hipMemcpyAsync(G3o, H3, size_t(s2) * n[2] * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
   DEMAG_TRY_HIP(hipStreamSynchronize(ctx->stream));
   return DEMAG_OK;
+}
+
+extern "C" demag_status demag_cp_to_tt(demag_ctx *ctx, const int32_t n[3], int32_t R, const double *lam,
+                                       const double *const U[3], double *G1, double *G2, double *G3) {
+  DEMAG_REQUIRE(ctx != nullptr && n != nullptr && lam != nullptr && U != nullptr && G1 != nullptr && G2 != nullptr &&
+                    G3 != nullptr,
+                "demag_cp_to_tt: NULL argument");
+  DEMAG_REQUIRE(R >= 1, "demag_cp_to_tt: R >= 1");
+  for (int p = 0; p < 3; ++p) {
+    DEMAG_REQUIRE(U[p] != nullptr, "demag_cp_to_tt: NULL factor rows");
+    DEMAG_REQUIRE(n[p] >= 1, "demag_cp_to_tt: mode sizes >= 1");
+  }
+  DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  DEMAG_TRY_HIP(hipMemcpyAsync(G1, U[0], size_t(R) * n[0] * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  DEMAG_TRY_HIP(hipMemcpyAsync(G3, U[2], size_t(R) * n[2] * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  const int64_t total = int64_t(R) * R * n[1];
+  k_cp_tt_mid<<<grid_for(total), 256, 0, ctx->stream>>>(lam, U[1], R, n[1], G2);
+  TK_LAUNCH();
+  return DEMAG_OK;
+}
+
+extern "C" demag_status demag_tucker_to_tt(demag_ctx *ctx, const int32_t n[3], const demag_tucker_in *t, double *G1,
+                                           double *G2, double *G3) {
+  DEMAG_REQUIRE(ctx != nullptr && n != nullptr && t != nullptr && G1 != nullptr && G2 != nullptr && G3 != nullptr,
+                "demag_tucker_to_tt: NULL argument");
+  demag_status st = check_terms(t, 1, "demag_tucker_to_tt");
+  if (st != DEMAG_OK) return st;
+  for (int p = 0; p < 3; ++p) DEMAG_REQUIRE(n[p] >= 1, "demag_tucker_to_tt: mode sizes >= 1");
+  DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  DEMAG_TRY_HIP(hipMemcpyAsync(G1, t->rows[0], size_t(t->r[0]) * n[0] * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+  DEMAG_TRY_HIP(hipMemcpyAsync(G3, t->rows[2], size_t(t->r[2]) * n[2] * sizeof(double), hipMemcpyDeviceToDevice,
+                               ctx->stream));
+  const int64_t total = int64_t(t->r[0]) * t->r[2] * n[1];
+  k_tucker_tt_mid<<<grid_for(total), 256, 0, ctx->stream>>>(t->core, t->r[0], t->r[1], t->r[2], t->rows[1], n[1], G2);
+  TK_LAUNCH();
+  return DEMAG_OK;
+}
+
+extern "C" demag_status demag_tt_to_tucker(demag_ctx *ctx, const int32_t n[3], int32_t r1, int32_t r2,
+                                           const double *G1, const double *G2, const double *G3, double tol,
+                                           int32_t rmax, int32_t rout[3], double *core, double *const rows[3]) {
+  DEMAG_REQUIRE(ctx != nullptr && n != nullptr && G1 != nullptr && G2 != nullptr && G3 != nullptr && rout != nullptr &&
+                    core != nullptr && rows != nullptr,
+                "demag_tt_to_tucker: NULL argument");
+  DEMAG_REQUIRE(r1 >= 1 && r1 <= kSvd && r2 >= 1 && r2 <= kSvd && int64_t(r1) * r2 <= kOMax,
+                "demag_tt_to_tucker: ranks 1..128 with r1 r2 <= 512");
+  for (int p = 0; p < 3; ++p) {
+    DEMAG_REQUIRE(n[p] >= 1 && n[p] <= kOLen, "demag_tt_to_tucker: mode sizes 1..16384");
+    DEMAG_REQUIRE(rows[p] != nullptr, "demag_tt_to_tucker: NULL output rows");
+  }
+  DEMAG_REQUIRE(tol > 0.0 && tol < 1.0, "demag_tt_to_tucker: tol must lie in (0, 1)");
+  DEMAG_REQUIRE(rmax >= 1, "demag_tt_to_tucker: rmax >= 1");
+  DEMAG_TRY_HIP(hipSetDevice(ctx->device));
+  DevMem mem(ctx->stream);
+  // the middle mode: an orthonormal basis of the r1 r2 fibres G2[a, b, :]
+  double *Q2 = nullptr, *C2 = nullptr;
+  int rho = 0;
+  const int kmax = std::min(r1 * r2, kSvd);
+  demag_status st = orth_rows(ctx, mem, contiguous(G2, n[1], n[1]), r1 * r2, n[1], kmax, true, &Q2, &C2, &rho);
+  if (st == DEMAG_E_UNSUPPORTED) {
+    set_error("demag_tt_to_tucker: the middle core's fibres span more than 128 dimensions");
+    return st;
+  }
+  if (st != DEMAG_OK) return st;
+  TK_ALLOC(c0, double, size_t(r1) * rho * r2);
+  k_tt_core<<<grid_for(int64_t(r1) * rho * r2), 256, 0, ctx->stream>>>(C2, kmax, r1, r2, rho, c0);
+  TK_LAUNCH();
+  const int nn[3] = {n[0], n[1], n[2]};
+  DTucker term{{r1, rho, r2}, c0, {G1, Q2, G3}};
+  TuckerOut out;
+  st = recompress_sum(ctx, mem, nn, {term}, tol, out);
+  if (st != DEMAG_OK) return st;
+  return copy_out(ctx, out, nn, rmax, rout, core, rows);
 }

@@ -270,3 +270,28 @@ def test_tucker_sum_with_zero_term(ctx):
     G = tk.tucker_dense(core, rows)
     assert np.all(np.isfinite(G)) and core.shape == (2, 2, 2)
     assert _rel(G, tk.tucker_dense(*a)) < 1e-13
+
+
+def test_format_conversions_match_oracle(ctx):
+    """CP -> TT (bit-exact: copies and one product), Tucker -> TT, TT ->
+    Tucker (ranks and dense tensor as the oracle's HOOI), and CP -> TT ->
+    rounding (the ranks of a rank-3 CP tensor stored as rank 6)."""
+    rng = np.random.default_rng(22)
+    n = (11, 9, 8)
+    lam = rng.standard_normal(6)
+    U = [rng.standard_normal((n[p], 6)) for p in range(3)]
+    U = [np.concatenate([u[:, :3], u[:, :3] @ rng.standard_normal((3, 3))], axis=1) for u in U[:1]] + U[1:]
+    T = ctx.cp_to_tt(torch.from_numpy(lam).cuda(), [torch.from_numpy(np.ascontiguousarray(U[p].T)).cuda()
+                                                    for p in range(3)])
+    O = tk.tt_from_cp(lam, U)
+    assert np.array_equal(T[0].cpu().numpy().T, O[0]) and np.array_equal(T[2].cpu().numpy(), O[2])
+    assert np.array_equal(np.transpose(T[1].cpu().numpy(), (0, 2, 1)), O[1])
+    core, rows = _host(*ctx.tt_to_tucker(*T, 1e-12))
+    c_o, U_o = tk.tucker_from_tt(*O, 1e-12)
+    assert core.shape == c_o.shape
+    X = tk.tt_dense(*O)
+    assert _rel(tk.tucker_dense(core, rows), X) < 1e-12
+    assert _rel(tk.tucker_dense(core, rows), tk.tucker_dense(c_o, U_o)) < 1e-12
+    t = (rng.standard_normal((2, 3, 4)), [rng.standard_normal((n[p], r)) for p, r in enumerate((2, 3, 4))])
+    T2 = ctx.tucker_to_tt(*_dev(t))
+    assert _rel(_tt_dense_dev(*T2), tk.tucker_dense(*t)) < 1e-14

@@ -233,3 +233,16 @@ def test_tt_from_tucker():
     rng = np.random.default_rng(11)
     core, U = _rand_tucker(rng, (6, 5, 4), (2, 3, 2))
     assert np.allclose(tk.tt_dense(*tk.tt_from_tucker(core, U)), tk.tucker_dense(core, U), rtol=1e-13, atol=1e-13)
+
+
+def test_tt_from_cp_and_tucker_from_tt():
+    rng = np.random.default_rng(21)
+    n = (7, 6, 5)
+    lam = rng.standard_normal(4)
+    U = [rng.standard_normal((n[p], 4)) for p in range(3)]
+    X = np.einsum("r,ir,jr,kr->ijk", lam, U[0], U[1], U[2])
+    T = tk.tt_from_cp(lam, U)
+    assert np.allclose(tk.tt_dense(*T), X, rtol=1e-13, atol=1e-13)
+    core, V = tk.tucker_from_tt(*T, 1e-12)
+    assert max(core.shape) <= 4
+    assert np.linalg.norm(tk.tucker_dense(core, V) - X) < 1e-12 * np.linalg.norm(X)
