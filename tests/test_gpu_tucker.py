@@ -107,13 +107,15 @@ def test_potential_long_axis_8192_point_transforms(ctx):
     assert _rel(G, O) < 1e-9
 
 
-def test_potential_full_size_sampled(ctx):
-    """The paper's Alg. scpot_fft_tucker case of uniform magnetization at
-    n = 4096 per axis (M = 40, tol 1e-8): 8 sampled cells of the compressed
-    potential against the uncompressed Kronecker operator, row by row."""
+@pytest.mark.parametrize("kind", ["uniform", "smooth"])
+def test_potential_full_size_sampled(ctx, kind):
+    """The paper's Alg. scpot_fft_tucker case of uniform magnetization, and a
+    smooth rank-(2,2,2) one, at n = 4096 per axis (M = 40, tol 1e-8): 8
+    sampled cells of the compressed potential against the uncompressed
+    Kronecker operator, row by row."""
     n, M, tol = (4096, 4096, 4096), 40, 1e-8
     h = _h(n)
-    mag = inputs.tucker_magnetization(n, "uniform")
+    mag = inputs.tucker_magnetization(n, kind, (2, 2, 2))
     kt = ctx.ktucker(ctx.assemble(n, h, M=M), tol)
     core, rows = ctx.potential_tucker(kt, [_dev(mag[q]) for q in range(3)], tol)
     core, rows = _host(core, rows)
@@ -123,7 +125,7 @@ def test_potential_full_size_sampled(ctx):
     _t, tau, alpha = sinc.sinc_nodes(M)
     ref = tk.potential_at_cells(mag, n, h, tau, alpha, cells)
     err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    print(f"4096^3 uniform: ranks {core.shape}, sampled rel err {err:.2e}")
+    print(f"4096^3 {kind}: ranks {core.shape}, sampled rel err {err:.2e}")
     assert err < 30 * tol
     assert max(core.shape) < 64
 
