@@ -164,14 +164,37 @@ __global__ __launch_bounds__(kOT) void k_orth(RowView Y, int k, int len, int chu
         acc[i] += s;
       }
       __syncthreads();
+      // v -= sum_i coef_i q_i: short chunks load GRP basis rows at a time
+      // (long chunks have no registers for that)
+      if constexpr (PER >= 16) {
 #pragma unroll 4
-      for (int i = 0; i < kept; ++i) {
-        const double cf = coef[i];
-        const double *qi = Qc + size_t(i) * chunk;
+        for (int i = 0; i < kept; ++i) {
+          const double cf = coef[i];
+          const double *qi = Qc + size_t(i) * chunk;
 #pragma unroll
-        for (int e = 0; e < PER; ++e) {
-          const int x = tid + kOT * e;
-          if (x < m) v[e] -= cf * qi[x];
+          for (int e = 0; e < PER; ++e) {
+            const int x = tid + kOT * e;
+            if (x < m) v[e] -= cf * qi[x];
+          }
+        }
+      } else {
+        for (int i0 = 0; i0 < kept; i0 += GRP) {
+          double qv[GRP][PER];
+#pragma unroll
+          for (int u = 0; u < GRP; ++u) {
+            const double *qi = Qc + size_t(i0 + u) * chunk;
+#pragma unroll
+            for (int e = 0; e < PER; ++e) {
+              const int x = tid + kOT * e;
+              qv[u][e] = (i0 + u < kept && x < m) ? qi[x] : 0.0;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < GRP; ++u) {
+            const double cf = i0 + u < kept ? coef[i0 + u] : 0.0;
+#pragma unroll
+            for (int e = 0; e < PER; ++e) v[e] -= cf * qv[u][e];
+          }
         }
       }
     }
