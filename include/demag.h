@@ -412,8 +412,8 @@ demag_status demag_tt_to_tucker(demag_ctx *ctx, const int32_t n[3], int32_t r1, 
 
 /* ---------------------------------------------------------------- learned rule
  * A network proposes shortened rules (R' = 16..32 nodes); the operator error
- * of a rule is certified against an accurate reference rule; the full rule
- * is the fallback.  Not part of the paper's method: it shortens the sinc rule
+ * of a rule is certified against an accurate reference rule; a theorem-step
+ * rule with 33..64 nodes is the fallback.  Not part of the paper's method: it shortens the sinc rule
  * of Cor. kron_op.
  *
  * Network: 6 -> 64 -> 64 -> 64 -> 65, GELU hidden layers, FP32, parameters a
@@ -523,7 +523,7 @@ typedef enum {
 /* Result of demag_quad_predict (host). */
 typedef struct {
   int32_t R;          /* nodes of the returned rule (64 if fell back) */
-  int32_t fell_back;  /* 1: the theorem-step rule with 64 nodes */
+  int32_t fell_back;  /* 1: the theorem-step rule (33..64 nodes) */
   int32_t fits;       /* Levenberg-Marquardt fits run */
   int32_t mode;
   double err_phi;     /* certificate of the returned rule */
@@ -541,9 +541,10 @@ typedef struct {
  * on the weighted offsets and are certified; the network modes start at the
  * smallest R' whose predicted log10 error is <= log10 tol and step R' by 1 up
  * to 32 on a miss, the search mode bisects R' = 16..32.  If no candidate
- * meets tol the sinc rule with the step of Thm. sinc_theo and 64 nodes is
- * certified and returned (fell_back = 1), and if that misses tol too the
- * call returns DEMAG_E_ACCURACY with *out filled.  params (device) may be
+ * meets tol, the sinc rule with the step of Thm. sinc_theo is returned with
+ * the fewest nodes in 33..64 whose certificate meets tol (64 tried first,
+ * then bisection; fell_back = 1), and if even 64 nodes miss tol the call
+ * returns DEMAG_E_ACCURACY with *out filled by the 64-node rule.  params (device) may be
  * NULL in the search mode. */
 demag_status demag_quad_predict(demag_ctx *ctx, const float *params, const demag_grid *grid, double tol,
                                 int32_t fit_iters, int32_t mode, demag_quad_result *out);

@@ -12,7 +12,8 @@ outputs modify a base rule, and a judge measures the resulting operator error:
               (y: network output; the weight follows its node, so moving a
               node keeps the trapezoid weight of the substituted integrand);
   reference   the sinc rule with the step of Thm. sinc_theo and 96 nodes;
-  fallback    the same with 64 nodes;
+  fallback    the same with the fewest nodes in 33..64 whose certificate meets
+              the tolerance (64 when none does);
   kernels     at an offset J, nine values: the potential kernels K^x, K^y,
               K^z (Cor. kron_op) and the field kernels F_pq of h_p <- m_q for
               p <= q (the same with the derivative factors; F_pq = F_qp);

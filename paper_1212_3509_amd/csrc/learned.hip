@@ -1261,9 +1261,9 @@ demag_status demag_quad_certify(demag_ctx *ctx, const demag_grid *grid, int32_t 
 //   DEMAG_PREDICT_SEARCH: no network: bisection over R' = 16..32 for the
 //     smallest R' whose fit (from the plain base rule) is certified within
 //     tol (R' = 32 first; the certified error falls with R').
-// If nothing meets tol, the sinc rule with the step of Thm. sinc_theo and 64
-// nodes is certified and returned (fell_back = 1; DEMAG_E_ACCURACY if it
-// misses tol too).
+// If nothing meets tol, the sinc rule with the step of Thm. sinc_theo is
+// returned with the fewest nodes in 33..64 whose certificate meets tol
+// (fell_back = 1; with 64 nodes and DEMAG_E_ACCURACY if even 64 miss tol).
 demag_status demag_quad_predict(demag_ctx *ctx, const float *params, const demag_grid *grid, double tol,
                                 int32_t fit_iters, int32_t mode, demag_quad_result *out) {
   DEMAG_REQUIRE(ctx && grid && out, "demag_quad_predict: NULL argument");
@@ -1403,20 +1403,40 @@ demag_status demag_quad_predict(demag_ctx *ctx, const float *params, const demag
     if (best.ok) {
       out->fell_back = 0;
     } else {
-      // fallback: the sinc rule with the step of Thm. sinc_theo, 64 nodes
-      const int M = 64;
-      const double a = 2.0, bb = 0.25 * (0.5 * hmin) * (0.5 * hmin);
-      const double theta = std::log(2.0 * kPi * a * M / bb) / (a * M);
-      best.R = M;
-      best.t.resize(M);
-      best.a.resize(M);
-      for (int k = 0; k < M; ++k) {
-        const double tk = (k + 1) * theta, sh = std::sinh(tk);
-        best.t[k] = tk;
-        best.a[k] = 2.0 * theta * std::cosh(tk) * sh * sh;
+      // fallback: the sinc rule with the step of Thm. sinc_theo, the fewest
+      // nodes in 33..64 whose certificate meets tol (64 first; then
+      // bisection, keeping only certified candidates), 64 if none does
+      auto theorem_rule = [&](int M, Cand &c) -> demag_status {
+        const double a = 2.0, bb = 0.25 * (0.5 * hmin) * (0.5 * hmin);
+        const double theta = std::log(2.0 * kPi * a * M / bb) / (a * M);
+        c.R = M;
+        c.t.resize(M);
+        c.a.resize(M);
+        for (int k = 0; k < M; ++k) {
+          const double tk = (k + 1) * theta, sh = std::sinh(tk);
+          c.t[k] = tk;
+          c.a[k] = 2.0 * theta * std::cosh(tk) * sh * sh;
+        }
+        demag_status s2 = certify_rule(ctx, n, hs, M, c.t.data(), c.a.data(), c.e);
+        c.ok = (s2 == DEMAG_OK) && std::max(c.e[0], c.e[1]) <= tol;
+        return s2;
+      };
+      st = theorem_rule(64, best);
+      if (st == DEMAG_OK && best.ok) {
+        int lo = 33, hi = 63;
+        while (st == DEMAG_OK && lo <= hi) {
+          const int mid = (lo + hi) / 2;
+          Cand c;
+          st = theorem_rule(mid, c);
+          if (st != DEMAG_OK) break;
+          if (c.ok) {
+            best = c;
+            hi = mid - 1;
+          } else {
+            lo = mid + 1;
+          }
+        }
       }
-      st = certify_rule(ctx, n, hs, M, best.t.data(), best.a.data(), best.e);
-      best.ok = (st == DEMAG_OK) && std::max(best.e[0], best.e[1]) <= tol;
       out->fell_back = 1;
     }
   }
