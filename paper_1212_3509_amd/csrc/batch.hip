@@ -2,7 +2,9 @@
 //
 // Every state has its own grid and factor tables (same quadrature rule).
 // The 23 products per node of each state (see build_chunk in api.hip) are
-// cut into tiles (64 columns x 16*RB rows of one job); all tiles of one
+// cut into tiles (64 columns x 16*RB rows of one job; on axes of at most
+// kThinN cells, vector-ALU tiles of 256 thin_cols columns, launched apart
+// before the stage's matrix-core tiles, one workgroup each); the tiles of one
 // stage, over all states, form one list that a single persistent launch
 // works off through a counter (each workgroup draws the next item; the tiles
 // write disjoint outputs, so results are bitwise reproducible).  Items are
@@ -41,6 +43,8 @@ struct demag_batch {
   struct Launch {
     demag::BatchItem *d_items = nullptr;
     int nitems = 0;
+    demag::BatchItem *d_thin = nullptr;           // thin-axis items, one workgroup each
+    int nthin = 0;
   };
   std::vector<std::vector<Launch>> launches;
   demag::MPJob *d_jobs = nullptr;
@@ -85,6 +89,7 @@ demag_status build(demag_ctx *ctx, demag_batch *b) {
   b->launches.assign(b->nchunks, std::vector<demag_batch::Launch>(3));
   std::vector<std::vector<std::vector<BatchItem>>> items(b->nchunks, std::vector<std::vector<BatchItem>>(3));
   std::vector<std::vector<std::vector<double>>> costs(b->nchunks, std::vector<std::vector<double>>(3));
+  std::vector<std::vector<std::vector<BatchItem>>> thin(b->nchunks, std::vector<std::vector<BatchItem>>(3));
   b->flops = 0;
   for (int s = 0; s < b->count; ++s) {
     const demag_factors *f = b->factors[s];
@@ -128,6 +133,14 @@ demag_status build(demag_ctx *ctx, demag_batch *b) {
         const int jid = int(jobs.size());
         jobs.push_back(j);
         const MPGeom &g = geoms[gz + stage];
+        b->flops += 2.0 * g.n * double(g.n) * g.C * j.nterms * nout;
+        if (g.n <= kThinN) {
+          // thin axis: vector-ALU tiles of 256 thin_cols columns, own launch
+          const int cols = 256 * thin_cols(thin_nmax(g.n), int(esize));
+          for (int ct = 0; ct < ceil_div(g.C, cols); ++ct)
+            thin[c][stage].push_back(BatchItem{jid, gz + stage, ct, 0, 0, int8_t(nout)});
+          return;
+        }
         int rb = default_rb(g.n);
         auto it = b->rb_choice.find({g.n, nout});
         if (it != b->rb_choice.end()) rb = it->second;
@@ -138,7 +151,6 @@ demag_status build(demag_ctx *ctx, demag_batch *b) {
             items[c][stage].push_back(BatchItem{jid, gz + stage, ct, int16_t(rg), int8_t(rb), int8_t(nout)});
             costs[c][stage].push_back(cost);
           }
-        b->flops += 2.0 * g.n * double(g.n) * g.C * j.nterms * nout;
       };
       for (int kl = 0; kl < kcc; ++kl) {
         const int k = k0 + kl;
@@ -190,6 +202,12 @@ demag_status build(demag_ctx *ctx, demag_batch *b) {
       L.nitems = int(sorted.size());
       DEMAG_TRY_HIP(hipMalloc(&L.d_items, sizeof(BatchItem) * std::max<size_t>(1, sorted.size())));
       DEMAG_TRY_HIP(hipMemcpy(L.d_items, sorted.data(), sizeof(BatchItem) * sorted.size(), hipMemcpyHostToDevice));
+      const auto &tv = thin[c][st];
+      L.nthin = int(tv.size());
+      if (L.nthin > 0) {
+        DEMAG_TRY_HIP(hipMalloc(&L.d_thin, sizeof(BatchItem) * tv.size()));
+        DEMAG_TRY_HIP(hipMemcpy(L.d_thin, tv.data(), sizeof(BatchItem) * tv.size(), hipMemcpyHostToDevice));
+      }
     }
   DEMAG_TRY_HIP(hipMalloc(&b->d_counters, sizeof(int) * size_t(b->nchunks) * 3));
   b->ws_bytes = size_t(12) * kc * Ntot * esize;
@@ -204,8 +222,10 @@ demag_status build(demag_ctx *ctx, demag_batch *b) {
 
 void release_tables(demag_batch *b) {
   for (auto &v : b->launches)
-    for (auto &L : v)
+    for (auto &L : v) {
       if (L.d_items) (void)hipFree(L.d_items);
+      if (L.d_thin) (void)hipFree(L.d_thin);
+    }
   b->launches.clear();
   if (b->d_jobs) (void)hipFree(b->d_jobs);
   if (b->d_terms) (void)hipFree(b->d_terms);
@@ -235,6 +255,8 @@ demag_status enqueue(demag_ctx *ctx, demag_batch *b, const void *m, void *phi, v
     for (int st = 0; st < 3; ++st) {
       const auto &L = b->launches[c][st];
       const int beta = (st == 2 && c > 0) ? 1 : 0;
+      s = launch_thin_items(ctx, b->prec, L.d_thin, L.nthin, b->d_jobs, b->d_terms, b->d_geoms, bufs, b->gens, beta);
+      if (s != DEMAG_OK) return s;
       s = launch_items(ctx, b->prec, L.d_items, L.nitems, b->grid, b->d_jobs, b->d_terms, b->d_geoms, bufs, b->gens,
                        b->nmax, beta, b->d_counters + c * 3 + st);
       if (s != DEMAG_OK) return s;
@@ -478,8 +500,8 @@ demag_status demag_batch_tune(demag_ctx *ctx, demag_batch *b, const char *path, 
   if (st == DEMAG_OK) st = apply(best);
   if (st == DEMAG_OK) st = time_apply(best_ms);
   for (int bk = 0; bk < 3 && st == DEMAG_OK; ++bk) {
-    bool present = false;
-    for (int n : lens) present |= (bucket(n) == bk);
+    bool present = false;   // thin axes (vector-ALU tiles) have no row-block shape
+    for (int n : lens) present |= (bucket(n) == bk && n > kThinN);
     if (!present) continue;
     for (int sh : {-1, 1}) {
       int trial[3] = {best[0], best[1], best[2]};

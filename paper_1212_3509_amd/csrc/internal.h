@@ -76,7 +76,8 @@ struct Bufs {
   void *p[6];
 };
 
-// A tile of the persistent batched launch.
+// A tile of the persistent batched launch.  rb = 0: a thin-axis tile
+// (n <= kThinN) of 256 thin_cols(...) consecutive columns, ct counting those.
 struct BatchItem {
   int32_t job;
   int32_t geom;
@@ -85,6 +86,12 @@ struct BatchItem {
   int8_t rb;
   int8_t nout;
 };
+
+// Axes of at most kThinN cells take the vector-ALU tile: rows padded to
+// thin_nmax(n), thin_cols(...) columns per lane.
+constexpr int kThinN = 16;
+__host__ __device__ constexpr int thin_nmax(int n) { return n <= 4 ? 4 : n <= 8 ? 8 : 16; }
+__host__ __device__ constexpr int thin_cols(int nmax, int esize) { return nmax >= (esize == 8 ? 8 : 16) ? 1 : (esize == 8 ? 8 : 16) / nmax; }
 
 // A stage launch: jobs with the same NOUT and geometry.
 struct StagePlan {
@@ -180,6 +187,9 @@ void build_chunk_plan(const demag_factors *f, int k0, int kc, double phi_scale, 
 demag_status launch_items(demag_ctx *ctx, demag_prec prec, const BatchItem *items, int nitems, int grid,
                           const MPJob *jobs, const MPTerm *terms, const MPGeom *geoms, void *const bufp[6],
                           const void *gens, int nmax, int beta, int *counter);
+demag_status launch_thin_items(demag_ctx *ctx, demag_prec prec, const BatchItem *items, int nitems, const MPJob *jobs,
+                               const MPTerm *terms, const MPGeom *geoms, void *const bufp[6], const void *gens,
+                               int beta);
 demag_status launch_reset_counters(demag_ctx *ctx, int *counters, int count);
 demag_status launch_build_windows(demag_ctx *ctx, demag_factors *f);
 // non-uniform grids: dense factors from the scaled cell edges (host, n_d + 1 per axis)

@@ -311,6 +311,107 @@ __device__ __forceinline__ void left_tile(const MPJob &job, const MPTerm *__rest
   }
 }
 
+// Thin axes (n <= kThinN): the products of one job on the vector ALU.  A
+// workgroup covers 256 CPT consecutive columns, lane l taking columns
+// (ct CPT + k) 256 + l, k < CPT; each lane holds the n inputs of its columns
+// and issues a term's n CPT loads at once.  A 16-row MFMA block would leave
+// most rows empty here, and a 64-column tile holds too little work to hide
+// its load latency.  Rows are padded to NMAX: inputs past n are zero and
+// rows past n are never stored.  Each output sums term by term with j
+// ascending, the same in the single-state and the batched launch.
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <class T, int NMAX, int NOUT>
+__device__ __forceinline__ void thin_tile(const MPJob &job, const MPTerm *__restrict__ terms, const Bufs &bufs,
+                                          const T *__restrict__ gens, const MPGeom &g, int ct, int beta) {
+  constexpr int CPT = thin_cols(NMAX, sizeof(T));
+  const int n = g.n;
+  size_t cin[CPT], cout[CPT];
+  bool ok[CPT];
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int c = (ct * CPT + k) * 256 + int(threadIdx.x);
+    ok[k] = c < g.C;
+    const int cl = ok[k] ? c : g.C - 1;
+    const int co = cl / g.C1, ci = cl % g.C1;
+    cin[k] = size_t(co) * g.in_S1 + ci;
+    cout[k] = size_t(co) * g.out_S1 + size_t(ci) * g.out_cs;
+  }
+  T acc[NOUT][NMAX][CPT];
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o)
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i)
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) acc[o][i][k] = T(0);
+  for (int t = 0; t < job.nterms; ++t) {
+    const MPTerm &tm = terms[job.term0 + t];
+    const T *in = static_cast<const T *>(bufs.p[tm.in_buf]) + tm.in_off;
+    T x[NMAX][CPT];
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j)
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) x[j][k] = T(0);
+#pragma unroll
+    for (int j = 0; j < NMAX; ++j)
+      if (j < n) {
+#pragma unroll
+        for (int k = 0; k < CPT; ++k) x[j][k] = in[cin[k] + size_t(j) * g.kstride];
+      }
+#pragma unroll
+    for (int o = 0; o < NOUT; ++o) {
+      // gv[d] = T[i][j] for i - j = d - (NMAX - 1): generator entry d + n - NMAX
+      const T *gp = gens + tm.gen_off[o];
+      T gv[2 * NMAX - 1];
+#pragma unroll
+      for (int d = 0; d < 2 * NMAX - 1; ++d) {
+        const int e = d + n - NMAX;
+        gv[d] = (e >= 0 && e < g.genlen) ? gp[e] : T(0);
+      }
+#pragma unroll
+      for (int j = 0; j < NMAX; ++j)
+        if (j < n) {
+#pragma unroll
+          for (int i = 0; i < NMAX; ++i)
+#pragma unroll
+            for (int k = 0; k < CPT; ++k) acc[o][i][k] = fma_t(gv[i - j + NMAX - 1], x[j][k], acc[o][i][k]);
+        }
+    }
+  }
+#pragma unroll
+  for (int o = 0; o < NOUT; ++o) {
+    T *out = static_cast<T *>(bufs.p[job.out_buf[o]]) + job.out_off[o];
+    const T scale = T(job.scale[o]);
+#pragma unroll
+    for (int i = 0; i < NMAX; ++i)
+      if (i < n) {
+#pragma unroll
+        for (int k = 0; k < CPT; ++k)
+          if (ok[k]) {
+            const size_t idx = cout[k] + size_t(i) * g.out_is;
+            T v = scale * acc[o][i][k];
+            if (beta) v += out[idx];
+            out[idx] = v;
+          }
+      }
+  }
+}
+
+template <class T, int NOUT>
+__device__ __forceinline__ void thin_dispatch(const MPJob &job, const MPTerm *__restrict__ terms, const Bufs &bufs,
+                                              const T *__restrict__ gens, const MPGeom &g, int ct, int beta) {
+  if (g.n <= 4) thin_tile<T, 4, NOUT>(job, terms, bufs, gens, g, ct, beta);
+  else if (g.n <= 8) thin_tile<T, 8, NOUT>(job, terms, bufs, gens, g, ct, beta);
+  else thin_tile<T, 16, NOUT>(job, terms, bufs, gens, g, ct, beta);
+}
+
+template <class T, int NMAX, int NOUT>
+__global__ __launch_bounds__(256) void k_thin(const MPJob *__restrict__ jobs, const MPTerm *__restrict__ terms,
+                                              Bufs bufs, const T *__restrict__ gens, MPGeom g, int beta) {
+  thin_tile<T, NMAX, NOUT>(jobs[blockIdx.y], terms, bufs, gens, g, blockIdx.x, beta);
+}
+
 template <class T, int RB, int NOUT, int AXIS, bool WHOLE>
 __global__ __launch_bounds__(256, 2) void k_left(const MPJob *__restrict__ jobs, const MPTerm *__restrict__ terms,
                                               Bufs bufs, const T *__restrict__ gens, MPGeom g, int col_tiles,
@@ -364,6 +465,21 @@ __global__ __launch_bounds__(256, 2) void k_left_items(const BatchItem *__restri
   }
 }
 
+// Thin-axis items of a batched stage (BatchItem.rb = 0), one workgroup per
+// item.  Kept apart from k_left_items, whose register allocation the
+// vector-ALU tile would change.
+template <class T>
+__global__ __launch_bounds__(256) void k_thin_items(const BatchItem *__restrict__ items,
+                                                    const MPJob *__restrict__ jobs, const MPTerm *__restrict__ terms,
+                                                    const MPGeom *__restrict__ geoms, Bufs bufs,
+                                                    const T *__restrict__ gens, int beta) {
+  const BatchItem item = items[blockIdx.x];
+  const MPJob job = jobs[item.job];
+  const MPGeom g = geoms[item.geom];
+  if (item.nout == 1) thin_dispatch<T, 1>(job, terms, bufs, gens, g, item.ct, beta);
+  else thin_dispatch<T, 2>(job, terms, bufs, gens, g, item.ct, beta);
+}
+
 template <class T, int RB, int NOUT, int AXIS>
 demag_status launch_axis(hipStream_t s, const StagePlan &sp, const T *gens, const Bufs &bufs, int beta) {
   const MPGeom &g = sp.geom;
@@ -398,8 +514,25 @@ demag_status launch_nout(hipStream_t s, int rb, const StagePlan &sp, const T *ge
   }
 }
 
+template <class T, int NMAX>
+demag_status launch_thin_nmax(hipStream_t s, const StagePlan &sp, const T *gens, const Bufs &bufs, int beta) {
+  const MPGeom &g = sp.geom;
+  const int cols = 256 * thin_cols(NMAX, sizeof(T));
+  dim3 grid(unsigned((g.C + cols - 1) / cols), unsigned(sp.jobs.size()));
+  if (sp.nout == 1) k_thin<T, NMAX, 1><<<grid, 256, 0, s>>>(sp.d_jobs, sp.d_terms, bufs, gens, g, beta);
+  else k_thin<T, NMAX, 2><<<grid, 256, 0, s>>>(sp.d_jobs, sp.d_terms, bufs, gens, g, beta);
+  DEMAG_TRY_HIP(hipGetLastError());
+  return DEMAG_OK;
+}
+
 template <class T>
 demag_status launch_typed(hipStream_t s, int rb, const StagePlan &sp, const T *gens, const Bufs &bufs, int beta) {
+  if (sp.geom.n <= kThinN) {
+    const int nmax = thin_nmax(sp.geom.n);
+    if (nmax == 4) return launch_thin_nmax<T, 4>(s, sp, gens, bufs, beta);
+    if (nmax == 8) return launch_thin_nmax<T, 8>(s, sp, gens, bufs, beta);
+    return launch_thin_nmax<T, 16>(s, sp, gens, bufs, beta);
+  }
   if (sp.nout == 1) return launch_nout<T, 1>(s, rb, sp, gens, bufs, beta);
   return launch_nout<T, 2>(s, rb, sp, gens, bufs, beta);
 }
@@ -461,6 +594,22 @@ demag_status launch_items(demag_ctx *ctx, demag_prec prec, const BatchItem *item
     k_left_items<float><<<grid, 256, lds, ctx->stream>>>(items, nitems, jobs, terms, geoms, bufs,
                                                           static_cast<const float *>(gens), beta, counter);
   }
+  DEMAG_TRY_HIP(hipGetLastError());
+  return DEMAG_OK;
+}
+
+demag_status launch_thin_items(demag_ctx *ctx, demag_prec prec, const BatchItem *items, int nitems, const MPJob *jobs,
+                               const MPTerm *terms, const MPGeom *geoms, void *const bufp[6], const void *gens,
+                               int beta) {
+  if (nitems == 0) return DEMAG_OK;
+  Bufs bufs;
+  for (int i = 0; i < 6; ++i) bufs.p[i] = bufp[i];
+  if (prec == DEMAG_FP64)
+    k_thin_items<double><<<nitems, 256, 0, ctx->stream>>>(items, jobs, terms, geoms, bufs,
+                                                          static_cast<const double *>(gens), beta);
+  else
+    k_thin_items<float><<<nitems, 256, 0, ctx->stream>>>(items, jobs, terms, geoms, bufs,
+                                                         static_cast<const float *>(gens), beta);
   DEMAG_TRY_HIP(hipGetLastError());
   return DEMAG_OK;
 }

@@ -19,8 +19,9 @@ from paper_1212_3509_amd import api, inputs
 
 pytestmark = pytest.mark.gpu
 
+# axes of at most 16 cells (thin, vector-ALU tiles) in every orientation
 GRIDS = [((16, 16, 16), None), ((17, 9, 5), None), ((24, 24, 24), None), ((40, 32, 4), None),
-         ((33, 20, 12), None), ((7, 1, 9), None)]
+         ((33, 20, 12), None), ((7, 1, 9), None), ((6, 40, 36), None), ((300, 9, 2), None)]
 
 
 def _grids():
@@ -93,7 +94,7 @@ def test_batch_fp64_matches_oracle(ctx):
     _m, phi, h, off = _run_batch(ctx, b, fields, torch.float64)
     got = _unpack(phi, h, off, grids)
     _t, tau, alpha = sinc.sinc_nodes(12)
-    for s in (1, 3):
+    for s in (1, 3, 6, 7):
         n, hcell = grids[s]
         pr, hr = apply.kron_apply_dense(fields[s], hcell, tau, alpha)   # unit longest edge: L = 1
         assert apply.rel_l2(got[s][0], pr) < 1e-12 and apply.rel_l2(got[s][1], hr) < 1e-12

@@ -128,6 +128,32 @@ def test_full_chunked_equals_unchunked(ctx):
     assert _rel(p2, p1) < 1e-14 and _rel(h2, h1) < 1e-14
 
 
+@pytest.mark.parametrize("n", [(70, 60, 4), (6, 50, 48), (40, 11, 45), (3, 2, 130)])
+def test_full_thin_axes_match_oracle(ctx, n):
+    """Axes of at most 16 cells take the vector-ALU tile (rows padded to 4,
+    8 or 16, columns over several workgroups with a ragged last one), in the
+    z, x and y orientations: FP64 against the oracle's dense-Toeplitz apply,
+    FP32 within 1e-6 of FP64, and three nodes per chunk (the x stage then
+    accumulates) equal to one chunk."""
+    M = 12
+    hc = 1.0 / max(n)
+    f = ctx.assemble(n, (hc,) * 3, M=M)
+    _t, tau, alpha = sinc.sinc_nodes(M)
+    m = inputs.random_unit_field(n, seed=17)
+    p64, h64 = _run_full(ctx, f, m, "fp64")
+    pref, href = apply.kron_apply_dense(m, (hc,) * 3, tau, alpha)
+    assert _rel(p64, pref) < 1e-12 and _rel(h64, href) < 1e-12
+    p32, h32 = _run_full(ctx, f, m, "fp32")
+    assert _rel(p32, p64) < 1e-6 and _rel(h32, h64) < 1e-6
+    N = n[0] * n[1] * n[2]
+    ctx.set_workspace_limit((12 * 3 + 4) * N * 8)
+    try:
+        p2, h2 = _run_full(ctx, f, m, "fp64")
+    finally:
+        ctx.set_workspace_limit(16 << 30)
+    assert _rel(p2, p64) < 1e-14 and _rel(h2, h64) < 1e-14
+
+
 def _sample_cells(n, count, seed):
     """All 8 corners, the 12 edge centres and 6 face centres of an n^3 grid,
     then random interior cells up to `count` (iz, iy, ix)."""
