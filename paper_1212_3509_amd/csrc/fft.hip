@@ -78,36 +78,6 @@ __device__ inline void load_twiddles(cplx *tlo, cplx *thi, int N, const double2 
   }
 }
 
-// ---------------------------------------------------------------- spectra
-// FP64 spectra of the circulant embeddings (direct sums): for even
-// generators  G[f] = g_0 + 2 sum_{J>=1} g_J cos(2 pi f J / L),
-// for odd ones the imaginary part  -2 sum_{J>=1} g_J sin(2 pi f J / L).
-__global__ void k_spectra(const double *__restrict__ gens, double *__restrict__ spec, int n, int L, int M) {
-  extern __shared__ double sh[];
-  double *ctab = sh;           // cos(2 pi e / L), e < L
-  double *g = sh + L;          // g_J, J = 0..n-1
-  const int gen = blockIdx.y;  // type * M + k
-  const int type = gen / M;
-  const bool odd = (type == F_X || type == F_Q);
-  for (int e = threadIdx.x; e < L; e += blockDim.x) ctab[e] = cospi(2.0 * double(e) / double(L));
-  const double *src = gens + size_t(gen) * (2 * n - 1) + (n - 1);
-  for (int J = threadIdx.x; J < n; J += blockDim.x) g[J] = src[J];
-  __syncthreads();
-  const int nf = L / 2 + 1;
-  for (int f = blockIdx.x * blockDim.x + threadIdx.x; f < nf; f += gridDim.x * blockDim.x) {
-    double acc = 0.0;
-    if (odd) {
-      // sin(2 pi e / L) = cos(2 pi (e - L/4) / L)
-      for (int J = 1; J < n; ++J) acc += g[J] * ctab[(int)((int64_t(f) * J - L / 4) & (L - 1))];
-      acc = -2.0 * acc;
-    } else {
-      for (int J = 1; J < n; ++J) acc += g[J] * ctab[(int)((int64_t(f) * J) & (L - 1))];
-      acc = g[0] + 2.0 * acc;
-    }
-    spec[size_t(gen) * nf + f] = acc;
-  }
-}
-
 __global__ void k_twiddles(double2 *__restrict__ tw, int N) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= N) return;
@@ -211,6 +181,45 @@ __global__ __launch_bounds__(kThreads) void k_fft_fwd(const ColAxes P, void *__r
       Ac[f] = cplx32{float(0.5 * a.x), float(0.5 * a.y)};
       Bc[f] = cplx32{float(0.5 * b.x), float(0.5 * b.y)};
     }
+  }
+}
+
+// FP64 spectra of the circulant embeddings, one workgroup per generator
+// (type * M + k): with A the forward real transform of the one-sided
+// generator a_J = g_J, J < n, zero-padded to L (A[f] = sum_J a_J W_L^(fJ)),
+// an even generator's embedding has the real spectrum
+//   G[f] = g_0 + 2 sum_{J>=1} g_J cos(2 pi f J / L) = 2 Re A[f] - g_0,
+// an odd one's (g_0 = 0) the imaginary part
+//   -2 sum_{J>=1} g_J sin(2 pi f J / L) = 2 Im A[f],   f = 0..L/2.
+__global__ __launch_bounds__(kThreads) void k_spectra(const double *__restrict__ gens, double *__restrict__ spec,
+                                                      int n, int L, int M, const double2 *__restrict__ tw,
+                                                      int lds_points) {
+  extern __shared__ cplx wk[];   // N points (padded), then the twiddle tables
+  const int N = L / 2;
+  cplx *tlo = wk + lds_points, *thi = tlo + 64;
+  const int gen = blockIdx.x;
+  const int type = gen / M;
+  const bool odd = (type == F_X || type == F_Q);
+  load_twiddles(tlo, thi, N, tw);
+  const double *a = gens + size_t(gen) * (2 * n - 1) + (n - 1);
+  for (int m = threadIdx.x; m < N; m += kThreads) {
+    const int i0 = 2 * m, i1 = 2 * m + 1;
+    wk[slot<true>(m)] = cplx{i0 < n ? a[i0] : 0.0, i1 < n ? a[i1] : 0.0};
+  }
+  __syncthreads();
+  fft_lines<false, kThreads, kPoints, true>(wk, N, padded_points(N), 1, tlo, thi);
+  double sw, cw;
+  sincospi(-1.0 / double(N), &sw, &cw);
+  const cplx w1{cw, sw};         // W_L^1
+  const double g0 = a[0];
+  double *out = spec + size_t(gen) * (N + 1);
+  for (int f = threadIdx.x; f <= N; f += kThreads) {
+    // A[f] = E + W_L^f O, E = (Z[f] + conj Z[N-f])/2, O = (Z[f] - conj Z[N-f])/(2i)
+    const cplx zf = wk[slot<true>(f & (N - 1))];
+    const cplx zcc = cconj(wk[slot<true>((N - f) & (N - 1))]);
+    const cplx D{0.5 * (zf.x - zcc.x), 0.5 * (zf.y - zcc.y)};
+    const cplx X = cadd(cplx{0.5 * (zf.x + zcc.x), 0.5 * (zf.y + zcc.y)}, cmul(wl(f, N, tlo, thi, w1), cplx{D.y, -D.x}));
+    out[f] = odd ? 2.0 * X.y : 2.0 * X.x - g0;
   }
 }
 
@@ -463,11 +472,13 @@ demag_status prepare_spectra(demag_ctx *ctx, demag_factors *f) {
     DEMAG_TRY_HIP(hipMalloc(&f->twiddle[d], size_t(N) * sizeof(double2)));
     k_twiddles<<<(N + 255) / 256, 256, 0, ctx->stream>>>(reinterpret_cast<double2 *>(f->twiddle[d]), N);
     DEMAG_TRY_HIP(hipGetLastError());
-    const size_t lds = sizeof(double) * (size_t(L) + n);
+    const int lds_points = padded_points(N);
+    const size_t lds = sizeof(double2) * (size_t(lds_points) + 128);
     DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_spectra),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-    dim3 grid((N + 1 + 255) / 256, F_NTYPES * f->M);
-    k_spectra<<<grid, 256, lds, ctx->stream>>>(f->f64[d], f->spec[d], n, L, f->M);
+    k_spectra<<<F_NTYPES * f->M, kThreads, lds, ctx->stream>>>(f->f64[d], f->spec[d], n, L, f->M,
+                                                               reinterpret_cast<const double2 *>(f->twiddle[d]),
+                                                               lds_points);
     DEMAG_TRY_HIP(hipGetLastError());
     // FP32 spectra, then the FP32 twiddles W_N^e (2 N floats, 8-byte aligned: nspec is even or padded)
     const size_t nspec_pad = nspec + (nspec & 1);
