@@ -86,6 +86,21 @@ __global__ void k_twiddles(double2 *__restrict__ tw, int N) {
   tw[e] = make_double2(c, s);
 }
 
+// Pass-major FP32 twiddles (see pm_offset): entry i of the pass of
+// sub-transform length Ns and radix R = W_N^(k r N / (Ns R)) rounded from
+// the FP64 table, r = 1 + (i - off) / Ns, k = (i - off) % Ns.
+__global__ void k_pm_twiddles(const double2 *__restrict__ tw, float *__restrict__ out, int N) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= pm_twiddle_count(N)) return;
+  const bool first = i < pm_offset(256);
+  const int Ns = first ? 16 : 256, R = first ? 16 : N / 256;
+  const int loc = i - pm_offset(Ns);
+  const int r = 1 + loc / Ns, k = loc % Ns;
+  const int e = int((int64_t(k) * r * (N / (Ns * R))) & (N - 1));
+  out[2 * i] = float(tw[e].x);
+  out[2 * i + 1] = float(tw[e].y);
+}
+
 __global__ void k_to_f32(const double *__restrict__ src, float *__restrict__ dst, size_t count, double scale) {
   const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (i < count) dst[i] = float(src[i] * scale);
@@ -103,6 +118,7 @@ struct ColAxis {
   const double *spec;
   const float *spec32;       // FP32 copies of the kernel spectra (FP32 transforms)
   const cplx32 *tw32;        // FP32 twiddles W_N^e, e < N (FP32 transforms)
+  const cplx32 *twpm;        // the same in pass-major order (pm_twiddle_count(N) entries)
   const double2 *tw;
   size_t u_off;              // first spectrum of this axis in U (points)
   int n, L, R;
@@ -342,13 +358,15 @@ struct OutSink32 {
 
 // Passes of the inverse transform after the first (radix 16, done by the
 // caller in registers), with the last pass writing the outputs.
+// Twiddles: the pass-major table (tlo, pm_twiddle_count(N) entries).
 template <int N>
 __device__ inline void inverse_rest(cplx32 *wk, const cplx32 *tlo, const cplx32 *thi, const OutSink32 &sink) {
-  if constexpr (N == 4096) run_passes<true, kThreads, kPoints, 4096, 16, OutSink32, true, 16, 16>(wk, 0, 1, tlo, thi, sink);
-  if constexpr (N == 2048) run_passes<true, kThreads, kPoints, 2048, 16, OutSink32, true, 16, 8>(wk, 0, 1, tlo, thi, sink);
-  if constexpr (N == 1024) run_passes<true, kThreads, kPoints, 1024, 16, OutSink32, true, 16, 4>(wk, 0, 1, tlo, thi, sink);
-  if constexpr (N == 512) run_passes<true, kThreads, kPoints, 512, 16, OutSink32, true, 16, 2>(wk, 0, 1, tlo, thi, sink);
-  if constexpr (N == 256) run_passes<true, kThreads, kPoints, 256, 16, OutSink32, true, 16>(wk, 0, 1, tlo, thi, sink);
+  if constexpr (N == 256) {
+    pass<true, 16, kThreads, kPoints, N, 16, OutSink32, true, true>(wk, 0, 1, tlo, thi, sink);
+  } else {
+    pass<true, 16, kThreads, kPoints, N, 16, ToLds, true, true>(wk, 0, 1, tlo, thi);
+    pass<true, N / 256, kThreads, kPoints, N, 256, OutSink32, true, true>(wk, 0, 1, tlo, thi, sink);
+  }
 }
 
 // FP32 jobs of one column on a line of N >= 256 points: thread g < N / 16
@@ -406,7 +424,7 @@ __device__ inline void jobs32_line(const ColAxis &A, int axis, int M, int q, int
 // k_fft_jobs, on the column's FP32 packing factors A, B.
 __global__ __launch_bounds__(kThreads) void k_fft_jobs32(const ColAxes P, const cplx32 *__restrict__ ABall) {
   __shared__ cplx32 wk[kPoints];
-  __shared__ cplx32 tlo[kPoints];   // W_N^e, e < N (FP32 twiddles: the whole table)
+  __shared__ cplx32 tlo[kPoints];   // FP32 twiddles: pass-major (N >= 256) or W_N^e, e < N
   const cplx32 *thi = nullptr;
   const int w = int(xcd_work_index(blockIdx.x, gridDim.x));
   const int axis = axis_of(P, w, true);
@@ -415,7 +433,12 @@ __global__ __launch_bounds__(kThreads) void k_fft_jobs32(const ColAxes P, const 
   const int local = w - A.wg0;
   const int col = local / A.groups, grp = local - col * A.groups;   // col = q * R + l
   const int q = col / R, l = col % R;
-  for (int e = threadIdx.x; e < N; e += kThreads) tlo[e] = A.tw32[e];
+  // lines of N >= 256 points: the pass-major twiddles; shorter ones: W_N^e, e < N
+  if (N >= 256) {
+    for (int e = threadIdx.x; e < pm_twiddle_count(N); e += kThreads) tlo[e] = A.twpm[e];
+  } else {
+    for (int e = threadIdx.x; e < N; e += kThreads) tlo[e] = A.tw32[e];
+  }
   __syncthreads();
   const cplx32 *AB = ABall + A.u_off + size_t(col) * (2 * N);
   const int njobs = 2 * M;
@@ -482,13 +505,17 @@ demag_status prepare_spectra(demag_ctx *ctx, demag_factors *f) {
     DEMAG_TRY_HIP(hipGetLastError());
     // FP32 spectra, then the FP32 twiddles W_N^e (2 N floats, 8-byte aligned: nspec is even or padded)
     const size_t nspec_pad = nspec + (nspec & 1);
-    DEMAG_TRY_HIP(hipMalloc(&f->spec32[d], (nspec_pad + 2 * size_t(N)) * sizeof(float)));
+    DEMAG_TRY_HIP(hipMalloc(&f->spec32[d], (nspec_pad + 2 * size_t(N) + 2 * size_t(pm_twiddle_count(N))) *
+                                               sizeof(float)));
     // the FP32 spectra carry the inverse transform's 1 / N (a power of two:
     // exact in the normal range)
     k_to_f32<<<unsigned((nspec + 255) / 256), 256, 0, ctx->stream>>>(f->spec[d], f->spec32[d], nspec,
                                                                       1.0 / double(N));
     k_to_f32<<<unsigned((2 * size_t(N) + 255) / 256), 256, 0, ctx->stream>>>(
         reinterpret_cast<const double *>(f->twiddle[d]), f->spec32[d] + nspec_pad, 2 * size_t(N), 1.0);
+    if (pm_twiddle_count(N) > 0)
+      k_pm_twiddles<<<unsigned((pm_twiddle_count(N) + 255) / 256), 256, 0, ctx->stream>>>(
+          reinterpret_cast<const double2 *>(f->twiddle[d]), f->spec32[d] + nspec_pad + 2 * size_t(N), N);
     DEMAG_TRY_HIP(hipGetLastError());
   }
   f->spec_ready = true;
@@ -529,6 +556,7 @@ demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, demag_prec p
       // the FP32 twiddles follow the FP32 spectra (see prepare_spectra)
       const size_t nspec = size_t(F_NTYPES) * f->M * (fft_length(f->n[d]) / 2 + 1);
       A.tw32 = reinterpret_cast<const cplx32 *>(f->spec32[d] + nspec + (nspec & 1));
+      A.twpm = A.tw32 + fft_length(f->n[d]) / 2;
     }
     A.tw = reinterpret_cast<const double2 *>(f->twiddle[d]);
     A.n = f->n[d];

@@ -150,7 +150,18 @@ template <class T> __device__ inline void make_twiddles(cx<T> *lo, cx<T> *hi, in
 // last pass of a transform, a functor sink(line, index, value).
 struct ToLds {};
 
-template <bool INV, int R, int KT, int KP, int N, int Ns, typename Sink = ToLds, bool XS = false, class T>
+// FP32 twiddles in pass-major order (PM) for the inverse transforms whose
+// first radix-16 pass runs in registers: the pass of sub-transform length
+// Ns and radix R reads entry pm_offset(Ns) + (r - 1) Ns + k = W_N^(k r N /
+// (Ns R)), k < Ns, 1 <= r < R, so the 16 lanes of a read group (consecutive
+// k) read consecutive entries.  The whole table W_N^e, indexed by e = k r N
+// / (Ns R), puts those lanes N R / (Ns R) entries apart: on one bank for
+// Ns = 16.  Passes: Ns = 16 (R = 16, 240 entries), then Ns = 256 (R = N / 256).
+__host__ __device__ constexpr int pm_offset(int Ns) { return Ns == 16 ? 0 : 15 * 16; }
+__host__ __device__ constexpr int pm_twiddle_count(int N) { return N >= 256 ? 15 * 16 + (N / 256 - 1) * 256 : 0; }
+
+template <bool INV, int R, int KT, int KP, int N, int Ns, typename Sink = ToLds, bool XS = false, bool PM = false,
+          class T>
 __device__ inline void pass(cx<T> *buf, int LS, int nlines, const cx<T> *tlo, const cx<T> *thi,
                             const Sink &sink = Sink{}) {
   constexpr int per = N / R;             // butterflies per line
@@ -166,7 +177,17 @@ __device__ inline void pass(cx<T> *buf, int LS, int nlines, const cx<T> *tlo, co
       const cx<T> *lb = buf + line * LS;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = lb[slot<XS>(j + r * per)];
-      if constexpr (Ns > 1 && std::is_same_v<T, float>) {
+      if constexpr (Ns > 1 && std::is_same_v<T, float> && PM) {
+        static_assert(Ns == 16 || Ns == 256, "pass-major twiddles: passes Ns = 16 and 256");
+        const int k = j & (Ns - 1);
+        const cx<T> *tp = tlo + pm_offset(Ns) + k;
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cx<T> w = tp[(r - 1) * Ns];
+          if (INV) w = cconj(w);
+          v[q][r] = cmul(v[q][r], w);
+        }
+      } else if constexpr (Ns > 1 && std::is_same_v<T, float>) {
         // FP32: every power w^r straight from the table (one rounded entry
         // each); a chain of products would compound FP32 roundoff over the
         // passes
