@@ -86,15 +86,21 @@ __global__ void k_twiddles(double2 *__restrict__ tw, int N) {
   tw[e] = make_double2(c, s);
 }
 
-// Pass-major FP32 twiddles (see pm_offset): entry i of the pass of
+// Pass-major FP32 twiddles of plan PM (see pm_offset): entry i of the pass of
 // sub-transform length Ns and radix R = W_N^(k r N / (Ns R)) rounded from
 // the FP64 table, r = 1 + (i - off) / Ns, k = (i - off) % Ns.
-__global__ void k_pm_twiddles(const double2 *__restrict__ tw, float *__restrict__ out, int N) {
+__global__ void k_pm_twiddles(const double2 *__restrict__ tw, float *__restrict__ out, int N, int PM) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= pm_twiddle_count(N)) return;
-  const bool first = i < pm_offset(256);
-  const int Ns = first ? 16 : 256, R = first ? 16 : N / 256;
-  const int loc = i - pm_offset(Ns);
+  if (i >= (PM == 16 ? pm_twiddle_count(N) : pm8_twiddle_count(N))) return;
+  int Ns, R;
+  if (PM == 16) {
+    Ns = i < pm_offset(16, 256) ? 16 : 256;
+    R = Ns == 16 ? 16 : N / 256;
+  } else {
+    Ns = i < pm_offset(8, 64) ? 8 : i < pm_offset(8, 512) ? 64 : 512;
+    R = 8;
+  }
+  const int loc = i - pm_offset(PM, Ns);
   const int r = 1 + loc / Ns, k = loc % Ns;
   const int e = int((int64_t(k) * r * (N / (Ns * R))) & (N - 1));
   out[2 * i] = float(tw[e].x);
@@ -119,6 +125,7 @@ struct ColAxis {
   const float *spec32;       // FP32 copies of the kernel spectra (FP32 transforms)
   const cplx32 *tw32;        // FP32 twiddles W_N^e, e < N (FP32 transforms)
   const cplx32 *twpm;        // the same in pass-major order (pm_twiddle_count(N) entries)
+  const cplx32 *twpm8;       // pass-major for the radix-8 plan (pm8_twiddle_count(N) entries)
   const double2 *tw;
   size_t u_off;              // first spectrum of this axis in U (points)
   int n, L, R;
@@ -362,10 +369,10 @@ struct OutSink32 {
 template <int N>
 __device__ inline void inverse_rest(cplx32 *wk, const cplx32 *tlo, const cplx32 *thi, const OutSink32 &sink) {
   if constexpr (N == 256) {
-    pass<true, 16, kThreads, kPoints, N, 16, OutSink32, true, true>(wk, 0, 1, tlo, thi, sink);
+    pass<true, 16, kThreads, kPoints, N, 16, OutSink32, true, 16>(wk, 0, 1, tlo, thi, sink);
   } else {
-    pass<true, 16, kThreads, kPoints, N, 16, ToLds, true, true>(wk, 0, 1, tlo, thi);
-    pass<true, N / 256, kThreads, kPoints, N, 256, OutSink32, true, true>(wk, 0, 1, tlo, thi, sink);
+    pass<true, 16, kThreads, kPoints, N, 16, ToLds, true, 16>(wk, 0, 1, tlo, thi);
+    pass<true, N / 256, kThreads, kPoints, N, 256, OutSink32, true, 16>(wk, 0, 1, tlo, thi, sink);
   }
 }
 
@@ -475,6 +482,70 @@ __global__ __launch_bounds__(kThreads) void k_fft_jobs32(const ColAxes P, const 
   }
 }
 
+// FP32 jobs on 4096-point lines with 512 threads: thread g owns the points
+// f = g + 512 r, r < 8, of the first pass (radix 8, in registers), then
+// three radix-8 passes in LDS (layout slot<2>) with the radix-8 pass-major
+// twiddles.  Half the points per lane of k_fft_jobs32 (8 pairs of packing
+// factors held across jobs instead of 16), so four waves per SIMD instead
+// of two.
+constexpr int kThreadsW = 512;
+__global__ __launch_bounds__(kThreadsW, 2) void k_fft_jobs32w(const ColAxes P, const cplx32 *__restrict__ ABall) {
+  constexpr int N = 4096, per = N / 8;
+  __shared__ cplx32 wk[N];
+  __shared__ cplx32 tpm[N];
+  const int w = int(xcd_work_index(blockIdx.x, gridDim.x));
+  const int axis = axis_of(P, w, true);
+  const ColAxis &A = P.a[axis];
+  const int n = A.n, R = A.R, M = P.M;
+  const int local = w - A.wg0;
+  const int col = local / A.groups, grp = local - col * A.groups;   // col = q * R + l
+  const int q = col / R, l = col % R;
+  for (int e = threadIdx.x; e < pm8_twiddle_count(N); e += kThreadsW) tpm[e] = A.twpm8[e];
+  __syncthreads();
+  const cplx32 *AB = ABall + A.u_off + size_t(col) * (2 * N);
+  const int g = threadIdx.x;
+  cplx32 a[8], b[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    a[r] = AB[g + per * r];
+    b[r] = AB[N + g + per * r];
+  }
+  const int njobs = 2 * M;
+  const int j0 = grp * A.per;
+  const int j1 = min(njobs, j0 + A.per);
+  for (int j = j0; j < j1; ++j) {
+    const int s = j / M, k = j % M;
+    const int type = (axis == q) ? (s ? F_P : F_X) : (s ? F_Q : F_E);
+    const bool odd = (type == F_X || type == F_Q);
+    const float *gs = A.spec32 + size_t(type * M + k) * (N + 1);
+    float gf[8], gc[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      gf[r] = gs[g + per * r];
+      gc[r] = gs[N - g - per * r];
+    }
+    cplx32 v[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (odd) {
+        const float re = gf[r] * a[r].x - gc[r] * b[r].x, im = gf[r] * a[r].y - gc[r] * b[r].y;
+        v[r] = cplx32{-im, re};
+      } else {
+        v[r] = cplx32{gf[r] * a[r].x + gc[r] * b[r].x, gf[r] * a[r].y + gc[r] * b[r].y};
+      }
+    }
+    dftR<true, 8>(v);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) wk[slot<2>(8 * g + r)] = v[r];
+    __syncthreads();
+    float *y = A.out + ((size_t(q) * 2 + s) * M + k) * size_t(R) * n + size_t(l) * n;
+    pass<true, 8, kThreadsW, N, N, 8, ToLds, 2, 8>(wk, 0, 1, tpm, tpm);
+    pass<true, 8, kThreadsW, N, N, 64, ToLds, 2, 8>(wk, 0, 1, tpm, tpm);
+    pass<true, 8, kThreadsW, N, N, 512, OutSink32, 2, 8>(wk, 0, 1, tpm, tpm, OutSink32{y, n});
+    __syncthreads();
+  }
+}
+
 }  // namespace
 
 int fft_length(int n) {
@@ -505,8 +576,8 @@ demag_status prepare_spectra(demag_ctx *ctx, demag_factors *f) {
     DEMAG_TRY_HIP(hipGetLastError());
     // FP32 spectra, then the FP32 twiddles W_N^e (2 N floats, 8-byte aligned: nspec is even or padded)
     const size_t nspec_pad = nspec + (nspec & 1);
-    DEMAG_TRY_HIP(hipMalloc(&f->spec32[d], (nspec_pad + 2 * size_t(N) + 2 * size_t(pm_twiddle_count(N))) *
-                                               sizeof(float)));
+    const size_t npm = size_t(pm_twiddle_count(N)) + size_t(pm8_twiddle_count(N));
+    DEMAG_TRY_HIP(hipMalloc(&f->spec32[d], (nspec_pad + 2 * size_t(N) + 2 * npm) * sizeof(float)));
     // the FP32 spectra carry the inverse transform's 1 / N (a power of two:
     // exact in the normal range)
     k_to_f32<<<unsigned((nspec + 255) / 256), 256, 0, ctx->stream>>>(f->spec[d], f->spec32[d], nspec,
@@ -515,7 +586,11 @@ demag_status prepare_spectra(demag_ctx *ctx, demag_factors *f) {
         reinterpret_cast<const double *>(f->twiddle[d]), f->spec32[d] + nspec_pad, 2 * size_t(N), 1.0);
     if (pm_twiddle_count(N) > 0)
       k_pm_twiddles<<<unsigned((pm_twiddle_count(N) + 255) / 256), 256, 0, ctx->stream>>>(
-          reinterpret_cast<const double2 *>(f->twiddle[d]), f->spec32[d] + nspec_pad + 2 * size_t(N), N);
+          reinterpret_cast<const double2 *>(f->twiddle[d]), f->spec32[d] + nspec_pad + 2 * size_t(N), N, 16);
+    if (pm8_twiddle_count(N) > 0)
+      k_pm_twiddles<<<unsigned((pm8_twiddle_count(N) + 255) / 256), 256, 0, ctx->stream>>>(
+          reinterpret_cast<const double2 *>(f->twiddle[d]),
+          f->spec32[d] + nspec_pad + 2 * size_t(N) + 2 * size_t(pm_twiddle_count(N)), N, 8);
     DEMAG_TRY_HIP(hipGetLastError());
   }
   f->spec_ready = true;
@@ -557,6 +632,7 @@ demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, demag_prec p
       const size_t nspec = size_t(F_NTYPES) * f->M * (fft_length(f->n[d]) / 2 + 1);
       A.tw32 = reinterpret_cast<const cplx32 *>(f->spec32[d] + nspec + (nspec & 1));
       A.twpm = A.tw32 + fft_length(f->n[d]) / 2;
+      A.twpm8 = A.twpm + pm_twiddle_count(fft_length(f->n[d]) / 2);
     }
     A.tw = reinterpret_cast<const double2 *>(f->twiddle[d]);
     A.n = f->n[d];
@@ -602,7 +678,11 @@ demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, demag_prec p
     if (st != DEMAG_OK) return st;
     k_fft_fwd<true><<<ncols_all, kThreads, lds, ctx->stream>>>(P, ws, lds_points);
     DEMAG_TRY_HIP(hipGetLastError());
-    k_fft_jobs32<<<wg0, kThreads, 0, ctx->stream>>>(P, static_cast<const cplx32 *>(ws));
+    // 4096-point lines on every axis with columns: the 512-thread kernel
+    bool w4096 = true;
+    for (int d = 0; d < 3; ++d) w4096 = w4096 && (R[d] == 0 || P.a[d].L == 8192);
+    if (w4096) k_fft_jobs32w<<<wg0, kThreadsW, 0, ctx->stream>>>(P, static_cast<const cplx32 *>(ws));
+    else k_fft_jobs32<<<wg0, kThreads, 0, ctx->stream>>>(P, static_cast<const cplx32 *>(ws));
     DEMAG_TRY_HIP(hipGetLastError());
     if (ev) st = prof_end(ctx, ev, "fft32/xyz", flops, bytes);
     return st;

@@ -44,7 +44,14 @@ __device__ inline int pd(int i) { return i + (i >> 4); }
 // 16: the pad of pd puts two lanes of such a group on one bank when lanes
 // read consecutive points, the swizzle does not, and the Stockham stride-R
 // stores stay distinct modulo 8.
-template <bool XS> __device__ inline int slot(int i) { return XS ? (i ^ ((i >> 4) & 15)) : pd(i); }
+// XS = 2: the same with bit 6 of i also folded into bit 3, for the radix-8
+// plan of 4096-point FP32 lines (8-byte points: groups of 16 lanes,
+// conflict-free for slots distinct modulo 16): its Ns = 8 pass stores the
+// two halves of a group 64 points apart, on the same banks under XS = 1.
+template <int XS> __device__ inline int slot(int i) {
+  if constexpr (XS == 2) return i ^ (((i >> 4) ^ ((i >> 3) & 8)) & 15);
+  else return XS ? (i ^ ((i >> 4) & 15)) : pd(i);
+}
 __host__ __device__ constexpr int line_stride(int N, int nl) {
   const int base = N + (N - 1) / 16;                  // pd(N - 1) + 1
   const int t = nl >= 8 ? 1 : 8 / nl;                 // wanted residue modulo 8
@@ -150,17 +157,22 @@ template <class T> __device__ inline void make_twiddles(cx<T> *lo, cx<T> *hi, in
 // last pass of a transform, a functor sink(line, index, value).
 struct ToLds {};
 
-// FP32 twiddles in pass-major order (PM) for the inverse transforms whose
+// FP32 twiddles in pass-major order (PM = 16) for the inverse transforms whose
 // first radix-16 pass runs in registers: the pass of sub-transform length
 // Ns and radix R reads entry pm_offset(Ns) + (r - 1) Ns + k = W_N^(k r N /
 // (Ns R)), k < Ns, 1 <= r < R, so the 16 lanes of a read group (consecutive
 // k) read consecutive entries.  The whole table W_N^e, indexed by e = k r N
 // / (Ns R), puts those lanes N R / (Ns R) entries apart: on one bank for
 // Ns = 16.  Passes: Ns = 16 (R = 16, 240 entries), then Ns = 256 (R = N / 256).
-__host__ __device__ constexpr int pm_offset(int Ns) { return Ns == 16 ? 0 : 15 * 16; }
+// PM = 8: the radix-8 plan of 4096-point lines (first pass in registers,
+// then Ns = 8, 64, 512, radix 8 each; 56 + 448 + 3584 entries).
+__host__ __device__ constexpr int pm_offset(int PM, int Ns) {
+  return PM == 16 ? (Ns == 16 ? 0 : 15 * 16) : (Ns == 8 ? 0 : Ns == 64 ? 7 * 8 : 7 * 8 + 7 * 64);
+}
 __host__ __device__ constexpr int pm_twiddle_count(int N) { return N >= 256 ? 15 * 16 + (N / 256 - 1) * 256 : 0; }
+__host__ __device__ constexpr int pm8_twiddle_count(int N) { return N == 4096 ? 7 * 8 + 7 * 64 + 7 * 512 : 0; }
 
-template <bool INV, int R, int KT, int KP, int N, int Ns, typename Sink = ToLds, bool XS = false, bool PM = false,
+template <bool INV, int R, int KT, int KP, int N, int Ns, typename Sink = ToLds, int XS = 0, int PM = 0,
           class T>
 __device__ inline void pass(cx<T> *buf, int LS, int nlines, const cx<T> *tlo, const cx<T> *thi,
                             const Sink &sink = Sink{}) {
@@ -177,10 +189,11 @@ __device__ inline void pass(cx<T> *buf, int LS, int nlines, const cx<T> *tlo, co
       const cx<T> *lb = buf + line * LS;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = lb[slot<XS>(j + r * per)];
-      if constexpr (Ns > 1 && std::is_same_v<T, float> && PM) {
-        static_assert(Ns == 16 || Ns == 256, "pass-major twiddles: passes Ns = 16 and 256");
+      if constexpr (Ns > 1 && std::is_same_v<T, float> && PM != 0) {
+        static_assert(PM == 16 ? (Ns == 16 || Ns == 256) : (N == 4096 && R == 8 && (Ns == 8 || Ns == 64 || Ns == 512)),
+                      "pass-major twiddles: passes of the radix-16 or the radix-8 plan");
         const int k = j & (Ns - 1);
-        const cx<T> *tp = tlo + pm_offset(Ns) + k;
+        const cx<T> *tp = tlo + pm_offset(PM, Ns) + k;
 #pragma unroll
         for (int r = 1; r < R; ++r) {
           cx<T> w = tp[(r - 1) * Ns];
