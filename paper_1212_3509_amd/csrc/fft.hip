@@ -60,6 +60,7 @@ namespace {
 using namespace fftc;
 
 constexpr int kThreads = 256;
+constexpr int kThreadsW = 512;  // the 4096-point job kernels with half the points per lane
 constexpr int kPoints = 4096;   // largest transform (N = L / 2)
 
 __host__ __device__ inline int padded_points(int N) { return N + N / 16 + 1; }
@@ -348,6 +349,83 @@ __global__ __launch_bounds__(kThreads) void k_fft_jobs(const ColAxes P, const cp
   }
 }
 
+// FP64 jobs on 4096-point lines with 512 threads (as k_fft_jobs): each
+// thread packs the pairs f = t + 512 p, then the inverse transform runs as
+// four radix-8 passes, the last writing the outputs.  Half the points per
+// lane of the radix-16 plan, so four waves per SIMD instead of two.
+__global__ __launch_bounds__(kThreadsW, 2) void k_fft_jobs64w(const ColAxes P, const cplx *__restrict__ Uall,
+                                                              int lds_points) {
+  constexpr int N = 4096;
+  constexpr int kPairs = (N / 2 + 1 + kThreadsW - 1) / kThreadsW;
+  extern __shared__ cplx wk[];   // N points, then the twiddle tables
+  const int w = int(xcd_work_index(blockIdx.x, gridDim.x));
+  const int axis = axis_of(P, w, true);
+  const ColAxis &A = P.a[axis];
+  const int n = A.n, R = A.R, M = P.M;
+  cplx *tlo = wk + lds_points, *thi = tlo + 64;
+  const int local = w - A.wg0;
+  const int col = local / A.groups, grp = local - col * A.groups;   // col = q * R + l
+  const int q = col / R, l = col % R;
+  load_twiddles(tlo, thi, N, A.tw);
+  double sw, cw;
+  sincospi(-1.0 / double(N), &sw, &cw);
+  const cplx w1{cw, sw};         // W_L^1
+  const cplx *Uc = Uall + A.u_off + size_t(col) * (N + 1);
+  __syncthreads();
+  const int njobs = 2 * M;
+  const int j0 = grp * A.per;
+  const int j1 = min(njobs, j0 + A.per);
+  const double inv_n = 1.0 / double(N);
+  for (int j = j0; j < j1; ++j) {
+    const int s = j / M, k = j % M;
+    const int type = (axis == q) ? (s ? F_P : F_X) : (s ? F_Q : F_E);
+    const bool odd = (type == F_X || type == F_Q);
+    const double *gs = A.spec + size_t(type * M + k) * (N + 1);
+    // pairs in batches of kB whose loads are in flight together
+    constexpr int kB = 1;
+#pragma unroll 1
+    for (int p0 = 0; p0 < kPairs; p0 += kB) {
+    cplx uf[kB], uc[kB];
+    double gf[kB], gc[kB];
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+      const int f = min(int(threadIdx.x) + (p0 + i) * kThreadsW, N / 2);
+      uf[i] = Uc[f];
+      uc[i] = Uc[N - f];
+      gf[i] = gs[f];
+      gc[i] = gs[N - f];
+    }
+#pragma unroll
+    for (int i = 0; i < kB; ++i) {
+      const int f = threadIdx.x + (p0 + i) * kThreadsW;
+      if (p0 + i >= kPairs || f > N / 2) continue;
+      const int fc = N - f;
+      cplx yf = uf[i], yc = uc[i];
+      yf = odd ? cplx{-yf.y * gf[i], yf.x * gf[i]} : cplx{yf.x * gf[i], yf.y * gf[i]};
+      yc = odd ? cplx{-yc.y * gc[i], yc.x * gc[i]} : cplx{yc.x * gc[i], yc.y * gc[i]};
+      {
+        const cplx ycc = cconj(yc);
+        const cplx E{0.5 * (yf.x + ycc.x), 0.5 * (yf.y + ycc.y)};
+        const cplx Dm{0.5 * (yf.x - ycc.x), 0.5 * (yf.y - ycc.y)};
+        const cplx O = cmul(Dm, cconj(wl(f, N, tlo, thi, w1)));
+        wk[slot<true>(f & (N - 1))] = cplx{E.x - O.y, E.y + O.x};
+      }
+      if (fc != f && fc < N) {
+        const cplx yfc = cconj(yf);
+        const cplx E{0.5 * (yc.x + yfc.x), 0.5 * (yc.y + yfc.y)};
+        const cplx Dm{0.5 * (yc.x - yfc.x), 0.5 * (yc.y - yfc.y)};
+        const cplx O = cmul(Dm, cconj(wl(fc, N, tlo, thi, w1)));
+        wk[slot<true>(fc)] = cplx{E.x - O.y, E.y + O.x};
+      }
+    }
+    }
+    __syncthreads();
+    float *y = A.out + ((size_t(q) * 2 + s) * M + k) * size_t(R) * n + size_t(l) * n;
+    run_passes<true, kThreadsW, N, N, 1, OutSink, true, 8, 8, 8, 8>(wk, 0, 1, tlo, thi, OutSink{y, n, inv_n});
+    __syncthreads();
+  }
+}
+
 // Output of the FP32 inverse transform (as OutSink; the 1 / N is in the
 // FP32 kernel spectra).
 struct OutSink32 {
@@ -488,7 +566,6 @@ __global__ __launch_bounds__(kThreads) void k_fft_jobs32(const ColAxes P, const 
 // twiddles.  Half the points per lane of k_fft_jobs32 (8 pairs of packing
 // factors held across jobs instead of 16), so four waves per SIMD instead
 // of two.
-constexpr int kThreadsW = 512;
 __global__ __launch_bounds__(kThreadsW, 2) void k_fft_jobs32w(const ColAxes P, const cplx32 *__restrict__ ABall) {
   constexpr int N = 4096, per = N / 8;
   __shared__ cplx32 wk[N];
@@ -691,11 +768,16 @@ demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, demag_prec p
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_jobs),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_jobs64w),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   st = prof_begin(ctx, &ev);
   if (st != DEMAG_OK) return st;
   k_fft_fwd<false><<<ncols_all, kThreads, lds, ctx->stream>>>(P, ws, lds_points);
   DEMAG_TRY_HIP(hipGetLastError());
-  k_fft_jobs<<<wg0, kThreads, lds, ctx->stream>>>(P, static_cast<const cplx *>(ws), lds_points);
+  bool w4096 = true;   // 4096-point lines on every axis with columns: the 512-thread kernel
+  for (int d = 0; d < 3; ++d) w4096 = w4096 && (R[d] == 0 || P.a[d].L == 8192);
+  if (w4096) k_fft_jobs64w<<<wg0, kThreadsW, lds, ctx->stream>>>(P, static_cast<const cplx *>(ws), lds_points);
+  else k_fft_jobs<<<wg0, kThreads, lds, ctx->stream>>>(P, static_cast<const cplx *>(ws), lds_points);
   DEMAG_TRY_HIP(hipGetLastError());
   if (ev) st = prof_end(ctx, ev, "fft/xyz", flops, bytes);
   return st;
