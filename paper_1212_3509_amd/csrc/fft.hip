@@ -208,6 +208,79 @@ __global__ __launch_bounds__(kThreads) void k_fft_fwd(const ColAxes P, void *__r
   }
 }
 
+// Forward real transforms of 4096-point lines (L = 8192, n = 2049..4096) with
+// 512 threads, as k_fft_fwd otherwise.  z[m] = x[2m] + i x[2m+1] vanishes for
+// m >= 2048 (2m >= n), so the first radix-8 pass takes its four nonzero
+// inputs straight from the column into registers; three radix-8 passes in
+// LDS follow.  The unpacking forms X[f] and X[N - f] together from one
+// product W_L^f O_f (f <= N / 2):
+//   X[f] = E_f + W_L^f O_f,   conj X[N - f] = E_f - W_L^f O_f,
+// since E_(N-f) = conj E_f, O_(N-f) = conj O_f and W_L^(N-f) = -conj W_L^f.
+template <bool AB>
+__global__ __launch_bounds__(kThreadsW) void k_fft_fwd_w(const ColAxes P, void *__restrict__ Uout, int lds_points) {
+  constexpr int N = 4096, per = N / 8;
+  extern __shared__ cplx wk[];   // N points, then the twiddle tables
+  const int d = axis_of(P, blockIdx.x, false);
+  const ColAxis &A = P.a[d];
+  const int n = A.n;
+  cplx *tlo = wk + lds_points, *thi = tlo + 64;
+  const int col = blockIdx.x - A.col0;
+  load_twiddles(tlo, thi, N, A.tw);
+  const float *u = A.in + size_t(col) * n;
+  const int g = threadIdx.x;
+  cplx v[8];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int a = 2 * (g + per * r), b = a + 1;
+    v[r] = cplx{a < n ? double(u[a]) : 0.0, b < n ? double(u[b]) : 0.0};
+  }
+#pragma unroll
+  for (int r = 4; r < 8; ++r) v[r] = cplx{0.0, 0.0};
+  dftR<false, 8>(v);
+#pragma unroll
+  for (int r = 0; r < 8; ++r) wk[slot<1>(8 * g + r)] = v[r];
+  __syncthreads();
+  pass<false, 8, kThreadsW, N, N, 8, ToLds, 1>(wk, 0, 1, tlo, thi);
+  pass<false, 8, kThreadsW, N, N, 64, ToLds, 1>(wk, 0, 1, tlo, thi);
+  pass<false, 8, kThreadsW, N, N, 512, ToLds, 1>(wk, 0, 1, tlo, thi);
+  double sw, cw;
+  sincospi(-1.0 / double(N), &sw, &cw);
+  const cplx w1{cw, sw};         // W_L^1
+  for (int f = g; f <= N / 2; f += kThreadsW) {
+    const cplx zf = wk[slot<1>(f)];
+    const cplx zcc = cconj(wk[slot<1>((N - f) & (N - 1))]);
+    const cplx E{0.5 * (zf.x + zcc.x), 0.5 * (zf.y + zcc.y)};
+    const cplx D{0.5 * (zf.x - zcc.x), 0.5 * (zf.y - zcc.y)};
+    const cplx W = wl(f, N, tlo, thi, w1);
+    const cplx WO = cmul(W, cplx{D.y, -D.x});   // W_L^f O_f, O_f = D / i
+    const cplx xf = cadd(E, WO);                // X[f]
+    const cplx xcc = csub(E, WO);               // conj X[N - f]
+    const int fc = N - f;
+    if constexpr (!AB) {
+      cplx *Uc = static_cast<cplx *>(Uout) + A.u_off + size_t(col) * (N + 1);
+      Uc[f] = xf;
+      if (fc != f) Uc[fc] = cconj(xcc);
+    } else {
+      // A[f] = X[f] (1 + i conj W_L^f) / 2, B[f] = conj X[N - f] (1 - i conj W_L^f) / 2;
+      // at fc = N - f: i conj W_L^fc = -i W_L^f, X[fc] = conj(xcc), conj X[N - fc] = conj(xf)
+      cplx32 *Ac = static_cast<cplx32 *>(Uout) + A.u_off + size_t(col) * (2 * N);
+      cplx32 *Bc = Ac + N;
+      const cplx iw{W.y, W.x};                  // i conj W_L^f
+      const cplx a = cmul(xf, cplx{1.0 + iw.x, iw.y});
+      const cplx b = cmul(xcc, cplx{1.0 - iw.x, -iw.y});
+      Ac[f] = cplx32{float(0.5 * a.x), float(0.5 * a.y)};
+      Bc[f] = cplx32{float(0.5 * b.x), float(0.5 * b.y)};
+      if (f > 0 && fc != f) {
+        const cplx iwc{W.y, -W.x};              // i conj W_L^fc = -i W_L^f
+        const cplx ac = cmul(cconj(xcc), cplx{1.0 + iwc.x, iwc.y});
+        const cplx bc = cmul(cconj(xf), cplx{1.0 - iwc.x, -iwc.y});
+        Ac[fc] = cplx32{float(0.5 * ac.x), float(0.5 * ac.y)};
+        Bc[fc] = cplx32{float(0.5 * bc.x), float(0.5 * bc.y)};
+      }
+    }
+  }
+}
+
 // FP64 spectra of the circulant embeddings, one workgroup per generator
 // (type * M + k): with A the forward real transform of the one-sided
 // generator a_J = g_J, J < n, zero-padded to L (A[f] = sum_J a_J W_L^(fJ)),
@@ -748,16 +821,19 @@ demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, demag_prec p
   const int lds_points = padded_points(maxN);
   const size_t lds = sizeof(double2) * (size_t(lds_points) + 128);
   hipEvent_t ev = nullptr;
+  // 4096-point lines on every axis with columns: the 512-thread kernels
+  bool w4096 = true;
+  for (int d = 0; d < 3; ++d) w4096 = w4096 && (R[d] == 0 || P.a[d].L == 8192);
   if (f32) {
     DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_fwd<true>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_fwd_w<true>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
     st = prof_begin(ctx, &ev);
     if (st != DEMAG_OK) return st;
-    k_fft_fwd<true><<<ncols_all, kThreads, lds, ctx->stream>>>(P, ws, lds_points);
+    if (w4096) k_fft_fwd_w<true><<<ncols_all, kThreadsW, lds, ctx->stream>>>(P, ws, lds_points);
+    else k_fft_fwd<true><<<ncols_all, kThreads, lds, ctx->stream>>>(P, ws, lds_points);
     DEMAG_TRY_HIP(hipGetLastError());
-    // 4096-point lines on every axis with columns: the 512-thread kernel
-    bool w4096 = true;
-    for (int d = 0; d < 3; ++d) w4096 = w4096 && (R[d] == 0 || P.a[d].L == 8192);
     if (w4096) k_fft_jobs32w<<<wg0, kThreadsW, 0, ctx->stream>>>(P, static_cast<const cplx32 *>(ws));
     else k_fft_jobs32<<<wg0, kThreads, 0, ctx->stream>>>(P, static_cast<const cplx32 *>(ws));
     DEMAG_TRY_HIP(hipGetLastError());
@@ -770,12 +846,13 @@ demag_status launch_columns(demag_ctx *ctx, const demag_factors *f, demag_prec p
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_jobs64w),
                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  DEMAG_TRY_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_fwd_w<false>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
   st = prof_begin(ctx, &ev);
   if (st != DEMAG_OK) return st;
-  k_fft_fwd<false><<<ncols_all, kThreads, lds, ctx->stream>>>(P, ws, lds_points);
+  if (w4096) k_fft_fwd_w<false><<<ncols_all, kThreadsW, lds, ctx->stream>>>(P, ws, lds_points);
+  else k_fft_fwd<false><<<ncols_all, kThreads, lds, ctx->stream>>>(P, ws, lds_points);
   DEMAG_TRY_HIP(hipGetLastError());
-  bool w4096 = true;   // 4096-point lines on every axis with columns: the 512-thread kernel
-  for (int d = 0; d < 3; ++d) w4096 = w4096 && (R[d] == 0 || P.a[d].L == 8192);
   if (w4096) k_fft_jobs64w<<<wg0, kThreadsW, lds, ctx->stream>>>(P, static_cast<const cplx *>(ws), lds_points);
   else k_fft_jobs<<<wg0, kThreads, lds, ctx->stream>>>(P, static_cast<const cplx *>(ws), lds_points);
   DEMAG_TRY_HIP(hipGetLastError());

@@ -169,6 +169,41 @@ def test_cp_4096_rank10_sampled(ctx, prec):
     print(f"cp 4096 {prec}: worst sampled column rel err {worst:.2e}")
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cp_4096_lines_ragged(ctx, prec):
+    """Axes of 2049, 3001 and 4096 cells: every axis on 4096-point half-length
+    lines (the 512-thread forward and job kernels) with the column shorter
+    than the line on two axes; CP rank 2 (seed 4), M = 12, 25 sampled jobs
+    per axis against direct FP64 convolution with the oracle's generators."""
+    n, M, r = (2049, 3001, 4096), 12, 2
+    h = (1 / 4096,) * 3
+    f = ctx.assemble(n, h, M=M)
+    cp = inputs.cp_input(n, rank=r, seed=4, dtype=np.float32)
+    U = [_dev(np.stack([cp.U[q][d].T for q in range(3)])) for d in range(3)]
+    out, table = ctx.apply_cp(f, U, prec=prec)
+    torch.cuda.synchronize()
+    assert np.array_equal(table, structured.term_table(M, r))
+    hs, tau, alpha = _oracle_rule(n, h, M)
+    rng = np.random.default_rng(3)
+    got_all = [o.cpu().numpy() for o in out]
+    worst = 0.0
+    for d in range(3):
+        F = sinc.scaled_factors(n[d], hs[d], tau, alpha)
+        for _ in range(25):
+            q, s, k, l = int(rng.integers(3)), int(rng.integers(2)), int(rng.integers(M)), int(rng.integers(r))
+            t = structured.type_of(q, d, s)
+            u = cp.U[q][d][:, l].astype(np.float64)
+            ref = np.convolve(F[t, k], u)[n[d] - 1:2 * n[d] - 1]
+            got = got_all[d][q, s, k, l].astype(np.float64)
+            nrm = np.linalg.norm(ref)
+            err = np.linalg.norm(got - ref)
+            floor = 1e-12 * np.abs(F[t]).sum(axis=1).max() * np.linalg.norm(u)
+            assert err <= 1e-6 * nrm + floor, (d, q, s, k, l, err / nrm)
+            if nrm > 0:
+                worst = max(worst, err / nrm)
+    print(f"cp 4096-point lines ragged {prec}: worst sampled column rel err {worst:.2e}")
+
+
 def _check_sampled(got_all, cols_of, R, n, F, M, rng, label, count=40):
     """count sampled (q, s, k, column) jobs per axis against direct FP64
     convolutions of the oracle's generators with the input columns."""
