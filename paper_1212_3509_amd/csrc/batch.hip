@@ -53,6 +53,7 @@ struct demag_batch {
   int *d_counters = nullptr;                      // one item counter per launch
   std::map<std::pair<int, int>, int> rb_choice;   // (n, nout) -> RB
   double flops = 0;                               // algorithmic FLOPs of one apply
+  hipEvent_t used = nullptr;                      // recorded after each apply's work
   // captured graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -322,7 +323,18 @@ demag_status demag_batch_create(demag_ctx *ctx, int32_t count, const demag_grid 
   const int per_cu = items_blocks_per_cu(prec == DEMAG_FP64, items_lds_bytes(b->nmax, prec == DEMAG_FP64));
   b->grid = std::max(1, dev_cus * std::max(1, per_cu));
   demag_status st = build(ctx, b.get());
+  if (st == DEMAG_OK) {
+    // the table copies above are asynchronous: demag_batch_free waits for them
+    if (hipEventCreateWithFlags(&b->used, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(b->used, ctx->stream) != hipSuccess) {
+      (void)hipStreamSynchronize(ctx->stream);
+      set_error("demag_batch_create: event record failed");
+      st = DEMAG_E_HIP;
+    }
+  }
   if (st != DEMAG_OK) {
+    (void)hipStreamSynchronize(ctx->stream);
+    if (b->used) (void)hipEventDestroy(b->used);
     release_tables(b.get());
     for (auto *g : b->factors) demag_factors_free(g);
     return st;
@@ -333,7 +345,12 @@ demag_status demag_batch_create(demag_ctx *ctx, int32_t count, const demag_grid 
 
 demag_status demag_batch_free(demag_batch *b) {
   if (!b) return DEMAG_OK;
-  (void)hipDeviceSynchronize();
+  // wait for the last work that reads the batch's tables: the set-up's
+  // copies or the last apply (the tuner synchronizes its own work)
+  if (b->used) {
+    (void)hipEventSynchronize(b->used);
+    (void)hipEventDestroy(b->used);
+  }
   release_tables(b);
   if (b->gens) (void)hipFree(b->gens);
   for (auto *f : b->factors) demag_factors_free(f);
@@ -356,8 +373,8 @@ demag_status demag_batch_info(const demag_batch *b, int32_t *node_chunk, int32_t
   return DEMAG_OK;
 }
 
-demag_status demag_batch_apply(demag_ctx *ctx, demag_batch *b, const void *m, void *phi, void *h, int32_t use_graph) {
-  DEMAG_REQUIRE(ctx && b && m && phi && h, "demag_batch_apply: NULL argument");
+namespace {
+demag_status batch_apply(demag_ctx *ctx, demag_batch *b, const void *m, void *phi, void *h, int32_t use_graph) {
   DEMAG_TRY_HIP(hipSetDevice(ctx->device));
   {
     const demag_status cs = check_finite(ctx, m, size_t(3) * size_t(b->off.back()), b->prec == DEMAG_FP64,
@@ -404,6 +421,16 @@ demag_status demag_batch_apply(demag_ctx *ctx, demag_batch *b, const void *m, vo
   if (st != DEMAG_OK) return st;
   DEMAG_TRY_HIP(hipGraphLaunch(b->exec, ctx->stream));
   if (ev) return prof_end(ctx, ev, std::string(b->prec == DEMAG_FP64 ? "fp64" : "fp32") + "/batch_graph", b->flops, 0.0);
+  return DEMAG_OK;
+}
+}  // namespace
+
+demag_status demag_batch_apply(demag_ctx *ctx, demag_batch *b, const void *m, void *phi, void *h, int32_t use_graph) {
+  DEMAG_REQUIRE(ctx && b && m && phi && h, "demag_batch_apply: NULL argument");
+  const demag_status st = batch_apply(ctx, b, m, phi, h, use_graph);
+  if (st != DEMAG_OK) return st;
+  if (!b->used) DEMAG_TRY_HIP(hipEventCreateWithFlags(&b->used, hipEventDisableTiming));
+  DEMAG_TRY_HIP(hipEventRecord(b->used, ctx->stream));
   return DEMAG_OK;
 }
 
