@@ -9,7 +9,7 @@
 // entries of the circular convolution c * u are the Toeplitz product T(g) u.
 // E and P generators are even in J, so their spectra are real; X and Q are
 // odd, so their spectra are imaginary.  The spectra are formed once per
-// factor set in FP64 (direct cosine/sine sums).
+// factor set in FP64 (forward real FFTs of the one-sided generators).
 //
 // Transforms run in FP64: the roundoff of an FFT convolution is of order
 // eps log2(L) |G|_inf |u|, which for the wide (low-pass) E factors on rough
@@ -20,7 +20,8 @@
 // A real transform of length L is computed through a complex transform of
 // length N = L/2 on z[m] = x[2m] + i x[2m+1], with the usual even/odd
 // unpacking by W_L^f.  The complex transform runs in LDS as Stockham passes
-// of radix 16/8/4/2 (N/R butterflies per pass, 256 threads).  Twiddles come
+// of radix 16/8/4/2 (N/R butterflies per pass, 256 threads; 4096-point lines:
+// radix 8 with 512 threads).  Twiddles come
 // from two 64-entry tables in LDS, W_N^e = W_N^(e mod 64) W_N^(64 (e div 64)),
 // so no pass waits on global memory.
 //
@@ -43,7 +44,7 @@
 //   Z[f] = G[f] A[f] + G[N-f] B[f]   (even kernels, G real),
 //   Z[f] = i (g[f] A[f] - g[N-f] B[f])   (odd kernels, G = i g),
 //   A[f] = U[f] (1 + i conj W_L^f) / 2,  B[f] = conj U[N-f] (1 - i conj W_L^f) / 2,
-// so k_fft_fwd32 stores A and B (FP32) per column, and k_fft_jobs32 keeps
+// so k_fft_fwd<true> stores A and B (FP32) per column, and k_fft_jobs32 keeps
 // each thread's 16 pairs in registers across the workgroup's jobs, forms its
 // 16 points of Z per job and runs the first radix-16 pass on them in
 // registers (no LDS round for the packing).
