@@ -152,6 +152,49 @@ __device__ inline int axis_of(const ColAxes &P, int idx, bool wg) {
   return d;
 }
 
+// Unpacking of a forward real transform from its half-length complex
+// transform Z (in LDS, layout slot<1>) at f and N - f together, f <= N / 2:
+//   X[f] = E_f + W_L^f O_f,   conj X[N - f] = E_f - W_L^f O_f,
+// E_f = (Z[f] + conj Z[N-f]) / 2, O_f = (Z[f] - conj Z[N-f]) / (2i), since
+// E_(N-f) = conj E_f, O_(N-f) = conj O_f and W_L^(N-f) = -conj W_L^f.
+// AB == false: U[f] = X[f] and U[N - f] into dst (N + 1 values).  AB == true:
+// the FP32 packing factors A[g] = X[g] (1 + i conj W_L^g) / 2 and
+// B[g] = conj X[N - g] (1 - i conj W_L^g) / 2 at g = f and g = N - f < N
+// into dst (A) and dst + N (B), using i conj W_L^(N-f) = -i W_L^f.
+template <bool AB>
+__device__ inline void unpack_pair(const cplx *wk, int f, int N, const cplx *tlo, const cplx *thi, cplx w1,
+                                   void *dst) {
+  const cplx zf = wk[slot<1>(f & (N - 1))];
+  const cplx zcc = cconj(wk[slot<1>((N - f) & (N - 1))]);
+  const cplx E{0.5 * (zf.x + zcc.x), 0.5 * (zf.y + zcc.y)};
+  const cplx D{0.5 * (zf.x - zcc.x), 0.5 * (zf.y - zcc.y)};
+  const cplx W = wl(f, N, tlo, thi, w1);
+  const cplx WO = cmul(W, cplx{D.y, -D.x});   // W_L^f O_f, O_f = D / i
+  const cplx xf = cadd(E, WO);                // X[f]
+  const cplx xcc = csub(E, WO);               // conj X[N - f]
+  const int fc = N - f;
+  if constexpr (!AB) {
+    cplx *U = static_cast<cplx *>(dst);
+    U[f] = xf;
+    if (fc != f) U[fc] = cconj(xcc);
+  } else {
+    cplx32 *Ac = static_cast<cplx32 *>(dst);
+    cplx32 *Bc = Ac + N;
+    const cplx iw{W.y, W.x};                  // i conj W_L^f
+    const cplx a = cmul(xf, cplx{1.0 + iw.x, iw.y});
+    const cplx b = cmul(xcc, cplx{1.0 - iw.x, -iw.y});
+    Ac[f] = cplx32{float(0.5 * a.x), float(0.5 * a.y)};
+    Bc[f] = cplx32{float(0.5 * b.x), float(0.5 * b.y)};
+    if (f > 0 && fc != f) {
+      const cplx iwc{W.y, -W.x};              // i conj W_L^fc = -i W_L^f
+      const cplx ac = cmul(cconj(xcc), cplx{1.0 + iwc.x, iwc.y});
+      const cplx bc = cmul(cconj(xf), cplx{1.0 - iwc.x, -iwc.y});
+      Ac[fc] = cplx32{float(0.5 * ac.x), float(0.5 * ac.y)};
+      Bc[fc] = cplx32{float(0.5 * bc.x), float(0.5 * bc.y)};
+    }
+  }
+}
+
 // Forward real transform of every column (FP64).  AB == false: the unpacked
 // spectrum U[col][f], f = 0..N (N + 1 values, FP64).  AB == true: the FP32
 // packing factors A[col][f], B[col][f], f < N (2 N values per column, A first).
@@ -184,39 +227,16 @@ __global__ __launch_bounds__(kThreads) void k_fft_fwd(const ColAxes P, void *__r
   double sw, cw;
   sincospi(-1.0 / double(N), &sw, &cw);
   const cplx w1{cw, sw};         // W_L^1
-  // X[f] = E + W_L^f O with E = (Z[f] + conj Z[N-f])/2, O = (Z[f] - conj Z[N-f])/(2i)
-  auto spectrum = [&](int f) {
-    const cplx zf = wk[slot<true>(f & (N - 1))];
-    const cplx zcc = cconj(wk[slot<true>((N - f) & (N - 1))]);
-    const cplx D{0.5 * (zf.x - zcc.x), 0.5 * (zf.y - zcc.y)};
-    return cadd(cplx{0.5 * (zf.x + zcc.x), 0.5 * (zf.y + zcc.y)}, cmul(wl(f, N, tlo, thi, w1), cplx{D.y, -D.x}));
-  };
-  if constexpr (!AB) {
-    cplx *Uc = static_cast<cplx *>(Uout) + A.u_off + size_t(col) * (N + 1);
-    for (int f = threadIdx.x; f <= N; f += kThreads) Uc[f] = spectrum(f);
-  } else {
-    cplx32 *Ac = static_cast<cplx32 *>(Uout) + A.u_off + size_t(col) * (2 * N);
-    cplx32 *Bc = Ac + N;
-    for (int f = threadIdx.x; f < N; f += kThreads) {
-      const cplx uf = spectrum(f), uc = cconj(spectrum(N - f));
-      const cplx wc = cconj(wl(f, N, tlo, thi, w1));
-      const cplx iw{-wc.y, wc.x};                       // i conj W_L^f
-      const cplx a = cmul(uf, cplx{1.0 + iw.x, iw.y});
-      const cplx b = cmul(uc, cplx{1.0 - iw.x, -iw.y});
-      Ac[f] = cplx32{float(0.5 * a.x), float(0.5 * a.y)};
-      Bc[f] = cplx32{float(0.5 * b.x), float(0.5 * b.y)};
-    }
-  }
+  void *dst = AB ? static_cast<void *>(static_cast<cplx32 *>(Uout) + A.u_off + size_t(col) * (2 * N))
+                 : static_cast<void *>(static_cast<cplx *>(Uout) + A.u_off + size_t(col) * (N + 1));
+  for (int f = threadIdx.x; f <= N / 2; f += kThreads) unpack_pair<AB>(wk, f, N, tlo, thi, w1, dst);
 }
 
 // Forward real transforms of 4096-point lines (L = 8192, n = 2049..4096) with
 // 512 threads, as k_fft_fwd otherwise.  z[m] = x[2m] + i x[2m+1] vanishes for
 // m >= 2048 (2m >= n), so the first radix-8 pass takes its four nonzero
 // inputs straight from the column into registers; three radix-8 passes in
-// LDS follow.  The unpacking forms X[f] and X[N - f] together from one
-// product W_L^f O_f (f <= N / 2):
-//   X[f] = E_f + W_L^f O_f,   conj X[N - f] = E_f - W_L^f O_f,
-// since E_(N-f) = conj E_f, O_(N-f) = conj O_f and W_L^(N-f) = -conj W_L^f.
+// LDS follow; unpack_pair forms the outputs.
 template <bool AB>
 __global__ __launch_bounds__(kThreadsW) void k_fft_fwd_w(const ColAxes P, void *__restrict__ Uout, int lds_points) {
   constexpr int N = 4096, per = N / 8;
@@ -247,39 +267,9 @@ __global__ __launch_bounds__(kThreadsW) void k_fft_fwd_w(const ColAxes P, void *
   double sw, cw;
   sincospi(-1.0 / double(N), &sw, &cw);
   const cplx w1{cw, sw};         // W_L^1
-  for (int f = g; f <= N / 2; f += kThreadsW) {
-    const cplx zf = wk[slot<1>(f)];
-    const cplx zcc = cconj(wk[slot<1>((N - f) & (N - 1))]);
-    const cplx E{0.5 * (zf.x + zcc.x), 0.5 * (zf.y + zcc.y)};
-    const cplx D{0.5 * (zf.x - zcc.x), 0.5 * (zf.y - zcc.y)};
-    const cplx W = wl(f, N, tlo, thi, w1);
-    const cplx WO = cmul(W, cplx{D.y, -D.x});   // W_L^f O_f, O_f = D / i
-    const cplx xf = cadd(E, WO);                // X[f]
-    const cplx xcc = csub(E, WO);               // conj X[N - f]
-    const int fc = N - f;
-    if constexpr (!AB) {
-      cplx *Uc = static_cast<cplx *>(Uout) + A.u_off + size_t(col) * (N + 1);
-      Uc[f] = xf;
-      if (fc != f) Uc[fc] = cconj(xcc);
-    } else {
-      // A[f] = X[f] (1 + i conj W_L^f) / 2, B[f] = conj X[N - f] (1 - i conj W_L^f) / 2;
-      // at fc = N - f: i conj W_L^fc = -i W_L^f, X[fc] = conj(xcc), conj X[N - fc] = conj(xf)
-      cplx32 *Ac = static_cast<cplx32 *>(Uout) + A.u_off + size_t(col) * (2 * N);
-      cplx32 *Bc = Ac + N;
-      const cplx iw{W.y, W.x};                  // i conj W_L^f
-      const cplx a = cmul(xf, cplx{1.0 + iw.x, iw.y});
-      const cplx b = cmul(xcc, cplx{1.0 - iw.x, -iw.y});
-      Ac[f] = cplx32{float(0.5 * a.x), float(0.5 * a.y)};
-      Bc[f] = cplx32{float(0.5 * b.x), float(0.5 * b.y)};
-      if (f > 0 && fc != f) {
-        const cplx iwc{W.y, -W.x};              // i conj W_L^fc = -i W_L^f
-        const cplx ac = cmul(cconj(xcc), cplx{1.0 + iwc.x, iwc.y});
-        const cplx bc = cmul(cconj(xf), cplx{1.0 - iwc.x, -iwc.y});
-        Ac[fc] = cplx32{float(0.5 * ac.x), float(0.5 * ac.y)};
-        Bc[fc] = cplx32{float(0.5 * bc.x), float(0.5 * bc.y)};
-      }
-    }
-  }
+  void *dst = AB ? static_cast<void *>(static_cast<cplx32 *>(Uout) + A.u_off + size_t(col) * (2 * N))
+                 : static_cast<void *>(static_cast<cplx *>(Uout) + A.u_off + size_t(col) * (N + 1));
+  for (int f = g; f <= N / 2; f += kThreadsW) unpack_pair<AB>(wk, f, N, tlo, thi, w1, dst);
 }
 
 // FP64 spectra of the circulant embeddings, one workgroup per generator
