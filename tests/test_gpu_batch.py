@@ -177,3 +177,26 @@ def test_uneven_batch_recipe_sampled(ctx):
     print(f"batch of 256: {len(res)} states sampled, worst rel L2 vs oracle {worst:.2e}")
     for s, ep, eh in res:
         assert ep < 1e-6 and eh < 1e-6, (s, grids[s][0], ep, eh)
+
+
+def test_batch_free_waits_for_its_work(ctx):
+    """Freeing a batch right after creation (its table copies are
+    asynchronous) and right after an apply (no synchronization by the
+    caller) waits for that work; a new batch on the same grids then gives
+    the same fields."""
+    grids = _grids()[:3]
+    b0 = ctx.batch(grids, M=8, prec="fp32")
+    b0.free()
+    fields = [inputs.random_unit_field(n, seed=20 + s) for s, (n, _h) in enumerate(grids)]
+    b1 = ctx.batch(grids, M=8, prec="fp32")
+    off = b1.offsets()
+    m = _pack(fields, torch.float32)
+    phi = torch.empty(int(off[-1]), dtype=torch.float32, device="cuda")
+    h = torch.empty(3 * int(off[-1]), dtype=torch.float32, device="cuda")
+    b1.apply(m, phi, h)
+    b1.free()
+    torch.cuda.synchronize()
+    b2 = ctx.batch(grids, M=8, prec="fp32")
+    _m, phi2, h2, _off = _run_batch(ctx, b2, fields, torch.float32)
+    b2.free()
+    assert torch.equal(phi, phi2) and torch.equal(h, h2)
