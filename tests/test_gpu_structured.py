@@ -204,6 +204,41 @@ def test_cp_4096_lines_ragged(ctx, prec):
     print(f"cp 4096-point lines ragged {prec}: worst sampled column rel err {worst:.2e}")
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cp_mixed_line_lengths(ctx, prec):
+    """Axes of 3000, 64 and 200 cells (half-length lines of 4096, 64 and 256
+    points): a 4096-point line beside shorter ones takes the 256-thread
+    kernels for every axis.  CP rank 3 (seed 8), M = 10, 20 sampled jobs per
+    axis against direct FP64 convolution with the oracle's generators."""
+    n, M, r = (3000, 64, 200), 10, 3
+    h = (1 / 3000,) * 3
+    f = ctx.assemble(n, h, M=M)
+    cp = inputs.cp_input(n, rank=r, seed=8, dtype=np.float32)
+    U = [_dev(np.stack([cp.U[q][d].T for q in range(3)])) for d in range(3)]
+    out, table = ctx.apply_cp(f, U, prec=prec)
+    torch.cuda.synchronize()
+    assert np.array_equal(table, structured.term_table(M, r))
+    hs, tau, alpha = _oracle_rule(n, h, M)
+    rng = np.random.default_rng(2)
+    got_all = [o.cpu().numpy() for o in out]
+    worst = 0.0
+    for d in range(3):
+        F = sinc.scaled_factors(n[d], hs[d], tau, alpha)
+        for _ in range(20):
+            q, s, k, l = int(rng.integers(3)), int(rng.integers(2)), int(rng.integers(M)), int(rng.integers(r))
+            t = structured.type_of(q, d, s)
+            u = cp.U[q][d][:, l].astype(np.float64)
+            ref = np.convolve(F[t, k], u)[n[d] - 1:2 * n[d] - 1]
+            got = got_all[d][q, s, k, l].astype(np.float64)
+            nrm = np.linalg.norm(ref)
+            err = np.linalg.norm(got - ref)
+            floor = 1e-12 * np.abs(F[t]).sum(axis=1).max() * np.linalg.norm(u)
+            assert err <= 1e-6 * nrm + floor, (d, q, s, k, l, err / nrm)
+            if nrm > 0:
+                worst = max(worst, err / nrm)
+    print(f"cp mixed line lengths {prec}: worst sampled column rel err {worst:.2e}")
+
+
 def _check_sampled(got_all, cols_of, R, n, F, M, rng, label, count=40):
     """count sampled (q, s, k, column) jobs per axis against direct FP64
     convolutions of the oracle's generators with the input columns."""
