@@ -220,7 +220,8 @@ def _cpu_baseline(m, n, runs):
     per run.  All cores: the oracle run unchanged on one node per core in a
     thread pool (its einsum loops release the interpreter lock).  Median of
     `runs` runs each.  Beside it: the exact collocation (closed-form cell
-    kernels + FFT convolution) at 32^3, and the structured reference (dense
+    kernels + FFT convolution) at 32^3 and, on samples, at 128^3 (one core
+    and all cores), and the structured reference (dense
     Toeplitz products of the factor columns) at n = 4096 on one (node, type)
     pair of CP rank 10 columns, scaled to the apply's 7200 products."""
     import os
@@ -255,6 +256,43 @@ def _cpu_baseline(m, n, runs):
     wall, cpu = _median_wall(lambda: apply.collocated_apply_fft(m32, (1.0 / 32,) * 3), runs)
     out["exact_fft_32"] = {"value": round(32 ** 3 / wall / 1e6, 6), "unit": "Mcell-field evals/s",
                            "seconds": round(wall, 3), "cores": max(1, round(cpu / wall))}
+    # exact collocation at 128^3: closed-form cell kernels on all 255^3
+    # offsets, then 12 FFT convolutions of 255^3 kernels with 128^3 fields
+    # (3 for phi, 9 for h).  Timed on samples scaled to the whole: the
+    # kernels of 7 of the 255 z-offset planes (the 128 x 128 x 4 grid; the
+    # cost per offset does not depend on it) and one of the convolutions.
+    # All cores: one kernel sample per thread (its planes stand for 7 more),
+    # the convolution with scipy.fft's workers.
+    from scipy import fft as sfft
+
+    from oracle import exact
+    h128 = (1.0 / n,) * 3
+    ker = np.random.default_rng(3).standard_normal((2 * n - 1,) * 3)
+    wk1, ck1 = _median_wall(lambda: exact.offset_kernels((n, n, 4), h128), runs)
+    wv1, cv1 = _median_wall(lambda: apply._linear_conv_same(ker, m[0]), runs)
+
+    def kern_all():
+        with ThreadPoolExecutor(cores) as ex:
+            list(ex.map(lambda _i: exact.offset_kernels((n, n, 4), h128), range(cores)))
+
+    def conv_all():
+        with sfft.set_workers(cores):
+            apply._linear_conv_same(ker, m[0])
+    wkc, ckc = _median_wall(kern_all, runs)
+    wvc, cvc = _median_wall(conv_all, runs)
+    del ker
+    planes = 2 * n - 1
+    t1 = wk1 * planes / 7 + wv1 * 12
+    tc = wkc * planes / (7 * cores) + wvc * 12
+    out["exact_fft_128"] = {
+        "value": round(n ** 3 / tc / 1e6, 6), "unit": "Mcell-field evals/s", "seconds_per_apply": round(tc, 2),
+        "cores": max(1, round((ckc + cvc) / (wkc + wvc))),
+        "one_core": {"value": round(n ** 3 / t1 / 1e6, 6), "seconds_per_apply": round(t1, 2),
+                     "cores": max(1, round((ck1 + cv1) / (wk1 + wv1)))},
+        "sample": f"oracle exact collocation (closed-form kernels + FFT convolution, FP64): kernels of 7 of "
+                  f"{planes} offset planes ({wk1:.2f} s on one core, {wkc:.2f} s for {cores} threads' samples) "
+                  f"scaled x{planes / 7:.1f}, one of 12 convolutions ({wv1:.2f} s on one core, {wvc:.2f} s "
+                  f"with {cores} workers) scaled x12; median of {runs}"}
     # structured reference at n = 4096: one Toeplitz (type, node) times the
     # ten columns of one component, scaled to 3 axes x 3 components x 2
     # slots x 40 nodes
