@@ -219,17 +219,21 @@ def _cpu_baseline(m, n, runs):
     nodes of the rule (the apply is a sum over nodes).  One core: one node
     per run.  All cores: the oracle run unchanged on one node per core in a
     thread pool (its einsum loops release the interpreter lock).  Median of
-    `runs` runs each.  Beside it: the exact collocation (closed-form cell
-    kernels + FFT convolution) at 32^3 and, on samples, at 128^3 (one core
-    and all cores), and the structured reference (dense
-    Toeplitz products of the factor columns) at n = 4096 on one (node, type)
-    pair of CP rank 10 columns, scaled to the apply's 7200 products."""
+    `runs` runs each.  Beside it, each at one core and all cores: the exact
+    collocation (closed-form cell kernels + FFT convolution) at 32^3 and, on
+    samples, at 128^3; the Kronecker method at 32^3; the batch of 256 uneven
+    states on a sample of states; and the structured reference (dense
+    Toeplitz products of the factor columns) at n = 4096 for CP rank 10,
+    Tucker (8,8,8) and TT (1,8,8,1) inputs, on one component and node per
+    axis, scaled to the whole apply."""
     import os
     from concurrent.futures import ThreadPoolExecutor
 
     import numpy as np
+    from scipy import fft as sfft
+    from threadpoolctl import threadpool_limits
 
-    from oracle import apply, sinc, structured
+    from oracle import apply, exact, sinc, structured
     from paper_1212_3509_amd import inputs
     _t, tau, alpha = sinc.sinc_nodes(40)
     h = (1.0 / n,) * 3
@@ -253,9 +257,34 @@ def _cpu_baseline(m, n, runs):
                         "sample": f"one node, median of {runs}: {wall1:.2f} s, scaled x40"}}
     out["host"] = _host_info()
     m32 = inputs.random_unit_field(32, seed=0)
-    wall, cpu = _median_wall(lambda: apply.collocated_apply_fft(m32, (1.0 / 32,) * 3), runs)
+    h32 = (1.0 / 32,) * 3
+    wall, cpu = _median_wall(lambda: apply.collocated_apply_fft(m32, h32), runs)
+
+    def exact32_all():
+        with sfft.set_workers(cores):
+            apply.collocated_apply_fft(m32, h32)
+    wallc32, cpuc32 = _median_wall(exact32_all, runs)
     out["exact_fft_32"] = {"value": round(32 ** 3 / wall / 1e6, 6), "unit": "Mcell-field evals/s",
-                           "seconds": round(wall, 3), "cores": max(1, round(cpu / wall))}
+                           "seconds": round(wall, 3), "cores": max(1, round(cpu / wall)),
+                           "all_cores": {"value": round(32 ** 3 / wallc32 / 1e6, 6), "seconds": round(wallc32, 3),
+                                         "cores": max(1, round(cpuc32 / wallc32)),
+                                         "sample": f"the same with scipy.fft's workers = {cores}"}}
+    # the Kronecker method at 32^3, all 40 nodes: one core, and one node per
+    # thread in a pool of all cores
+    with threadpool_limits(1):
+        wk32, ck32 = _median_wall(lambda: apply.kron_apply_dense(m32, h32, tau, alpha), runs)
+
+    def kron32_all():
+        with ThreadPoolExecutor(cores) as ex:
+            list(ex.map(lambda k: apply.kron_apply_dense(m32, h32, tau[k:k + 1], alpha[k:k + 1]), range(40)))
+    wkc32, ckc32 = _median_wall(kron32_all, runs)
+    out["kron_32"] = {"value": round(32 ** 3 / wkc32 / 1e6, 6), "unit": "Mcell-field evals/s",
+                      "seconds": round(wkc32, 3), "cores": max(1, round(ckc32 / wkc32)),
+                      "one_core": {"value": round(32 ** 3 / wk32 / 1e6, 6), "seconds": round(wk32, 3),
+                                   "cores": max(1, round(ck32 / wk32))},
+                      "sample": f"oracle dense-Toeplitz Kronecker apply (FP64 NumPy) of a random unit field at "
+                                f"32^3, all 40 nodes (one core: BLAS limited to one thread; all cores: one node "
+                                f"per thread on {cores} threads), median of {runs}"}
     # exact collocation at 128^3: closed-form cell kernels on all 255^3
     # offsets, then 12 FFT convolutions of 255^3 kernels with 128^3 fields
     # (3 for phi, 9 for h).  Timed on samples scaled to the whole: the
@@ -263,9 +292,6 @@ def _cpu_baseline(m, n, runs):
     # cost per offset does not depend on it) and one of the convolutions.
     # All cores: one kernel sample per thread (its planes stand for 7 more),
     # the convolution with scipy.fft's workers.
-    from scipy import fft as sfft
-
-    from oracle import exact
     h128 = (1.0 / n,) * 3
     ker = np.random.default_rng(3).standard_normal((2 * n - 1,) * 3)
     wk1, ck1 = _median_wall(lambda: exact.offset_kernels((n, n, 4), h128), runs)
@@ -293,21 +319,68 @@ def _cpu_baseline(m, n, runs):
                   f"{planes} offset planes ({wk1:.2f} s on one core, {wkc:.2f} s for {cores} threads' samples) "
                   f"scaled x{planes / 7:.1f}, one of 12 convolutions ({wv1:.2f} s on one core, {wvc:.2f} s "
                   f"with {cores} workers) scaled x12; median of {runs}"}
-    # structured reference at n = 4096: one Toeplitz (type, node) times the
-    # ten columns of one component, scaled to 3 axes x 3 components x 2
-    # slots x 40 nodes
+    # structured reference at n = 4096: the oracle's columns of one axis,
+    # component and node (two dense Toeplitz products, FP64 BLAS) for the
+    # column counts of each format, scaled to 3 components x 40 nodes and
+    # summed over the axes (CP rank 10: 10 columns per axis; Tucker
+    # (8,8,8): 8; TT (1,8,8,1): 8, 64, 8); one core (BLAS limited to one
+    # thread) and all cores
     N4 = 4096
     F = sinc.scaled_factors(N4, 1.0 / N4, tau[:1], alpha[:1])
-    cols = np.random.default_rng(1).uniform(-1, 1, (N4, 10))
-    wall, cpu = _median_wall(lambda: structured._columns(F, 0, 0, cols, 1), runs)
-    per_apply = wall * 3 * 3 * 40
-    out["structured_4096_cp_r10"] = {"value": round(N4 ** 3 / per_apply / 1e12, 6),
-                                     "unit": "implicit Tcell/s", "seconds_per_apply": round(per_apply, 3),
-                                     "cores": max(1, round(cpu / wall)),
-                                     "sample": f"the oracle's columns of one axis, component and node (two dense "
-                                               f"4096 x 4096 Toeplitz products with 10 columns, FP64 BLAS), median "
-                                               f"of {runs}: {wall * 1e3:.1f} ms, scaled x360 (3 axes, 3 components, "
-                                               f"40 nodes)"}
+    rng4 = np.random.default_rng(1)
+    widths = {"cp_r10": (10, 10, 10), "tucker_888": (8, 8, 8), "tt_188_1": (8, 64, 8)}
+    cols = {w: rng4.uniform(-1, 1, (N4, w)) for w in (8, 10, 64)}
+    for name, ws in widths.items():
+        rec = {}
+        for label, limit in (("one_core", 1), ("all_cores", None)):
+            per_apply = 0.0
+            cpu_tot = wall_tot = 0.0
+            for w in ws:
+                with threadpool_limits(limit):
+                    wall, cpu = _median_wall(lambda w=w: structured._columns(F, 0, 0, cols[w], 1), runs)
+                per_apply += wall * 3 * 40
+                wall_tot += wall
+                cpu_tot += cpu
+            rec[label] = {"value": round(N4 ** 3 / per_apply / 1e12, 6), "unit": "implicit Tcell/s",
+                          "seconds_per_apply": round(per_apply, 3), "cores": max(1, round(cpu_tot / wall_tot))}
+        out[f"structured_4096_{name}"] = dict(rec["all_cores"], one_core=rec["one_core"],
+                                              sample=f"the oracle's columns of one component and node per axis "
+                                                     f"({'/'.join(str(w) for w in ws)} columns, two dense 4096 x "
+                                                     f"4096 Toeplitz products each, FP64 BLAS), median of {runs}, "
+                                                     f"scaled x120 (3 components, 40 nodes) and summed over the axes")
+    # the batch of 256 uneven states: the Kronecker method on a sample of
+    # states (one node each), scaled by the ratio of the mode-product work
+    # sum_s N_s (nx + ny + nz) of the whole batch to the sample's, and by 40
+    # nodes; one core, and the sample's (state, node) pairs on a pool of all
+    # cores
+    states = inputs.batch_grids(256, seed=2, with_fields=False)
+    work = lambda st: float(np.prod(st.n)) * sum(st.n)  # noqa: E731
+    pick = [0, 3, 15, 23]   # two cubes, films with 8 and 16 cells across
+    sample = [(states[i].n, states[i].h, inputs.random_unit_field(states[i].n, seed=states[i].seed)) for i in pick]
+    scale = sum(work(st) for st in states) / sum(work(states[i]) for i in pick) * 40
+    cells = sum(int(np.prod(st.n)) for st in states)
+
+    def batch_one():
+        for nn, hh, mm in sample:
+            apply.kron_apply_dense(mm, hh, tau[:1], alpha[:1])
+    with threadpool_limits(1):
+        wb1, cb1 = _median_wall(batch_one, runs)
+
+    def batch_all():
+        with ThreadPoolExecutor(cores) as ex:
+            list(ex.map(lambda t: apply.kron_apply_dense(sample[t[0]][2], sample[t[0]][1], tau[t[1]:t[1] + 1],
+                                                         alpha[t[1]:t[1] + 1]),
+                        [(i, k) for i in range(len(sample)) for k in range(cores // len(sample) or 1)]))
+    wbc, cbc = _median_wall(batch_all, runs)
+    per_node_all = wbc / (cores // len(sample) or 1)
+    out["batch_256"] = {"value": round(cells / (per_node_all * scale) / 1e6, 6), "unit": "Mcell-field evals/s",
+                        "seconds_per_batch": round(per_node_all * scale, 1), "cores": max(1, round(cbc / wbc)),
+                        "one_core": {"value": round(cells / (wb1 * scale) / 1e6, 6),
+                                     "seconds_per_batch": round(wb1 * scale, 1), "cores": max(1, round(cb1 / wb1))},
+                        "sample": f"oracle dense-Toeplitz Kronecker apply (FP64 NumPy) of states {pick} (grids "
+                                  f"{[states[i].n for i in pick]}), one node each, median of {runs}, scaled "
+                                  f"x{scale:.0f} by the mode-product work of the 256 states and the 40 nodes; all "
+                                  f"cores: {cores // len(sample) or 1} nodes per sampled state on {cores} threads"}
     return out
 
 
