@@ -117,6 +117,11 @@ __global__ void k_convert(const double *__restrict__ src, float *__restrict__ f3
   bf[2 * count + i] = l2;
 }
 
+__global__ void k_to_float(const double *__restrict__ src, float *__restrict__ dst, size_t count) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < count) dst[i] = float(src[i]);
+}
+
 }  // namespace
 
 size_t axis_table_len(const demag_factors *f, int d) {
@@ -161,6 +166,11 @@ demag_status launch_assemble_dense(demag_ctx *ctx, demag_factors *f, const std::
     dim3 grid(unsigned((size_t(n) * n + 255) / 256), unsigned(f->M));
     k_assemble_dense<<<grid, 256, 0, ctx->stream>>>(f->f64[d], d_edges + off, n, f->M, d_tau, d_w);
     DEMAG_TRY_HIP(hipGetLastError());
+    if (f->f32[d]) {   // FP32 copy for the FP32 apply
+      const size_t cnt = axis_table_len(f, d);
+      k_to_float<<<unsigned((cnt + 255) / 256), 256, 0, ctx->stream>>>(f->f64[d], f->f32[d], cnt);
+      DEMAG_TRY_HIP(hipGetLastError());
+    }
     off += edges[d].size();
   }
   // the host vectors are copied before these frees run (stream order); the

@@ -194,7 +194,8 @@ demag_status launch_reset_counters(demag_ctx *ctx, int *counters, int count);
 demag_status launch_build_windows(demag_ctx *ctx, demag_factors *f);
 // non-uniform grids: dense factors from the scaled cell edges (host, n_d + 1 per axis)
 demag_status launch_assemble_dense(demag_ctx *ctx, demag_factors *f, const std::vector<double> edges[3]);
-demag_status launch_dense_stage(hipStream_t s, const StagePlan &sp, const double *mats, const Bufs &bufs, int beta);
+template <class T>
+demag_status launch_dense_stage(hipStream_t s, const StagePlan &sp, const T *mats, const Bufs &bufs, int beta);
 // Outputs from the x stage's partial sums (FP64 for DEMAG_FP64, else FP32):
 // phi = phi_scale sum_s partials[4 s], h_p = sum_s partials[4 s + 1 + p]
 // (element blocks of N), added in FP64, added to the outputs when

@@ -625,8 +625,11 @@ demag_status launch_left_stage(demag_ctx *ctx, const demag_factors *f, demag_pre
   const char *pname = "?";
   size_t esize = 4;
   const int rb = ctx->tile_rows > 0 ? ctx->tile_rows : stage_rows(sp, prec);
-  if (f->dense) {
-    st = launch_dense_stage(ctx->stream, sp, f->f64[sp.axis], bufs, beta);
+  if (f->dense && prec == DEMAG_FP32) {
+    st = launch_dense_stage<float>(ctx->stream, sp, f->f32[sp.axis], bufs, beta);
+    pname = "dense32";
+  } else if (f->dense) {
+    st = launch_dense_stage<double>(ctx->stream, sp, f->f64[sp.axis], bufs, beta);
     pname = "dense64";
     esize = 8;
   } else if (prec == DEMAG_FP64) {

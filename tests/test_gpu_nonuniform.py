@@ -1,5 +1,8 @@
 """GPU parity of the full-format apply on non-uniform tensor-product grids
-(dense FP64 factors and mode products) with the oracle."""
+(dense factors, FP64 and FP32 mode products) with the oracle.  FP32: the
+dense tables rounded once from FP64, FP32 products with FP32 accumulation
+and the x stage's node sums as four partial sums added in FP64, within 1e-6
+relative L2 of the FP64 result, the bar of the uniform-grid FP32 apply."""
 import numpy as np
 import pytest
 import torch
@@ -58,6 +61,24 @@ def test_graded_grid_matches_oracle(ctx):
     assert apply.rel_l2(hf.cpu().numpy(), href) < 1e-12
 
 
+def test_graded_grid_fp32_matches_oracle(ctx):
+    edges = [_graded(37, 1.03, 1.2), _graded(29, 0.97, 0.9), _graded(21, 1.08, 0.7)]
+    n = tuple(len(e) - 1 for e in edges)
+    m = inputs.random_unit_field(n, seed=8)
+    f = ctx.assemble_grid(edges, M=20, step_rule=1)
+    L = max(e[-1] - e[0] for e in edges)
+    scaled = [(e - e[0]) / L for e in edges]
+    _t, tau, alpha = f.nodes()
+    phi, hf = ctx.apply_full(f, _dev(m).float(), prec="fp32")
+    torch.cuda.synchronize()
+    assert phi.dtype == torch.float32 and hf.dtype == torch.float32
+    pref, href = nu.kron_apply(m, scaled, tau, alpha)
+    e_phi = apply.rel_l2(phi.double().cpu().numpy(), L * pref)
+    e_h = apply.rel_l2(hf.double().cpu().numpy(), href)
+    print(f"graded grid FP32: phi {e_phi:.2e}, h {e_h:.2e}")
+    assert e_phi < 1e-6 and e_h < 1e-6
+
+
 def test_graded_grid_approximates_exact_collocation(ctx):
     """The theorem-step rule with 60 nodes against the closed-form box
     kernels summed directly (physical units)."""
@@ -76,7 +97,7 @@ def test_dense_factors_are_rejected_elsewhere(ctx):
     f = ctx.assemble_grid(edges, M=4)
     m64 = torch.zeros((3, 8, 8, 8), dtype=torch.float64, device="cuda")
     with pytest.raises(api.DemagError):
-        ctx.apply_full(f, m64.float(), prec="fp32")
+        ctx.apply_full(f, m64.float(), prec="bf16x3")
     with pytest.raises(api.DemagError):
         ctx.apply_fft(f, m64)
     with pytest.raises(api.DemagError):
@@ -110,3 +131,25 @@ def test_benchmark_grid_sampled():
     gh = np.array([hh[:, c[0], c[1], c[2]] for c in cells])
     assert apply.rel_l2(gp, rp) < 1e-12, apply.rel_l2(gp, rp)
     assert apply.rel_l2(gh, rh) < 1e-12, apply.rel_l2(gh, rh)
+
+
+def test_benchmark_grid_fp32():
+    """The benchmarked graded 128^3 grid in FP32 against the FP64 apply on
+    the GPU (pinned to the oracle by test_benchmark_grid_sampled): every
+    cell, within 1e-6 relative L2."""
+    ctx = api.Context(0)
+    n = 128
+    edges = []
+    for r in (1.01, 0.99, 1.005):
+        w = r ** np.arange(n)
+        e = np.concatenate([[0.0], np.cumsum(w)])
+        edges.append(e / e[-1] - 0.5)
+    f = ctx.assemble_grid(edges, M=40, c0=2.15)
+    m = _dev(inputs.vortex_field(n, seed=0))
+    p64, h64 = ctx.apply_full(f, m, prec="fp64")
+    p32, h32 = ctx.apply_full(f, m.float(), prec="fp32")
+    torch.cuda.synchronize()
+    rel = lambda a, b: float(torch.linalg.norm((a.double() - b).reshape(-1)) / torch.linalg.norm(b.reshape(-1)))  # noqa: E731
+    e_phi, e_h = rel(p32, p64), rel(h32, h64)
+    print(f"graded 128^3 FP32 vs FP64: phi {e_phi:.2e}, h {e_h:.2e}")
+    assert e_phi < 1e-6 and e_h < 1e-6
