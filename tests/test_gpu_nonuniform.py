@@ -153,3 +153,24 @@ def test_benchmark_grid_fp32():
     e_phi, e_h = rel(p32, p64), rel(h32, h64)
     print(f"graded 128^3 FP32 vs FP64: phi {e_phi:.2e}, h {e_h:.2e}")
     assert e_phi < 1e-6 and e_h < 1e-6
+
+
+@pytest.mark.parametrize("n", [(1, 5, 3), (17, 1, 33), (2, 70, 1)])
+def test_degenerate_axes_fp32_and_fp64(ctx, n):
+    """Non-uniform grids with single-cell axes and ragged lengths (tiles
+    mostly padding): FP64 within 1e-12 and FP32 within 1e-6 of the oracle."""
+    rng = np.random.default_rng(sum(n))
+    edges = [np.concatenate([[0.0], np.cumsum(rng.uniform(0.5, 1.5, k))]) / 40.0 for k in n]
+    m = inputs.random_unit_field(n, seed=11)
+    f = ctx.assemble_grid(edges, M=10, step_rule=1)
+    L = max(e[-1] - e[0] for e in edges)
+    scaled = [(e - e[0]) / L for e in edges]
+    _t, tau, alpha = f.nodes()
+    pref, href = nu.kron_apply(m, scaled, tau, alpha)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
+        md = _dev(m) if prec == "fp64" else _dev(m).float()
+        phi, hf = ctx.apply_full(f, md, prec=prec)
+        torch.cuda.synchronize()
+        e_phi = apply.rel_l2(phi.double().cpu().numpy(), L * pref)
+        e_h = apply.rel_l2(hf.double().cpu().numpy(), href)
+        assert e_phi < tol and e_h < tol, (prec, e_phi, e_h)
