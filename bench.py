@@ -545,16 +545,19 @@ def headline(args):
         nonuni = {"value": round(N / (ms * 1e-3) / 1e6, 3), "ms_per_step": round(ms, 4), "dtype": "f64",
                   "grid": "128^3 graded cells (width ratios 1.01, 0.99, 1.005 per cell), M=40",
                   "roofline": _roofline(prof, "fp64"), "kernels": _kernels(prof, max(2, args.steps // 2))}
-        # the same in FP32 (dense tables rounded once from FP64), against the FP64 result
+        # the same in FP32 (dense tables rounded once from FP64) and BF16x3
+        # (tables split into three bfloat16 parts), against the FP64 result
         m32 = m.float()
         phi32 = torch.empty((n, n, n), dtype=torch.float32, device="cuda")
         h32 = torch.empty((3, n, n, n), dtype=torch.float32, device="cuda")
-        ms32, prof32 = _timed(ctx, lambda: ctx.apply_full(fn, m32, phi32, h32, prec="fp32"),
-                              max(2, args.steps // 2), 1)
         rel = lambda a, b: float(torch.linalg.norm((a.double() - b).reshape(-1)) / torch.linalg.norm(b.reshape(-1)))  # noqa: E731
-        nonuni["fp32"] = {"value": round(N / (ms32 * 1e-3) / 1e6, 3), "ms_per_step": round(ms32, 4), "dtype": "f32",
-                          "rel_l2_vs_fp64": {"phi": rel(phi32, phi), "h": rel(h32, h)},
-                          "roofline": _roofline(prof32, "fp32"), "kernels": _kernels(prof32, max(2, args.steps // 2))}
+        for prec in ("fp32", "bf16x3"):
+            ms32, prof32 = _timed(ctx, lambda: ctx.apply_full(fn, m32, phi32, h32, prec=prec),
+                                  max(2, args.steps // 2), 1)
+            nonuni[prec] = {"value": round(N / (ms32 * 1e-3) / 1e6, 3), "ms_per_step": round(ms32, 4),
+                            "dtype": "f32" if prec == "fp32" else prec,
+                            "rel_l2_vs_fp64": {"phi": rel(phi32, phi), "h": rel(h32, h)},
+                            "roofline": _roofline(prof32, prec), "kernels": _kernels(prof32, max(2, args.steps // 2))}
         del m, phi, h, fn, m32, phi32, h32
         torch.cuda.empty_cache()
         _progress("non-uniform grid timed")

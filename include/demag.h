@@ -141,11 +141,12 @@ demag_status demag_assemble_factors(demag_ctx *ctx, const demag_grid *grid,
  * longest extent is 1 (the potential is scaled back); the theorem-step rule
  * uses the smallest scaled cell.  Factors are dense n x n matrices per type
  * and node, entry (i, j) integrating over source cell j seen from the centre
- * of cell i: E, X, P = -X', Q = 2 tau^2 X as for uniform grids, in FP64
- * and as an FP32 copy rounded once from them.  Such factors serve
- * demag_apply_full with DEMAG_FP64 or DEMAG_FP32 (dense mode products on the
- * matrix cores in that precision; the bfloat16 splits give DEMAG_E_INVAL);
- * the FFT, structured and batched paths need uniform grids and reject them.
+ * of cell i: E, X, P = -X', Q = 2 tau^2 X as for uniform grids, in FP64,
+ * as an FP32 copy rounded once from them and as three bfloat16 parts of
+ * that copy.  Such factors serve demag_apply_full in every precision (dense
+ * mode products on the matrix cores: FP64, FP32, or split bfloat16 products
+ * accumulated in FP32); the FFT, structured and batched paths need uniform
+ * grids and reject them.
  * demag_factors_download returns [4][M][n][n]. */
 demag_status demag_assemble_factors_grid(demag_ctx *ctx, const int32_t n[3], const double *const edges[3],
                                          const demag_quad *quad, demag_factors **out);

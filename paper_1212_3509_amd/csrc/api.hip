@@ -718,7 +718,8 @@ demag_status demag_assemble_factors_grid(demag_ctx *ctx, const int32_t n[3], con
   for (int d = 0; d < 3; ++d) {
     const size_t cnt = size_t(F_NTYPES) * f->M * size_t(n[d]) * n[d];
     if (hipMalloc(&f->f64[d], cnt * sizeof(double)) != hipSuccess ||
-        hipMalloc(&f->f32[d], cnt * sizeof(float)) != hipSuccess) {
+        hipMalloc(&f->f32[d], cnt * sizeof(float)) != hipSuccess ||
+        hipMalloc(&f->bf[d], 3 * cnt * sizeof(uint16_t)) != hipSuccess) {
       set_error("dense factor tables: device allocation failed");
       demag_factors_free(f.release());
       return DEMAG_E_NOMEM;
@@ -798,8 +799,6 @@ demag_status apply_full_impl(demag_ctx *ctx, const demag_factors *fc, demag_prec
                 std::string(where) + ": unknown precision");
   DEMAG_REQUIRE(aligned16(m) && aligned16(phi) && aligned16(h) && aligned16(ws_user),
                 std::string(where) + ": buffers must be 16-byte aligned");
-  DEMAG_REQUIRE(!fc->dense || prec == DEMAG_FP64 || prec == DEMAG_FP32,
-                std::string(where) + ": non-uniform grids are applied in FP64 or FP32");
   for (int d = 0; d < 3; ++d)
     DEMAG_REQUIRE(fc->n[d] <= 1024, std::string(where) + ": full format supports n <= 1024 per axis");
   auto *f = const_cast<demag_factors *>(fc);

@@ -166,10 +166,14 @@ demag_status launch_assemble_dense(demag_ctx *ctx, demag_factors *f, const std::
     dim3 grid(unsigned((size_t(n) * n + 255) / 256), unsigned(f->M));
     k_assemble_dense<<<grid, 256, 0, ctx->stream>>>(f->f64[d], d_edges + off, n, f->M, d_tau, d_w);
     DEMAG_TRY_HIP(hipGetLastError());
-    if (f->f32[d]) {   // FP32 copy for the FP32 apply
+    if (f->f32[d]) {   // FP32 copy for the FP32 apply, its bfloat16 parts for the split ones
       const size_t cnt = axis_table_len(f, d);
       k_to_float<<<unsigned((cnt + 255) / 256), 256, 0, ctx->stream>>>(f->f64[d], f->f32[d], cnt);
       DEMAG_TRY_HIP(hipGetLastError());
+      if (f->bf[d]) {
+        const demag_status st = launch_split(ctx, f->f32[d], f->bf[d], cnt, 3);
+        if (st != DEMAG_OK) return st;
+      }
     }
     off += edges[d].size();
   }

@@ -205,6 +205,10 @@ demag_status launch_reduce_partials(demag_ctx *ctx, demag_prec prec, const void 
 demag_status launch_left_stage_bf16(demag_ctx *ctx, const demag_factors *f, demag_prec prec,
                                     const StagePlan &sp, void *const bufs[6], int beta);
 demag_status launch_split(demag_ctx *ctx, const float *x, uint16_t *parts, size_t count, int nparts);
+// Dense-factor stage (non-uniform grids) with bfloat16-split products: parts
+// = [3][table] bfloat16 bits of the axis' dense tables, part_stride elements apart.
+demag_status launch_dense_stage_bf16(hipStream_t s, const StagePlan &sp, demag_prec prec, const uint16_t *parts,
+                                     size_t part_stride, void *const bufp[6], int beta);
 int fft_length(int n);
 demag_status prepare_spectra(demag_ctx *ctx, demag_factors *f);
 demag_status ensure_workspace(demag_ctx *ctx, size_t bytes);

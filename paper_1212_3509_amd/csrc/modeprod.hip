@@ -625,7 +625,10 @@ demag_status launch_left_stage(demag_ctx *ctx, const demag_factors *f, demag_pre
   const char *pname = "?";
   size_t esize = 4;
   const int rb = ctx->tile_rows > 0 ? ctx->tile_rows : stage_rows(sp, prec);
-  if (f->dense && prec == DEMAG_FP32) {
+  if (f->dense && (prec == DEMAG_BF16X2 || prec == DEMAG_BF16X3)) {
+    st = launch_dense_stage_bf16(ctx->stream, sp, prec, f->bf[sp.axis], axis_table_len(f, sp.axis), bufp, beta);
+    pname = (prec == DEMAG_BF16X3) ? "dense_bf16x3" : "dense_bf16x2";
+  } else if (f->dense && prec == DEMAG_FP32) {
     st = launch_dense_stage<float>(ctx->stream, sp, f->f32[sp.axis], bufs, beta);
     pname = "dense32";
   } else if (f->dense) {

@@ -1,8 +1,11 @@
 """GPU parity of the full-format apply on non-uniform tensor-product grids
-(dense factors, FP64 and FP32 mode products) with the oracle.  FP32: the
-dense tables rounded once from FP64, FP32 products with FP32 accumulation
-and the x stage's node sums as four partial sums added in FP64, within 1e-6
-relative L2 of the FP64 result, the bar of the uniform-grid FP32 apply."""
+(dense factors; FP64, FP32 and bfloat16-split mode products) with the
+oracle.  FP32: the dense tables rounded once from FP64, FP32 products with
+FP32 accumulation and the x stage's node sums as four partial sums added in
+FP64, within 1e-6 relative L2 of the FP64 result, the bar of the
+uniform-grid FP32 apply; BF16x3 (tables and inputs split into three
+bfloat16 parts, six products) within the same 1e-6, BF16x2 within 3e-5, the
+bars of the uniform-grid split applies."""
 import numpy as np
 import pytest
 import torch
@@ -79,6 +82,24 @@ def test_graded_grid_fp32_matches_oracle(ctx):
     assert e_phi < 1e-6 and e_h < 1e-6
 
 
+@pytest.mark.parametrize("prec,tol", [("bf16x3", 1e-6), ("bf16x2", 3e-5)])
+def test_graded_grid_bf16_matches_oracle(ctx, prec, tol):
+    edges = [_graded(37, 1.03, 1.2), _graded(29, 0.97, 0.9), _graded(21, 1.08, 0.7)]
+    n = tuple(len(e) - 1 for e in edges)
+    m = inputs.random_unit_field(n, seed=8)
+    f = ctx.assemble_grid(edges, M=20, step_rule=1)
+    L = max(e[-1] - e[0] for e in edges)
+    scaled = [(e - e[0]) / L for e in edges]
+    _t, tau, alpha = f.nodes()
+    phi, hf = ctx.apply_full(f, _dev(m).float(), prec=prec)
+    torch.cuda.synchronize()
+    pref, href = nu.kron_apply(m, scaled, tau, alpha)
+    e_phi = apply.rel_l2(phi.double().cpu().numpy(), L * pref)
+    e_h = apply.rel_l2(hf.double().cpu().numpy(), href)
+    print(f"graded grid {prec}: phi {e_phi:.2e}, h {e_h:.2e}")
+    assert e_phi < tol and e_h < tol
+
+
 def test_graded_grid_approximates_exact_collocation(ctx):
     """The theorem-step rule with 60 nodes against the closed-form box
     kernels summed directly (physical units)."""
@@ -96,8 +117,6 @@ def test_dense_factors_are_rejected_elsewhere(ctx):
     edges = [_graded(8, 1.1) for _ in range(3)]
     f = ctx.assemble_grid(edges, M=4)
     m64 = torch.zeros((3, 8, 8, 8), dtype=torch.float64, device="cuda")
-    with pytest.raises(api.DemagError):
-        ctx.apply_full(f, m64.float(), prec="bf16x3")
     with pytest.raises(api.DemagError):
         ctx.apply_fft(f, m64)
     with pytest.raises(api.DemagError):
@@ -134,9 +153,9 @@ def test_benchmark_grid_sampled():
 
 
 def test_benchmark_grid_fp32():
-    """The benchmarked graded 128^3 grid in FP32 against the FP64 apply on
-    the GPU (pinned to the oracle by test_benchmark_grid_sampled): every
-    cell, within 1e-6 relative L2."""
+    """The benchmarked graded 128^3 grid in FP32 and BF16x3 against the FP64
+    apply on the GPU (pinned to the oracle by test_benchmark_grid_sampled):
+    every cell, within 1e-6 relative L2."""
     ctx = api.Context(0)
     n = 128
     edges = []
@@ -147,18 +166,20 @@ def test_benchmark_grid_fp32():
     f = ctx.assemble_grid(edges, M=40, c0=2.15)
     m = _dev(inputs.vortex_field(n, seed=0))
     p64, h64 = ctx.apply_full(f, m, prec="fp64")
-    p32, h32 = ctx.apply_full(f, m.float(), prec="fp32")
-    torch.cuda.synchronize()
     rel = lambda a, b: float(torch.linalg.norm((a.double() - b).reshape(-1)) / torch.linalg.norm(b.reshape(-1)))  # noqa: E731
-    e_phi, e_h = rel(p32, p64), rel(h32, h64)
-    print(f"graded 128^3 FP32 vs FP64: phi {e_phi:.2e}, h {e_h:.2e}")
-    assert e_phi < 1e-6 and e_h < 1e-6
+    for prec in ("fp32", "bf16x3"):
+        p32, h32 = ctx.apply_full(f, m.float(), prec=prec)
+        torch.cuda.synchronize()
+        e_phi, e_h = rel(p32, p64), rel(h32, h64)
+        print(f"graded 128^3 {prec} vs FP64: phi {e_phi:.2e}, h {e_h:.2e}")
+        assert e_phi < 1e-6 and e_h < 1e-6, prec
 
 
 @pytest.mark.parametrize("n", [(1, 5, 3), (17, 1, 33), (2, 70, 1)])
 def test_degenerate_axes_fp32_and_fp64(ctx, n):
     """Non-uniform grids with single-cell axes and ragged lengths (tiles
-    mostly padding): FP64 within 1e-12 and FP32 within 1e-6 of the oracle."""
+    mostly padding): FP64 within 1e-12, FP32 and BF16x3 within 1e-6 of the
+    oracle."""
     rng = np.random.default_rng(sum(n))
     edges = [np.concatenate([[0.0], np.cumsum(rng.uniform(0.5, 1.5, k))]) / 40.0 for k in n]
     m = inputs.random_unit_field(n, seed=11)
@@ -167,7 +188,7 @@ def test_degenerate_axes_fp32_and_fp64(ctx, n):
     scaled = [(e - e[0]) / L for e in edges]
     _t, tau, alpha = f.nodes()
     pref, href = nu.kron_apply(m, scaled, tau, alpha)
-    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-6), ("bf16x3", 1e-6)):
         md = _dev(m) if prec == "fp64" else _dev(m).float()
         phi, hf = ctx.apply_full(f, md, prec=prec)
         torch.cuda.synchronize()
