@@ -375,19 +375,20 @@ demag_status launch_bf_n(hipStream_t s, int rb, int cb, const StagePlan &sp, con
 // sum_j A[i][j] in[j][c] with the n x n matrices A split at assembly into
 // PARTS bfloat16 parts ([part][type * M + k][n][n]) and the inputs split in
 // registers, the products formed from the parts as above.  Tile: 64 rows
-// (4 blocks of 16) x 64 columns (4 waves of 16), K chunks of 32 (one
-// 16x16x32 step): per chunk the A tiles of the NOUT outputs (64 x 32 per
-// part, a 16-byte row segment per thread) and the FP32 input tile (32 x 64)
+// (4 blocks of 16) x 64 CB columns (4 waves of CB blocks of 16), K chunks of
+// 32 (one 16x16x32 step): per chunk the A tiles of the NOUT outputs (64 x 32
+// per part, a 16-byte row segment per thread) and the FP32 input tile (32 x 64 CB)
 // go through LDS; the next chunk's are loaded into registers while the
 // current one is multiplied.  A lane's fragment of a row block is one
 // 16-byte LDS read per part (rows padded to 40 values); its input fragment is
 // eight values down one column of the input tile, split into parts.
-template <int NOUT, int PARTS, bool TRANS>
+template <int NOUT, int PARTS, bool TRANS, int CB>
 __global__ __launch_bounds__(256, 2) void k_dense_bf16(const MPJob *__restrict__ jobs,
                                                        const MPTerm *__restrict__ terms, Bufs bufs,
                                                        const uint16_t *__restrict__ parts, size_t part_stride,
                                                        MPGeom g, int col_tiles, int beta) {
-  constexpr int KC = 32, AS = 40, BS = 64 + 4;
+  constexpr int KC = 32, AS = 40, NC = 64 * CB, BS = NC + 4;
+  constexpr int kBr = KC * NC / 256;   // input tile values per thread
   __shared__ uint4 As[NOUT][PARTS][64][AS / 8];
   __shared__ float Bs[KC][BS];
   const MPJob job = jobs[blockIdx.y];
@@ -398,27 +399,30 @@ __global__ __launch_bounds__(256, 2) void k_dense_bf16(const MPJob *__restrict__
   const int row0 = rg * 64;
   // A staging: thread -> (row t / 4, 8 K values at (t % 4) * 8)
   const int ar = tid >> 2, ak = (tid & 3) * 8;
-  // input staging: thread -> (column t % 64, rows t / 64 + 4 q, q < 8)
-  const int bc = tid & 63, bk = tid >> 6;
-  const int cs = ct * 64 + bc;
+  // input staging: thread -> (column t % NC, rows t / NC + (256 / NC) q)
+  constexpr int kBrows = 256 / NC;
+  const int bc = tid % NC, bk = tid / NC;
+  const int cs = ct * NC + bc;
   const int cl = cs < g.C ? cs : g.C - 1;
   const size_t cin = size_t(cl / g.C1) * g.in_S1 + size_t(cl % g.C1);
-  f4 acc[NOUT][4];
+  f4 acc[NOUT][4][CB];
 #pragma unroll
   for (int o = 0; o < NOUT; ++o)
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb) acc[o][rb] = f4{0, 0, 0, 0};
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) acc[o][rb][cb] = f4{0, 0, 0, 0};
   const int nch = (n + KC - 1) / KC;
   const int nq = job.nterms * nch;
   uint4 av[NOUT][PARTS];
-  float bv[8];
+  float bv[kBr];
   auto load = [&](int q) {
     const int t = q / nch, j0 = (q - t * nch) * KC;
     const MPTerm &tm = terms[job.term0 + t];
     const float *in = static_cast<const float *>(bufs.p[tm.in_buf]) + tm.in_off + cin;
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int j = j0 + bk + 4 * r;
+    for (int r = 0; r < kBr; ++r) {
+      const int j = j0 + bk + kBrows * r;
       bv[r] = j < n ? in[size_t(j) * g.kstride] : 0.0f;
     }
     const int i = row0 + ar, j = j0 + ak;
@@ -439,21 +443,24 @@ __global__ __launch_bounds__(256, 2) void k_dense_bf16(const MPJob *__restrict__
       }
   };
   load(0);
-  const int wc = wave * 16 + (lane & 15);   // this lane's column in the tile
   for (int q = 0; q < nq; ++q) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r) Bs[bk + 4 * r][bc] = bv[r];
+    for (int r = 0; r < kBr; ++r) Bs[bk + kBrows * r][bc] = bv[r];
 #pragma unroll
     for (int o = 0; o < NOUT; ++o)
 #pragma unroll
       for (int p = 0; p < PARTS; ++p) As[o][p][ar][ak / 8] = av[o][p];
     __syncthreads();
     if (q + 1 < nq) load(q + 1);
-    // input fragment: rows 8 kq .. 8 kq + 7 of this lane's column, split
-    Frag bh, bl, bl2;
+    // input fragments: rows 8 kq .. 8 kq + 7 of this lane's columns, split
+    Frag bh[CB], bl[CB], bl2[CB];
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-      split_pair(Bs[8 * kq + 2 * e][wc], Bs[8 * kq + 2 * e + 1][wc], bh.p[e], bl.p[e], bl2.p[e]);
+    for (int cb = 0; cb < CB; ++cb) {
+      const int wc = wave * 16 * CB + 16 * cb + (lane & 15);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        split_pair(Bs[8 * kq + 2 * e][wc], Bs[8 * kq + 2 * e + 1][wc], bh[cb].p[e], bl[cb].p[e], bl2[cb].p[e]);
+    }
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
@@ -462,16 +469,19 @@ __global__ __launch_bounds__(256, 2) void k_dense_bf16(const MPJob *__restrict__
         ah.u = As[o][0][16 * rb + (lane & 15)][kq];
         if (PARTS > 1) al.u = As[o][1][16 * rb + (lane & 15)][kq];
         if (PARTS > 2) al2.u = As[o][2][16 * rb + (lane & 15)][kq];
-        f4 a = acc[o][rb];
-        a = mma<TRANS>(ah.v, bh.v, a);
-        a = mma<TRANS>(ah.v, bl.v, a);
-        a = mma<TRANS>(al.v, bh.v, a);
-        if (PARTS == 3) {
-          a = mma<TRANS>(ah.v, bl2.v, a);
-          a = mma<TRANS>(al2.v, bh.v, a);
-          a = mma<TRANS>(al.v, bl.v, a);
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          f4 a = acc[o][rb][cb];
+          a = mma<TRANS>(ah.v, bh[cb].v, a);
+          a = mma<TRANS>(ah.v, bl[cb].v, a);
+          a = mma<TRANS>(al.v, bh[cb].v, a);
+          if (PARTS == 3) {
+            a = mma<TRANS>(ah.v, bl2[cb].v, a);
+            a = mma<TRANS>(al2.v, bh[cb].v, a);
+            a = mma<TRANS>(al.v, bl[cb].v, a);
+          }
+          acc[o][rb][cb] = a;
         }
-        acc[o][rb] = a;
       }
     __syncthreads();
   }
@@ -482,20 +492,22 @@ __global__ __launch_bounds__(256, 2) void k_dense_bf16(const MPJob *__restrict__
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        // register r of lane l: block element (4 (l >> 4) + r, l % 16); with
-        // swapped operands row and column trade places
-        const int bi = TRANS ? (lane & 15) : 4 * kq + r;
-        const int bj = TRANS ? 4 * kq + r : (lane & 15);
-        const int i = row0 + 16 * rb + bi;
-        const int c = ct * 64 + wave * 16 + bj;
-        if (i < n && c < g.C) {
-          float *dst = out + size_t(c / g.C1) * g.out_S1 + size_t(c % g.C1) * g.out_cs + size_t(i) * g.out_is;
-          float v = scale * acc[o][rb][r];
-          if (beta) v += *dst;
-          *dst = v;
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          // register r of lane l: block element (4 (l >> 4) + r, l % 16); with
+          // swapped operands row and column trade places
+          const int bi = TRANS ? (lane & 15) : 4 * kq + r;
+          const int bj = TRANS ? 4 * kq + r : (lane & 15);
+          const int i = row0 + 16 * rb + bi;
+          const int c = ct * NC + wave * 16 * CB + 16 * cb + bj;
+          if (i < n && c < g.C) {
+            float *dst = out + size_t(c / g.C1) * g.out_S1 + size_t(c % g.C1) * g.out_cs + size_t(i) * g.out_is;
+            float v = scale * acc[o][rb][cb][r];
+            if (beta) v += *dst;
+            *dst = v;
+          }
         }
-      }
   }
 }
 
@@ -574,13 +586,15 @@ demag_status launch_dense_stage_bf16(hipStream_t s, const StagePlan &sp, demag_p
   Bufs bufs;
   for (int i = 0; i < 6; ++i) bufs.p[i] = bufp[i];
   const MPGeom &g = sp.geom;
-  const int col_tiles = (g.C + 63) / 64;
+  constexpr int kCB = 2;   // 16-column blocks per wave (each A fragment read feeds kCB product sets)
+  const int col_tiles = (g.C + 64 * kCB - 1) / (64 * kCB);
   const int row_groups = (g.n + 63) / 64;
   dim3 grid(unsigned(col_tiles * row_groups), unsigned(sp.jobs.size()));
   const bool tr = g.out_is == 1;   // rows contiguous in the output (x and y stages)
   const bool p3 = prec == DEMAG_BF16X3;
 #define DEMAG_DENSE_BF(NO, PA, TR) \
-  k_dense_bf16<NO, PA, TR><<<grid, 256, 0, s>>>(sp.d_jobs, sp.d_terms, bufs, parts, part_stride, g, col_tiles, beta)
+  k_dense_bf16<NO, PA, TR, kCB><<<grid, 256, 0, s>>>(sp.d_jobs, sp.d_terms, bufs, parts, part_stride, g, col_tiles, \
+                                                     beta)
   if (sp.nout == 2) {
     if (p3) { if (tr) DEMAG_DENSE_BF(2, 3, true); else DEMAG_DENSE_BF(2, 3, false); }
     else { if (tr) DEMAG_DENSE_BF(2, 2, true); else DEMAG_DENSE_BF(2, 2, false); }
