@@ -195,3 +195,26 @@ def test_degenerate_axes_fp32_and_fp64(ctx, n):
         e_phi = apply.rel_l2(phi.double().cpu().numpy(), L * pref)
         e_h = apply.rel_l2(hf.double().cpu().numpy(), href)
         assert e_phi < tol and e_h < tol, (prec, e_phi, e_h)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-6), ("bf16x3", 1e-6), ("bf16x2", 3e-5)])
+def test_graded_grid_several_row_tiles(ctx, prec, tol):
+    """Axes of 72, 40 and 24 cells: two 64-row tiles on x, K chunks that end
+    inside the axis, and lengths that are multiples of 8 but not of 32, so
+    the dense kernels mix their vector and masked table loads; each
+    precision against the oracle at its bar."""
+    edges = [_graded(72, 1.01, 1.0), _graded(40, 0.985, 0.6), _graded(24, 1.04, 0.45)]
+    n = tuple(len(e) - 1 for e in edges)
+    m = inputs.random_unit_field(n, seed=21)
+    f = ctx.assemble_grid(edges, M=12, step_rule=1)
+    L = max(e[-1] - e[0] for e in edges)
+    scaled = [(e - e[0]) / L for e in edges]
+    _t, tau, alpha = f.nodes()
+    md = _dev(m) if prec == "fp64" else _dev(m).float()
+    phi, hf = ctx.apply_full(f, md, prec=prec)
+    torch.cuda.synchronize()
+    pref, href = nu.kron_apply(m, scaled, tau, alpha)
+    e_phi = apply.rel_l2(phi.double().cpu().numpy(), L * pref)
+    e_h = apply.rel_l2(hf.double().cpu().numpy(), href)
+    print(f"graded 72x40x24 {prec}: phi {e_phi:.2e}, h {e_h:.2e}")
+    assert e_phi < tol and e_h < tol
