@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import apply, sinc
+from oracle import apply, exact, sinc
 from paper_1212_3509_amd import api, inputs
 
 pytestmark = pytest.mark.gpu
@@ -177,6 +177,48 @@ def test_uneven_batch_recipe_sampled(ctx):
     print(f"batch of 256: {len(res)} states sampled, worst rel L2 vs oracle {worst:.2e}")
     for s, ep, eh in res:
         assert ep < 1e-6 and eh < 1e-6, (s, grids[s][0], ep, eh)
+
+
+def test_uneven_batch_uniform_against_exact_collocation(ctx):
+    """The whole 256-state recipe (seed 2, M = 40) in one FP32 batch with a
+    uniform magnetization (0.3, -0.5, 0.8) in every state: 8 cells per state
+    (two corners, random interior) against the exact collocated potential
+    and field of the state's box (closed-form box kernels at the cell
+    centres).  Cubes (16..96 cells per edge) within 1e-6 relative L2 per
+    state.  The films (256 x 256 x 4/8/16) carry the M = 40 rule's own error
+    at 256 cells per edge (the rule is sized for a fixed smallest offset and
+    loses accuracy as the cells shrink): within 3e-5, not 1e-6."""
+    states = inputs.batch_grids(256, seed=2, with_fields=False)
+    grids = [(st.n, st.h) for st in states]
+    mv = np.array([0.3, -0.5, 0.8])
+    fields = [mv[:, None, None, None] * np.ones((3, n[2], n[1], n[0])) for n, _h in grids]
+    ctx.set_workspace_limit(64 << 30)
+    try:
+        b = ctx.batch(grids, M=40, prec="fp32")
+        _m, phi, h, off = _run_batch(ctx, b, fields, torch.float32)
+    finally:
+        ctx.set_workspace_limit(16 << 30)
+    phi, h = phi.cpu().numpy().astype(np.float64), h.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(11)
+    worst_cube, worst_film = 0.0, 0.0
+    for s, (n, hc) in enumerate(grids):
+        nx, ny, nz = n
+        cells = [(0, 0, 0), (nz - 1, ny - 1, nx - 1)]
+        cells += [(int(rng.integers(nz)), int(rng.integers(ny)), int(rng.integers(nx))) for _ in range(6)]
+        ps = phi[off[s]:off[s + 1]].reshape(nz, ny, nx)
+        hs = h[3 * off[s]:3 * off[s + 1]].reshape(3, nz, ny, nx)
+        got = np.array([[ps[c]] + [hs[(k,) + c] for k in range(3)] for c in cells])
+        pts = np.array([((c[2] + 0.5) * hc[0], (c[1] + 0.5) * hc[1], (c[0] + 0.5) * hc[2]) for c in cells])
+        K, N = exact.box_kernels_at_points(pts, (0.0, 0.0, 0.0), (nx * hc[0], ny * hc[1], nz * hc[2]))
+        ref = np.concatenate([np.tensordot(mv, K, axes=1)[:, None], -np.tensordot(N, mv, axes=([1], [0])).T], axis=1)
+        err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        if s % 8 == 7:
+            worst_film = max(worst_film, err)
+            assert err < 3e-5, (s, n, err)
+        else:
+            worst_cube = max(worst_cube, err)
+            assert err < 1e-6, (s, n, err)
+    print(f"batch of 256, uniform m vs exact collocation: worst cube {worst_cube:.2e}, worst film {worst_film:.2e}")
 
 
 def test_batch_free_waits_for_its_work(ctx):
