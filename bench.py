@@ -496,7 +496,8 @@ def headline(args):
     f = ctx.assemble((n, n, n), (1.0 / n,) * 3, M=40, c0=2.15)
     results = {}
     ref = None
-    for prec in args.precs.split(","):
+    # FP64 first: it is the headline and the reference of the other precisions
+    for prec in ["fp64"] + [p for p in args.precs.split(",") if p and p != "fp64"]:
         dt = torch.float64 if prec == "fp64" else torch.float32
         m = torch.from_numpy(m_host).to(device="cuda", dtype=dt)
         phi = torch.empty((n, n, n), dtype=dt, device="cuda")

@@ -377,20 +377,21 @@ demag_status launch_bf_n(hipStream_t s, int rb, int cb, const StagePlan &sp, con
 // registers, the products formed from the parts as above.  Tile: 64 rows
 // (4 blocks of 16) x 64 CB columns (4 waves of CB blocks of 16), K chunks of
 // 32 (one 16x16x32 step): per chunk the A tiles of the NOUT outputs (64 x 32
-// per part, a 16-byte row segment per thread) and the FP32 input tile (32 x 64 CB)
-// go through LDS; the next chunk's are loaded into registers while the
-// current one is multiplied.  A lane's fragment of a row block is one
-// 16-byte LDS read per part (rows padded to 40 values); its input fragment is
-// eight values down one column of the input tile, split into parts.
+// per part, a 16-byte row segment per thread) go through LDS, and each lane
+// loads its input fragments (eight values down each of its CB columns)
+// straight from memory into registers, as the Toeplitz kernel does, and
+// splits them before the chunk's barrier; the next chunk's A segments and
+// inputs are loaded while the current one is multiplied.  A lane's fragment
+// of a row block is one 16-byte LDS read per part (rows padded to 40
+// values).  Staging the inputs through LDS as well measured 1.5 % slower
+// (more LDS and vector instructions around the same products).
 template <int NOUT, int PARTS, bool TRANS, int CB>
 __global__ __launch_bounds__(256, 2) void k_dense_bf16(const MPJob *__restrict__ jobs,
                                                        const MPTerm *__restrict__ terms, Bufs bufs,
                                                        const uint16_t *__restrict__ parts, size_t part_stride,
                                                        MPGeom g, int col_tiles, int beta) {
-  constexpr int KC = 32, AS = 40, NC = 64 * CB, BS = NC + 4;
-  constexpr int kBr = KC * NC / 256;   // input tile values per thread
+  constexpr int KC = 32, AS = 40, NC = 64 * CB;
   __shared__ uint4 As[NOUT][PARTS][64][AS / 8];
-  __shared__ float Bs[KC][BS];
   const MPJob job = jobs[blockIdx.y];
   if (job.nterms <= 0) return;
   const int ct = blockIdx.x % col_tiles, rg = blockIdx.x / col_tiles;
@@ -399,12 +400,15 @@ __global__ __launch_bounds__(256, 2) void k_dense_bf16(const MPJob *__restrict__
   const int row0 = rg * 64;
   // A staging: thread -> (row t / 4, 8 K values at (t % 4) * 8)
   const int ar = tid >> 2, ak = (tid & 3) * 8;
-  // input staging: thread -> (column t % NC, rows t / NC + (256 / NC) q)
-  constexpr int kBrows = 256 / NC;
-  const int bc = tid % NC, bk = tid / NC;
-  const int cs = ct * NC + bc;
-  const int cl = cs < g.C ? cs : g.C - 1;
-  const size_t cin = size_t(cl / g.C1) * g.in_S1 + size_t(cl % g.C1);
+  // input fragments straight from memory: K rows 8 kq .. 8 kq + 7 of this
+  // lane's columns (past C: column C - 1, never stored)
+  size_t cin[CB];
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const int cs = ct * NC + wave * 16 * CB + 16 * cb + (lane & 15);
+    const int cl = cs < g.C ? cs : g.C - 1;
+    cin[cb] = size_t(cl / g.C1) * g.in_S1 + size_t(cl % g.C1);
+  }
   f4 acc[NOUT][4][CB];
 #pragma unroll
   for (int o = 0; o < NOUT; ++o)
@@ -415,16 +419,18 @@ __global__ __launch_bounds__(256, 2) void k_dense_bf16(const MPJob *__restrict__
   const int nch = (n + KC - 1) / KC;
   const int nq = job.nterms * nch;
   uint4 av[NOUT][PARTS];
-  float bv[kBr];
+  float raw[CB][8];
   auto load = [&](int q) {
     const int t = q / nch, j0 = (q - t * nch) * KC;
     const MPTerm &tm = terms[job.term0 + t];
-    const float *in = static_cast<const float *>(bufs.p[tm.in_buf]) + tm.in_off + cin;
+    const float *in = static_cast<const float *>(bufs.p[tm.in_buf]) + tm.in_off;
 #pragma unroll
-    for (int r = 0; r < kBr; ++r) {
-      const int j = j0 + bk + kBrows * r;
-      bv[r] = j < n ? in[size_t(j) * g.kstride] : 0.0f;
-    }
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int j = j0 + 8 * kq + e;
+        raw[cb][e] = j < n ? in[cin[cb] + size_t(j) * g.kstride] : 0.0f;
+      }
     const int i = row0 + ar, j = j0 + ak;
 #pragma unroll
     for (int o = 0; o < NOUT; ++o)
@@ -445,22 +451,17 @@ __global__ __launch_bounds__(256, 2) void k_dense_bf16(const MPJob *__restrict__
   load(0);
   for (int q = 0; q < nq; ++q) {
 #pragma unroll
-    for (int r = 0; r < kBr; ++r) Bs[bk + kBrows * r][bc] = bv[r];
-#pragma unroll
     for (int o = 0; o < NOUT; ++o)
 #pragma unroll
       for (int p = 0; p < PARTS; ++p) As[o][p][ar][ak / 8] = av[o][p];
-    __syncthreads();
-    if (q + 1 < nq) load(q + 1);
-    // input fragments: rows 8 kq .. 8 kq + 7 of this lane's columns, split
     Frag bh[CB], bl[CB], bl2[CB];
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-      const int wc = wave * 16 * CB + 16 * cb + (lane & 15);
+    for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
       for (int e = 0; e < 4; ++e)
-        split_pair(Bs[8 * kq + 2 * e][wc], Bs[8 * kq + 2 * e + 1][wc], bh[cb].p[e], bl[cb].p[e], bl2[cb].p[e]);
-    }
+        split_pair(raw[cb][2 * e], raw[cb][2 * e + 1], bh[cb].p[e], bl[cb].p[e], bl2[cb].p[e]);
+    __syncthreads();
+    if (q + 1 < nq) load(q + 1);
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
