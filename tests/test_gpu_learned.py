@@ -303,6 +303,35 @@ def test_learned_rule_needs_fewer_nodes_than_plain_sinc(ctx, gain):
     assert r["R"] <= 0.8 * plain
 
 
+def test_mixed_learned_apply_against_exact_collocation(ctx, gain):
+    """The mixed form at 128^3: the learned rule (certified within 1e-6) with
+    BF16x3 products, for a uniform magnetization, at every cell against the
+    exact collocated potential and field of the cube (closed-form box
+    kernels of the whole cube at the cell centres).  The FP64 apply with the
+    same rule shows the rule's own error, which its certificate bounds for
+    the operator; the BF16x3 apply adds its rounding and stays within the
+    1e-6 target."""
+    from oracle import exact
+    r = gain[0]["network"]
+    n = 128
+    f = ctx.assemble((n, n, n), (1 / n,) * 3, t=r["t"], alpha=r["alpha"])
+    mv = np.array([0.3, -0.5, 0.8])
+    m = mv[:, None, None, None] * np.ones((3, n, n, n))
+    c = (np.arange(n) + 0.5) / n
+    pts = np.stack(np.meshgrid(c, c, c, indexing="ij")[::-1], axis=-1)
+    K, N = exact.box_kernels_at_points(pts, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    pe, he = np.tensordot(mv, K, axes=1), -np.tensordot(N, mv, axes=([1], [0]))
+    errs = {}
+    for prec, dt in (("fp64", torch.float64), ("bf16x3", torch.float32)):
+        phi, hf = ctx.apply_full(f, torch.from_numpy(m).to(device="cuda", dtype=dt), prec=prec)
+        torch.cuda.synchronize()
+        p, h = phi.double().cpu().numpy(), hf.double().cpu().numpy()
+        errs[prec] = (np.linalg.norm(p - pe) / np.linalg.norm(pe), np.linalg.norm(h - he) / np.linalg.norm(he))
+    print(f"learned rule R' = {r['R']} (certified {r['judged']:.2e}) vs exact collocation, uniform 128^3:", errs)
+    assert max(errs["fp64"]) <= r["judged"]
+    assert max(errs["bf16x3"]) < 1e-6
+
+
 def test_network_versus_search_without_network(ctx, gain):
     """Ablation.  Without the network, bisection over R' finds the smallest
     fitted rule; the network's error head lands within 2 nodes of it with
