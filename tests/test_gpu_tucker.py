@@ -130,6 +130,32 @@ def test_potential_full_size_sampled(ctx, kind):
     assert max(core.shape) < 64
 
 
+def test_potential_full_size_uniform_against_exact_collocation(ctx):
+    """Alg. scpot_fft_tucker's uniform-magnetization case at n = 4096 per axis
+    with the 64-node theorem-step rule (tol 1e-8): 8 cells of the compressed
+    potential against the exact collocated potential of the uniformly
+    magnetized cube (closed-form box kernels of the whole cube at the cell
+    centres), within 30 tol."""
+    from oracle import exact
+    n, tol = (4096, 4096, 4096), 1e-8
+    h = _h(n)
+    mag = inputs.tucker_magnetization(n, "uniform", (2, 2, 2))
+    mv = np.array([np.einsum("abc,a,b,c->", mag[q][0], mag[q][1][0][0], mag[q][1][1][0], mag[q][1][2][0])
+                   for q in range(3)])
+    kt = ctx.ktucker(ctx.assemble(n, h, M=64, step_rule=1), tol)
+    core, rows = ctx.potential_tucker(kt, [_dev(mag[q]) for q in range(3)], tol)
+    core, rows = _host(core, rows)
+    rng = np.random.default_rng(17)
+    cells = [tuple(int(v) for v in rng.integers(0, 4096, 3)) for _ in range(6)] + [(0, 0, 0), (4095, 2048, 17)]
+    got = np.array([np.einsum("abc,a,b,c->", core, rows[0][i], rows[1][j], rows[2][k]) for i, j, k in cells])
+    pts = (np.array(cells, dtype=np.float64) + 0.5) * h[0]
+    K, _N = exact.box_kernels_at_points(pts, (0.0, 0.0, 0.0), (1.0, 1.0, 1.0))
+    ref = np.tensordot(mv, K, axes=1)
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    print(f"4096^3 uniform, 64-node theorem rule: ranks {core.shape}, rel err vs exact collocation {err:.2e}")
+    assert err < 30 * tol
+
+
 @pytest.mark.parametrize("tol", [1e-3, 1e-7, 1e-12])
 def test_tucker_sum_matches_oracle(ctx, tol):
     rng = np.random.default_rng(14)
